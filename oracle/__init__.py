@@ -1,0 +1,196 @@
+"""CPU oracle for the periodic 1D heat stencil -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library never imports, links or
+calls it and shares no code with it.
+
+Two independent implementations of the same definition live here:
+
+* ``heat_oracle.c`` (plain C, built with ``-O2 -ffp-contract=off``), loaded
+  through ctypes: ``solve``, ``solve_parts``, ``cone``, ``solve_f32``,
+  ``cone_f32``, ``solve_f32c``, ``cone_f32c``;
+* NumPy ring shifts (``np_solve``, ``np_solve_f32``, ``np_solve_f32c``), one
+  ufunc per arithmetic operation, so every operation is rounded on its own
+  exactly as in the C code.
+
+Both follow the paper's Section 2 ("Model problem"): Eq. (heat:discrete) with
+r = alpha*dt/h^2, the periodic boundary u(t, x) = u(t, L + x), and the
+segment-plus-ghost-zone parallel algorithm of that section's last paragraph.
+The FP32 and compensated-FP32 forms are the library's reduced-precision forms
+of the same update; their definition is in ``heat_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "heat_oracle.c")
+_LIB = os.path.join(_HERE, "libheat_oracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile heat_oracle.c with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+            "-fexcess-precision=standard", "-shared", "-fPIC", "-o", tmp, _SRC,
+        ])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    d, f, i64 = ctypes.c_double, ctypes.c_float, ctypes.c_int64
+    p = ctypes.c_void_p
+    lib.heat_oracle_solve.argtypes = [p, p, i64, d, i64]
+    lib.heat_oracle_solve.restype = None
+    lib.heat_oracle_solve_parts.argtypes = [p, p, i64, i64, d, i64]
+    lib.heat_oracle_solve_parts.restype = None
+    lib.heat_oracle_cone.argtypes = [p, i64, d]
+    lib.heat_oracle_cone.restype = d
+    lib.heat_oracle_solve_f32.argtypes = [p, p, i64, f, i64]
+    lib.heat_oracle_solve_f32.restype = None
+    lib.heat_oracle_cone_f32.argtypes = [p, i64, f]
+    lib.heat_oracle_cone_f32.restype = f
+    lib.heat_oracle_solve_f32c.argtypes = [p, p, p, i64, f, i64, i64]
+    lib.heat_oracle_solve_f32c.restype = None
+    lib.heat_oracle_cone_f32c.argtypes = [p, i64, f, i64]
+    lib.heat_oracle_cone_f32c.restype = f
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _f64(u) -> np.ndarray:
+    return np.ascontiguousarray(u, dtype=np.float64)
+
+
+def _f32(u) -> np.ndarray:
+    return np.ascontiguousarray(u, dtype=np.float32)
+
+
+# ---------------------------------------------------------------- C oracle
+
+def solve(u0, r: float, nt: int) -> np.ndarray:
+    """nt steps of Eq. (heat:discrete) on the periodic ring, binary64."""
+    a = _f64(u0)
+    out = np.empty_like(a)
+    if a.size:
+        _load().heat_oracle_solve(_ptr(a), _ptr(out), a.size, float(r), int(nt))
+    return out
+
+
+def solve_parts(u0, nparts: int, r: float, nt: int) -> np.ndarray:
+    """Segmented solver with a ghost-zone exchange every step (Section 2)."""
+    a = _f64(u0)
+    if not 1 <= nparts <= a.size:
+        raise ValueError("need 1 <= nparts <= N")
+    out = np.empty_like(a)
+    _load().heat_oracle_solve_parts(_ptr(a), _ptr(out), a.size, int(nparts), float(r), int(nt))
+    return out
+
+
+def cone_window(u0: np.ndarray, i: int, nt: int) -> np.ndarray:
+    """The 2*nt+1 initial values around cell i, taken around the ring."""
+    n = u0.size
+    idx = (np.arange(i - nt, i + nt + 1, dtype=np.int64)) % n
+    return u0[idx]
+
+
+def cone(u0, i: int, r: float, nt: int) -> float:
+    """Value of cell i after nt steps, from its light cone only (binary64)."""
+    w = _f64(cone_window(np.asarray(u0), int(i), int(nt)))
+    return float(_load().heat_oracle_cone(_ptr(w), int(nt), float(r)))
+
+
+def solve_f32(u0, r: float, nt: int) -> np.ndarray:
+    """Plain binary32 form: c + r*((l - c) + (q - c))."""
+    a = _f32(u0)
+    out = np.empty_like(a)
+    if a.size:
+        _load().heat_oracle_solve_f32(_ptr(a), _ptr(out), a.size, np.float32(r), int(nt))
+    return out
+
+
+def cone_f32(u0, i: int, r: float, nt: int) -> np.float32:
+    w = _f32(cone_window(np.asarray(u0), int(i), int(nt)))
+    return np.float32(_load().heat_oracle_cone_f32(_ptr(w), int(nt), np.float32(r)))
+
+
+def solve_f32c(u0, r: float, nt: int, T: int, return_pair: bool = False):
+    """Compensated binary32 form in rounds of T steps.
+
+    With ``return_pair`` the last fold is skipped and (u, e) is returned, whose
+    unevaluated sum carries the compensated state.
+    """
+    a = _f32(u0)
+    out = np.empty_like(a)
+    e = np.empty_like(a) if return_pair else None
+    if a.size:
+        _load().heat_oracle_solve_f32c(_ptr(a), _ptr(out), _ptr(e) if e is not None else None,
+                                       a.size, np.float32(r), int(nt), int(T))
+    return (out, e) if return_pair else out
+
+
+def cone_f32c(u0, i: int, r: float, nt: int, T: int) -> np.float32:
+    w = _f32(cone_window(np.asarray(u0), int(i), int(nt)))
+    return np.float32(_load().heat_oracle_cone_f32c(_ptr(w), int(nt), np.float32(r), int(T)))
+
+
+# -------------------------------------------------------- NumPy second oracle
+
+def np_solve(u0, r: float, nt: int) -> np.ndarray:
+    """Same definition with NumPy ring shifts; one rounding per ufunc."""
+    a = _f64(u0).copy()
+    r = np.float64(r)
+    for _ in range(int(nt)):
+        left = np.roll(a, 1)     # left[i]  = a[i-1 mod N]
+        right = np.roll(a, -1)   # right[i] = a[i+1 mod N]
+        a = a + r * ((left - 2.0 * a) + right)
+    return a
+
+
+def np_solve_f32(u0, r: float, nt: int) -> np.ndarray:
+    a = _f32(u0).copy()
+    r = np.float32(r)
+    for _ in range(int(nt)):
+        left = np.roll(a, 1)
+        right = np.roll(a, -1)
+        a = a + r * ((left - a) + (right - a))
+    return a
+
+
+def np_solve_f32c(u0, r: float, nt: int, T: int) -> np.ndarray:
+    u = _f32(u0).copy()
+    r = np.float32(r)
+    done = 0
+    while done < nt:
+        s = min(T, nt - done)
+        e = np.zeros_like(u)
+        for _ in range(s):
+            l, q = np.roll(u, 1), np.roll(u, -1)
+            el, eq = np.roll(e, 1), np.roll(e, -1)
+            d = r * (((l - u) + (q - u)) + ((el - e) + (eq - e)))
+            y = d + e
+            t = u + y
+            e = y - (t - u)
+            u = t
+        u = u + e
+        done += s
+    return u

@@ -1,0 +1,293 @@
+/*
+ * heat_oracle.c -- CPU oracle for the periodic 1D heat stencil.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark load it; the GPU
+ * library never includes, links or calls it, and it shares no code with it.
+ *
+ * What it computes (paper, Section 2 "Model problem"):
+ *   - Eq. (heat:discrete): one explicit-Euler step of the heat equation with a
+ *     second-order central difference,
+ *         u(t+dt, x_i) = u(t, x_i) + dt*alpha*(u_{i-1} - 2 u_i + u_{i+1}) / h^2,
+ *     written here with r = alpha*dt/h^2.  The printed denominator is garbled
+ *     (it reads "2h"); the consistent second-order Laplacian divides by h^2,
+ *     and the caller passes r directly, so the reading only fixes what r means.
+ *   - the periodic boundary condition u(t, x) = u(t, L + x): index i-1 of
+ *     cell 0 is cell N-1, and index i+1 of cell N-1 is cell 0;
+ *   - every right-hand-side value is taken at time t (Jacobi update: the
+ *     new array is written from the old one, never in place);
+ *   - the parallel algorithm of Section 2 (last paragraph): the grid is cut
+ *     into contiguous segments, each one updated on its own after its ghost
+ *     cells have been received from the two neighbouring segments.
+ *
+ * Arithmetic: IEEE binary64, round to nearest even, evaluated exactly in the
+ * order written (build with -ffp-contract=off, no -ffast-math):
+ *         new = c + r * ((l - 2.0 * c) + q)
+ * 2.0*c is exact, so (l - 2.0*c) + q is the left-to-right reading of the
+ * paper's numerator.
+ *
+ * The FP32 forms are not in the paper; they are the reduced-precision forms of
+ * the same update that the GPU library offers:
+ *   - plain FP32:  new = c + r * ((l - c) + (q - c))   (all in binary32)
+ *   - compensated FP32: the state is the unevaluated sum u + e of two binary32
+ *     numbers.  One step is
+ *         d  = r * (((l - c) + (q - c)) + ((el - ec) + (eq - ec)))
+ *         y  = d + ec
+ *         t  = c + y
+ *         e' = y - (t - c)          (Fast2Sum error term of c + y)
+ *         u' = t
+ *     Steps are grouped into rounds of T steps; at the end of every round
+ *     (and at the end of the run) u := fl32(u + e), e := 0.
+ *
+ * Error behaviour: no argument checks beyond what is needed not to crash
+ * (N < 1 or nt < 0 do nothing); r is NOT range-checked, so unstable r can be
+ * exercised as a negative control.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* One Jacobi step over the whole ring (Eq. heat:discrete + periodic BC). */
+static void step_ring_f64(const double *a, double *b, int64_t N, double r)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        double l = a[(i - 1 + N) % N];
+        double c = a[i];
+        double q = a[(i + 1) % N];
+        b[i] = c + r * ((l - 2.0 * c) + q);
+    }
+}
+
+/* Unpartitioned solver: nt steps of Eq. (heat:discrete) on the ring. */
+void heat_oracle_solve(const double *u0, double *out, int64_t N, double r, int64_t nt)
+{
+    if (N < 1) return;
+    double *a = (double *)malloc((size_t)N * sizeof(double));
+    double *b = (double *)malloc((size_t)N * sizeof(double));
+    memcpy(a, u0, (size_t)N * sizeof(double));
+    for (int64_t n = 0; n < nt; ++n) {
+        step_ring_f64(a, b, N, r);
+        double *t = a; a = b; b = t;
+    }
+    memcpy(out, a, (size_t)N * sizeof(double));
+    free(a);
+    free(b);
+}
+
+/*
+ * Partitioned solver (Section 2, last paragraph): nparts contiguous segments,
+ * segment p = [floor(p*N/P), floor((p+1)*N/P)).  Each segment keeps its own
+ * array with one ghost cell on each side.  Every step first exchanges ghost
+ * zones (segment p receives the last cell of p-1 and the first cell of p+1,
+ * both taken mod P), then every segment applies the update to its own cells.
+ * The result must equal the unpartitioned solver exactly.
+ */
+void heat_oracle_solve_parts(const double *u0, double *out, int64_t N, int64_t nparts,
+                             double r, int64_t nt)
+{
+    if (N < 1 || nparts < 1 || nparts > N) return;
+    int64_t P = nparts;
+    int64_t *start = (int64_t *)malloc((size_t)(P + 1) * sizeof(int64_t));
+    for (int64_t p = 0; p <= P; ++p) start[p] = (p * N) / P;
+    double **seg = (double **)malloc((size_t)P * sizeof(double *));
+    double **nxt = (double **)malloc((size_t)P * sizeof(double *));
+    for (int64_t p = 0; p < P; ++p) {
+        int64_t len = start[p + 1] - start[p];
+        seg[p] = (double *)malloc((size_t)(len + 2) * sizeof(double));
+        nxt[p] = (double *)malloc((size_t)(len + 2) * sizeof(double));
+        memcpy(seg[p] + 1, u0 + start[p], (size_t)len * sizeof(double));
+    }
+    for (int64_t n = 0; n < nt; ++n) {
+        /* ghost exchange: every value comes from the state at step n */
+        for (int64_t p = 0; p < P; ++p) {
+            int64_t pl = (p - 1 + P) % P, pr = (p + 1) % P;
+            int64_t len_l = start[pl + 1] - start[pl];
+            seg[p][0] = seg[pl][len_l];          /* last interior cell of p-1 */
+            int64_t len = start[p + 1] - start[p];
+            seg[p][len + 1] = seg[pr][1];        /* first interior cell of p+1 */
+        }
+        /* local sweeps */
+        for (int64_t p = 0; p < P; ++p) {
+            int64_t len = start[p + 1] - start[p];
+            const double *a = seg[p];
+            double *b = nxt[p];
+            for (int64_t j = 1; j <= len; ++j) {
+                double l = a[j - 1], c = a[j], q = a[j + 1];
+                b[j] = c + r * ((l - 2.0 * c) + q);
+            }
+        }
+        double **t = seg; seg = nxt; nxt = t;
+    }
+    for (int64_t p = 0; p < P; ++p) {
+        int64_t len = start[p + 1] - start[p];
+        memcpy(out + start[p], seg[p] + 1, (size_t)len * sizeof(double));
+        free(seg[p]);
+        free(nxt[p]);
+    }
+    free(seg);
+    free(nxt);
+    free(start);
+}
+
+/*
+ * Light cone of one cell: w holds the 2*nt+1 initial values centred on the
+ * cell (taken around the ring, so they may repeat when N <= 2*nt).  After s
+ * steps only the cells [s, 2*nt - s] of the window are still exact; each is
+ * computed with the very same operations as in the full ring, so the centre
+ * after nt steps is bit-identical to that cell of heat_oracle_solve.
+ */
+double heat_oracle_cone(const double *w, int64_t nt, double r)
+{
+    int64_t len = 2 * nt + 1;
+    double *a = (double *)malloc((size_t)len * sizeof(double));
+    double *b = (double *)malloc((size_t)len * sizeof(double));
+    memcpy(a, w, (size_t)len * sizeof(double));
+    for (int64_t s = 1; s <= nt; ++s) {
+        for (int64_t j = s; j <= len - 1 - s; ++j) {
+            double l = a[j - 1], c = a[j], q = a[j + 1];
+            b[j] = c + r * ((l - 2.0 * c) + q);
+        }
+        double *t = a; a = b; b = t;
+    }
+    double v = a[nt];
+    free(a);
+    free(b);
+    return v;
+}
+
+/* ---------------------------------------------------------------- FP32 */
+
+void heat_oracle_solve_f32(const float *u0, float *out, int64_t N, float r, int64_t nt)
+{
+    if (N < 1) return;
+    float *a = (float *)malloc((size_t)N * sizeof(float));
+    float *b = (float *)malloc((size_t)N * sizeof(float));
+    memcpy(a, u0, (size_t)N * sizeof(float));
+    for (int64_t n = 0; n < nt; ++n) {
+        for (int64_t i = 0; i < N; ++i) {
+            float l = a[(i - 1 + N) % N];
+            float c = a[i];
+            float q = a[(i + 1) % N];
+            b[i] = c + r * ((l - c) + (q - c));
+        }
+        float *t = a; a = b; b = t;
+    }
+    memcpy(out, a, (size_t)N * sizeof(float));
+    free(a);
+    free(b);
+}
+
+float heat_oracle_cone_f32(const float *w, int64_t nt, float r)
+{
+    int64_t len = 2 * nt + 1;
+    float *a = (float *)malloc((size_t)len * sizeof(float));
+    float *b = (float *)malloc((size_t)len * sizeof(float));
+    memcpy(a, w, (size_t)len * sizeof(float));
+    for (int64_t s = 1; s <= nt; ++s) {
+        for (int64_t j = s; j <= len - 1 - s; ++j) {
+            float l = a[j - 1], c = a[j], q = a[j + 1];
+            b[j] = c + r * ((l - c) + (q - c));
+        }
+        float *t = a; a = b; b = t;
+    }
+    float v = a[nt];
+    free(a);
+    free(b);
+    return v;
+}
+
+/* ------------------------------------------------------ compensated FP32 */
+
+/* One compensated step of the pair (u, e) on the ring. */
+static void step_ring_f32c(const float *u, const float *e, float *un, float *en,
+                           int64_t N, float r)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t il = (i - 1 + N) % N, iq = (i + 1) % N;
+        float l = u[il], c = u[i], q = u[iq];
+        float el = e[il], ec = e[i], eq = e[iq];
+        float d = r * (((l - c) + (q - c)) + ((el - ec) + (eq - ec)));
+        float y = d + ec;
+        float t = c + y;
+        en[i] = y - (t - c);
+        un[i] = t;
+    }
+}
+
+/*
+ * Compensated FP32 over nt steps in rounds of T steps (T >= 1; the last round
+ * may be shorter).  At every round end u := fl32(u + e) and e := 0.  If
+ * e_out is not NULL the run stops short of the final fold: out receives u and
+ * e_out receives e of the last round, so that the unrounded pair can be
+ * inspected.
+ */
+void heat_oracle_solve_f32c(const float *u0, float *out, float *e_out, int64_t N, float r,
+                            int64_t nt, int64_t T)
+{
+    if (N < 1) return;
+    if (T < 1) T = 1;
+    float *u = (float *)malloc((size_t)N * sizeof(float));
+    float *e = (float *)calloc((size_t)N, sizeof(float));
+    float *un = (float *)malloc((size_t)N * sizeof(float));
+    float *en = (float *)malloc((size_t)N * sizeof(float));
+    memcpy(u, u0, (size_t)N * sizeof(float));
+    int64_t done = 0;
+    while (done < nt) {
+        int64_t s = nt - done < T ? nt - done : T;
+        for (int64_t i = 0; i < N; ++i) e[i] = 0.0f;
+        for (int64_t k = 0; k < s; ++k) {
+            step_ring_f32c(u, e, un, en, N, r);
+            float *t1 = u; u = un; un = t1;
+            float *t2 = e; e = en; en = t2;
+        }
+        done += s;
+        if (done < nt || e_out == NULL)
+            for (int64_t i = 0; i < N; ++i) u[i] = u[i] + e[i];
+    }
+    memcpy(out, u, (size_t)N * sizeof(float));
+    if (e_out) {
+        if (nt > 0) memcpy(e_out, e, (size_t)N * sizeof(float));
+        else memset(e_out, 0, (size_t)N * sizeof(float));
+    }
+    free(u); free(e); free(un); free(en);
+}
+
+/*
+ * Light cone of one cell for the compensated form: w holds the 2*nt+1 initial
+ * binary32 values centred on the cell.  Rounds of T steps as above; the fold
+ * u := fl32(u + e) is applied to every still-exact cell of the window.
+ */
+float heat_oracle_cone_f32c(const float *w, int64_t nt, float r, int64_t T)
+{
+    if (T < 1) T = 1;
+    int64_t len = 2 * nt + 1;
+    float *u = (float *)malloc((size_t)len * sizeof(float));
+    float *e = (float *)calloc((size_t)len, sizeof(float));
+    float *un = (float *)malloc((size_t)len * sizeof(float));
+    float *en = (float *)malloc((size_t)len * sizeof(float));
+    memcpy(u, w, (size_t)len * sizeof(float));
+    int64_t s = 0;
+    while (s < nt) {
+        int64_t rs = nt - s < T ? nt - s : T;
+        for (int64_t j = 0; j < len; ++j) e[j] = 0.0f;
+        for (int64_t k = 0; k < rs; ++k) {
+            ++s;
+            for (int64_t j = s; j <= len - 1 - s; ++j) {
+                float l = u[j - 1], c = u[j], q = u[j + 1];
+                float el = e[j - 1], ec = e[j], eq = e[j + 1];
+                float d = r * (((l - c) + (q - c)) + ((el - ec) + (eq - ec)));
+                float y = d + ec;
+                float t = c + y;
+                en[j] = y - (t - c);
+                un[j] = t;
+            }
+            float *t1 = u; u = un; un = t1;
+            float *t2 = e; e = en; en = t2;
+        }
+        for (int64_t j = s; j <= len - 1 - s; ++j) u[j] = u[j] + e[j];
+    }
+    float v = u[nt];
+    free(u); free(e); free(un); free(en);
+    return v;
+}

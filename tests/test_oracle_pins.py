@@ -1,0 +1,293 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here re-types the oracle's formula.  Each check comes from an
+independent source:
+
+* exact rational arithmetic of the matrix (I + r L)^n applied to u0, with L
+  the circulant second difference built from its definition (brute force);
+* the discrete Fourier transform (numpy.fft): every mode m decays by the
+  closed-form amplification factor g_m = 1 - 4 r sin^2(pi m / N);
+* conservation of sum(u) on a ring, the maximum principle for r <= 1/2;
+* exact special cases (constant state, r = 0, the Nyquist mode);
+* structural invariances (partitions, shifts, composition, scaling by 2^k);
+* a negative control with an unstable r.
+
+Paper anchors: Section 2 ("Model problem") -- Eq. (heat), Eq. (heat:discrete),
+the grid x_i = i*h, the periodic condition u(t, x) = u(t, L + x), and the
+segmented algorithm with ghost zones of that section's last paragraph.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_01117_amd import inputs
+
+DYADIC_R = [Fraction(0), Fraction(1, 8), Fraction(1, 4), Fraction(3, 8), Fraction(1, 2)]
+
+
+def exact_solution(u0, r: Fraction, nt: int):
+    """(I + r L)^nt u0 in exact rationals, L = circulant second difference.
+
+    The matrix is assembled entry by entry from the ring's neighbour relation
+    (cell i touches (i-1) mod N and (i+1) mod N), which for N = 1 and N = 2
+    makes the same cell appear more than once, exactly as the periodic
+    extension of the grid does."""
+    N = len(u0)
+    M = [[Fraction(0)] * N for _ in range(N)]
+    for i in range(N):
+        M[i][i] += 1 - 2 * r
+        M[i][(i - 1) % N] += r
+        M[i][(i + 1) % N] += r
+    v = [Fraction(float(x)) for x in u0]
+    for _ in range(nt):
+        v = [sum(M[i][j] * v[j] for j in range(N)) for i in range(N)]
+    return v
+
+
+def as_fractions(a):
+    return [Fraction(float(x)) for x in a]
+
+
+# ------------------------------------------------------------ P1 brute force
+
+@pytest.mark.parametrize("N", list(range(1, 17)))
+def test_brute_force_exact_fp64(N):
+    rng = np.random.default_rng(100 + N)
+    for r in DYADIC_R:
+        nt = int(rng.integers(0, 13))
+        u0 = inputs.small_integer_ring(N, (7, N, int(r * 8)))
+        want = exact_solution(u0, r, nt)
+        got = oracle.solve(u0, float(r), nt)
+        assert as_fractions(got) == want, (N, r, nt)
+        # every partition count gives the same exact result (Section 2, last paragraph)
+        for P in range(1, N + 1):
+            gp = oracle.solve_parts(u0, P, float(r), nt)
+            assert as_fractions(gp) == want, (N, P, r, nt)
+        assert as_fractions(oracle.np_solve(u0, float(r), nt)) == want
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 8, 12])
+def test_brute_force_exact_fp32_forms(N):
+    # binary32 holds the exact values for nt <= 6 (3 + 3*6 bits < 24)
+    for r in DYADIC_R:
+        for nt in (0, 1, 2, 6):
+            u0 = inputs.small_integer_ring(N, (8, N, nt)).astype(np.float32)
+            want = exact_solution(u0, r, nt)
+            assert as_fractions(oracle.solve_f32(u0, float(r), nt)) == want
+            assert as_fractions(oracle.np_solve_f32(u0, float(r), nt)) == want
+            for T in (1, 2, 4, 100):
+                assert as_fractions(oracle.solve_f32c(u0, float(r), nt, T)) == want
+                u, e = oracle.solve_f32c(u0, float(r), nt, T, return_pair=True)
+                assert as_fractions(u) == want and not np.any(e)
+
+
+def _mutants():
+    """Plausible mistakes, written as full-ring NumPy steppers."""
+    def make(step):
+        def run(u0, r, nt):
+            a = np.asarray(u0, dtype=np.float64).copy()
+            for _ in range(nt):
+                a = step(a, r)
+            return a
+        return run
+
+    def gauss_seidel(a, r):            # in-place sweep instead of Jacobi
+        a = a.copy()
+        n = a.size
+        for i in range(n):
+            a[i] = a[i] + r * ((a[i - 1] - 2 * a[i]) + a[(i + 1) % n])
+        return a
+
+    return {
+        "dropped_right": make(lambda a, r: a + r * (np.roll(a, 1) - 2 * a)),
+        "wrong_sign": make(lambda a, r: a - r * ((np.roll(a, 1) - 2 * a) + np.roll(a, -1))),
+        "one_instead_of_two": make(lambda a, r: a + r * ((np.roll(a, 1) - a) + np.roll(a, -1))),
+        "shifted_index": make(lambda a, r: a + r * ((np.roll(a, 2) - 2 * a) + np.roll(a, -1))),
+        "no_wrap": make(lambda a, r: a + r * ((np.concatenate([[0.0], a[:-1]]) - 2 * a)
+                                              + np.concatenate([a[1:], [0.0]]))),
+        "gauss_seidel": make(gauss_seidel),
+        "denominator_2h": make(lambda a, r: a + (r / 2) * ((np.roll(a, 1) - 2 * a) + np.roll(a, -1))),
+    }
+
+
+@pytest.mark.parametrize("name", sorted(_mutants()))
+def test_brute_force_rejects_mutants(name):
+    """The exact check is strong enough to reject each plausible mistake."""
+    run = _mutants()[name]
+    caught = False
+    for N in (3, 5, 8):
+        u0 = inputs.small_integer_ring(N, (9, N))
+        for r in (Fraction(1, 4), Fraction(1, 2)):
+            if as_fractions(run(u0, float(r), 3)) != exact_solution(u0, r, 3):
+                caught = True
+    assert caught, name
+
+
+# ------------------------------------------------------------ P2 spectral
+
+@pytest.mark.parametrize("N,r,nt", [(1000, 0.5, 50), (4096, 0.25, 200), (99991, 0.37, 30)])
+def test_spectral_closed_form(N, r, nt):
+    u0 = inputs.uniform_ring(N, (2, N))
+    m = np.arange(N)
+    g = 1.0 - 4.0 * r * np.sin(np.pi * m / N) ** 2
+    want = np.fft.ifft(np.fft.fft(u0) * g ** nt).real
+    got = oracle.solve(u0, r, nt)
+    assert np.abs(got - want).max() / np.abs(want).max() <= 1e-12
+
+
+# ------------------------------------------------------------ P3 sine mode
+
+@pytest.mark.slow
+def test_sine_mode_decay_full_size():
+    """u0 = sin(2 pi 3 i / N), N = 1e6, r = 1/2, 100 steps: u_100 = g^100 u0
+    with g = cos(6 pi / N); the decay itself (1.78e-8) is resolved 1e5 times
+    above the tolerance."""
+    N, r, nt = 1_000_000, 0.5, 100
+    u0 = inputs.sine_mode(N, 3)
+    g = math.cos(2 * math.pi * 3 / N)
+    u = oracle.solve(u0, r, nt)
+    assert np.abs(u - g ** nt * u0).max() <= 1e-13
+    decay = np.abs(u - u0).max()
+    assert 1.7e-8 < decay < 1.85e-8
+    ratio = math.fsum(u * u0) / math.fsum(u0 * u0)
+    assert abs(ratio - g ** nt) <= 1e-3 * (1 - g ** nt)
+
+
+# ------------------------------------------------------------ P4 / P5 invariants
+
+@pytest.mark.parametrize("N,r,nt,seed", [(1000, 0.5, 100, 0), (77777, 0.3, 40, 1), (4097, 0.125, 300, 2)])
+def test_conservation_and_maximum_principle(N, r, nt, seed):
+    u0 = inputs.uniform_ring(N, seed) * 2.0 - 0.5
+    u = oracle.solve(u0, r, nt)
+    amax = np.abs(u0).max()
+    eps = 2.0 ** -53
+    drift = abs(math.fsum(u) - math.fsum(u0))
+    assert drift <= 8 * eps * N * nt * amax
+    delta = 4 * eps * nt * amax
+    assert u.min() >= u0.min() - delta and u.max() <= u0.max() + delta
+
+
+def test_maximum_principle_ramp():
+    """The paper's initial condition u(0, x_i) = x_i (h = 1) on the ring: the
+    jump at the wrap diffuses but stays inside [0, N-1]."""
+    N = 1000
+    u0 = inputs.ramp(N)
+    u = oracle.solve(u0, 0.5, 500)
+    assert u.min() >= -1e-9 and u.max() <= (N - 1) + 1e-9
+    assert abs(math.fsum(u) - math.fsum(u0)) <= 1e-7
+
+
+# ------------------------------------------------------------ P6 exact special cases
+
+def test_exact_special_cases():
+    N = 64
+    c = np.full(N, 0.7853981633974483)
+    for r in (0.1, 0.25, 0.5):
+        assert np.array_equal(oracle.solve(c, r, 17), c)
+    u0 = inputs.uniform_ring(N, 3)
+    assert np.array_equal(oracle.solve(u0, 0.0, 25), u0)
+    nyq = np.array([(-1.0) ** i for i in range(N)]) * 3.25
+    for n in range(6):
+        assert np.array_equal(oracle.solve(nyq, 0.5, n), ((-1.0) ** n) * nyq)
+    assert np.array_equal(oracle.solve(nyq, 0.25, 1), np.zeros(N))
+    # N = 1: both neighbours are the cell itself, nothing changes
+    one = np.array([2.5])
+    assert np.array_equal(oracle.solve(one, 0.5, 9), one)
+    # nt = 0 is the identity
+    assert np.array_equal(oracle.solve(u0, 0.4, 0), u0)
+
+
+# ------------------------------------------------------------ P7 structural
+
+def test_partition_invariance():
+    N = 1009
+    u0 = inputs.uniform_ring(N, 11)
+    want = oracle.solve(u0, 0.5, 37)
+    for P in (1, 2, 3, 10, 40, 1000, N):
+        assert np.array_equal(oracle.solve_parts(u0, P, 0.5, 37), want), P
+
+
+def test_shift_composition_scaling():
+    N = 2048
+    u0 = inputs.uniform_ring(N, 12)
+    r = 0.3
+    base = oracle.solve(u0, r, 50)
+    for s in (1, 63, 960, 1023, 2047):
+        assert np.array_equal(oracle.solve(np.roll(u0, s), r, 50), np.roll(base, s))
+    mid = oracle.solve(u0, r, 20)
+    assert np.array_equal(oracle.solve(mid, r, 30), base)
+    for k in (-3, 1, 7):
+        assert np.array_equal(oracle.solve(u0 * 2.0 ** k, r, 50), base * 2.0 ** k)
+
+
+# ------------------------------------------------------------ P8 negative control
+
+def test_unstable_r_grows():
+    """r = 0.6 lies outside the stable range: the Nyquist mode is amplified by
+    |1 - 4r| = 1.4 per step (the oracle itself does not damp anything)."""
+    N = 32
+    nyq = np.array([(-1.0) ** i for i in range(N)])
+    u = oracle.solve(nyq, 0.6, 20)
+    want = (-1.4) ** 20 * nyq
+    assert np.abs(u - want).max() <= 1e-12 * abs(want).max()
+
+
+# ------------------------------------------------------------ P9 two oracles agree
+
+@pytest.mark.parametrize("N,r,nt", [(1, 0.5, 3), (2, 0.25, 5), (1000, 0.5, 40), (1531, 0.1234, 25)])
+def test_c_and_numpy_oracles_bitwise(N, r, nt):
+    u0 = inputs.uniform_ring(N, (3, N))
+    assert np.array_equal(oracle.solve(u0, r, nt), oracle.np_solve(u0, r, nt))
+    f = u0.astype(np.float32)
+    assert np.array_equal(oracle.solve_f32(f, r, nt), oracle.np_solve_f32(f, r, nt))
+    for T in (1, 7, 32, nt):
+        assert np.array_equal(oracle.solve_f32c(f, r, nt, T), oracle.np_solve_f32c(f, r, nt, T))
+
+
+# ------------------------------------------------------------ light cones
+
+@pytest.mark.parametrize("N,nt", [(1, 5), (2, 7), (5, 9), (300, 40), (5000, 64)])
+def test_cone_matches_full_ring(N, nt):
+    u0 = inputs.uniform_ring(N, (4, N))
+    r = 0.45
+    full = oracle.solve(u0, r, nt)
+    f32 = u0.astype(np.float32)
+    full32 = oracle.solve_f32(f32, r, nt)
+    full32c = oracle.solve_f32c(f32, r, nt, 16)
+    for i in sorted({0, N - 1, N // 2, min(N - 1, 3)}):
+        assert oracle.cone(u0, i, r, nt) == full[i]
+        assert oracle.cone_f32(f32, i, r, nt) == full32[i]
+        assert oracle.cone_f32c(f32, i, r, nt, 16) == full32c[i]
+
+
+# ------------------------------------------------------------ compensated FP32
+
+def test_compensated_pair_tracks_fp64():
+    """With e carried through all steps, u + e follows the binary64 solution of
+    the same (binary32) initial state to ~1e-13, far below one binary32 ulp;
+    dropping the diffusion of e (a plausible mistake) gives ~1e-7."""
+    N, r, nt = 4096, 0.25, 1000
+    u0 = inputs.perturbed_ring(N, 2).astype(np.float32)
+    want = oracle.solve(u0.astype(np.float64), r, nt)
+    u, e = oracle.solve_f32c(u0, r, nt, nt, return_pair=True)
+    pair_err = np.abs(u.astype(np.float64) + e.astype(np.float64) - want).max()
+    assert pair_err <= 1e-11
+    folded = oracle.solve_f32c(u0, r, nt, nt)
+    # one final rounding: within half an ulp of binary32 near 1 (plus the pair error)
+    assert np.abs(folded - want).max() <= 2.0 ** -24 * 1.002 + 1e-11
+
+
+def test_compensated_rounds_beat_plain_fp32():
+    """Rounds of T steps: one binary32 rounding per round, so the error is set
+    by the number of rounds, not by the number of steps; plain binary32 loses
+    increments smaller than half an ulp and drifts much further."""
+    N, r, nt = 4096, 0.25, 1000
+    u0 = inputs.perturbed_ring(N, 2).astype(np.float32)
+    want = oracle.solve(u0.astype(np.float64), r, nt)
+    plain = np.abs(oracle.solve_f32(u0, r, nt) - want).max()
+    for T in (16, 32, 64):
+        err = np.abs(oracle.solve_f32c(u0, r, nt, T) - want).max()
+        assert err <= 1e-6 and err < plain / 50, (T, err, plain)
