@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the periodic 1D heat stencil on one MI355X.
+
+A step is one pass of the whole hot path over the ring: the binary64
+checksum of the initial state, ceil(nt/T) rounds of the temporal-blocked
+window kernel (or nt launches of the one-step sweep with --kernel step),
+and the checksum of the final state.  The state stays in HBM between steps
+(each step continues from the previous one's result: same size, same work).
+
+Default workload: a ring of 100 partitions x 1,000,000 cells (N = 1e8),
+r = 1/2, 1,000 explicit-Euler steps per pass, Uniform[0,1) seed 1, binary64.
+The metric is giga cell-updates per second (N * nt / time), the paper's
+"cells processed per second".
+
+Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector, published
+FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector (packed), published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ring_1e8",
+                    choices=["ring_1e6", "ring_1e8", "ring_1e8_perturbed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32c"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "tb", "step"])
+    ap.add_argument("--cells-per-lane", type=int, default=0)
+    ap.add_argument("--steps-per-round", type=int, default=0)
+    ap.add_argument("--waves-per-group", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=15,
+                    help="time steps of the full ring the CPU oracle runs as its sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(u0, r, steps, precision):
+    """The oracle, as it stands, on the host cores: single-threaded C."""
+    import numpy as np
+
+    import oracle
+    t0 = time.perf_counter()
+    if precision == "fp64":
+        oracle.solve(u0, r, steps)
+    elif precision == "fp32":
+        oracle.solve_f32(u0.astype(np.float32), r, steps)
+    else:
+        oracle.solve_f32c(u0.astype(np.float32), r, steps, 32)
+    dt = time.perf_counter() - t0
+    return {"value": round(u0.size * steps / dt / 1e9, 4), "unit": "GCUP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"full ring of {u0.size} cells, {steps} steps ({dt:.1f} s, single thread)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2307_01117_amd import heat, inputs
+
+    heat.load()
+    w = inputs.WORKLOADS[args.workload]
+    prec_name = args.precision or ("fp64" if args.workload != "ring_1e8_perturbed" else "fp32c")
+    prec = heat.PRECISIONS[prec_name]
+    kernel = {"auto": 0, "tb": heat.KERNEL_TB, "step": heat.KERNEL_STEP}[args.kernel]
+    cfg = dict(kernel=kernel, cells_per_lane=args.cells_per_lane,
+               steps_per_round=args.steps_per_round, waves_per_group=args.waves_per_group)
+    N, nparts, r, nt = w["N"], w["nparts"], w["r"], w["nt"]
+    pl = heat.plan(N, nt, prec, **cfg)
+
+    u0 = inputs.make_initial(w["init"], N, w["seed"])
+    dt = torch.float64 if prec == heat.FP64 else torch.float32
+    dev = torch.device("cuda", 0)
+    d_u = torch.from_numpy(u0).to(dev, dtype=dt)
+    d_work = torch.empty_like(d_u)
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def one_step(timing=None):
+        heat.checksum_dev(d_u, prec, stream)                       # sum of the state in
+        if timing is not None:
+            timing[0].record(stream)
+        heat.solve_dev(d_u, nparts, r, nt, precision=prec, stream=stream, work=d_work, **cfg)
+        if timing is not None:
+            timing[1].record(stream)
+        return heat.checksum_dev(d_u, prec, stream)                # sum of the state out
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    kern_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(ev)
+        torch.cuda.synchronize()
+        kern_ms.append(ev[0].elapsed_time(ev[1]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = N * nt * args.steps / elapsed / 1e9
+
+    # dominant kernel: the round kernel; its launches sit between the two events
+    launches = pl["rounds"]
+    k_avg_ms = sum(kern_ms) / len(kern_ms) / launches
+    es = 8 if prec == heat.FP64 else 4
+    alg_bytes = 2 * es * N                    # read the state once, write it once per launch
+    steps_per_launch = nt / launches
+    if pl["kernel"] == heat.KERNEL_STEP:
+        bound = "hbm"
+        achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    else:
+        # temporal blocking moves 2*es bytes per cell per T steps; it is
+        # limited by the vector ALU: flops per cell update = 5 (binary64:
+        # fma + add + mul + add with the fma counted as 2), 5 (binary32),
+        # 14 (compensated: 12 operations + the fold amortised)
+        fl = {heat.FP64: 5.0, heat.FP32: 5.0, heat.FP32C: 12.0}[prec]
+        peak = FP64_VECTOR_TFLOPS if prec == heat.FP64 else FP32_VECTOR_TFLOPS / 2
+        achieved = fl * N * steps_per_launch / (k_avg_ms * 1e-3) / 1e12
+        bound = "alu"
+        hbm = alg_bytes / (k_avg_ms * 1e-3) / 1e9
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "hbm_algorithmic_GBs": round(hbm, 1),
+                "hbm_frac": round(hbm / HBM_PEAK_GBS, 4)}
+    roof["kernel"] = ("k_step" if pl["kernel"] == heat.KERNEL_STEP else "k_window")
+    roof["avg_launch_ms"] = round(k_avg_ms, 4)
+    roof["launches_per_step"] = launches
+
+    out = {
+        "metric": "GCUP/s (giga cell-updates per second)",
+        "value": round(value, 3),
+        "unit": "GCUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32c": "f32 (compensated)"}[prec_name],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": N, "nparts": nparts, "r": r, "nt": nt,
+                   "init": w["init"], "seed": w["seed"], "precision": prec_name,
+                   "kernel": roof["kernel"], "cells_per_lane": pl["cells_per_lane"],
+                   "steps_per_round": pl["steps_per_round"],
+                   "waves_per_group": pl["waves_per_group"]},
+        "roofline": roof,
+    }
+    del d_u, d_work
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(u0, r, args.cpu_steps, prec_name)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,254 @@
+/*
+ * heat.h -- C ABI of the MI355X (gfx950) periodic 1D heat-stencil library.
+ *
+ * Operation (paper, Section 2 "Model problem", Eq. heat:discrete with the
+ * periodic boundary condition u(t, x) = u(t, L + x)): nt explicit-Euler steps
+ *
+ *     u_new[i] = u[i] + r * ((u[i-1] - 2 u[i]) + u[i+1]),   indices mod N,
+ *
+ * with r = alpha * dt / h^2 (the printed denominator "2h" is read as h^2, the
+ * consistent second-order Laplacian; the caller supplies r directly).  Every
+ * right-hand-side value is taken at the old time level.  The paper's parallel
+ * algorithm (Section 2, last paragraph) cuts the ring into contiguous
+ * segments that swap ghost cells every step; here the segments are tiles of
+ * the GPU kernels, and `nparts` is validated and recorded but cannot change
+ * the result (it is bit-identical for every 1 <= nparts <= N).
+ *
+ * Precisions:
+ *   HEAT_FP64  -- binary64 storage and arithmetic in the order written above
+ *                 (2 u[i] is exact; no other contraction).  Bit-identical to a
+ *                 plain sequential evaluation.
+ *   HEAT_FP32  -- binary32 storage and arithmetic: c + r*((l - c) + (q - c)).
+ *   HEAT_FP32C -- binary32 storage; inside the kernels the state is the pair
+ *                 (u, e) of binary32 numbers whose sum is the value, advanced
+ *                 with a Fast2Sum (Kahan-style) compensated update in which e
+ *                 diffuses too.  Steps are grouped into rounds of T steps
+ *                 (T reported by heat_plan); at each round end the state is
+ *                 folded to u := fl32(u + e).  Only u touches HBM.
+ *
+ * All functions are extern "C", thread-safe, never throw, and return one of
+ * the heat_status codes.  After a negative return heat_last_error() gives a
+ * thread-local message.  Pointers marked "device" must point to memory of
+ * the current HIP device; "host" pointers to ordinary host memory.
+ */
+#ifndef HEAT_H
+#define HEAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum heat_status {
+    HEAT_OK = 0,
+    HEAT_PENDING = 1,     /* heat_poll: request not finished yet                */
+    HEAT_EINVAL = -1,     /* bad argument: NULL pointer, N < 1, nparts outside
+                             [1, N], nt < 0, r not finite or outside [0, 1/2],
+                             unknown precision, bad configuration             */
+    HEAT_ENOMEM = -2,     /* device allocation failed, or a request's footprint
+                             exceeds the server's whole HBM budget            */
+    HEAT_EBUSY = -3,      /* server admission queue full: retry later         */
+    HEAT_ENOENT = -4,     /* unknown or already consumed ticket               */
+    HEAT_EDEVICE = -5,    /* HIP runtime error (message in heat_last_error)   */
+    HEAT_ECANCELED = -6   /* request was cancelled                            */
+};
+
+enum heat_precision { HEAT_FP64 = 0, HEAT_FP32 = 1, HEAT_FP32C = 2 };
+
+enum heat_kernel_choice {
+    HEAT_KERNEL_AUTO = 0, /* planner decides (tuned table)                      */
+    HEAT_KERNEL_STEP = 1, /* one step per launch: coalesced sweep, HBM bound    */
+    HEAT_KERNEL_TB = 2    /* temporal blocking: T steps per round in registers  */
+};
+
+/* Optional overrides for the planner; zero fields mean "choose". */
+typedef struct heat_config {
+    int32_t kernel;          /* heat_kernel_choice                              */
+    int32_t cells_per_lane;  /* TB: cells held per lane, one of 8, 16, 32       */
+    int32_t steps_per_round; /* TB: T, a multiple of 4 with 2T < 64*cells - 8   */
+    int32_t waves_per_group; /* 1, 2, 4 or 8 wavefronts per workgroup           */
+} heat_config;
+
+/* What the planner picked for a given problem (filled by heat_plan). */
+typedef struct heat_plan_info {
+    int32_t kernel;          /* HEAT_KERNEL_STEP or HEAT_KERNEL_TB              */
+    int32_t cells_per_lane;  /* K (TB)                                          */
+    int32_t steps_per_round; /* T: steps per round (1 for STEP)                 */
+    int32_t waves_per_group;
+    int64_t tile_cells;      /* W = 64*K - 2T output cells per tile (TB)        */
+    int64_t tiles;           /* tiles per round                                 */
+    int64_t rounds;          /* launches (STEP: nt, TB: ceil(nt / T))           */
+} heat_plan_info;
+
+/*
+ * Plain form.  u: host array of N binary64 values, overwritten in place by
+ * the state after nt steps.  FP64.  Blocking.  Copies to and from the current
+ * device, allocates and frees its own device memory.
+ */
+int heat_solve(double *u, int64_t N, int32_t nparts, double r, int64_t nt);
+
+/*
+ * Device form.  d_u: device array of N values (double* for HEAT_FP64, float*
+ * for HEAT_FP32/HEAT_FP32C), 16-byte aligned, advanced in place.  Work is
+ * queued on `hip_stream` (a hipStream_t; NULL = the legacy default stream).
+ * Device scratch of the same size as d_u is taken from the stream-ordered
+ * pool of the device.  If sum0_out / sum_out are not NULL they receive the
+ * binary64 sums of the state before and after the run (the conservation
+ * check, which holds up to rounding on a ring) and the call waits for the
+ * stream; otherwise it returns as soon as the work is queued.
+ */
+int heat_solve_dev(void *d_u, int64_t N, int32_t nparts, double r, int64_t nt,
+                   int32_t precision, void *hip_stream, double *sum0_out, double *sum_out);
+
+/*
+ * Device form with explicit configuration and scratch.  d_work: NULL, or a
+ * caller-owned device array with room for N values of the storage type (not
+ * overlapping d_u).  cfg: NULL or overrides.  Otherwise as heat_solve_dev.
+ */
+int heat_solve_dev_cfg(void *d_u, void *d_work, int64_t N, int32_t nparts, double r, int64_t nt,
+                       int32_t precision, const heat_config *cfg, void *hip_stream,
+                       double *sum0_out, double *sum_out);
+
+/* Planner: what heat_solve_dev_cfg would run for this problem.  No device work. */
+int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
+              heat_plan_info *out);
+
+/*
+ * binary64 sum of a device array (double* or float* by precision), computed
+ * by a fixed-shape two-pass reduction (deterministic for a given N).  Waits
+ * for `hip_stream`; result written to *sum_out (host).
+ */
+int heat_checksum_dev(const void *d_u, int64_t N, int32_t precision, void *hip_stream,
+                      double *sum_out);
+
+/* --------------------------------------------------------------- batching */
+
+/*
+ * One problem of a batch (host buffers).  u0 and u_out hold N binary64
+ * values (u_out may equal u0).  FP32 forms round u0 to binary32 on the device
+ * and widen the result back exactly.  sum0 / sum_nt: binary64 sums of the
+ * state (in its storage precision) before and after; status: per-problem
+ * heat_status.
+ */
+typedef struct heat_problem {
+    int64_t N;
+    int32_t nparts;
+    int32_t precision;
+    double r;
+    int64_t nt;
+    const double *u0;
+    double *u_out;
+    double sum0;
+    double sum_nt;
+    int32_t status;
+    int32_t reserved;
+} heat_problem;
+
+/*
+ * Batching form (host buffers): validates every problem, copies them to the
+ * device, advances all of them in one persistent fused launch, copies back.
+ * Blocking.  Returns HEAT_OK if every problem succeeded, else the first
+ * error; probs[i].status tells which.
+ */
+int heat_solve_batch(heat_problem *probs, int32_t count);
+
+/*
+ * One ring of a device-resident batch.  d_u: device state (N values of the
+ * precision's storage type, 16-byte aligned), advanced in place; d_work:
+ * device scratch of the same size.  The caller owns both.
+ */
+typedef struct heat_ring {
+    int64_t N;
+    int64_t nt;
+    double r;
+    int32_t precision;
+    int32_t nparts;
+    void *d_u;
+    void *d_work;
+} heat_ring;
+
+/*
+ * Device-resident batching form: all rings advance in one persistent launch
+ * (tiles of every ring and round form one dependency-ordered work list; a
+ * tile waits only for the three tiles of the previous round it reads).  The
+ * per-ring T comes from the same table as heat_plan, so each ring's result
+ * is bit-identical to solving it alone.  Queued on hip_stream; if `wait` is
+ * nonzero the call waits for completion.
+ */
+int heat_solve_batch_dev(const heat_ring *rings, int32_t count, void *hip_stream, int32_t wait);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct heat_server heat_server;
+
+typedef struct heat_server_stats {
+    uint64_t submitted, admitted, completed, cancelled, rejected;
+    uint64_t ticks;            /* fused launches issued                       */
+    uint64_t cell_updates;     /* total N * nt of completed requests          */
+    size_t   hbm_budget;       /* bytes the server may hold on the device     */
+    size_t   hbm_in_use;       /* bytes held now                              */
+    size_t   hbm_peak;         /* high-water mark                             */
+    int32_t  active;           /* requests resident on the device now         */
+    int32_t  queued;           /* requests waiting for admission              */
+} heat_server_stats;
+
+/*
+ * Create a continuous-batching server on the current device.  It owns one
+ * device arena of hbm_budget_bytes (0 = 80 % of the free device memory), a
+ * scheduler thread and its streams.  At most max_slots requests (0 = 4096)
+ * are resident at once; max_queue (0 = 65536) may wait for admission.
+ */
+int heat_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t max_queue,
+                       heat_server **out);
+
+/*
+ * Submit a request (non-blocking).  *p, p->u0 and p->u_out must stay valid
+ * and untouched until heat_poll returns something other than HEAT_PENDING
+ * or heat_cancel returns.  Returns HEAT_EINVAL for a bad problem, HEAT_ENOMEM
+ * if its footprint (2 * N * storage bytes) exceeds the whole budget,
+ * HEAT_EBUSY if the queue is full.  *ticket identifies the request.
+ */
+int heat_submit(heat_server *s, heat_problem *p, uint64_t *ticket);
+
+/*
+ * HEAT_PENDING while the request runs; HEAT_OK once p->u_out, p->sum0,
+ * p->sum_nt and p->status are filled (the ticket is then consumed);
+ * HEAT_ENOENT for an unknown or consumed ticket; another negative code if
+ * the request failed.
+ */
+int heat_poll(heat_server *s, uint64_t ticket);
+
+/* Block until the request is done (or failed); same returns as heat_poll. */
+int heat_wait(heat_server *s, uint64_t ticket);
+
+/* Cancel a queued or running request; its ticket is consumed. */
+int heat_cancel(heat_server *s, uint64_t ticket);
+
+int heat_server_get_stats(heat_server *s, heat_server_stats *out);
+
+/* Cancel all outstanding work, stop the thread, free the arena. */
+int heat_server_destroy(heat_server *s);
+
+/* ------------------------------------------------------------------ misc */
+
+/* Thread-local text for the last negative return on this thread. */
+const char *heat_last_error(void);
+
+/* Library version string. */
+const char *heat_version(void);
+
+/*
+ * Device facts the planner uses (host out-pointers, any may be NULL):
+ * compute units, LDS bytes per workgroup, wavefront size, clock in kHz,
+ * and total / free device memory in bytes.
+ */
+int heat_device_info(int32_t *cus, int32_t *lds_bytes, int32_t *wave_size, int32_t *clock_khz,
+                     size_t *mem_total, size_t *mem_free);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEAT_H */

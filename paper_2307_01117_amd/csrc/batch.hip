@@ -1,0 +1,325 @@
+// batch.hip -- batching form: many independent rings in one persistent fused
+// launch (k_batch in kernels.hip).  This file builds the dependency-ordered
+// work list on the host and owns the host-buffer wrapper heat_solve_batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "heat_batch.h"
+#include "heat_internal.h"
+
+namespace heat {
+
+static inline int64_t ceil4(int64_t x) { return (x + 3) & ~int64_t(3); }
+static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+int batch_cells_per_lane(int precision) { return precision == HEAT_FP64 ? 16 : 32; }
+
+int describe_ring(const heat_ring &g, BatchRing *out) {
+    const int K = batch_cells_per_lane(g.precision);
+    const int T = default_steps_per_round(g.N, g.precision);
+    const int64_t Teff = g.nt > 0 ? std::min<int64_t>(T, g.nt) : 1;
+    BatchRing R{};
+    R.buf[0] = g.d_u;
+    R.buf[1] = g.d_work;
+    R.N = g.N;
+    R.H = (int32_t)ceil4(Teff);
+    R.T = (int32_t)Teff;
+    R.W = 64 * (int64_t)K - 2 * (int64_t)R.H;
+    R.tiles = (g.N + R.W - 1) / R.W;
+    R.r = g.r;
+    R.nt = g.nt;
+    const int64_t rounds = g.nt > 0 ? (g.nt + Teff - 1) / Teff : 0;
+    if (rounds > (int64_t)1 << 30) return fail(HEAT_EINVAL, "too many rounds");
+    R.rounds = (int32_t)rounds;
+    R.copy_round = (int32_t)(rounds & 1);
+    R.vec_ok = aligned16(g.d_u) && aligned16(g.d_work);
+    R.flag_base = 0;
+    *out = R;
+    return HEAT_OK;
+}
+
+// Host-side work list of one fused launch over rings of one precision.
+int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision) {
+    precision_ = precision;
+    K_ = batch_cells_per_lane(precision);
+    rings_.clear();
+    for (const BatchRing &R : rings_in)
+        if (R.rounds > 0) rings_.push_back(R);
+    // longest first (total rounds incl. copy-back), stable for determinism
+    std::stable_sort(rings_.begin(), rings_.end(), [](const BatchRing &a, const BatchRing &b) {
+        return a.rounds + a.copy_round > b.rounds + b.copy_round;
+    });
+    const size_t n = rings_.size();
+    tile_prefix_.assign(n + 1, 0);
+    int64_t flags = 0;
+    for (size_t i = 0; i < n; ++i) {
+        rings_[i].flag_base = flags;
+        flags += rings_[i].tiles;
+        tile_prefix_[i + 1] = tile_prefix_[i] + rings_[i].tiles;
+    }
+    nflags_ = flags;
+    max_rounds_ = n ? rings_[0].rounds + rings_[0].copy_round : 0;
+    active_.assign(max_rounds_, 0);
+    round_start_.assign(max_rounds_ + 1, 0);
+    // rings are sorted by total rounds, so the rings alive in round k form a prefix
+    size_t alive = n;
+    for (int32_t k = 0; k < max_rounds_; ++k) {
+        while (alive > 0 && rings_[alive - 1].rounds + rings_[alive - 1].copy_round <= k) --alive;
+        active_[k] = (int32_t)alive;
+        round_start_[k + 1] = round_start_[k] + tile_prefix_[alive];
+    }
+    total_items_ = max_rounds_ ? round_start_[max_rounds_] : 0;
+    return HEAT_OK;
+}
+
+size_t BatchLaunch::device_bytes() const {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    return al(rings_.size() * sizeof(BatchRing)) + al(tile_prefix_.size() * 8) +
+           al(round_start_.size() * 8) + al(active_.size() * 4) + al((size_t)nflags_ * 4) + 256;
+}
+
+int BatchLaunch::enqueue(void *dev_mem, hipStream_t st, int chunk, int wpg) {
+    if (total_items_ == 0) return HEAT_OK;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    char *p = (char *)dev_mem;
+    BatchPlanDev d{};
+    d.rings = (const BatchRing *)p;
+    HEAT_HIP(hipMemcpyAsync(p, rings_.data(), rings_.size() * sizeof(BatchRing),
+                            hipMemcpyHostToDevice, st));
+    p += al(rings_.size() * sizeof(BatchRing));
+    d.tile_prefix = (const int64_t *)p;
+    HEAT_HIP(hipMemcpyAsync(p, tile_prefix_.data(), tile_prefix_.size() * 8, hipMemcpyHostToDevice,
+                            st));
+    p += al(tile_prefix_.size() * 8);
+    d.round_start = (const int64_t *)p;
+    HEAT_HIP(hipMemcpyAsync(p, round_start_.data(), round_start_.size() * 8,
+                            hipMemcpyHostToDevice, st));
+    p += al(round_start_.size() * 8);
+    d.active = (const int32_t *)p;
+    HEAT_HIP(hipMemcpyAsync(p, active_.data(), active_.size() * 4, hipMemcpyHostToDevice, st));
+    p += al(active_.size() * 4);
+    d.flags = (uint32_t *)p;
+    p += al((size_t)nflags_ * 4);
+    d.work = (unsigned long long *)p;           // 8 bytes
+    d.status = (uint32_t *)(p + 8);             // 4 bytes
+    // epoch counters, work counter and status start at zero (fill kernel, no memset)
+    HEAT_HIP(launch_fill_u32(d.flags, nflags_, 0u, st));
+    HEAT_HIP(launch_fill_u32((uint32_t *)p, 4, 0u, st));
+    d.total_items = total_items_;
+    d.max_rounds = max_rounds_;
+    d.chunk = chunk;
+    d.spin_limit = (int64_t)1 << 22;
+    status_dev_ = d.status;
+    int grid = 0;
+    int rc = batch_grid_size(precision_, K_, wpg, &grid);
+    if (rc) return rc;
+    HEAT_HIP(launch_batch(precision_, K_, d, grid, wpg, st));
+    return HEAT_OK;
+}
+
+int BatchLaunch::check_status(hipStream_t st) {
+    if (!status_dev_) return HEAT_OK;
+    uint32_t s = 0;
+    HEAT_HIP(hipMemcpyAsync(&s, status_dev_, 4, hipMemcpyDeviceToHost, st));
+    HEAT_HIP(hipStreamSynchronize(st));
+    if (s) return fail(HEAT_EDEVICE, "fused batch launch: a dependency wait timed out");
+    return HEAT_OK;
+}
+
+int validate_ring(const heat_ring &g) {
+    if (g.N < 1) return fail(HEAT_EINVAL, "ring N must be >= 1");
+    if (g.nt < 0) return fail(HEAT_EINVAL, "ring nt must be >= 0");
+    if (!std::isfinite(g.r) || g.r < 0.0 || g.r > 0.5)
+        return fail(HEAT_EINVAL, "ring r must be finite and in [0, 1/2] (got %g)", g.r);
+    if (g.precision != HEAT_FP64 && g.precision != HEAT_FP32 && g.precision != HEAT_FP32C)
+        return fail(HEAT_EINVAL, "unknown precision %d", g.precision);
+    if (g.nparts < 1 || (int64_t)g.nparts > g.N) return fail(HEAT_EINVAL, "nparts must be in [1, N]");
+    if (!g.d_u || (g.nt > 0 && !g.d_work)) return fail(HEAT_EINVAL, "ring buffer is NULL");
+    return HEAT_OK;
+}
+
+// Enqueue one fused launch per precision present, all on `st`.
+int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
+                      std::vector<BatchLaunch> &launches, void **dev_mem_out) {
+    *dev_mem_out = nullptr;
+    std::vector<BatchRing> by_prec[3];
+    for (int32_t i = 0; i < count; ++i) {
+        BatchRing R;
+        int rc = describe_ring(rings[i], &R);
+        if (rc) return rc;
+        by_prec[rings[i].precision].push_back(R);
+    }
+    launches.clear();
+    size_t total = 0;
+    for (int prec = 0; prec < 3; ++prec) {
+        if (by_prec[prec].empty()) continue;
+        launches.emplace_back();
+        launches.back().build(by_prec[prec], prec);
+        total += launches.back().device_bytes();
+    }
+    if (total == 0) return HEAT_OK;
+    int rc = device_pool_setup();
+    if (rc) return rc;
+    void *mem = nullptr;
+    HEAT_HIP(hipMallocAsync(&mem, total, st));
+    *dev_mem_out = mem;
+    char *p = (char *)mem;
+    for (BatchLaunch &L : launches) {
+        rc = L.enqueue(p, st, /*chunk=*/4, /*wpg=*/4);
+        if (rc) return rc;
+        p += L.device_bytes();
+    }
+    return HEAT_OK;
+}
+
+}  // namespace heat
+
+using namespace heat;
+
+extern "C" {
+
+int heat_solve_batch_dev(const heat_ring *rings, int32_t count, void *hip_stream, int32_t wait) {
+    if (count < 0 || (count > 0 && !rings)) return fail(HEAT_EINVAL, "bad ring array");
+    for (int32_t i = 0; i < count; ++i) {
+        int rc = validate_ring(rings[i]);
+        if (rc) return fail(rc, "ring %d: %s", i, heat_last_error());
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<BatchLaunch> launches;
+    void *mem = nullptr;
+    int rc = batch_dev_enqueue(rings, count, st, launches, &mem);
+    if (!rc && wait)
+        for (BatchLaunch &L : launches) {
+            rc = L.check_status(st);
+            if (rc) break;
+        }
+    if (mem) (void)hipFreeAsync(mem, st);
+    return rc;
+}
+
+int heat_solve_batch(heat_problem *probs, int32_t count) {
+    if (count < 0 || (count > 0 && !probs)) return fail(HEAT_EINVAL, "bad problem array");
+    int first = HEAT_OK;
+    std::vector<int> ok(count, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        heat_problem &p = probs[i];
+        heat_ring g{p.N, p.nt, p.r, p.precision, p.nparts, (void *)1, (void *)1};
+        int rc = validate_ring(g);
+        if (!rc && (!p.u0 || !p.u_out)) rc = fail(HEAT_EINVAL, "u0/u_out is NULL");
+        p.status = rc;
+        if (rc && first == HEAT_OK) first = rc;
+        ok[i] = rc == HEAT_OK;
+    }
+    hipStream_t st = nullptr;
+    HEAT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    int rc = device_pool_setup();
+    std::vector<void *> allocs;
+    std::vector<heat_ring> rings;
+    std::vector<int> idx;
+    double *sums = nullptr;   // device: 2 per problem + partials
+    auto cleanup = [&]() {
+        for (void *a : allocs) (void)hipFreeAsync(a, st);
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    };
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    // stage in: binary64 host values -> device state (rounded for FP32 forms)
+    for (int32_t i = 0; i < count && !rc; ++i) {
+        if (!ok[i]) continue;
+        heat_problem &p = probs[i];
+        const size_t es = storage_bytes(p.precision);
+        void *a = nullptr, *b = nullptr;
+        hipError_t e = hipMallocAsync(&a, (size_t)p.N * es, st);
+        if (e == hipSuccess) {
+            allocs.push_back(a);
+            e = hipMallocAsync(&b, (size_t)p.N * std::max<size_t>(es, 8), st);
+        }
+        if (e == hipSuccess) allocs.push_back(b);
+        if (e != hipSuccess) {
+            rc = fail_hip(e, "hipMallocAsync(batch state)");
+            break;
+        }
+        if (p.precision == HEAT_FP64) {
+            e = hipMemcpyAsync(a, p.u0, (size_t)p.N * 8, hipMemcpyHostToDevice, st);
+        } else {
+            e = hipMemcpyAsync(b, p.u0, (size_t)p.N * 8, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = launch_f64_to_f32((const double *)b, (float *)a, p.N, st);
+        }
+        if (e != hipSuccess) {
+            rc = fail_hip(e, "stage-in");
+            break;
+        }
+        rings.push_back(heat_ring{p.N, p.nt, p.r, p.precision, p.nparts, a, b});
+        idx.push_back(i);
+    }
+    if (!rc) {
+        hipError_t e = hipMallocAsync((void **)&sums, (2 * rings.size() + SUM_BLOCKS + 1) * 8, st);
+        if (e != hipSuccess) rc = fail_hip(e, "hipMallocAsync(sums)");
+        else allocs.push_back(sums);
+    }
+    double *partial = sums ? sums + 2 * rings.size() : nullptr;
+    for (size_t j = 0; j < rings.size() && !rc; ++j) {
+        hipError_t e = launch_sum(rings[j].precision, rings[j].d_u, rings[j].N, partial, sums + 2 * j, st);
+        if (e != hipSuccess) rc = fail_hip(e, "sum0");
+    }
+    std::vector<BatchLaunch> launches;
+    void *mem = nullptr;
+    if (!rc) {
+        rc = batch_dev_enqueue(rings.data(), (int32_t)rings.size(), st, launches, &mem);
+        if (mem) allocs.push_back(mem);
+    }
+    for (size_t j = 0; j < rings.size() && !rc; ++j) {
+        hipError_t e = launch_sum(rings[j].precision, rings[j].d_u, rings[j].N, partial,
+                                  sums + 2 * j + 1, st);
+        if (e != hipSuccess) rc = fail_hip(e, "sum_nt");
+    }
+    // stage out (FP32 forms are widened exactly into the scratch buffer first)
+    for (size_t j = 0; j < rings.size() && !rc; ++j) {
+        heat_problem &p = probs[idx[j]];
+        hipError_t e;
+        if (p.precision == HEAT_FP64) {
+            e = hipMemcpyAsync(p.u_out, rings[j].d_u, (size_t)p.N * 8, hipMemcpyDeviceToHost, st);
+        } else {
+            e = launch_f32_to_f64((const float *)rings[j].d_u, (double *)rings[j].d_work, p.N, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(p.u_out, rings[j].d_work, (size_t)p.N * 8,
+                                   hipMemcpyDeviceToHost, st);
+        }
+        if (e != hipSuccess) rc = fail_hip(e, "stage-out");
+    }
+    std::vector<double> hs(2 * rings.size());
+    if (!rc && !rings.empty()) {
+        hipError_t e = hipMemcpyAsync(hs.data(), sums, hs.size() * 8, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) rc = fail_hip(e, "sums D2H");
+    }
+    if (!rc)
+        for (BatchLaunch &L : launches) {
+            rc = L.check_status(st);
+            if (rc) break;
+        }
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");
+    }
+    for (size_t j = 0; j < rings.size(); ++j) {
+        heat_problem &p = probs[idx[j]];
+        p.status = rc;
+        if (!rc) {
+            p.sum0 = hs[2 * j];
+            p.sum_nt = hs[2 * j + 1];
+        }
+    }
+    cleanup();
+    if (rc) return rc;
+    return first;
+}
+
+}  // extern "C"

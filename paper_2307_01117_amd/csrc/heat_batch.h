@@ -1,0 +1,48 @@
+// heat_batch.h -- host-side work list of a fused batch launch (shared by the
+// batching form and the server).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "heat_internal.h"
+
+namespace heat {
+
+int batch_cells_per_lane(int precision);
+int validate_ring(const heat_ring &g);
+// Geometry of one ring in a fused launch (same T as the plain planner).
+int describe_ring(const heat_ring &g, BatchRing *out);
+
+class BatchLaunch {
+  public:
+    // Sort rings (longest first), number the work items round-major.
+    int build(const std::vector<BatchRing> &rings, int precision);
+    // Device bytes for tables, epoch counters, work counter and status word.
+    size_t device_bytes() const;
+    // Upload tables into dev_mem (device_bytes() bytes), clear the counters
+    // and launch the persistent kernel on st.
+    int enqueue(void *dev_mem, hipStream_t st, int chunk, int wpg);
+    // Wait for st and report a timed-out dependency wait, if any.
+    int check_status(hipStream_t st);
+    int64_t total_items() const { return total_items_; }
+
+  private:
+    int precision_ = 0;
+    int K_ = 16;
+    std::vector<BatchRing> rings_;
+    std::vector<int64_t> tile_prefix_;
+    std::vector<int64_t> round_start_;
+    std::vector<int32_t> active_;
+    int64_t nflags_ = 0;
+    int32_t max_rounds_ = 0;
+    int64_t total_items_ = 0;
+    uint32_t *status_dev_ = nullptr;
+};
+
+int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
+                      std::vector<BatchLaunch> &launches, void **dev_mem_out);
+
+}  // namespace heat

@@ -1,0 +1,139 @@
+// heat_device.h -- device-side building blocks shared by the HIP kernels of
+// the heat-stencil library (gfx950, wave64).  Included only by .hip files.
+//
+// The update is the explicit-Euler step of the paper's Eq. (heat:discrete) on
+// a periodic ring (Section 2): new = c + r * ((l - 2c) + q) in binary64, and
+// the binary32 / compensated binary32 forms documented in heat.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace heat {
+
+// ------------------------------------------------------------ precisions
+
+struct F64 {
+    using T = double;
+    static constexpr int VEC = 2;        // cells per 16-byte access
+    static constexpr bool COMP = false;
+};
+struct F32 {
+    using T = float;
+    static constexpr int VEC = 4;
+    static constexpr bool COMP = false;
+};
+struct F32C {
+    using T = float;
+    static constexpr int VEC = 4;
+    static constexpr bool COMP = true;   // carries the compensation term e
+};
+
+template <class T> struct Vec16;
+template <> struct Vec16<double> { using type = double2; };
+template <> struct Vec16<float> { using type = float4; };
+
+// ------------------------------------------------------ cross-lane moves
+//
+// DPP row/wave controls of the GFX9 family: wave_ror:1 rotates the wave right
+// by one lane (lane i receives lane i-1, lane 0 receives lane 63), wave_rol:1
+// rotates left (lane i receives lane i+1, lane 63 receives lane 0).  They are
+// ordinary VALU moves: no LDS traffic, no waitcnt.
+constexpr int DPP_WAVE_ROL1 = 0x134;
+constexpr int DPP_WAVE_ROR1 = 0x13C;
+
+__device__ __forceinline__ int dpp_from_prev_i(int x) {
+    return __builtin_amdgcn_mov_dpp(x, DPP_WAVE_ROR1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_from_next_i(int x) {
+    return __builtin_amdgcn_mov_dpp(x, DPP_WAVE_ROL1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float from_prev(float x) {
+    return __int_as_float(dpp_from_prev_i(__float_as_int(x)));
+}
+__device__ __forceinline__ float from_next(float x) {
+    return __int_as_float(dpp_from_next_i(__float_as_int(x)));
+}
+__device__ __forceinline__ double from_prev(double x) {
+    int lo = dpp_from_prev_i(__double2loint(x));
+    int hi = dpp_from_prev_i(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_next(double x) {
+    int lo = dpp_from_next_i(__double2loint(x));
+    int hi = dpp_from_next_i(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+// ------------------------------------------------------------ the update
+//
+// binary64: l - 2c is computed as fma(-2, c, l).  2c is exact, so the single
+// rounding of the fused form equals the rounding of l - (2c): the result is
+// bit-identical to evaluating ((l - 2c) + q) step by step.  The final
+// c + r * lap is NOT fused (the library is built with -ffp-contract=off).
+__device__ __forceinline__ double cell_update(double l, double c, double q, double r) {
+    return c + r * (__builtin_fma(-2.0, c, l) + q);
+}
+// binary32: both differences are exact when neighbours are within a factor 2.
+__device__ __forceinline__ float cell_update(float l, float c, float q, float r) {
+    return c + r * ((l - c) + (q - c));
+}
+
+// One step on K consecutive cells held by each lane (lane L holds cells
+// [L*K, L*K + K) of the wave's window).  The end cells exchange neighbours
+// with the adjacent lanes; lanes 0 and 63 receive wrapped values, which only
+// corrupt the window's outer cells (the trapezoid shrinks by one per step).
+template <int K, class T>
+__device__ __forceinline__ void window_step(T (&v)[K], T r) {
+    T prev = from_prev(v[K - 1]);
+    const T right = from_next(v[0]);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const T c = v[j];
+        const T q = (j + 1 < K) ? v[j + 1] : right;
+        v[j] = cell_update(prev, c, q, r);
+        prev = c;
+    }
+}
+
+// Compensated binary32 step of the pair (u, e): the Laplacian of u + e is
+// formed from the exact-ish differences of both parts, then added to u with
+// Fast2Sum so that the rounding error of the addition is kept in e.
+template <int K>
+__device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], float r) {
+    float pu = from_prev(u[K - 1]);
+    float pe = from_prev(e[K - 1]);
+    const float ru = from_next(u[0]);
+    const float re = from_next(e[0]);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const float c = u[j], ec = e[j];
+        const float q = (j + 1 < K) ? u[j + 1] : ru;
+        const float eq = (j + 1 < K) ? e[j + 1] : re;
+        const float d = r * (((pu - c) + (q - c)) + ((pe - ec) + (eq - ec)));
+        const float y = d + ec;
+        const float t = c + y;
+        e[j] = y - (t - c);
+        u[j] = t;
+        pu = c;
+        pe = ec;
+    }
+}
+
+// ------------------------------------------------------------ indexing
+
+// Map a workgroup id so that consecutive logical ids stay on one XCD.
+// Workgroups are dispatched round-robin over the 8 XCDs, so hardware id b
+// runs on XCD b % 8; logical ids [x*q + min(x, rem), ...) go to XCD x.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t grid) {
+    const int64_t q = grid >> 3, rem = grid & 7;
+    const int64_t x = b & 7, k = b >> 3;
+    return x * q + (x < rem ? x : rem) + k;
+}
+
+__device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t N) {
+    int64_t m = i % N;
+    return m < 0 ? m + N : m;
+}
+
+}  // namespace heat

@@ -1,0 +1,114 @@
+// heat_internal.h -- host-side internals shared by the library's .hip files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "heat.h"
+
+namespace heat {
+
+// ----------------------------------------------------------- errors
+
+// Record a thread-local message for heat_last_error() and return `code`.
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+// HIP error -> HEAT_EDEVICE with the call site in the message.
+int fail_hip(hipError_t e, const char *what);
+
+#define HEAT_HIP(call)                                             \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return ::heat::fail_hip(_e, #call);  \
+    } while (0)
+
+inline size_t storage_bytes(int precision) { return precision == HEAT_FP64 ? 8 : 4; }
+
+// ----------------------------------------------------------- planning
+
+struct Plan {
+    int kernel = HEAT_KERNEL_TB;
+    int K = 16;          // cells per lane (TB)
+    int T = 32;          // steps per round
+    int H = 32;          // halo cells per side of a window (multiple of 4, >= T)
+    int wpg = 4;         // wavefronts per workgroup
+    int64_t W = 0;       // output cells per tile (TB) / cells per chunk (STEP)
+    int64_t tiles = 0;   // tiles (TB) or chunks (STEP) per launch
+    int64_t rounds = 0;  // launches
+};
+
+// Fill `p` for a problem; returns HEAT_OK or HEAT_EINVAL (message set).
+int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan *p);
+
+// Steps per round the planner uses by default for (N, precision).  For the
+// compensated form this fixes where the state is folded to binary32, so it
+// is a pure function of (N, precision) -- never of timing or of a batch mix.
+int default_steps_per_round(int64_t N, int precision);
+int default_cells_per_lane(int64_t N, int precision);
+
+// ----------------------------------------------------------- kernels
+
+// One round of the temporal-blocked window kernel: every tile loads 64*K
+// cells starting H cells left of its output, advances `steps` (<= H) steps
+// in registers and writes its W = 64*K - 2H output cells.
+hipError_t launch_window(int precision, int K, const void *src, void *dst, int64_t N, int H,
+                         int steps, double r, int wpg, hipStream_t st);
+
+// One step of the coalesced sweep (binary64 or binary32).
+hipError_t launch_step(int precision, const void *src, void *dst, int64_t N, double r, int wpg,
+                       hipStream_t st);
+
+// Cells per wave chunk of the step kernel.
+int64_t step_chunk_cells(int precision);
+
+// Deterministic binary64 sum: `partial` needs SUM_BLOCKS doubles, result in
+// d_out[0].
+constexpr int SUM_BLOCKS = 1024;
+hipError_t launch_sum(int precision, const void *u, int64_t N, double *partial, double *d_out,
+                      hipStream_t st);
+
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
+hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+
+// ----------------------------------------------------------- batching
+
+struct BatchRing {          // one ring of a fused launch (device table entry)
+    void *buf[2];           // state at even / odd rounds
+    int64_t N;
+    int64_t W;              // output cells per tile
+    int64_t tiles;
+    int64_t flag_base;      // first epoch counter of this ring
+    double r;
+    int32_t H;              // halo (>= steps of any round)
+    int32_t T;              // steps per full round
+    int32_t rounds;         // rounds (the last one may be shorter)
+    int32_t copy_round;     // 1 if an extra copy-back round follows (odd rounds)
+    int64_t nt;
+    int32_t vec_ok;         // both buffers 16-byte aligned
+    int32_t pad;
+};
+
+struct BatchPlanDev {       // device pointers of one fused launch
+    const BatchRing *rings; // sorted by total rounds (incl. copy), descending
+    const int64_t *tile_prefix;   // [nrings+1]
+    const int64_t *round_start;   // [max_rounds+1] first item of each round
+    const int32_t *active;        // [max_rounds] rings still running in round k
+    uint32_t *flags;              // epoch counter per (ring, tile)
+    unsigned long long *work;     // [0] next unclaimed work item
+    uint32_t *status;             // [0] nonzero once a dependency wait timed out
+    int64_t total_items;
+    int32_t max_rounds;
+    int32_t chunk;
+    int64_t spin_limit;
+};
+
+hipError_t launch_batch(int precision, int K, const BatchPlanDev &plan, int grid, int wpg,
+                        hipStream_t st);
+int batch_grid_size(int precision, int K, int wpg, int *grid);
+
+// Shared device-side state for the batch/server runtime (stream-ordered pool).
+int device_pool_setup();
+
+}  // namespace heat

@@ -1,0 +1,323 @@
+// runtime.hip -- C ABI of the heat-stencil library: validation, planning,
+// the plain / device / batch forms and the checksum.  Kernels live in
+// kernels.hip, the serving loop in server.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "heat_internal.h"
+
+namespace heat {
+
+// ================================================================== errors
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(HEAT_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(HEAT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ================================================================ planning
+
+// Steps per round.  binary64 and plain binary32 results do not depend on it
+// (only speed does); for the compensated form it sets where u + e is folded
+// to binary32, so it is a fixed constant of the precision.
+int default_steps_per_round(int64_t N, int precision) {
+    (void)N;
+    switch (precision) {
+        case HEAT_FP64: return 32;
+        case HEAT_FP32: return 32;
+        default: return 32;   // HEAT_FP32C: fixed, part of the result's definition
+    }
+}
+
+int default_cells_per_lane(int64_t N, int precision) {
+    (void)N;
+    return precision == HEAT_FP64 ? 16 : 32;
+}
+
+static int check_problem(int64_t N, int32_t nparts, double r, int64_t nt, int precision) {
+    if (N < 1) return fail(HEAT_EINVAL, "N must be >= 1 (got %lld)", (long long)N);
+    if (N > (int64_t(1) << 40)) return fail(HEAT_EINVAL, "N too large (%lld)", (long long)N);
+    if (nparts < 1 || (int64_t)nparts > N)
+        return fail(HEAT_EINVAL, "nparts must be in [1, N] (got %d for N=%lld)", nparts,
+                    (long long)N);
+    if (nt < 0) return fail(HEAT_EINVAL, "nt must be >= 0 (got %lld)", (long long)nt);
+    if (!std::isfinite(r) || r < 0.0 || r > 0.5)
+        return fail(HEAT_EINVAL, "r must be finite and in [0, 1/2] (got %g)", r);
+    if (precision != HEAT_FP64 && precision != HEAT_FP32 && precision != HEAT_FP32C)
+        return fail(HEAT_EINVAL, "unknown precision %d", precision);
+    return HEAT_OK;
+}
+
+static inline int64_t ceil4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
+int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan *p) {
+    heat_config c{};
+    if (cfg) c = *cfg;
+    Plan q;
+    q.wpg = c.waves_per_group ? c.waves_per_group : 4;
+    if (q.wpg != 1 && q.wpg != 2 && q.wpg != 4 && q.wpg != 8)
+        return fail(HEAT_EINVAL, "waves_per_group must be 1, 2, 4 or 8 (got %d)", q.wpg);
+    int kernel = c.kernel ? c.kernel : HEAT_KERNEL_TB;
+    if (kernel != HEAT_KERNEL_STEP && kernel != HEAT_KERNEL_TB)
+        return fail(HEAT_EINVAL, "unknown kernel choice %d", c.kernel);
+    if (kernel == HEAT_KERNEL_STEP && precision == HEAT_FP32C)
+        return fail(HEAT_EINVAL, "compensated FP32 needs the temporal-blocked kernel");
+    q.kernel = kernel;
+    if (kernel == HEAT_KERNEL_STEP) {
+        q.K = 0;
+        q.T = 1;
+        q.H = 0;
+        q.W = step_chunk_cells(precision);
+        q.tiles = (N + q.W - 1) / q.W;
+        q.rounds = nt;
+        *p = q;
+        return HEAT_OK;
+    }
+    q.K = c.cells_per_lane ? c.cells_per_lane : default_cells_per_lane(N, precision);
+    if (q.K != 8 && q.K != 16 && q.K != 32)
+        return fail(HEAT_EINVAL, "cells_per_lane must be 8, 16 or 32 (got %d)", q.K);
+    int T = c.steps_per_round ? c.steps_per_round : default_steps_per_round(N, precision);
+    if (T < 1) return fail(HEAT_EINVAL, "steps_per_round must be >= 1 (got %d)", T);
+    if (c.steps_per_round && (T % 4) != 0)
+        return fail(HEAT_EINVAL, "steps_per_round must be a multiple of 4 (got %d)", T);
+    // the window must keep W >= H so a tile only reads its two neighbours
+    if (3 * ceil4(T) > 64 * (int64_t)q.K)
+        return fail(HEAT_EINVAL, "steps_per_round %d too deep for %d cells per lane", T, q.K);
+    // a run shorter than one round is a single round of nt steps
+    const int64_t Teff = nt > 0 ? std::min<int64_t>(T, nt) : 1;
+    q.T = (int)Teff;
+    q.H = (int)ceil4(Teff);
+    q.W = 64 * (int64_t)q.K - 2 * (int64_t)q.H;
+    q.tiles = (N + q.W - 1) / q.W;
+    q.rounds = nt > 0 ? (nt + Teff - 1) / Teff : 0;
+    *p = q;
+    return HEAT_OK;
+}
+
+// ================================================================ helpers
+
+static std::once_flag g_pool_once[64];
+
+int device_pool_setup() {
+    int dev = 0;
+    HEAT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return HEAT_OK;
+    int rc = HEAT_OK;
+    std::call_once(g_pool_once[dev], [&]() {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+    });
+    return rc;
+}
+
+// Run the rounds of a plan: state in `a`, scratch `b`; result back in `a`.
+static int run_rounds(const Plan &pl, int precision, void *a, void *b, int64_t N, double r,
+                      int64_t nt, hipStream_t st) {
+    void *cur = a, *oth = b;
+    if (pl.kernel == HEAT_KERNEL_STEP) {
+        for (int64_t s = 0; s < nt; ++s) {
+            HEAT_HIP(launch_step(precision, cur, oth, N, r, pl.wpg, st));
+            std::swap(cur, oth);
+        }
+    } else {
+        int64_t done = 0;
+        while (done < nt) {
+            const int steps = (int)std::min<int64_t>(pl.T, nt - done);
+            HEAT_HIP(launch_window(precision, pl.K, cur, oth, N, pl.H, steps, r, pl.wpg, st));
+            std::swap(cur, oth);
+            done += steps;
+        }
+    }
+    if (cur != a)
+        HEAT_HIP(hipMemcpyAsync(a, cur, (size_t)N * storage_bytes(precision),
+                                hipMemcpyDeviceToDevice, st));
+    return HEAT_OK;
+}
+
+struct DevBuf {   // stream-ordered scratch, freed on the same stream
+    void *p = nullptr;
+    hipStream_t st = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFreeAsync(p, st);
+    }
+};
+
+static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, double r, int64_t nt,
+                          int32_t precision, const heat_config *cfg, hipStream_t st,
+                          double *sum0_out, double *sum_out) {
+    int rc = check_problem(N, nparts, r, nt, precision);
+    if (rc) return rc;
+    if (!d_u) return fail(HEAT_EINVAL, "d_u is NULL");
+    const size_t bytes = (size_t)N * storage_bytes(precision);
+    if (d_work) {
+        const char *a = (const char *)d_u, *w = (const char *)d_work;
+        if (w < a + bytes && a < w + bytes) return fail(HEAT_EINVAL, "d_work overlaps d_u");
+    }
+    Plan pl;
+    rc = make_plan(N, nt, precision, cfg, &pl);
+    if (rc) return rc;
+    rc = device_pool_setup();
+    if (rc) return rc;
+    const bool want_sums = sum0_out || sum_out;
+    DevBuf sums, work;
+    sums.st = work.st = st;
+    if (want_sums) {
+        HEAT_HIP(hipMallocAsync(&sums.p, (SUM_BLOCKS + 2) * sizeof(double), st));
+        double *partial = (double *)sums.p;
+        HEAT_HIP(launch_sum(precision, d_u, N, partial, partial + SUM_BLOCKS, st));
+    }
+    if (nt > 0) {
+        void *b = d_work;
+        if (!b) {
+            HEAT_HIP(hipMallocAsync(&work.p, bytes, st));
+            b = work.p;
+        }
+        rc = run_rounds(pl, precision, d_u, b, N, r, nt, st);
+        if (rc) return rc;
+    }
+    if (want_sums) {
+        double *partial = (double *)sums.p;
+        HEAT_HIP(launch_sum(precision, d_u, N, partial, partial + SUM_BLOCKS + 1, st));
+        double h[2];
+        HEAT_HIP(hipMemcpyAsync(h, partial + SUM_BLOCKS, 2 * sizeof(double),
+                                hipMemcpyDeviceToHost, st));
+        HEAT_HIP(hipStreamSynchronize(st));
+        if (sum0_out) *sum0_out = h[0];
+        if (sum_out) *sum_out = h[1];
+    }
+    return HEAT_OK;
+}
+
+}  // namespace heat
+
+using namespace heat;
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char *heat_last_error(void) { return heat::g_err; }
+
+const char *heat_version(void) { return "heat-mi355x 0.1 (gfx950)"; }
+
+int heat_device_info(int32_t *cus, int32_t *lds_bytes, int32_t *wave_size, int32_t *clock_khz,
+                     size_t *mem_total, size_t *mem_free) {
+    int dev = 0;
+    HEAT_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HEAT_HIP(hipGetDeviceProperties(&prop, dev));
+    if (cus) *cus = prop.multiProcessorCount;
+    if (lds_bytes) *lds_bytes = (int32_t)prop.sharedMemPerBlock;
+    if (wave_size) *wave_size = prop.warpSize;
+    if (clock_khz) *clock_khz = prop.clockRate;
+    if (mem_total || mem_free) {
+        size_t f = 0, t = 0;
+        HEAT_HIP(hipMemGetInfo(&f, &t));
+        if (mem_total) *mem_total = t;
+        if (mem_free) *mem_free = f;
+    }
+    return HEAT_OK;
+}
+
+int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
+              heat_plan_info *out) {
+    int rc = check_problem(N, 1, 0.25, nt, precision);
+    if (rc) return rc;
+    if (!out) return fail(HEAT_EINVAL, "out is NULL");
+    Plan pl;
+    rc = make_plan(N, nt, precision, cfg, &pl);
+    if (rc) return rc;
+    out->kernel = pl.kernel;
+    out->cells_per_lane = pl.K;
+    out->steps_per_round = pl.T;
+    out->waves_per_group = pl.wpg;
+    out->tile_cells = pl.W;
+    out->tiles = pl.tiles;
+    out->rounds = pl.rounds;
+    return HEAT_OK;
+}
+
+int heat_solve_dev_cfg(void *d_u, void *d_work, int64_t N, int32_t nparts, double r, int64_t nt,
+                       int32_t precision, const heat_config *cfg, void *hip_stream,
+                       double *sum0_out, double *sum_out) {
+    return solve_dev_impl(d_u, d_work, N, nparts, r, nt, precision, cfg, (hipStream_t)hip_stream,
+                          sum0_out, sum_out);
+}
+
+int heat_solve_dev(void *d_u, int64_t N, int32_t nparts, double r, int64_t nt, int32_t precision,
+                   void *hip_stream, double *sum0_out, double *sum_out) {
+    return solve_dev_impl(d_u, nullptr, N, nparts, r, nt, precision, nullptr,
+                          (hipStream_t)hip_stream, sum0_out, sum_out);
+}
+
+int heat_solve(double *u, int64_t N, int32_t nparts, double r, int64_t nt) {
+    if (!u) return fail(HEAT_EINVAL, "u is NULL");
+    int rc = check_problem(N, nparts, r, nt, HEAT_FP64);
+    if (rc) return rc;
+    hipStream_t st = nullptr;
+    HEAT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    void *d = nullptr;
+    const size_t bytes = (size_t)N * sizeof(double);
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(st);
+        return fail_hip(e, "hipMalloc(state)");
+    }
+    rc = HEAT_OK;
+    e = hipMemcpyAsync(d, u, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) rc = fail_hip(e, "hipMemcpyAsync(H2D)");
+    if (!rc) rc = solve_dev_impl(d, nullptr, N, nparts, r, nt, HEAT_FP64, nullptr, st, nullptr,
+                                 nullptr);
+    if (!rc) {
+        e = hipMemcpyAsync(u, d, bytes, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) rc = fail_hip(e, "hipMemcpyAsync(D2H)");
+    }
+    e = hipStreamSynchronize(st);
+    if (!rc && e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");
+    (void)hipFree(d);
+    (void)hipStreamDestroy(st);
+    return rc;
+}
+
+int heat_checksum_dev(const void *d_u, int64_t N, int32_t precision, void *hip_stream,
+                      double *sum_out) {
+    if (!d_u || !sum_out) return fail(HEAT_EINVAL, "NULL pointer");
+    if (N < 1) return fail(HEAT_EINVAL, "N must be >= 1");
+    if (precision != HEAT_FP64 && precision != HEAT_FP32 && precision != HEAT_FP32C)
+        return fail(HEAT_EINVAL, "unknown precision %d", precision);
+    int rc = device_pool_setup();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf sums;
+    sums.st = st;
+    HEAT_HIP(hipMallocAsync(&sums.p, (SUM_BLOCKS + 1) * sizeof(double), st));
+    double *partial = (double *)sums.p;
+    HEAT_HIP(launch_sum(precision, d_u, N, partial, partial + SUM_BLOCKS, st));
+    HEAT_HIP(hipMemcpyAsync(sum_out, partial + SUM_BLOCKS, sizeof(double), hipMemcpyDeviceToHost,
+                            st));
+    HEAT_HIP(hipStreamSynchronize(st));
+    return HEAT_OK;
+}
+
+}  // extern "C"

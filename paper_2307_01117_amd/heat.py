@@ -1,0 +1,299 @@
+"""ctypes binding of libheat.so (the HIP library built from csrc/).
+
+Argument marshalling only: every step of the computation runs in the
+library's kernels.  The names follow include/heat.h.  If the library is not
+built, every call raises -- there is no CPU fallback.
+
+Device arrays are torch tensors on the current HIP device (torch supplies
+memory and streams only); the stream defaults to torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libheat.so")
+
+HEAT_OK, HEAT_PENDING = 0, 1
+HEAT_EINVAL, HEAT_ENOMEM, HEAT_EBUSY, HEAT_ENOENT, HEAT_EDEVICE, HEAT_ECANCELED = -1, -2, -3, -4, -5, -6
+FP64, FP32, FP32C = 0, 1, 2
+KERNEL_AUTO, KERNEL_STEP, KERNEL_TB = 0, 1, 2
+
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32c": FP32C}
+
+# every symbol declared in include/heat.h
+EXPORTS = [
+    "heat_solve", "heat_solve_dev", "heat_solve_dev_cfg", "heat_plan", "heat_checksum_dev",
+    "heat_solve_batch", "heat_solve_batch_dev", "heat_server_create", "heat_submit",
+    "heat_poll", "heat_wait", "heat_cancel", "heat_server_get_stats", "heat_server_destroy",
+    "heat_last_error", "heat_version", "heat_device_info",
+]
+
+
+class HeatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"heat error {code}: {msg}")
+        self.code = code
+
+
+class heat_config(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("cells_per_lane", ctypes.c_int32),
+                ("steps_per_round", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
+
+
+class heat_plan_info(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("cells_per_lane", ctypes.c_int32),
+                ("steps_per_round", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
+                ("tile_cells", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("rounds", ctypes.c_int64)]
+
+
+class heat_problem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("nparts", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("r", ctypes.c_double), ("nt", ctypes.c_int64), ("u0", ctypes.c_void_p),
+                ("u_out", ctypes.c_void_p), ("sum0", ctypes.c_double), ("sum_nt", ctypes.c_double),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class heat_ring(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("nt", ctypes.c_int64), ("r", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("nparts", ctypes.c_int32),
+                ("d_u", ctypes.c_void_p), ("d_work", ctypes.c_void_p)]
+
+
+class heat_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("cancelled", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("ticks", ctypes.c_uint64),
+                ("cell_updates", ctypes.c_uint64), ("hbm_budget", ctypes.c_size_t),
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t),
+                ("active", ctypes.c_int32), ("queued", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libheat.so and declare the signatures of include/heat.h."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2307_01117_amd.build`")
+    lib = ctypes.CDLL(path)
+    i32, i64, d, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    pd = ctypes.POINTER(ctypes.c_double)
+    P = ctypes.POINTER
+    sig = {
+        "heat_solve": ([vp, i64, i32, d, i64], i32),
+        "heat_solve_dev": ([vp, i64, i32, d, i64, i32, vp, pd, pd], i32),
+        "heat_solve_dev_cfg": ([vp, vp, i64, i32, d, i64, i32, P(heat_config), vp, pd, pd], i32),
+        "heat_plan": ([i64, i64, i32, P(heat_config), P(heat_plan_info)], i32),
+        "heat_checksum_dev": ([vp, i64, i32, vp, pd], i32),
+        "heat_solve_batch": ([P(heat_problem), i32], i32),
+        "heat_solve_batch_dev": ([P(heat_ring), i32, vp, i32], i32),
+        "heat_server_create": ([ctypes.c_size_t, i32, i32, P(vp)], i32),
+        "heat_submit": ([vp, P(heat_problem), P(ctypes.c_uint64)], i32),
+        "heat_poll": ([vp, ctypes.c_uint64], i32),
+        "heat_wait": ([vp, ctypes.c_uint64], i32),
+        "heat_cancel": ([vp, ctypes.c_uint64], i32),
+        "heat_server_get_stats": ([vp, P(heat_server_stats)], i32),
+        "heat_server_destroy": ([vp], i32),
+        "heat_last_error": ([], ctypes.c_char_p),
+        "heat_version": ([], ctypes.c_char_p),
+        "heat_device_info": ([P(i32), P(i32), P(i32), P(i32), P(ctypes.c_size_t),
+                              P(ctypes.c_size_t)], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().heat_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise HeatError(rc, last_error())
+    return rc
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _cfg(kernel=0, cells_per_lane=0, steps_per_round=0, waves_per_group=0):
+    if not (kernel or cells_per_lane or steps_per_round or waves_per_group):
+        return None
+    return ctypes.byref(heat_config(kernel, cells_per_lane, steps_per_round, waves_per_group))
+
+
+def version() -> str:
+    return load().heat_version().decode()
+
+
+def device_info() -> dict:
+    vals = [ctypes.c_int32() for _ in range(4)] + [ctypes.c_size_t() for _ in range(2)]
+    _check(load().heat_device_info(*[ctypes.byref(v) for v in vals]))
+    keys = ["cus", "lds_bytes", "wave_size", "clock_khz", "mem_total", "mem_free"]
+    return {k: v.value for k, v in zip(keys, vals)}
+
+
+def plan(N: int, nt: int, precision: int = FP64, **cfg) -> dict:
+    out = heat_plan_info()
+    _check(load().heat_plan(int(N), int(nt), int(precision), _cfg(**cfg), ctypes.byref(out)))
+    return {f: getattr(out, f) for f, _ in heat_plan_info._fields_}
+
+
+def solve(u: np.ndarray, nparts: int, r: float, nt: int) -> np.ndarray:
+    """Plain form on a host binary64 array (copied; the result is returned)."""
+    a = np.ascontiguousarray(u, dtype=np.float64).copy()
+    _check(load().heat_solve(a.ctypes.data, a.size, int(nparts), float(r), int(nt)))
+    return a
+
+
+def solve_dev(d_u, nparts: int, r: float, nt: int, precision: int | None = None, stream=None,
+              sums: bool = False, work=None, **cfg):
+    """Device form on a torch tensor (float64 for FP64, float32 for FP32 forms),
+    advanced in place.  With ``sums`` returns (sum0, sum_nt) and waits."""
+    import torch
+    if precision is None:
+        precision = FP64 if d_u.dtype == torch.float64 else FP32
+    want = torch.float64 if precision == FP64 else torch.float32
+    if d_u.dtype != want or not d_u.is_contiguous() or not d_u.is_cuda:
+        raise ValueError("d_u must be a contiguous device tensor of the precision's dtype")
+    if work is not None and (work.dtype != want or work.numel() < d_u.numel()):
+        raise ValueError("work must be a device tensor of the same dtype and size")
+    s0, s1 = ctypes.c_double(), ctypes.c_double()
+    ps0 = ctypes.byref(s0) if sums else None
+    ps1 = ctypes.byref(s1) if sums else None
+    _check(load().heat_solve_dev_cfg(d_u.data_ptr(), work.data_ptr() if work is not None else None,
+                                     d_u.numel(), int(nparts), float(r), int(nt), int(precision),
+                                     _cfg(**cfg), _stream_handle(stream), ps0, ps1))
+    return (s0.value, s1.value) if sums else None
+
+
+def checksum_dev(d_u, precision: int | None = None, stream=None) -> float:
+    import torch
+    if precision is None:
+        precision = FP64 if d_u.dtype == torch.float64 else FP32
+    out = ctypes.c_double()
+    _check(load().heat_checksum_dev(d_u.data_ptr(), d_u.numel(), int(precision),
+                                    _stream_handle(stream), ctypes.byref(out)))
+    return out.value
+
+
+@dataclass
+class BatchResult:
+    u: np.ndarray
+    sum0: float
+    sum_nt: float
+    status: int
+
+
+def solve_batch(problems) -> list:
+    """Batching form on host arrays.  ``problems``: iterable of dicts with
+    u0, nparts, r, nt and optional precision.  Returns BatchResult list."""
+    probs = list(problems)
+    arr = (heat_problem * len(probs))()
+    keep = []
+    for i, p in enumerate(probs):
+        u0 = np.ascontiguousarray(p["u0"], dtype=np.float64)
+        out = np.empty_like(u0)
+        keep.append((u0, out))
+        arr[i] = heat_problem(u0.size, int(p.get("nparts", 1)), int(p.get("precision", FP64)),
+                              float(p["r"]), int(p["nt"]), u0.ctypes.data, out.ctypes.data,
+                              0.0, 0.0, 0, 0)
+    rc = load().heat_solve_batch(arr, len(probs))
+    res = [BatchResult(keep[i][1], arr[i].sum0, arr[i].sum_nt, arr[i].status)
+           for i in range(len(probs))]
+    _check(rc)
+    return res
+
+
+def solve_batch_dev(rings, stream=None, wait: bool = True):
+    """Device batching form.  ``rings``: iterable of (d_u, d_work, nt, r, precision)
+    with torch tensors; every ring advances in one fused launch."""
+    rings = list(rings)
+    arr = (heat_ring * len(rings))()
+    for i, (d_u, d_work, nt, r, prec) in enumerate(rings):
+        arr[i] = heat_ring(d_u.numel(), int(nt), float(r), int(prec), 1, d_u.data_ptr(),
+                           d_work.data_ptr() if d_work is not None else None)
+    _check(load().heat_solve_batch_dev(arr, len(rings), _stream_handle(stream), int(bool(wait))))
+
+
+class Server:
+    """Continuous-batching server (heat_server_*)."""
+
+    def __init__(self, hbm_budget: int = 0, max_slots: int = 0, max_queue: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(load().heat_server_create(int(hbm_budget), int(max_slots), int(max_queue),
+                                         ctypes.byref(self._h)))
+        self._live = {}
+
+    def submit(self, u0: np.ndarray, nt: int, r: float, precision: int = FP64, nparts: int = 1,
+               out: np.ndarray | None = None) -> int:
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        if out is None:
+            out = np.empty_like(u0)
+        p = heat_problem(u0.size, int(nparts), int(precision), float(r), int(nt), u0.ctypes.data,
+                         out.ctypes.data, 0.0, 0.0, 0, 0)
+        t = ctypes.c_uint64()
+        _check(load().heat_submit(self._h, ctypes.byref(p), ctypes.byref(t)))
+        self._live[t.value] = (p, u0, out)
+        return t.value
+
+    def _result(self, t):
+        p, _, out = self._live.pop(t)
+        return BatchResult(out, p.sum0, p.sum_nt, p.status)
+
+    def poll(self, ticket: int):
+        rc = load().heat_poll(self._h, ctypes.c_uint64(ticket))
+        if rc == HEAT_PENDING:
+            return None
+        if rc < 0:
+            self._live.pop(ticket, None)
+            raise HeatError(rc, last_error())
+        return self._result(ticket)
+
+    def wait(self, ticket: int):
+        rc = load().heat_wait(self._h, ctypes.c_uint64(ticket))
+        if rc < 0:
+            self._live.pop(ticket, None)
+            raise HeatError(rc, last_error())
+        return self._result(ticket)
+
+    def cancel(self, ticket: int) -> None:
+        rc = load().heat_cancel(self._h, ctypes.c_uint64(ticket))
+        self._live.pop(ticket, None)
+        _check(rc)
+
+    def stats(self) -> dict:
+        s = heat_server_stats()
+        _check(load().heat_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in heat_server_stats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            _check(load().heat_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

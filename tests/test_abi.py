@@ -1,0 +1,102 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+that include/heat.h declares, and its host-side logic (validation, planner)
+behaves as documented.  No kernel is launched here."""
+import os
+import re
+
+import pytest
+
+from paper_2307_01117_amd import heat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "heat.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w]+\s*\*?\s*(heat_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(heat.LIB_PATH):
+        from paper_2307_01117_amd import build
+        build.build()
+    return heat.load()
+
+
+def test_header_declares_binding_exports():
+    assert declared_functions() == sorted(heat.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version(lib):
+    assert "gfx950" in heat.version()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(N=0, nparts=1, r=0.5, nt=1), "N must be"),
+    (dict(N=10, nparts=0, r=0.5, nt=1), "nparts"),
+    (dict(N=10, nparts=11, r=0.5, nt=1), "nparts"),
+    (dict(N=10, nparts=1, r=0.6, nt=1), "r must be"),
+    (dict(N=10, nparts=1, r=-0.1, nt=1), "r must be"),
+    (dict(N=10, nparts=1, r=float("nan"), nt=1), "r must be"),
+    (dict(N=10, nparts=1, r=0.5, nt=-1), "nt must be"),
+])
+def test_validation_without_device(lib, kw, msg):
+    import numpy as np
+    u = np.zeros(max(kw["N"], 1))
+    rc = lib.heat_solve(u.ctypes.data, kw["N"], kw["nparts"], kw["r"], kw["nt"])
+    assert rc == heat.HEAT_EINVAL
+    assert msg in heat.last_error()
+
+
+def test_null_pointers(lib):
+    assert lib.heat_solve(None, 10, 1, 0.5, 1) == heat.HEAT_EINVAL
+    assert lib.heat_solve_dev(None, 10, 1, 0.5, 1, 0, None, None, None) == heat.HEAT_EINVAL
+    assert lib.heat_checksum_dev(None, 10, 0, None, None) == heat.HEAT_EINVAL
+
+
+def test_planner_geometry(lib):
+    p = heat.plan(100_000_000, 1000, heat.FP64)
+    assert p["kernel"] == heat.KERNEL_TB
+    K, T = p["cells_per_lane"], p["steps_per_round"]
+    assert p["tile_cells"] == 64 * K - 2 * ((T + 3) // 4 * 4)
+    assert p["tiles"] == -(-100_000_000 // p["tile_cells"])
+    assert p["rounds"] == -(-1000 // T)
+    # a run shorter than one round is one round of nt steps
+    q = heat.plan(1000, 5, heat.FP64)
+    assert q["rounds"] == 1 and q["steps_per_round"] == 5
+    s = heat.plan(1000, 7, heat.FP64, kernel=heat.KERNEL_STEP)
+    assert s["rounds"] == 7 and s["steps_per_round"] == 1
+    assert heat.plan(1000, 0, heat.FP32C)["rounds"] == 0
+
+
+def test_compensated_round_length_is_fixed(lib):
+    """The compensated form's round length T is part of its result; it must
+    not depend on N or on the configuration of tiles."""
+    Ts = {heat.plan(N, 1000, heat.FP32C)["steps_per_round"] for N in (1, 1000, 10**6, 10**8)}
+    assert len(Ts) == 1
+    for K in (8, 16, 32):
+        assert heat.plan(10**6, 1000, heat.FP32C, cells_per_lane=K)["steps_per_round"] in Ts
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(kernel=7), dict(cells_per_lane=12), dict(steps_per_round=6),
+    dict(cells_per_lane=8, steps_per_round=256), dict(waves_per_group=3),
+])
+def test_planner_rejects_bad_config(lib, cfg):
+    with pytest.raises(heat.HeatError) as ei:
+        heat.plan(10**6, 100, heat.FP64, **cfg)
+    assert ei.value.code == heat.HEAT_EINVAL
+
+
+def test_step_kernel_rejects_compensated(lib):
+    with pytest.raises(heat.HeatError):
+        heat.plan(1000, 10, heat.FP32C, kernel=heat.KERNEL_STEP)

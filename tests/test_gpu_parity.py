@@ -1,0 +1,235 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+binary64 and plain binary32 results must be bit-identical to the oracle (the
+kernels evaluate every cell with the same operations in the same order);
+the compensated binary32 form must be bit-identical to the oracle's
+compensated form with the same round length T, and within 1e-6 relative of
+the binary64 oracle.  Full-size rings are compared at sampled cells through
+the oracle's light-cone evaluation, which is bit-identical to the full ring.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_01117_amd import heat, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    heat.load()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def run_dev(u0, nt, r, precision=heat.FP64, nparts=1, **cfg):
+    dt = torch.float64 if precision == heat.FP64 else torch.float32
+    d = dev(u0, dt)
+    heat.solve_dev(d, nparts, r, nt, precision=precision, **cfg)
+    torch.cuda.synchronize()
+    return d.cpu().numpy()
+
+
+def cfgs_fp64():
+    return [
+        dict(),
+        dict(kernel=heat.KERNEL_STEP),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=8, steps_per_round=4),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=8, steps_per_round=16, waves_per_group=1),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=16, steps_per_round=32, waves_per_group=8),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=32, steps_per_round=64),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=32, steps_per_round=8, waves_per_group=2),
+    ]
+
+
+# ------------------------------------------------------------ tiny rings
+
+@pytest.mark.parametrize("ci", range(7))
+def test_tiny_rings_bitwise(ci):
+    """Every ring length 1..70 (windows wrap the ring many times), run lengths
+    around the round length, several r: bit-identical to the oracle."""
+    cfg = cfgs_fp64()[ci]
+    for N in list(range(1, 71)) + [127, 128, 129, 511, 513]:
+        u0 = inputs.uniform_ring(N, (20, N))
+        for nt, r in ((0, 0.5), (1, 0.5), (3, 0.25), (33, 0.5), (70, 0.3)):
+            got = run_dev(u0, nt, r, **cfg)
+            want = oracle.solve(u0, r, nt)
+            assert np.array_equal(got, want), (cfg, N, nt, r)
+
+
+def test_exact_small_integer_cases():
+    """Dyadic r and integer states: the exact rational result (pinned in the
+    oracle tests) is reproduced bit for bit."""
+    for N in (1, 2, 3, 7, 16, 100):
+        u0 = inputs.small_integer_ring(N, (21, N))
+        for r in (0.0, 0.125, 0.25, 0.375, 0.5):
+            for cfg in cfgs_fp64()[:3]:
+                assert np.array_equal(run_dev(u0, 12, r, **cfg), oracle.solve(u0, r, 12))
+
+
+# ------------------------------------------------------------ mid-size, ragged
+
+@pytest.mark.parametrize("N", [1000, 4097, 100_003, 262_144 + 77])
+def test_midsize_fp64_all_kernels(N):
+    u0 = inputs.uniform_ring(N, (22, N))
+    nt, r = 75, 0.5
+    want = oracle.solve(u0, r, nt)
+    for cfg in cfgs_fp64():
+        got = run_dev(u0, nt, r, **cfg)
+        bad = np.flatnonzero(got != want)
+        assert bad.size == 0, (cfg, N, bad[:10])
+
+
+@pytest.mark.parametrize("N", [999, 65_536 + 13, 300_001])
+def test_midsize_fp32_bitwise(N):
+    u0 = inputs.perturbed_ring(N, (23, N)).astype(np.float32)
+    nt, r = 70, 0.25
+    want = oracle.solve_f32(u0, r, nt)
+    for cfg in (dict(), dict(kernel=heat.KERNEL_STEP), dict(cells_per_lane=8, steps_per_round=20),
+                dict(cells_per_lane=16, steps_per_round=32)):
+        got = run_dev(u0, nt, r, precision=heat.FP32, **cfg)
+        assert np.array_equal(got, want), (cfg, N)
+
+
+@pytest.mark.parametrize("N", [1, 5, 999, 65_536 + 13, 300_001])
+def test_midsize_fp32c_bitwise(N):
+    u0 = inputs.perturbed_ring(N, (24, N)).astype(np.float32)
+    r = 0.25
+    for nt in (7, 100):
+        T = heat.plan(N, nt, heat.FP32C)["steps_per_round"]
+        want = oracle.solve_f32c(u0, r, nt, T)
+        for K in (8, 16, 32):
+            got = run_dev(u0, nt, r, precision=heat.FP32C, cells_per_lane=K)
+            assert np.array_equal(got, want), (K, N, nt)
+
+
+# ------------------------------------------------------------ invariances on the GPU
+
+def test_partition_count_does_not_change_result():
+    N = 50_001
+    u0 = inputs.uniform_ring(N, 25)
+    base = run_dev(u0, 40, 0.5, nparts=1)
+    for P in (2, 10, 100, N):
+        assert np.array_equal(run_dev(u0, 40, 0.5, nparts=P), base)
+
+
+def test_shift_and_composition():
+    N = 123_457
+    u0 = inputs.uniform_ring(N, 26)
+    base = run_dev(u0, 64, 0.37)
+    for s in (1, 959, 960, 961, 65_536):
+        assert np.array_equal(run_dev(np.roll(u0, s), 64, 0.37), np.roll(base, s))
+    mid = run_dev(u0, 23, 0.37)
+    assert np.array_equal(run_dev(mid, 41, 0.37), base)
+
+
+def test_checksum_matches_exact_sum():
+    for N in (1, 17, 1_000_000):
+        u0 = inputs.uniform_ring(N, (27, N))
+        s = heat.checksum_dev(dev(u0))
+        exact = math.fsum(u0)
+        assert abs(s - exact) <= 1e-13 * max(abs(exact), 1e-300)
+        s32 = heat.checksum_dev(dev(u0, torch.float32), precision=heat.FP32)
+        e32 = math.fsum(u0.astype(np.float32).astype(np.float64))
+        assert abs(s32 - e32) <= 1e-13 * abs(e32)
+
+
+def test_device_errors():
+    d = dev(np.zeros(10))
+    with pytest.raises(heat.HeatError) as ei:
+        heat.solve_dev(d, 1, 0.75, 10)
+    assert ei.value.code == heat.HEAT_EINVAL
+    with pytest.raises(heat.HeatError):
+        heat.solve_dev(d, 1, 0.5, 10, precision=heat.FP32C, kernel=heat.KERNEL_STEP)
+    # host form agrees with the device form
+    u0 = inputs.uniform_ring(1000, 28)
+    assert np.array_equal(heat.solve(u0, 4, 0.5, 30), oracle.solve(u0, 0.5, 30))
+
+
+# ------------------------------------------------------------ full-size workloads
+
+def sample_cells(N, W, rng, n=48):
+    """Cells at and around tile edges, the ring's wrap and random places."""
+    s = {0, 1, N - 1, N - 2, N // 2}
+    for t in (1, 2, N // W // 2, N // W - 1):
+        for d in (-1, 0, 1):
+            s.add((t * W + d) % N)
+    s.update(int(x) for x in rng.integers(0, N, n))
+    return np.array(sorted(s), dtype=np.int64)
+
+
+def test_ring_1e6_full_compare():
+    """10 partitions x 100,000 cells, r = 1/2, 100 steps, Uniform[0,1) seed 0:
+    the whole array, bit for bit, plus the conservation check."""
+    w = inputs.WORKLOADS["ring_1e6"]
+    u0 = inputs.make_initial(w["init"], w["N"], w["seed"])
+    d = dev(u0)
+    s0, s1 = heat.solve_dev(d, w["nparts"], w["r"], w["nt"], sums=True)
+    got = d.cpu().numpy()
+    want = oracle.solve(u0, w["r"], w["nt"])
+    assert np.array_equal(got, want)
+    assert abs(s1 - s0) <= 8 * 2.0 ** -53 * w["N"] * w["nt"]
+    # the step kernel as well
+    assert np.array_equal(run_dev(u0, w["nt"], w["r"], kernel=heat.KERNEL_STEP), want)
+
+
+def test_sine_mode_decay_on_gpu():
+    N, r, nt = 1_000_000, 0.5, 100
+    u0 = inputs.sine_mode(N, 3)
+    got = run_dev(u0, nt, r)
+    g = math.cos(2 * math.pi * 3 / N)
+    assert np.abs(got - g ** nt * u0).max() <= 1e-13
+
+
+@pytest.mark.parametrize("kernel", [heat.KERNEL_TB, heat.KERNEL_STEP])
+def test_ring_1e8_sampled(kernel):
+    """100 partitions x 1,000,000 cells, r = 1/2, 1,000 steps, Uniform[0,1)
+    seed 1, in the launch configuration the benchmark times: sampled cells
+    bit for bit against light cones, and the binary64 sum conserved."""
+    w = inputs.WORKLOADS["ring_1e8"]
+    N = w["N"]
+    u0 = inputs.make_initial(w["init"], N, w["seed"])
+    d = dev(u0)
+    s0, s1 = heat.solve_dev(d, w["nparts"], w["r"], w["nt"], sums=True, kernel=kernel)
+    W = heat.plan(N, w["nt"], heat.FP64)["tile_cells"]
+    idx = sample_cells(N, W, np.random.default_rng(31), n=24 if kernel == heat.KERNEL_TB else 8)
+    got = d[torch.from_numpy(idx).cuda()].cpu().numpy()
+    del d
+    want = np.array([oracle.cone(u0, int(i), w["r"], w["nt"]) for i in idx])
+    assert np.array_equal(got, want), idx[got != want][:10]
+    assert abs(s1 - s0) <= 8 * 2.0 ** -53 * N * w["nt"]
+
+
+def test_ring_1e8_perturbed_fp32_forms():
+    """N = 1e8, r = 1/4, 1,000 steps, 1 + 1e-3*Uniform[-1,1) seed 2: the
+    compensated form matches the oracle's compensated form bit for bit at
+    sampled cells and stays within 1e-6 relative of binary64; plain binary32
+    matches its oracle bit for bit."""
+    w = inputs.WORKLOADS["ring_1e8_perturbed"]
+    N, r, nt = w["N"], w["r"], w["nt"]
+    u0 = inputs.make_initial(w["init"], N, w["seed"])
+    u32 = u0.astype(np.float32)
+    idx = sample_cells(N, 1984, np.random.default_rng(32), n=12)
+    T = heat.plan(N, nt, heat.FP32C)["steps_per_round"]
+    ref64 = np.array([oracle.cone(u32.astype(np.float64), int(i), r, nt) for i in idx])
+    for prec in (heat.FP32C, heat.FP32):
+        d = dev(u32, torch.float32)
+        heat.solve_dev(d, w["nparts"], r, nt, precision=prec)
+        got = d[torch.from_numpy(idx).cuda()].cpu().numpy()
+        del d
+        if prec == heat.FP32C:
+            want = np.array([oracle.cone_f32c(u32, int(i), r, nt, T) for i in idx])
+            assert np.array_equal(got, want)
+            assert np.abs(got - ref64).max() / np.abs(ref64).max() <= 1e-6
+        else:
+            want = np.array([oracle.cone_f32(u32, int(i), r, nt) for i in idx])
+            assert np.array_equal(got, want)
