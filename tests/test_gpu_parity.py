@@ -149,7 +149,8 @@ def test_device_errors():
         heat.solve_dev(d, 1, 0.75, 10)
     assert ei.value.code == heat.HEAT_EINVAL
     with pytest.raises(heat.HeatError):
-        heat.solve_dev(d, 1, 0.5, 10, precision=heat.FP32C, kernel=heat.KERNEL_STEP)
+        heat.solve_dev(dev(np.zeros(10), torch.float32), 1, 0.5, 10, precision=heat.FP32C,
+                       kernel=heat.KERNEL_STEP)
     # host form agrees with the device form
     u0 = inputs.uniform_ring(1000, 28)
     assert np.array_equal(heat.solve(u0, 4, 0.5, 30), oracle.solve(u0, 0.5, 30))
