@@ -69,6 +69,8 @@ typedef struct heat_config {
     int32_t cells_per_lane;  /* TB: cells held per lane, one of 8, 16, 32       */
     int32_t steps_per_round; /* TB: T, a multiple of 4 with 2T < 64*cells - 8   */
     int32_t waves_per_group; /* 1, 2, 4 or 8 wavefronts per workgroup           */
+    int32_t register_form;   /* TB: 1 = in-place update (K state registers),
+                                2 = ping-pong (2K registers, no register copies) */
 } heat_config;
 
 /* What the planner picked for a given problem (filled by heat_plan). */
@@ -77,6 +79,8 @@ typedef struct heat_plan_info {
     int32_t cells_per_lane;  /* K (TB)                                          */
     int32_t steps_per_round; /* T: steps per round (1 for STEP)                 */
     int32_t waves_per_group;
+    int32_t register_form;   /* 1 in-place, 2 ping-pong (TB)                     */
+    int32_t reserved;
     int64_t tile_cells;      /* W = 64*K - 2T output cells per tile (TB)        */
     int64_t tiles;           /* tiles per round                                 */
     int64_t rounds;          /* launches (STEP: nt, TB: ceil(nt / T))           */
@@ -235,6 +239,15 @@ int heat_server_destroy(heat_server *s);
 
 /* Thread-local text for the last negative return on this thread. */
 const char *heat_last_error(void);
+
+/*
+ * Plain streaming copy of `bytes` bytes (a multiple of 16, both pointers
+ * 16-byte aligned) between two device buffers on hip_stream, with the same
+ * launch shape as the one-step kernel.  It measures the HBM bandwidth a
+ * read-once/write-once kernel reaches on this device, the ceiling the
+ * one-step sweep is judged against.  Asynchronous.
+ */
+int heat_copy_dev(const void *d_src, void *d_dst, size_t bytes, void *hip_stream);
 
 /* Library version string. */
 const char *heat_version(void);

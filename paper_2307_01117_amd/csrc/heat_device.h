@@ -96,6 +96,22 @@ __device__ __forceinline__ void window_step(T (&v)[K], T r) {
     }
 }
 
+// Ping-pong form of the same step: reads a[], writes b[].  Two of them in a
+// row return the state to a[] with no register copies (the in-place form
+// makes the compiler rotate the whole array through the registers once per
+// step).  Costs K more registers.
+template <int K, class T>
+__device__ __forceinline__ void window_step_pp(const T (&a)[K], T (&b)[K], T r) {
+    const T left = from_prev(a[K - 1]);
+    const T right = from_next(a[0]);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const T l = j == 0 ? left : a[j - 1];
+        const T q = (j + 1 < K) ? a[j + 1] : right;
+        b[j] = cell_update(l, a[j], q, r);
+    }
+}
+
 // Compensated binary32 step of the pair (u, e): the Laplacian of u + e is
 // formed from the exact-ish differences of both parts, then added to u with
 // Fast2Sum so that the rounding error of the addition is kept in e.
@@ -117,6 +133,28 @@ __device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], f
         u[j] = t;
         pu = c;
         pe = ec;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void window_step_comp_pp(const float (&u)[K], const float (&e)[K],
+                                                    float (&un)[K], float (&en)[K], float r) {
+    const float lu = from_prev(u[K - 1]);
+    const float le = from_prev(e[K - 1]);
+    const float ru = from_next(u[0]);
+    const float re = from_next(e[0]);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const float c = u[j], ec = e[j];
+        const float l = j == 0 ? lu : u[j - 1];
+        const float el = j == 0 ? le : e[j - 1];
+        const float q = (j + 1 < K) ? u[j + 1] : ru;
+        const float eq = (j + 1 < K) ? e[j + 1] : re;
+        const float d = r * (((l - c) + (q - c)) + ((el - ec) + (eq - ec)));
+        const float y = d + ec;
+        const float t = c + y;
+        en[j] = y - (t - c);
+        un[j] = t;
     }
 }
 

@@ -33,6 +33,7 @@ struct Plan {
     int T = 32;          // steps per round
     int H = 32;          // halo cells per side of a window (multiple of 4, >= T)
     int wpg = 4;         // wavefronts per workgroup
+    bool pingpong = true;  // TB register form: ping-pong (true) or in-place
     int64_t W = 0;       // output cells per tile (TB) / cells per chunk (STEP)
     int64_t tiles = 0;   // tiles (TB) or chunks (STEP) per launch
     int64_t rounds = 0;  // launches
@@ -46,14 +47,15 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
 // is a pure function of (N, precision) -- never of timing or of a batch mix.
 int default_steps_per_round(int64_t N, int precision);
 int default_cells_per_lane(int64_t N, int precision);
+bool default_pingpong(int64_t N, int precision);
 
 // ----------------------------------------------------------- kernels
 
 // One round of the temporal-blocked window kernel: every tile loads 64*K
 // cells starting H cells left of its output, advances `steps` (<= H) steps
 // in registers and writes its W = 64*K - 2H output cells.
-hipError_t launch_window(int precision, int K, const void *src, void *dst, int64_t N, int H,
-                         int steps, double r, int wpg, hipStream_t st);
+hipError_t launch_window(int precision, int K, bool pingpong, const void *src, void *dst, int64_t N,
+                         int H, int steps, double r, int wpg, hipStream_t st);
 
 // One step of the coalesced sweep (binary64 or binary32).
 hipError_t launch_step(int precision, const void *src, void *dst, int64_t N, double r, int wpg,
@@ -71,6 +73,8 @@ hipError_t launch_sum(int precision, const void *u, int64_t N, double *partial, 
 hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+// Streaming 16-byte copy (bandwidth probe), same launch shape as k_step.
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 
 // ----------------------------------------------------------- batching
 

@@ -77,8 +77,9 @@ __device__ __forceinline__ void window_store(typename P::T *__restrict__ dst, in
     }
 }
 
-// Process one tile: output cells [b, b + min(W, N - b)).
-template <class P, int K>
+// Process one tile: output cells [b, b + min(W, N - b)).  PP selects the
+// ping-pong register form (no register rotation, twice the state registers).
+template <class P, int K, bool PP>
 __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ src,
                                             typename P::T *__restrict__ dst, int64_t N, int H,
                                             int steps, typename P::T r, int64_t b, int64_t W,
@@ -94,16 +95,36 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
         T e[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) e[j] = T(0);
-        for (int s = 0; s < steps; ++s) window_step_comp<K>(v, e, r);
+        if constexpr (PP) {
+            T v2[K], e2[K];
+            int s = 0;
+            for (; s + 2 <= steps; s += 2) {
+                window_step_comp_pp<K>(v, e, v2, e2, r);
+                window_step_comp_pp<K>(v2, e2, v, e, r);
+            }
+            if (s < steps) window_step_comp<K>(v, e, r);
+        } else {
+            for (int s = 0; s < steps; ++s) window_step_comp<K>(v, e, r);
+        }
 #pragma unroll
         for (int j = 0; j < K; ++j) v[j] = v[j] + e[j];   // fold: u := fl32(u + e)
     } else {
-        for (int s = 0; s < steps; ++s) window_step<K>(v, r);
+        if constexpr (PP) {
+            T v2[K];
+            int s = 0;
+            for (; s + 2 <= steps; s += 2) {
+                window_step_pp<K>(v, v2, r);
+                window_step_pp<K>(v2, v, r);
+            }
+            if (s < steps) window_step<K>(v, r);
+        } else {
+            for (int s = 0; s < steps; ++s) window_step<K>(v, r);
+        }
     }
     window_store<P, K>(dst, b, H, W, wlen, fast, lane, v);
 }
 
-template <class P, int K>
+template <class P, int K, bool PP>
 __global__ void __launch_bounds__(512)
 k_window(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst, int64_t N,
          int32_t H, int32_t steps, double r, int64_t tiles, int32_t vec_ok) {
@@ -113,7 +134,7 @@ k_window(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst,
     const int64_t tile = blk * wpg + (threadIdx.x >> 6);
     if (tile >= tiles) return;
     const int64_t W = 64 * K - 2 * (int64_t)H;
-    window_tile<P, K>(src, dst, N, H, steps, (typename P::T)r, tile * W, W, vec_ok != 0, lane);
+    window_tile<P, K, PP>(src, dst, N, H, steps, (typename P::T)r, tile * W, W, vec_ok != 0, lane);
 }
 
 // ==================================================================== STEP
@@ -332,7 +353,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
                 T *dst = reinterpret_cast<T *>(R.buf[(k + 1) & 1]);
                 const int64_t done = k * (int64_t)R.T;
                 const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
-                window_tile<P, K>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0, lane);
+                window_tile<P, K, true>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0, lane);
             } else {
                 // copy-back round: the final state sits in buf[1]
                 const T *src = reinterpret_cast<const T *>(R.buf[1]);
@@ -357,11 +378,34 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
     }
 }
 
+// ==================================================================== COPY
+// Bandwidth probe: every wave moves U 16-byte vectors per lane, coalesced,
+// exactly like the fast path of k_step without the arithmetic.
+
+__global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                              int64_t nvec) {
+    constexpr int U = STEP_U;
+    const int lane = threadIdx.x & 63;
+    const int64_t chunk = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t base = chunk * 64 * U;
+    uint4 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = base + u * 64 + lane;
+        if (i < nvec) x[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = base + u * 64 + lane;
+        if (i < nvec) dst[i] = x[u];
+    }
+}
+
 // ================================================================ LAUNCHERS
 
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-template <class P, int K>
+template <class P, int K, bool PP>
 static hipError_t launch_window_t(const void *src, void *dst, int64_t N, int H, int steps, double r,
                                   int wpg, hipStream_t st) {
     using T = typename P::T;
@@ -369,29 +413,33 @@ static hipError_t launch_window_t(const void *src, void *dst, int64_t N, int H, 
     const int64_t tiles = (N + W - 1) / W;
     const int64_t blocks = (tiles + wpg - 1) / wpg;
     const int vec_ok = aligned16(src) && aligned16(dst);
-    hipLaunchKernelGGL((k_window<P, K>), dim3((unsigned)blocks), dim3(64 * wpg), 0, st,
+    hipLaunchKernelGGL((k_window<P, K, PP>), dim3((unsigned)blocks), dim3(64 * wpg), 0, st,
                        reinterpret_cast<const T *>(src), reinterpret_cast<T *>(dst), N, H, steps, r,
                        tiles, vec_ok);
     return hipGetLastError();
 }
 
-template <class P>
+template <class P, bool PP>
 static hipError_t launch_window_p(int K, const void *src, void *dst, int64_t N, int H, int steps,
                                   double r, int wpg, hipStream_t st) {
     switch (K) {
-        case 8: return launch_window_t<P, 8>(src, dst, N, H, steps, r, wpg, st);
-        case 16: return launch_window_t<P, 16>(src, dst, N, H, steps, r, wpg, st);
-        case 32: return launch_window_t<P, 32>(src, dst, N, H, steps, r, wpg, st);
+        case 8: return launch_window_t<P, 8, PP>(src, dst, N, H, steps, r, wpg, st);
+        case 16: return launch_window_t<P, 16, PP>(src, dst, N, H, steps, r, wpg, st);
+        case 32: return launch_window_t<P, 32, PP>(src, dst, N, H, steps, r, wpg, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_window(int precision, int K, const void *src, void *dst, int64_t N, int H,
-                         int steps, double r, int wpg, hipStream_t st) {
-    switch (precision) {
-        case HEAT_FP64: return launch_window_p<F64>(K, src, dst, N, H, steps, r, wpg, st);
-        case HEAT_FP32: return launch_window_p<F32>(K, src, dst, N, H, steps, r, wpg, st);
-        case HEAT_FP32C: return launch_window_p<F32C>(K, src, dst, N, H, steps, r, wpg, st);
+hipError_t launch_window(int precision, int K, bool pingpong, const void *src, void *dst, int64_t N,
+                         int H, int steps, double r, int wpg, hipStream_t st) {
+    switch (precision * 2 + (pingpong ? 1 : 0)) {
+        case HEAT_FP64 * 2: return launch_window_p<F64, false>(K, src, dst, N, H, steps, r, wpg, st);
+        case HEAT_FP64 * 2 + 1: return launch_window_p<F64, true>(K, src, dst, N, H, steps, r, wpg, st);
+        case HEAT_FP32 * 2: return launch_window_p<F32, false>(K, src, dst, N, H, steps, r, wpg, st);
+        case HEAT_FP32 * 2 + 1: return launch_window_p<F32, true>(K, src, dst, N, H, steps, r, wpg, st);
+        case HEAT_FP32C * 2: return launch_window_p<F32C, false>(K, src, dst, N, H, steps, r, wpg, st);
+        case HEAT_FP32C * 2 + 1:
+            return launch_window_p<F32C, true>(K, src, dst, N, H, steps, r, wpg, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -447,6 +495,15 @@ hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream
 
 hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st) {
+    const int64_t nvec = (int64_t)(bytes / 16);
+    const int64_t chunks = (nvec + 64 * STEP_U - 1) / (64 * STEP_U);
+    const int64_t blocks = (chunks + 3) / 4;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st,
+                       reinterpret_cast<const uint4 *>(src), reinterpret_cast<uint4 *>(dst), nvec);
     return hipGetLastError();
 }
 

@@ -52,6 +52,12 @@ int default_cells_per_lane(int64_t N, int precision) {
     return precision == HEAT_FP64 ? 16 : 32;
 }
 
+bool default_pingpong(int64_t N, int precision) {
+    (void)N;
+    (void)precision;
+    return true;
+}
+
 static int check_problem(int64_t N, int32_t nparts, double r, int64_t nt, int precision) {
     if (N < 1) return fail(HEAT_EINVAL, "N must be >= 1 (got %lld)", (long long)N);
     if (N > (int64_t(1) << 40)) return fail(HEAT_EINVAL, "N too large (%lld)", (long long)N);
@@ -81,6 +87,9 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     if (kernel == HEAT_KERNEL_STEP && precision == HEAT_FP32C)
         return fail(HEAT_EINVAL, "compensated FP32 needs the temporal-blocked kernel");
     q.kernel = kernel;
+    if (c.register_form != 0 && c.register_form != 1 && c.register_form != 2)
+        return fail(HEAT_EINVAL, "register_form must be 1 or 2 (got %d)", c.register_form);
+    q.pingpong = c.register_form ? c.register_form == 2 : default_pingpong(N, precision);
     if (kernel == HEAT_KERNEL_STEP) {
         q.K = 0;
         q.T = 1;
@@ -144,7 +153,8 @@ static int run_rounds(const Plan &pl, int precision, void *a, void *b, int64_t N
         int64_t done = 0;
         while (done < nt) {
             const int steps = (int)std::min<int64_t>(pl.T, nt - done);
-            HEAT_HIP(launch_window(precision, pl.K, cur, oth, N, pl.H, steps, r, pl.wpg, st));
+            HEAT_HIP(launch_window(precision, pl.K, pl.pingpong, cur, oth, N, pl.H, steps, r, pl.wpg,
+                                   st));
             std::swap(cur, oth);
             done += steps;
         }
@@ -252,6 +262,8 @@ int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
     out->cells_per_lane = pl.K;
     out->steps_per_round = pl.T;
     out->waves_per_group = pl.wpg;
+    out->register_form = pl.pingpong ? 2 : 1;
+    out->reserved = 0;
     out->tile_cells = pl.W;
     out->tiles = pl.tiles;
     out->rounds = pl.rounds;
@@ -298,6 +310,15 @@ int heat_solve(double *u, int64_t N, int32_t nparts, double r, int64_t nt) {
     (void)hipFree(d);
     (void)hipStreamDestroy(st);
     return rc;
+}
+
+int heat_copy_dev(const void *d_src, void *d_dst, size_t bytes, void *hip_stream) {
+    if (!d_src || !d_dst) return fail(HEAT_EINVAL, "NULL pointer");
+    if ((bytes & 15) || ((uintptr_t)d_src & 15) || ((uintptr_t)d_dst & 15))
+        return fail(HEAT_EINVAL, "copy needs 16-byte sizes and alignment");
+    if (bytes == 0) return HEAT_OK;
+    HEAT_HIP(launch_copy(d_src, d_dst, bytes, (hipStream_t)hip_stream));
+    return HEAT_OK;
 }
 
 int heat_checksum_dev(const void *d_u, int64_t N, int32_t precision, void *hip_stream,

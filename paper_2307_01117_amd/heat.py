@@ -30,7 +30,7 @@ EXPORTS = [
     "heat_solve", "heat_solve_dev", "heat_solve_dev_cfg", "heat_plan", "heat_checksum_dev",
     "heat_solve_batch", "heat_solve_batch_dev", "heat_server_create", "heat_submit",
     "heat_poll", "heat_wait", "heat_cancel", "heat_server_get_stats", "heat_server_destroy",
-    "heat_last_error", "heat_version", "heat_device_info",
+    "heat_last_error", "heat_version", "heat_device_info", "heat_copy_dev",
 ]
 
 
@@ -42,12 +42,14 @@ class HeatError(RuntimeError):
 
 class heat_config(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("cells_per_lane", ctypes.c_int32),
-                ("steps_per_round", ctypes.c_int32), ("waves_per_group", ctypes.c_int32)]
+                ("steps_per_round", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
+                ("register_form", ctypes.c_int32)]
 
 
 class heat_plan_info(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("cells_per_lane", ctypes.c_int32),
                 ("steps_per_round", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
+                ("register_form", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tile_cells", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("rounds", ctypes.c_int64)]
 
@@ -107,6 +109,7 @@ def load(path: str = LIB_PATH):
         "heat_version": ([], ctypes.c_char_p),
         "heat_device_info": ([P(i32), P(i32), P(i32), P(i32), P(ctypes.c_size_t),
                               P(ctypes.c_size_t)], i32),
+        "heat_copy_dev": ([vp, vp, ctypes.c_size_t, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -135,10 +138,11 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
-def _cfg(kernel=0, cells_per_lane=0, steps_per_round=0, waves_per_group=0):
-    if not (kernel or cells_per_lane or steps_per_round or waves_per_group):
+def _cfg(kernel=0, cells_per_lane=0, steps_per_round=0, waves_per_group=0, register_form=0):
+    if not (kernel or cells_per_lane or steps_per_round or waves_per_group or register_form):
         return None
-    return ctypes.byref(heat_config(kernel, cells_per_lane, steps_per_round, waves_per_group))
+    return ctypes.byref(heat_config(kernel, cells_per_lane, steps_per_round, waves_per_group,
+                                    register_form))
 
 
 def version() -> str:
@@ -184,6 +188,14 @@ def solve_dev(d_u, nparts: int, r: float, nt: int, precision: int | None = None,
                                      d_u.numel(), int(nparts), float(r), int(nt), int(precision),
                                      _cfg(**cfg), _stream_handle(stream), ps0, ps1))
     return (s0.value, s1.value) if sums else None
+
+
+def copy_dev(src, dst, stream=None) -> None:
+    """Streaming device-to-device copy (bandwidth probe)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst too small")
+    _check(load().heat_copy_dev(src.data_ptr(), dst.data_ptr(), nbytes, _stream_handle(stream)))
 
 
 def checksum_dev(d_u, precision: int | None = None, stream=None) -> float:
