@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--steps-per-round", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time the library's plain streaming copy of the state instead "
+                         "(the bandwidth reference for the roofline and traffic counters)")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="time steps of the full ring the CPU oracle runs as its sample")
     return ap.parse_args()
@@ -94,6 +97,21 @@ def main():
     d_work = torch.empty_like(d_u)
     stream = torch.cuda.current_stream(dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    if args.copy_probe:
+        torch.cuda.synchronize()
+        heat.copy_dev(d_u, d_work, stream)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(args.steps):
+            heat.copy_dev(d_u, d_work, stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / args.steps
+        nbytes = d_u.numel() * d_u.element_size()
+        print(json.dumps({"copy_bytes": nbytes, "avg_launch_ms": round(ms, 4),
+                          "GBs": round(2 * nbytes / ms / 1e6, 1)}), flush=True)
+        return
 
     def one_step(timing=None):
         heat.checksum_dev(d_u, prec, stream)                       # sum of the state in

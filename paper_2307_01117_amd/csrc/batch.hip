@@ -17,12 +17,11 @@ namespace heat {
 static inline int64_t ceil4(int64_t x) { return (x + 3) & ~int64_t(3); }
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-int batch_cells_per_lane(int precision) { return precision == HEAT_FP64 ? 16 : 32; }
+int batch_cells_per_lane(int precision) { (void)precision; return 32; }
 
 int describe_ring(const heat_ring &g, BatchRing *out) {
     const int K = batch_cells_per_lane(g.precision);
-    const int T = default_steps_per_round(g.N, g.precision);
-    const int64_t Teff = g.nt > 0 ? std::min<int64_t>(T, g.nt) : 1;
+    const int64_t Teff = planned_steps_per_round(g.N, g.nt, g.precision);
     BatchRing R{};
     R.buf[0] = g.d_u;
     R.buf[1] = g.d_work;

@@ -47,6 +47,9 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
 // is a pure function of (N, precision) -- never of timing or of a batch mix.
 int default_steps_per_round(int64_t N, int precision);
 int default_cells_per_lane(int64_t N, int precision);
+// Steps per round actually used by default for a run of nt steps (T for the
+// compensated form; a result-neutral even split near T otherwise).
+int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision);
 bool default_pingpong(int64_t N, int precision);
 
 // ----------------------------------------------------------- kernels

@@ -353,7 +353,8 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
                 T *dst = reinterpret_cast<T *>(R.buf[(k + 1) & 1]);
                 const int64_t done = k * (int64_t)R.T;
                 const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
-                window_tile<P, K, true>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0, lane);
+                window_tile<P, K, sizeof(T) == 8>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0,
+                                                  lane);
             } else {
                 // copy-back round: the final state sits in buf[1]
                 const T *src = reinterpret_cast<const T *>(R.buf[1]);
@@ -520,7 +521,7 @@ static hipError_t launch_batch_t(const BatchPlanDev &plan, int grid, int wpg, hi
 
 hipError_t launch_batch(int precision, int K, const BatchPlanDev &plan, int grid, int wpg,
                         hipStream_t st) {
-    if (precision == HEAT_FP64 && K == 16) return launch_batch_t<F64, 16>(plan, grid, wpg, st);
+    if (precision == HEAT_FP64 && K == 32) return launch_batch_t<F64, 32>(plan, grid, wpg, st);
     if (precision == HEAT_FP32 && K == 32) return launch_batch_t<F32, 32>(plan, grid, wpg, st);
     if (precision == HEAT_FP32C && K == 32) return launch_batch_t<F32C, 32>(plan, grid, wpg, st);
     return hipErrorInvalidValue;
@@ -539,7 +540,7 @@ int batch_grid_size(int precision, int K, int wpg, int *grid) {
     HEAT_HIP(hipGetDevice(&dev));
     HEAT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int nb = 0;
-    if (precision == HEAT_FP64 && K == 16) nb = occupancy_blocks<F64, 16>(wpg);
+    if (precision == HEAT_FP64 && K == 32) nb = occupancy_blocks<F64, 32>(wpg);
     else if (precision == HEAT_FP32 && K == 32) nb = occupancy_blocks<F32, 32>(wpg);
     else if (precision == HEAT_FP32C && K == 32) nb = occupancy_blocks<F32C, 32>(wpg);
     if (nb < 1) nb = 1;

@@ -35,27 +35,51 @@ int fail_hip(hipError_t e, const char *what) {
 
 // ================================================================ planning
 
+// Planner defaults, from a sweep on MI355X over cells per lane K in {8,16,32},
+// steps per round T in {8..128}, 1..8 waves per group and both register
+// forms (N = 1e8 ring): binary64 peaks at K = 32, T ~ 96, ping-pong form;
+// binary32 at K = 32, T ~ 96, in-place form; the compensated form at K = 32,
+// in-place form.
+//
 // Steps per round.  binary64 and plain binary32 results do not depend on it
-// (only speed does); for the compensated form it sets where u + e is folded
-// to binary32, so it is a fixed constant of the precision.
+// (only speed does), so the planner may rebalance it (see make_plan); for the
+// compensated form it sets where u + e is folded to binary32, so it is a
+// fixed constant, part of the definition of that form's result.
+constexpr int FP32C_STEPS_PER_ROUND = 64;
+
 int default_steps_per_round(int64_t N, int precision) {
     (void)N;
     switch (precision) {
-        case HEAT_FP64: return 32;
-        case HEAT_FP32: return 32;
-        default: return 32;   // HEAT_FP32C: fixed, part of the result's definition
+        case HEAT_FP64: return 96;
+        case HEAT_FP32: return 96;
+        default: return FP32C_STEPS_PER_ROUND;
     }
 }
 
 int default_cells_per_lane(int64_t N, int precision) {
     (void)N;
-    return precision == HEAT_FP64 ? 16 : 32;
+    (void)precision;
+    return 32;
 }
 
 bool default_pingpong(int64_t N, int precision) {
     (void)N;
-    (void)precision;
-    return true;
+    return precision == HEAT_FP64;
+}
+
+int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision) {
+    const int T = default_steps_per_round(N, precision);
+    // a run shorter than one round is a single round of nt steps
+    int64_t Teff = nt > 0 ? std::min<int64_t>(T, nt) : 1;
+    if (precision != HEAT_FP32C && nt >= 2) {
+        // Result-neutral rebalancing (binary64 and plain binary32 only): an
+        // even number of equal rounds, so the state ends in the caller's
+        // buffer (no copy-back) and no round is a short remainder.
+        int64_t R = (nt + Teff - 1) / Teff;
+        if (R & 1) ++R;
+        Teff = (nt + R - 1) / R;
+    }
+    return Teff;
 }
 
 static int check_problem(int64_t N, int32_t nparts, double r, int64_t nt, int precision) {
@@ -78,7 +102,7 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     heat_config c{};
     if (cfg) c = *cfg;
     Plan q;
-    q.wpg = c.waves_per_group ? c.waves_per_group : 4;
+    q.wpg = c.waves_per_group ? c.waves_per_group : 2;
     if (q.wpg != 1 && q.wpg != 2 && q.wpg != 4 && q.wpg != 8)
         return fail(HEAT_EINVAL, "waves_per_group must be 1, 2, 4 or 8 (got %d)", q.wpg);
     int kernel = c.kernel ? c.kernel : HEAT_KERNEL_TB;
@@ -110,8 +134,8 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     // the window must keep W >= H so a tile only reads its two neighbours
     if (3 * ceil4(T) > 64 * (int64_t)q.K)
         return fail(HEAT_EINVAL, "steps_per_round %d too deep for %d cells per lane", T, q.K);
-    // a run shorter than one round is a single round of nt steps
-    const int64_t Teff = nt > 0 ? std::min<int64_t>(T, nt) : 1;
+    const int64_t Teff =
+        c.steps_per_round ? (nt > 0 ? std::min<int64_t>(T, nt) : 1) : planned_steps_per_round(N, nt, precision);
     q.T = (int)Teff;
     q.H = (int)ceil4(Teff);
     q.W = 64 * (int64_t)q.K - 2 * (int64_t)q.H;

@@ -70,8 +70,15 @@ def test_planner_geometry(lib):
     assert p["tile_cells"] == 64 * K - 2 * ((T + 3) // 4 * 4)
     assert p["tiles"] == -(-100_000_000 // p["tile_cells"])
     assert p["rounds"] == -(-1000 // T)
-    # a run shorter than one round is one round of nt steps
-    q = heat.plan(1000, 5, heat.FP64)
+    # binary64 / binary32 results do not depend on T: the planner splits the
+    # run into an even number of equal rounds (no copy-back of the state)
+    for nt in (2, 5, 97, 1000, 4999):
+        for prec in (heat.FP64, heat.FP32):
+            q = heat.plan(10**6, nt, prec)
+            assert q["rounds"] % 2 == 0 and q["rounds"] * q["steps_per_round"] >= nt
+            assert (q["rounds"] - 1) * q["steps_per_round"] < nt
+    # the compensated form keeps its fixed T: a short run is one round
+    q = heat.plan(1000, 5, heat.FP32C)
     assert q["rounds"] == 1 and q["steps_per_round"] == 5
     s = heat.plan(1000, 7, heat.FP64, kernel=heat.KERNEL_STEP)
     assert s["rounds"] == 7 and s["steps_per_round"] == 1
