@@ -26,8 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector, published
-FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector (packed), published
+# Vector ALU ceilings in lane operations per second, from the published
+# vector peaks (which count an FMA as 2 flops): FP64 78.6 TFLOP/s -> 39.3e12
+# FP64 ops/s (256 CUs x 64 lanes x 2.4 GHz); FP32 157.3 TFLOP/s -> 78.65e12
+# FP32 ops/s (FP32 issues at twice the FP64 rate).
+VALU_PEAK_TOPS = {"fp64": 39.3, "fp32": 78.65, "fp32c": 78.65}
+# Minimal VALU operations per cell update of each form (the update formula,
+# nothing else): binary64 fma(-2,c,l), +q, *r, +c = 4; binary32 (l-c), (q-c),
+# +, *r, +c = 5; compensated 12 (two Laplacians 6, sum 1, *r 1, Fast2Sum 4).
+OPS_PER_CUP = {"fp64": 4, "fp32": 5, "fp32c": 12}
 
 
 def parse():
@@ -51,7 +58,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(u0, r, steps, precision):
+def cpu_baseline(u0, r, steps, precision, T):
     """The oracle, as it stands, on the host cores: single-threaded C."""
     import numpy as np
 
@@ -62,7 +69,7 @@ def cpu_baseline(u0, r, steps, precision):
     elif precision == "fp32":
         oracle.solve_f32(u0.astype(np.float32), r, steps)
     else:
-        oracle.solve_f32c(u0.astype(np.float32), r, steps, 32)
+        oracle.solve_f32c(u0.astype(np.float32), r, steps, T)
     dt = time.perf_counter() - t0
     return {"value": round(u0.size * steps / dt / 1e9, 4), "unit": "GCUP/s", "cores": 1,
             "kind": "oracle",
@@ -150,15 +157,13 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
     else:
         # temporal blocking moves 2*es bytes per cell per T steps; it is
-        # limited by the vector ALU: flops per cell update = 5 (binary64:
-        # fma + add + mul + add with the fma counted as 2), 5 (binary32),
-        # 14 (compensated: 12 operations + the fold amortised)
-        fl = {heat.FP64: 5.0, heat.FP32: 5.0, heat.FP32C: 12.0}[prec]
-        peak = FP64_VECTOR_TFLOPS if prec == heat.FP64 else FP32_VECTOR_TFLOPS / 2
-        achieved = fl * N * steps_per_launch / (k_avg_ms * 1e-3) / 1e12
-        bound = "alu"
+        # limited by the vector ALU: achieved = minimal lane operations of the
+        # update formula per second, against the chip's VALU op rate
+        ops = OPS_PER_CUP[prec_name] * N * steps_per_launch
+        peak = VALU_PEAK_TOPS[prec_name]
+        achieved = ops / (k_avg_ms * 1e-3) / 1e12
         hbm = alg_bytes / (k_avg_ms * 1e-3) / 1e9
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "Tops/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
                 "hbm_algorithmic_GBs": round(hbm, 1),
                 "hbm_frac": round(hbm / HBM_PEAK_GBS, 4)}
@@ -189,7 +194,8 @@ def main():
     del d_u, d_work
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(u0, r, args.cpu_steps, prec_name)
+        out["cpu_baseline"] = cpu_baseline(u0, r, args.cpu_steps, prec_name,
+                                           heat.plan(N, nt, prec)["steps_per_round"])
     print(json.dumps(out), flush=True)
 
 

@@ -14,7 +14,6 @@
 
 namespace heat {
 
-static inline int64_t ceil4(int64_t x) { return (x + 3) & ~int64_t(3); }
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 int batch_cells_per_lane(int precision) { (void)precision; return 32; }
@@ -26,7 +25,7 @@ int describe_ring(const heat_ring &g, BatchRing *out) {
     R.buf[0] = g.d_u;
     R.buf[1] = g.d_work;
     R.N = g.N;
-    R.H = (int32_t)ceil4(Teff);
+    R.H = (int32_t)halo_cells(Teff, g.precision, K);
     R.T = (int32_t)Teff;
     R.W = 64 * (int64_t)K - 2 * (int64_t)R.H;
     R.tiles = (g.N + R.W - 1) / R.W;

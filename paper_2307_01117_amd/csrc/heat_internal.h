@@ -50,6 +50,8 @@ int default_cells_per_lane(int64_t N, int precision);
 // Steps per round actually used by default for a run of nt steps (T for the
 // compensated form; a result-neutral even split near T otherwise).
 int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision);
+// Halo depth H >= steps for a window of 64*K cells (line-aligned when possible).
+int halo_cells(int64_t steps, int precision, int K);
 bool default_pingpong(int64_t N, int precision);
 
 // ----------------------------------------------------------- kernels
@@ -57,8 +59,23 @@ bool default_pingpong(int64_t N, int precision);
 // One round of the temporal-blocked window kernel: every tile loads 64*K
 // cells starting H cells left of its output, advances `steps` (<= H) steps
 // in registers and writes its W = 64*K - 2H output cells.
-hipError_t launch_window(int precision, int K, bool pingpong, const void *src, void *dst, int64_t N,
-                         int H, int steps, double r, int wpg, hipStream_t st);
+struct WindowLaunch {
+    int precision = HEAT_FP64;
+    int K = 32;
+    bool pingpong = true;
+    const void *src = nullptr;
+    void *dst = nullptr;
+    int64_t N = 0;
+    int H = 0;
+    int steps = 0;
+    double r = 0.0;
+    int wpg = 2;
+    double *part_in = nullptr;    // per-tile sums of the input (first round), or NULL
+    double *part_out = nullptr;   // per-tile sums of the output (last round), or NULL
+};
+hipError_t launch_window(const WindowLaunch &a, hipStream_t st);
+// Sum n per-tile partials (fixed order) into d_out[0].
+hipError_t launch_sum_partials(const double *partial, int64_t n, double *d_out, hipStream_t st);
 
 // One step of the coalesced sweep (binary64 or binary32).
 hipError_t launch_step(int precision, const void *src, void *dst, int64_t N, double r, int wpg,
@@ -69,7 +86,7 @@ int64_t step_chunk_cells(int precision);
 
 // Deterministic binary64 sum: `partial` needs SUM_BLOCKS doubles, result in
 // d_out[0].
-constexpr int SUM_BLOCKS = 1024;
+constexpr int SUM_BLOCKS = 4096;
 hipError_t launch_sum(int precision, const void *u, int64_t N, double *partial, double *d_out,
                       hipStream_t st);
 

@@ -79,11 +79,31 @@ __device__ __forceinline__ void window_store(typename P::T *__restrict__ dst, in
 
 // Process one tile: output cells [b, b + min(W, N - b)).  PP selects the
 // ping-pong register form (no register rotation, twice the state registers).
+// binary64 sum of the cells this tile owns (window positions [H, H + wlen)),
+// lane by lane in index order, then a fixed butterfly over the wave; lane 0's
+// value is returned.
+template <int K, class T>
+__device__ __forceinline__ double tile_sum(const T (&v)[K], int lane, int H, int64_t wlen) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int pos = lane * K + j;
+        if (pos >= H && pos < H + wlen) s += (double)v[j];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    return s;
+}
+
+// part_in / part_out (may be NULL): per-tile binary64 sums of the state
+// before and after the round, written at index `tile` -- the conservation
+// checksum fused into the first and last rounds (no extra pass over HBM).
 template <class P, int K, bool PP>
 __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ src,
                                             typename P::T *__restrict__ dst, int64_t N, int H,
                                             int steps, typename P::T r, int64_t b, int64_t W,
-                                            bool vec_ok, int lane) {
+                                            bool vec_ok, int lane, double *part_in = nullptr,
+                                            double *part_out = nullptr, int64_t tile = 0) {
     using T = typename P::T;
     constexpr int WIN = 64 * K;
     const int64_t g0 = b - H;
@@ -91,6 +111,10 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
     const bool fast = vec_ok && g0 >= 0 && g0 + WIN <= N && wlen == W;
     T v[K];
     window_load<P, K>(src, N, g0, fast, lane, v);
+    if (part_in) {
+        const double s = tile_sum<K>(v, lane, H, wlen);
+        if (lane == 0) part_in[tile] = s;
+    }
     if constexpr (P::COMP) {
         T e[K];
 #pragma unroll
@@ -121,20 +145,26 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
             for (int s = 0; s < steps; ++s) window_step<K>(v, r);
         }
     }
+    if (part_out) {
+        const double s = tile_sum<K>(v, lane, H, wlen);
+        if (lane == 0) part_out[tile] = s;
+    }
     window_store<P, K>(dst, b, H, W, wlen, fast, lane, v);
 }
 
 template <class P, int K, bool PP>
 __global__ void __launch_bounds__(512)
 k_window(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst, int64_t N,
-         int32_t H, int32_t steps, double r, int64_t tiles, int32_t vec_ok) {
+         int32_t H, int32_t steps, double r, int64_t tiles, int32_t vec_ok, double *part_in,
+         double *part_out) {
     const int lane = threadIdx.x & 63;
     const int wpg = blockDim.x >> 6;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t tile = blk * wpg + (threadIdx.x >> 6);
     if (tile >= tiles) return;
     const int64_t W = 64 * K - 2 * (int64_t)H;
-    window_tile<P, K, PP>(src, dst, N, H, steps, (typename P::T)r, tile * W, W, vec_ok != 0, lane);
+    window_tile<P, K, PP>(src, dst, N, H, steps, (typename P::T)r, tile * W, W, vec_ok != 0, lane,
+                          part_in, part_out, tile);
 }
 
 // ==================================================================== STEP
@@ -235,21 +265,38 @@ __device__ __forceinline__ double block_tree_sum(double v) {
     return red[0];
 }
 
+// Slices start on multiples of 4 elements so the body can use 16-byte
+// (binary64) or 16-byte (binary32, 4 at a time) loads when aligned.
 template <class T>
 __global__ void __launch_bounds__(256) k_sum_partial(const T *__restrict__ u, int64_t N,
-                                                     double *__restrict__ partial) {
+                                                     double *__restrict__ partial, int32_t vec_ok) {
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t lo = (b * N) / G, hi = ((b + 1) * N) / G;
+    const int64_t lo = ((b * N) / G) & ~int64_t(3);
+    const int64_t hi = b + 1 == G ? N : (((b + 1) * N) / G) & ~int64_t(3);
     double s = 0.0, c = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) neumaier_add(s, c, (double)u[i]);
+    if (vec_ok) {
+        using VT = typename Vec16<T>::type;
+        constexpr int VEC = 16 / sizeof(T);
+        const int64_t nv = (hi - lo) / VEC;
+        const VT *p = reinterpret_cast<const VT *>(u + lo);
+        for (int64_t i = threadIdx.x; i < nv; i += 256) {
+            VT x = p[i];
+            const T *xs = reinterpret_cast<const T *>(&x);
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) neumaier_add(s, c, (double)xs[k]);
+        }
+        for (int64_t i = lo + nv * VEC + threadIdx.x; i < hi; i += 256) neumaier_add(s, c, (double)u[i]);
+    } else {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) neumaier_add(s, c, (double)u[i]);
+    }
     const double tot = block_tree_sum(s + c);
     if (threadIdx.x == 0) partial[b] = tot;
 }
 
-__global__ void __launch_bounds__(256) k_sum_final(const double *__restrict__ partial, int G,
+__global__ void __launch_bounds__(256) k_sum_final(const double *__restrict__ partial, int64_t G,
                                                    double *__restrict__ out) {
     double s = 0.0, c = 0.0;
-    for (int i = threadIdx.x; i < G; i += 256) neumaier_add(s, c, partial[i]);
+    for (int64_t i = threadIdx.x; i < G; i += 256) neumaier_add(s, c, partial[i]);
     const double tot = block_tree_sum(s + c);
     if (threadIdx.x == 0) out[0] = tot;
 }
@@ -407,42 +454,43 @@ __global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uin
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 template <class P, int K, bool PP>
-static hipError_t launch_window_t(const void *src, void *dst, int64_t N, int H, int steps, double r,
-                                  int wpg, hipStream_t st) {
+static hipError_t launch_window_t(const WindowLaunch &a, hipStream_t st) {
     using T = typename P::T;
-    const int64_t W = 64 * K - 2 * (int64_t)H;
-    const int64_t tiles = (N + W - 1) / W;
-    const int64_t blocks = (tiles + wpg - 1) / wpg;
-    const int vec_ok = aligned16(src) && aligned16(dst);
-    hipLaunchKernelGGL((k_window<P, K, PP>), dim3((unsigned)blocks), dim3(64 * wpg), 0, st,
-                       reinterpret_cast<const T *>(src), reinterpret_cast<T *>(dst), N, H, steps, r,
-                       tiles, vec_ok);
+    const int64_t W = 64 * K - 2 * (int64_t)a.H;
+    const int64_t tiles = (a.N + W - 1) / W;
+    const int64_t blocks = (tiles + a.wpg - 1) / a.wpg;
+    const int vec_ok = aligned16(a.src) && aligned16(a.dst);
+    hipLaunchKernelGGL((k_window<P, K, PP>), dim3((unsigned)blocks), dim3(64 * a.wpg), 0, st,
+                       reinterpret_cast<const T *>(a.src), reinterpret_cast<T *>(a.dst), a.N, a.H,
+                       a.steps, a.r, tiles, vec_ok, a.part_in, a.part_out);
     return hipGetLastError();
 }
 
 template <class P, bool PP>
-static hipError_t launch_window_p(int K, const void *src, void *dst, int64_t N, int H, int steps,
-                                  double r, int wpg, hipStream_t st) {
-    switch (K) {
-        case 8: return launch_window_t<P, 8, PP>(src, dst, N, H, steps, r, wpg, st);
-        case 16: return launch_window_t<P, 16, PP>(src, dst, N, H, steps, r, wpg, st);
-        case 32: return launch_window_t<P, 32, PP>(src, dst, N, H, steps, r, wpg, st);
+static hipError_t launch_window_p(const WindowLaunch &a, hipStream_t st) {
+    switch (a.K) {
+        case 8: return launch_window_t<P, 8, PP>(a, st);
+        case 16: return launch_window_t<P, 16, PP>(a, st);
+        case 32: return launch_window_t<P, 32, PP>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_window(int precision, int K, bool pingpong, const void *src, void *dst, int64_t N,
-                         int H, int steps, double r, int wpg, hipStream_t st) {
-    switch (precision * 2 + (pingpong ? 1 : 0)) {
-        case HEAT_FP64 * 2: return launch_window_p<F64, false>(K, src, dst, N, H, steps, r, wpg, st);
-        case HEAT_FP64 * 2 + 1: return launch_window_p<F64, true>(K, src, dst, N, H, steps, r, wpg, st);
-        case HEAT_FP32 * 2: return launch_window_p<F32, false>(K, src, dst, N, H, steps, r, wpg, st);
-        case HEAT_FP32 * 2 + 1: return launch_window_p<F32, true>(K, src, dst, N, H, steps, r, wpg, st);
-        case HEAT_FP32C * 2: return launch_window_p<F32C, false>(K, src, dst, N, H, steps, r, wpg, st);
-        case HEAT_FP32C * 2 + 1:
-            return launch_window_p<F32C, true>(K, src, dst, N, H, steps, r, wpg, st);
+hipError_t launch_window(const WindowLaunch &a, hipStream_t st) {
+    switch (a.precision * 2 + (a.pingpong ? 1 : 0)) {
+        case HEAT_FP64 * 2: return launch_window_p<F64, false>(a, st);
+        case HEAT_FP64 * 2 + 1: return launch_window_p<F64, true>(a, st);
+        case HEAT_FP32 * 2: return launch_window_p<F32, false>(a, st);
+        case HEAT_FP32 * 2 + 1: return launch_window_p<F32, true>(a, st);
+        case HEAT_FP32C * 2: return launch_window_p<F32C, false>(a, st);
+        case HEAT_FP32C * 2 + 1: return launch_window_p<F32C, true>(a, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_sum_partials(const double *partial, int64_t n, double *d_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial, n, d_out);
+    return hipGetLastError();
 }
 
 int64_t step_chunk_cells(int precision) {
@@ -470,15 +518,16 @@ hipError_t launch_step(int precision, const void *src, void *dst, int64_t N, dou
 
 hipError_t launch_sum(int precision, const void *u, int64_t N, double *partial, double *d_out,
                       hipStream_t st) {
+    const int vec_ok = aligned16(u);
     if (precision == HEAT_FP64)
         hipLaunchKernelGGL(k_sum_partial<double>, dim3(SUM_BLOCKS), dim3(256), 0, st,
-                           reinterpret_cast<const double *>(u), N, partial);
+                           reinterpret_cast<const double *>(u), N, partial, vec_ok);
     else
         hipLaunchKernelGGL(k_sum_partial<float>, dim3(SUM_BLOCKS), dim3(256), 0, st,
-                           reinterpret_cast<const float *>(u), N, partial);
+                           reinterpret_cast<const float *>(u), N, partial, vec_ok);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial, SUM_BLOCKS, d_out);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial, (int64_t)SUM_BLOCKS, d_out);
     return hipGetLastError();
 }
 

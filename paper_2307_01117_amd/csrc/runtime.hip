@@ -82,6 +82,19 @@ int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision) {
     return Teff;
 }
 
+static inline int64_t ceil4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
+int halo_cells(int64_t steps, int precision, int K) {
+    // Windows start H cells left of their tile and tiles are W = 64K - 2H
+    // long, so an H that is a multiple of one 128-byte line keeps every
+    // lane's K-cell run on whole cache lines.  Fall back to a multiple of 4
+    // (16-byte groups) if the line-aligned halo would be too deep.
+    const int64_t line = 128 / (int64_t)storage_bytes(precision);
+    int64_t H = (steps + line - 1) / line * line;
+    if (3 * H > 64 * (int64_t)K) H = ceil4(steps);
+    return (int)H;
+}
+
 static int check_problem(int64_t N, int32_t nparts, double r, int64_t nt, int precision) {
     if (N < 1) return fail(HEAT_EINVAL, "N must be >= 1 (got %lld)", (long long)N);
     if (N > (int64_t(1) << 40)) return fail(HEAT_EINVAL, "N too large (%lld)", (long long)N);
@@ -96,7 +109,6 @@ static int check_problem(int64_t N, int32_t nparts, double r, int64_t nt, int pr
     return HEAT_OK;
 }
 
-static inline int64_t ceil4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
 int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan *p) {
     heat_config c{};
@@ -137,7 +149,7 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     const int64_t Teff =
         c.steps_per_round ? (nt > 0 ? std::min<int64_t>(T, nt) : 1) : planned_steps_per_round(N, nt, precision);
     q.T = (int)Teff;
-    q.H = (int)ceil4(Teff);
+    q.H = halo_cells(Teff, precision, q.K);
     q.W = 64 * (int64_t)q.K - 2 * (int64_t)q.H;
     q.tiles = (N + q.W - 1) / q.W;
     q.rounds = nt > 0 ? (nt + Teff - 1) / Teff : 0;
@@ -165,27 +177,54 @@ int device_pool_setup() {
 }
 
 // Run the rounds of a plan: state in `a`, scratch `b`; result back in `a`.
+// With `sums` (SUM area: partial buffers + 2 results), the binary64 sums of
+// the state before and after land in sums->d_out[0] and [1]: fused into the
+// first and last window rounds when the plan uses them, otherwise by the
+// standalone reduction.
+struct SumArea {
+    double *partial = nullptr;   // max(SUM_BLOCKS, 2 * tiles) doubles
+    double *d_out = nullptr;     // 2 doubles
+};
+
 static int run_rounds(const Plan &pl, int precision, void *a, void *b, int64_t N, double r,
-                      int64_t nt, hipStream_t st) {
+                      int64_t nt, hipStream_t st, const SumArea *sums) {
     void *cur = a, *oth = b;
+    const bool fused = sums && pl.kernel == HEAT_KERNEL_TB && nt > 0;
+    if (sums && !fused) HEAT_HIP(launch_sum(precision, a, N, sums->partial, sums->d_out, st));
     if (pl.kernel == HEAT_KERNEL_STEP) {
         for (int64_t s = 0; s < nt; ++s) {
             HEAT_HIP(launch_step(precision, cur, oth, N, r, pl.wpg, st));
             std::swap(cur, oth);
         }
     } else {
+        WindowLaunch w;
+        w.precision = precision;
+        w.K = pl.K;
+        w.pingpong = pl.pingpong;
+        w.N = N;
+        w.H = pl.H;
+        w.r = r;
+        w.wpg = pl.wpg;
         int64_t done = 0;
         while (done < nt) {
-            const int steps = (int)std::min<int64_t>(pl.T, nt - done);
-            HEAT_HIP(launch_window(precision, pl.K, pl.pingpong, cur, oth, N, pl.H, steps, r, pl.wpg,
-                                   st));
+            w.steps = (int)std::min<int64_t>(pl.T, nt - done);
+            w.src = cur;
+            w.dst = oth;
+            w.part_in = fused && done == 0 ? sums->partial : nullptr;
+            w.part_out = fused && done + w.steps == nt ? sums->partial + pl.tiles : nullptr;
+            HEAT_HIP(launch_window(w, st));
             std::swap(cur, oth);
-            done += steps;
+            done += w.steps;
+        }
+        if (fused) {
+            HEAT_HIP(launch_sum_partials(sums->partial, pl.tiles, sums->d_out, st));
+            HEAT_HIP(launch_sum_partials(sums->partial + pl.tiles, pl.tiles, sums->d_out + 1, st));
         }
     }
     if (cur != a)
         HEAT_HIP(hipMemcpyAsync(a, cur, (size_t)N * storage_bytes(precision),
                                 hipMemcpyDeviceToDevice, st));
+    if (sums && !fused) HEAT_HIP(launch_sum(precision, a, N, sums->partial, sums->d_out + 1, st));
     return HEAT_OK;
 }
 
@@ -216,26 +255,23 @@ static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, do
     const bool want_sums = sum0_out || sum_out;
     DevBuf sums, work;
     sums.st = work.st = st;
+    SumArea area;
     if (want_sums) {
-        HEAT_HIP(hipMallocAsync(&sums.p, (SUM_BLOCKS + 2) * sizeof(double), st));
-        double *partial = (double *)sums.p;
-        HEAT_HIP(launch_sum(precision, d_u, N, partial, partial + SUM_BLOCKS, st));
+        const int64_t np = std::max<int64_t>(SUM_BLOCKS, 2 * pl.tiles);
+        HEAT_HIP(hipMallocAsync(&sums.p, (size_t)(np + 2) * sizeof(double), st));
+        area.partial = (double *)sums.p;
+        area.d_out = area.partial + np;
     }
-    if (nt > 0) {
-        void *b = d_work;
-        if (!b) {
-            HEAT_HIP(hipMallocAsync(&work.p, bytes, st));
-            b = work.p;
-        }
-        rc = run_rounds(pl, precision, d_u, b, N, r, nt, st);
-        if (rc) return rc;
+    void *b = d_work;
+    if (nt > 0 && !b) {
+        HEAT_HIP(hipMallocAsync(&work.p, bytes, st));
+        b = work.p;
     }
+    rc = run_rounds(pl, precision, d_u, b, N, r, nt, st, want_sums ? &area : nullptr);
+    if (rc) return rc;
     if (want_sums) {
-        double *partial = (double *)sums.p;
-        HEAT_HIP(launch_sum(precision, d_u, N, partial, partial + SUM_BLOCKS + 1, st));
         double h[2];
-        HEAT_HIP(hipMemcpyAsync(h, partial + SUM_BLOCKS, 2 * sizeof(double),
-                                hipMemcpyDeviceToHost, st));
+        HEAT_HIP(hipMemcpyAsync(h, area.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         HEAT_HIP(hipStreamSynchronize(st));
         if (sum0_out) *sum0_out = h[0];
         if (sum_out) *sum_out = h[1];

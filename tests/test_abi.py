@@ -67,7 +67,8 @@ def test_planner_geometry(lib):
     p = heat.plan(100_000_000, 1000, heat.FP64)
     assert p["kernel"] == heat.KERNEL_TB
     K, T = p["cells_per_lane"], p["steps_per_round"]
-    assert p["tile_cells"] == 64 * K - 2 * ((T + 3) // 4 * 4)
+    H = (64 * K - p["tile_cells"]) // 2          # halo: >= T, whole 128-byte lines
+    assert H >= T and H % 16 == 0 and 3 * H <= 64 * K
     assert p["tiles"] == -(-100_000_000 // p["tile_cells"])
     assert p["rounds"] == -(-1000 // T)
     # binary64 / binary32 results do not depend on T: the planner splits the
