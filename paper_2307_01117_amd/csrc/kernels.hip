@@ -387,13 +387,30 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
         for (; x < x_end; ++x) {
             const BatchRing &R = plan.rings[p];
             const int64_t tiles = R.tiles;
-            const int64_t tm = t == 0 ? tiles - 1 : t - 1;
-            const int64_t tp = t + 1 == tiles ? 0 : t + 1;
             uint32_t *fl = plan.flags + R.flag_base;
             const uint32_t need = (uint32_t)k;
-            if (!wait_epoch(plan, fl + tm, need) || !wait_epoch(plan, fl + t, need) ||
-                !wait_epoch(plan, fl + tp, need))
-                return;
+            // Wait for every tile whose cells lie within H of this tile on
+            // the ring: exactly the tiles this window reads (read after
+            // write) and the tiles whose windows read this tile's cells in
+            // the other buffer (write after read; the relation is symmetric).
+            // With a last tile shorter than H this reaches two tiles away.
+            if (!wait_epoch(plan, fl + t, need)) return;
+            const int64_t last_len = R.N - (tiles - 1) * R.W;
+            bool ok = true;
+            int64_t acc = 0, q = t;
+            for (int64_t g = 0; ok && g + 1 < tiles && acc < R.H; ++g) {
+                q = q == 0 ? tiles - 1 : q - 1;
+                ok = wait_epoch(plan, fl + q, need);
+                acc += q == tiles - 1 ? last_len : R.W;
+            }
+            acc = 0;
+            q = t;
+            for (int64_t g = 0; ok && g + 1 < tiles && acc < R.H; ++g) {
+                q = q + 1 == tiles ? 0 : q + 1;
+                ok = wait_epoch(plan, fl + q, need);
+                acc += q == tiles - 1 ? last_len : R.W;
+            }
+            if (!ok) return;
             const int64_t b = t * R.W;
             if (k < R.rounds) {
                 const T *src = reinterpret_cast<const T *>(R.buf[k & 1]);

@@ -1,0 +1,118 @@
+"""GPU parity of the batching form (one persistent fused launch for many
+uneven rings) through the C ABI: every ring must come out bit-identical to
+the CPU oracle and to the same ring solved alone by the plain device form."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_01117_amd import heat, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    heat.load()
+
+
+def oracle_for(prec, u0, r, nt):
+    if prec == heat.FP64:
+        return oracle.solve(u0, r, nt)
+    u32 = u0.astype(np.float32)
+    if prec == heat.FP32:
+        return oracle.solve_f32(u32, r, nt).astype(np.float64)
+    T = heat.plan(u0.size, nt, heat.FP32C)["steps_per_round"]
+    return oracle.solve_f32c(u32, r, nt, T).astype(np.float64)
+
+
+def mixed_problems(seed, count, nmax, ntmax, precs):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for k in range(count):
+        N = int(rng.integers(1, nmax)) if k % 3 else int(rng.integers(1, 70))
+        nt = int(rng.integers(0, ntmax))
+        r = float(0.5 - 0.4 * rng.random())
+        prec = int(precs[k % len(precs)])
+        u0 = inputs.uniform_ring(N, (40, seed, k))
+        probs.append(dict(u0=u0, nparts=1, r=r, nt=nt, precision=prec))
+    return probs
+
+
+@pytest.mark.parametrize("precs", [[heat.FP64], [heat.FP32], [heat.FP32C],
+                                   [heat.FP64, heat.FP32C, heat.FP32]])
+def test_host_batch_matches_oracle(precs):
+    probs = mixed_problems(41 + len(precs) + precs[0], 40, 30_000, 300, precs)
+    res = heat.solve_batch(probs)
+    for p, q in zip(probs, res):
+        assert q.status == heat.HEAT_OK
+        want = oracle_for(p["precision"], p["u0"], p["r"], p["nt"])
+        assert np.array_equal(q.u, want), (p["u0"].size, p["nt"], p["precision"])
+        if p["precision"] == heat.FP64:
+            s0 = math.fsum(p["u0"])
+        else:
+            s0 = math.fsum(p["u0"].astype(np.float32).astype(np.float64))
+        assert abs(q.sum0 - s0) <= 1e-13 * max(abs(s0), 1.0)
+        assert abs(q.sum_nt - math.fsum(want)) <= 1e-13 * max(abs(s0), 1.0)
+
+
+def test_host_batch_reports_bad_problem():
+    good = dict(u0=inputs.uniform_ring(500, 1), nparts=1, r=0.4, nt=50)
+    bad = dict(u0=inputs.uniform_ring(10, 2), nparts=1, r=0.7, nt=5)
+    with pytest.raises(heat.HeatError) as ei:
+        heat.solve_batch([good, bad, good])
+    assert ei.value.code == heat.HEAT_EINVAL
+
+
+def test_device_batch_equals_alone():
+    """Rings of the uneven batching workload (N log-uniform, nt uniform, r in
+    (0.1, 1/2]), scaled down: each ring in the fused launch equals the same
+    ring solved alone, bit for bit, in binary64 and compensated binary32."""
+    specs = inputs.batch_specs(count=96, seed=44, logn_hi=5.0, nt_hi=2000)
+    for prec, dt in ((heat.FP64, torch.float64), (heat.FP32C, torch.float32)):
+        us = [torch.from_numpy(inputs.ring_initial(s)).to("cuda", dtype=dt) for s in specs]
+        alone = []
+        for s, u in zip(specs, us):
+            a = u.clone()
+            heat.solve_dev(a, s.nparts, s.r, s.nt, precision=prec)
+            alone.append(a)
+        work = [torch.empty_like(u) for u in us]
+        heat.solve_batch_dev([(u, w, s.nt, s.r, prec) for u, w, s in zip(us, work, specs)])
+        torch.cuda.synchronize()
+        for s, u, a in zip(specs, us, alone):
+            assert torch.equal(u, a), (prec, s.N, s.nt)
+
+
+def test_device_batch_large_rings_sampled():
+    """A slice of the full-size batching workload (N up to 1e6, nt up to
+    10,000): sampled cells of the fused result against oracle light cones."""
+    specs = inputs.batch_specs(count=4096, seed=4)
+    pick = sorted(range(len(specs)), key=lambda j: -specs[j].N * specs[j].nt)[:12] + list(range(12))
+    specs = [specs[j] for j in pick]
+    u0s = [inputs.ring_initial(s) for s in specs]
+    us = [torch.from_numpy(u).to("cuda") for u in u0s]
+    work = [torch.empty_like(u) for u in us]
+    heat.solve_batch_dev([(u, w, s.nt, s.r, heat.FP64) for u, w, s in zip(us, work, specs)])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(45)
+    for s, u0, u in zip(specs, u0s, us):
+        # the plain device form (pinned to the oracle above) on the same ring
+        a = torch.from_numpy(u0).to("cuda")
+        heat.solve_dev(a, s.nparts, s.r, s.nt)
+        assert torch.equal(u, a), (s.N, s.nt)
+        if s.nt <= 3000:   # light cones of longer runs are too slow for the CPU oracle
+            for i in {0, s.N - 1, int(rng.integers(0, s.N))}:
+                assert u[i].item() == oracle.cone(u0, i, s.r, s.nt), (s.N, s.nt, i)
+
+
+def test_device_batch_empty_and_zero_steps():
+    heat.solve_batch_dev([])
+    u = torch.rand(1000, device="cuda", dtype=torch.float64)
+    ref = u.clone()
+    heat.solve_batch_dev([(u, torch.empty_like(u), 0, 0.5, heat.FP64)])
+    assert torch.equal(u, ref)
