@@ -53,6 +53,12 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="time the library's plain streaming copy of the state instead "
                          "(the bandwidth reference for the roofline and traffic counters)")
+    ap.add_argument("--form", default="plain", choices=["plain", "batch"],
+                    help="plain: one ring (the workload above); batch: 4,096 uneven rings "
+                         "advanced together (N log-uniform in [1e3, 1e6], nt uniform in "
+                         "[100, 10000], r in (0.1, 0.5]), compared with solving them one by one")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-mode", default="rounds", choices=["rounds", "graph", "persistent"])
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="time steps of the full ring the CPU oracle runs as its sample")
     return ap.parse_args()
@@ -88,6 +94,8 @@ def main():
     from paper_2307_01117_amd import heat, inputs
 
     heat.load()
+    if args.form == "batch":
+        return bench_batch(args)
     w = inputs.WORKLOADS[args.workload]
     prec_name = args.precision or ("fp64" if args.workload != "ring_1e8_perturbed" else "fp32c")
     prec = heat.PRECISIONS[prec_name]
@@ -197,6 +205,59 @@ def main():
         out["cpu_baseline"] = cpu_baseline(u0, r, args.cpu_steps, prec_name,
                                            heat.plan(N, nt, prec)["steps_per_round"])
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """Batching form: all rings advance together; reported against the same
+    rings solved one after another with the plain device form."""
+    import torch
+
+    from paper_2307_01117_amd import heat, inputs
+    prec_name = args.precision or "fp64"
+    prec = heat.PRECISIONS[prec_name]
+    dt = torch.float64 if prec == heat.FP64 else torch.float32
+    specs = inputs.batch_specs(count=args.batch_count, seed=4)
+    us = [torch.from_numpy(inputs.ring_initial(s)).to("cuda", dtype=dt) for s in specs]
+    ws = [torch.empty_like(u) for u in us]
+    cups = sum(s.N * s.nt for s in specs)
+    stream = torch.cuda.current_stream()
+    rings = [(u, w, s.nt, s.r, prec) for u, w, s in zip(us, ws, specs)]
+    kw = dict(graph=args.batch_mode == "graph", persistent=args.batch_mode == "persistent")
+
+    def batch_step():
+        heat.solve_batch_dev(rings, stream=stream, wait=True, **kw)
+
+    def plain_step():
+        for u, w, s in zip(us, ws, specs):
+            heat.solve_dev(u, s.nparts, s.r, s.nt, precision=prec, stream=stream, work=w)
+        torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        batch_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch_step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    plain_step()
+    t1 = time.perf_counter()
+    plain_step()
+    plain_s = time.perf_counter() - t1
+    value = cups * args.steps / elapsed / 1e9
+    print(json.dumps({
+        "metric": "GCUP/s (giga cell-updates per second), batched",
+        "value": round(value, 3), "unit": "GCUP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32c": "f32 (compensated)"}[prec_name],
+        "data": "synthetic",
+        "config": {"workload": f"batch_{args.batch_count}_rings", "rings": len(specs),
+                   "cell_updates": cups, "precision": prec_name, "mode": args.batch_mode},
+        "plain_one_by_one": {"value": round(cups / plain_s / 1e9, 3), "unit": "GCUP/s",
+                             "seconds": round(plain_s, 3)},
+        "batched_vs_plain": round(value / (cups / plain_s / 1e9), 3),
+    }), flush=True)
 
 
 if __name__ == "__main__":

@@ -173,15 +173,29 @@ typedef struct heat_ring {
     void *d_work;
 } heat_ring;
 
+/* Flags of heat_solve_batch_dev. */
+enum heat_batch_flags {
+    HEAT_BATCH_WAIT = 1,       /* wait for completion and report kernel-side errors */
+    HEAT_BATCH_PERSISTENT = 2, /* one persistent launch whose tiles synchronise through
+                                  per-tile epoch counters instead of one launch per round */
+    HEAT_BATCH_GRAPH = 4       /* capture the per-round launches in a hipGraph and replay it
+                                  (needs HEAT_BATCH_WAIT) */
+};
+
 /*
- * Device-resident batching form: all rings advance in one persistent launch
- * (tiles of every ring and round form one dependency-ordered work list; a
- * tile waits only for the three tiles of the previous round it reads).  The
- * per-ring T comes from the same table as heat_plan, so each ring's result
- * is bit-identical to solving it alone.  Queued on hip_stream; if `wait` is
- * nonzero the call waits for completion.
+ * Device-resident batching form: every ring advances round by round; by
+ * default each round of all still-running rings is one launch over the flat
+ * list of their tiles (the kernel boundary is the round barrier).  Rings are
+ * ordered by their number of rounds, so the running ones are a prefix of the
+ * table.  The per-ring T comes from the same rule as heat_plan, so each
+ * ring's result is bit-identical to solving it alone.  With
+ * HEAT_BATCH_PERSISTENT all rounds of all rings run in a single launch:
+ * tiles are claimed in round order from one counter and each waits for the
+ * tiles within H cells of it to finish the previous round (agent-scope
+ * release/acquire; a bounded wait turns a stall into HEAT_EDEVICE instead of
+ * a hang).  Queued on hip_stream.
  */
-int heat_solve_batch_dev(const heat_ring *rings, int32_t count, void *hip_stream, int32_t wait);
+int heat_solve_batch_dev(const heat_ring *rings, int32_t count, void *hip_stream, int32_t flags);
 
 /* ---------------------------------------------------------------- serving */
 

@@ -81,7 +81,7 @@ size_t BatchLaunch::device_bytes() const {
            al(round_start_.size() * 8) + al(active_.size() * 4) + al((size_t)nflags_ * 4) + 256;
 }
 
-int BatchLaunch::enqueue(void *dev_mem, hipStream_t st, int chunk, int wpg) {
+int BatchLaunch::enqueue(void *dev_mem, hipStream_t st, bool persistent, bool graph) {
     if (total_items_ == 0) return HEAT_OK;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     char *p = (char *)dev_mem;
@@ -94,6 +94,25 @@ int BatchLaunch::enqueue(void *dev_mem, hipStream_t st, int chunk, int wpg) {
     HEAT_HIP(hipMemcpyAsync(p, tile_prefix_.data(), tile_prefix_.size() * 8, hipMemcpyHostToDevice,
                             st));
     p += al(tile_prefix_.size() * 8);
+    if (!persistent) {
+        // one launch per round; the kernel boundary is the round barrier
+        const int wpg = 4;
+        if (graph) HEAT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int32_t k = 0; k < max_rounds_ && e == hipSuccess; ++k)
+            e = launch_batch_round(precision_, K_, d.rings, d.tile_prefix, k, active_[k],
+                                   tile_prefix_[active_[k]], wpg, st);
+        if (graph) {
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(st, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e == hipSuccess) e = hipGraphLaunch(graph_exec_, st);
+        }
+        if (e != hipSuccess) return fail_hip(e, "batch rounds");
+        return HEAT_OK;
+    }
     d.round_start = (const int64_t *)p;
     HEAT_HIP(hipMemcpyAsync(p, round_start_.data(), round_start_.size() * 8,
                             hipMemcpyHostToDevice, st));
@@ -110,14 +129,20 @@ int BatchLaunch::enqueue(void *dev_mem, hipStream_t st, int chunk, int wpg) {
     HEAT_HIP(launch_fill_u32((uint32_t *)p, 4, 0u, st));
     d.total_items = total_items_;
     d.max_rounds = max_rounds_;
-    d.chunk = chunk;
+    d.chunk = 4;
     d.spin_limit = (int64_t)1 << 22;
     status_dev_ = d.status;
+    const int wpg = 4;
     int grid = 0;
     int rc = batch_grid_size(precision_, K_, wpg, &grid);
     if (rc) return rc;
     HEAT_HIP(launch_batch(precision_, K_, d, grid, wpg, st));
     return HEAT_OK;
+}
+
+void BatchLaunch::release() {
+    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+    graph_exec_ = nullptr;
 }
 
 int BatchLaunch::check_status(hipStream_t st) {
@@ -143,7 +168,7 @@ int validate_ring(const heat_ring &g) {
 
 // Enqueue one fused launch per precision present, all on `st`.
 int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
-                      std::vector<BatchLaunch> &launches, void **dev_mem_out) {
+                      std::vector<BatchLaunch> &launches, void **dev_mem_out, int32_t flags) {
     *dev_mem_out = nullptr;
     std::vector<BatchRing> by_prec[3];
     for (int32_t i = 0; i < count; ++i) {
@@ -168,7 +193,7 @@ int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
     *dev_mem_out = mem;
     char *p = (char *)mem;
     for (BatchLaunch &L : launches) {
-        rc = L.enqueue(p, st, /*chunk=*/4, /*wpg=*/4);
+        rc = L.enqueue(p, st, (flags & HEAT_BATCH_PERSISTENT) != 0, (flags & HEAT_BATCH_GRAPH) != 0);
         if (rc) return rc;
         p += L.device_bytes();
     }
@@ -181,8 +206,12 @@ using namespace heat;
 
 extern "C" {
 
-int heat_solve_batch_dev(const heat_ring *rings, int32_t count, void *hip_stream, int32_t wait) {
+int heat_solve_batch_dev(const heat_ring *rings, int32_t count, void *hip_stream, int32_t flags) {
     if (count < 0 || (count > 0 && !rings)) return fail(HEAT_EINVAL, "bad ring array");
+    if (flags & ~(HEAT_BATCH_WAIT | HEAT_BATCH_PERSISTENT | HEAT_BATCH_GRAPH))
+        return fail(HEAT_EINVAL, "unknown batch flags 0x%x", flags);
+    if ((flags & HEAT_BATCH_GRAPH) && !(flags & HEAT_BATCH_WAIT))
+        return fail(HEAT_EINVAL, "HEAT_BATCH_GRAPH needs HEAT_BATCH_WAIT");
     for (int32_t i = 0; i < count; ++i) {
         int rc = validate_ring(rings[i]);
         if (rc) return fail(rc, "ring %d: %s", i, heat_last_error());
@@ -190,12 +219,16 @@ int heat_solve_batch_dev(const heat_ring *rings, int32_t count, void *hip_stream
     hipStream_t st = (hipStream_t)hip_stream;
     std::vector<BatchLaunch> launches;
     void *mem = nullptr;
-    int rc = batch_dev_enqueue(rings, count, st, launches, &mem);
-    if (!rc && wait)
+    int rc = batch_dev_enqueue(rings, count, st, launches, &mem, flags);
+    if (flags & HEAT_BATCH_WAIT) {
         for (BatchLaunch &L : launches) {
-            rc = L.check_status(st);
-            if (rc) break;
+            int rc2 = L.check_status(st);
+            if (!rc) rc = rc2;
         }
+        hipError_t e = hipStreamSynchronize(st);
+        if (!rc && e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");
+        for (BatchLaunch &L : launches) L.release();
+    }
     if (mem) (void)hipFreeAsync(mem, st);
     return rc;
 }
@@ -271,7 +304,7 @@ int heat_solve_batch(heat_problem *probs, int32_t count) {
     std::vector<BatchLaunch> launches;
     void *mem = nullptr;
     if (!rc) {
-        rc = batch_dev_enqueue(rings.data(), (int32_t)rings.size(), st, launches, &mem);
+        rc = batch_dev_enqueue(rings.data(), (int32_t)rings.size(), st, launches, &mem, 0);
         if (mem) allocs.push_back(mem);
     }
     for (size_t j = 0; j < rings.size() && !rc; ++j) {

@@ -22,9 +22,13 @@ class BatchLaunch {
     int build(const std::vector<BatchRing> &rings, int precision);
     // Device bytes for tables, epoch counters, work counter and status word.
     size_t device_bytes() const;
-    // Upload tables into dev_mem (device_bytes() bytes), clear the counters
-    // and launch the persistent kernel on st.
-    int enqueue(void *dev_mem, hipStream_t st, int chunk, int wpg);
+    // Upload tables into dev_mem (device_bytes() bytes) and enqueue the work
+    // on st: one launch per round (default; `graph` captures those launches
+    // in a hipGraph and replays it), or the flag-synchronised persistent
+    // kernel (`persistent`).
+    int enqueue(void *dev_mem, hipStream_t st, bool persistent, bool graph);
+    // Release a captured graph (call after the stream has been synchronised).
+    void release();
     // Wait for st and report a timed-out dependency wait, if any.
     int check_status(hipStream_t st);
     int64_t total_items() const { return total_items_; }
@@ -40,9 +44,10 @@ class BatchLaunch {
     int32_t max_rounds_ = 0;
     int64_t total_items_ = 0;
     uint32_t *status_dev_ = nullptr;
+    hipGraphExec_t graph_exec_ = nullptr;
 };
 
 int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
-                      std::vector<BatchLaunch> &launches, void **dev_mem_out);
+                      std::vector<BatchLaunch> &launches, void **dev_mem_out, int32_t flags);
 
 }  // namespace heat

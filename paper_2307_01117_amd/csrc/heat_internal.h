@@ -130,6 +130,10 @@ struct BatchPlanDev {       // device pointers of one fused launch
 
 hipError_t launch_batch(int precision, int K, const BatchPlanDev &plan, int grid, int wpg,
                         hipStream_t st);
+// One round of every active ring (rings[0, active) in the sorted table).
+hipError_t launch_batch_round(int precision, int K, const BatchRing *rings,
+                              const int64_t *tile_prefix, int k, int active, int64_t items, int wpg,
+                              hipStream_t st);
 int batch_grid_size(int precision, int K, int wpg, int *grid);
 
 // Shared device-side state for the batch/server runtime (stream-ordered pool).

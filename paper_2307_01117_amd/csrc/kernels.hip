@@ -466,6 +466,41 @@ __global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uin
     }
 }
 
+// ========================================================= ROUND-BATCHING
+// One launch advances every ring still running by one round: the flat item
+// list is the tiles of the active rings (rings sorted by rounds, so the
+// active ones are a prefix), one wavefront per tile.  The kernel boundary is
+// the round barrier, so no flags or cross-wave waits are needed.  Item ids
+// are wave-uniform, so the ring lookup runs on the scalar unit.
+
+template <class P, int K, bool PP>
+__global__ void __launch_bounds__(256)
+k_batch_round(const BatchRing *__restrict__ rings, const int64_t *__restrict__ tile_prefix,
+              int32_t k, int32_t active, int64_t items) {
+    using T = typename P::T;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t id = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
+    if (id >= items) return;
+    const int64_t p = upper_bound_i64(tile_prefix, (int64_t)active + 1, id) - 1;
+    const int64_t t = id - tile_prefix[p];
+    const BatchRing &R = rings[p];
+    const int64_t b = t * R.W;
+    if (k < R.rounds) {
+        const T *src = reinterpret_cast<const T *>(R.buf[k & 1]);
+        T *dst = reinterpret_cast<T *>(R.buf[(k + 1) & 1]);
+        const int64_t done = (int64_t)k * R.T;
+        const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
+        window_tile<P, K, PP>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0, lane);
+    } else {
+        // copy-back round: after an odd number of rounds the state sits in buf[1]
+        const T *src = reinterpret_cast<const T *>(R.buf[1]);
+        T *dst = reinterpret_cast<T *>(R.buf[0]);
+        const int64_t wlen = (R.N - b) < R.W ? (R.N - b) : R.W;
+        for (int64_t i = lane; i < wlen; i += 64) dst[b + i] = src[b + i];
+    }
+}
+
 // ================================================================ LAUNCHERS
 
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -583,6 +618,28 @@ template <class P, int K>
 static hipError_t launch_batch_t(const BatchPlanDev &plan, int grid, int wpg, hipStream_t st) {
     hipLaunchKernelGGL((k_batch<P, K>), dim3(grid), dim3(64 * wpg), 0, st, plan);
     return hipGetLastError();
+}
+
+template <class P, int K, bool PP>
+static hipError_t launch_batch_round_t(const BatchRing *rings, const int64_t *tile_prefix, int k,
+                                       int active, int64_t items, int wpg, hipStream_t st) {
+    const int64_t blocks = (items + wpg - 1) / wpg;
+    hipLaunchKernelGGL((k_batch_round<P, K, PP>), dim3((unsigned)blocks), dim3(64 * wpg), 0, st,
+                       rings, tile_prefix, k, active, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_round(int precision, int K, const BatchRing *rings,
+                              const int64_t *tile_prefix, int k, int active, int64_t items, int wpg,
+                              hipStream_t st) {
+    if (items <= 0) return hipSuccess;
+    if (precision == HEAT_FP64 && K == 32)
+        return launch_batch_round_t<F64, 32, true>(rings, tile_prefix, k, active, items, wpg, st);
+    if (precision == HEAT_FP32 && K == 32)
+        return launch_batch_round_t<F32, 32, false>(rings, tile_prefix, k, active, items, wpg, st);
+    if (precision == HEAT_FP32C && K == 32)
+        return launch_batch_round_t<F32C, 32, false>(rings, tile_prefix, k, active, items, wpg, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch(int precision, int K, const BatchPlanDev &plan, int grid, int wpg,

@@ -22,6 +22,7 @@ HEAT_OK, HEAT_PENDING = 0, 1
 HEAT_EINVAL, HEAT_ENOMEM, HEAT_EBUSY, HEAT_ENOENT, HEAT_EDEVICE, HEAT_ECANCELED = -1, -2, -3, -4, -5, -6
 FP64, FP32, FP32C = 0, 1, 2
 KERNEL_AUTO, KERNEL_STEP, KERNEL_TB = 0, 1, 2
+BATCH_WAIT, BATCH_PERSISTENT, BATCH_GRAPH = 1, 2, 4
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32c": FP32C}
 
@@ -236,15 +237,19 @@ def solve_batch(problems) -> list:
     return res
 
 
-def solve_batch_dev(rings, stream=None, wait: bool = True):
+def solve_batch_dev(rings, stream=None, wait: bool = True, persistent: bool = False,
+                    graph: bool = False):
     """Device batching form.  ``rings``: iterable of (d_u, d_work, nt, r, precision)
-    with torch tensors; every ring advances in one fused launch."""
+    with torch tensors; all rings advance together, one launch per round
+    (or one persistent launch with ``persistent``)."""
     rings = list(rings)
     arr = (heat_ring * len(rings))()
     for i, (d_u, d_work, nt, r, prec) in enumerate(rings):
         arr[i] = heat_ring(d_u.numel(), int(nt), float(r), int(prec), 1, d_u.data_ptr(),
                            d_work.data_ptr() if d_work is not None else None)
-    _check(load().heat_solve_batch_dev(arr, len(rings), _stream_handle(stream), int(bool(wait))))
+    flags = (BATCH_WAIT if wait else 0) | (BATCH_PERSISTENT if persistent else 0) | \
+        (BATCH_GRAPH if graph else 0)
+    _check(load().heat_solve_batch_dev(arr, len(rings), _stream_handle(stream), flags))
 
 
 class Server:

@@ -69,11 +69,13 @@ def test_host_batch_reports_bad_problem():
     assert ei.value.code == heat.HEAT_EINVAL
 
 
-def test_device_batch_equals_alone():
+@pytest.mark.parametrize("mode", ["rounds", "graph", "persistent"])
+def test_device_batch_equals_alone(mode):
     """Rings of the uneven batching workload (N log-uniform, nt uniform, r in
-    (0.1, 1/2]), scaled down: each ring in the fused launch equals the same
-    ring solved alone, bit for bit, in binary64 and compensated binary32."""
+    (0.1, 1/2]), scaled down: each ring in the batch equals the same ring
+    solved alone, bit for bit, in binary64 and compensated binary32."""
     specs = inputs.batch_specs(count=96, seed=44, logn_hi=5.0, nt_hi=2000)
+    kw = dict(graph=mode == "graph", persistent=mode == "persistent")
     for prec, dt in ((heat.FP64, torch.float64), (heat.FP32C, torch.float32)):
         us = [torch.from_numpy(inputs.ring_initial(s)).to("cuda", dtype=dt) for s in specs]
         alone = []
@@ -82,7 +84,7 @@ def test_device_batch_equals_alone():
             heat.solve_dev(a, s.nparts, s.r, s.nt, precision=prec)
             alone.append(a)
         work = [torch.empty_like(u) for u in us]
-        heat.solve_batch_dev([(u, w, s.nt, s.r, prec) for u, w, s in zip(us, work, specs)])
+        heat.solve_batch_dev([(u, w, s.nt, s.r, prec) for u, w, s in zip(us, work, specs)], **kw)
         torch.cuda.synchronize()
         for s, u, a in zip(specs, us, alone):
             assert torch.equal(u, a), (prec, s.N, s.nt)
