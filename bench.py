@@ -53,11 +53,16 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="time the library's plain streaming copy of the state instead "
                          "(the bandwidth reference for the roofline and traffic counters)")
-    ap.add_argument("--form", default="plain", choices=["plain", "batch"],
+    ap.add_argument("--form", default="plain", choices=["plain", "batch", "serve"],
                     help="plain: one ring (the workload above); batch: 4,096 uneven rings "
                          "advanced together (N log-uniform in [1e3, 1e6], nt uniform in "
                          "[100, 10000], r in (0.1, 0.5]), compared with solving them one by one")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--rates", default="50,200,1000",
+                    help="serve: Poisson arrival rates (requests/s)")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
+    ap.add_argument("--warm-s", type=float, default=5.0,
+                    help="serve: arrivals before this time are excluded from latency stats")
     ap.add_argument("--batch-mode", default="rounds", choices=["rounds", "graph", "persistent"])
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="time steps of the full ring the CPU oracle runs as its sample")
@@ -96,6 +101,8 @@ def main():
     heat.load()
     if args.form == "batch":
         return bench_batch(args)
+    if args.form == "serve":
+        return bench_serve(args)
     w = inputs.WORKLOADS[args.workload]
     prec_name = args.precision or ("fp64" if args.workload != "ring_1e8_perturbed" else "fp32c")
     prec = heat.PRECISIONS[prec_name]
@@ -258,6 +265,81 @@ def bench_batch(args):
                              "seconds": round(plain_s, 3)},
         "batched_vs_plain": round(value / (cups / plain_s / 1e9), 3),
     }), flush=True)
+
+
+def bench_serve(args):
+    """Serving form: Poisson arrivals of heat-solve requests (N log-uniform in
+    [1e3, 1e7], nt uniform in [100, 5000], r in (0.1, 0.5], FP64 or
+    compensated FP32 with probability 1/2) into one continuous-batching
+    server.  Latency = completion - scheduled arrival.  One JSON line per rate."""
+    import numpy as np
+    import torch
+
+    from paper_2307_01117_amd import heat, inputs
+    P = 1 << 24
+    nmax = 10_000_000
+    pool = torch.empty(P + nmax, dtype=torch.float64, pin_memory=True).numpy()
+    pool[:P] = inputs.serving_pool(P)
+    pool[P:] = pool[:nmax]           # u0[i] = pool[(off + i) mod P] as one contiguous slice
+    sink = torch.empty(nmax, dtype=torch.float64, pin_memory=True).numpy()
+    for rate in [float(x) for x in args.rates.split(",")]:
+        trace = inputs.serving_trace(rate, args.duration, pool_size=P)
+        server = heat.Server()
+        submitted = []          # (req, ticket, t_submit_rel, private_out)
+        rejected = 0
+        t0 = time.perf_counter()
+        for k, q in enumerate(trace):
+            delay = t0 + q.t_arrival - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            u0 = pool[q.offset:q.offset + q.N]
+            check = k % 97 == 0
+            out = np.empty(q.N) if check else sink[:q.N]
+            try:
+                t = server.submit(u0, q.nt, q.r, q.precision, out=out)
+            except heat.HeatError as e:
+                if e.code != heat.HEAT_EBUSY:
+                    raise
+                rejected += 1
+                continue
+            submitted.append((q, t, time.perf_counter() - t0, check))
+        results = [(q, server.wait(t), ts, check) for (q, t, ts, check) in submitted]
+        t_end = time.perf_counter() - t0
+        stats = server.stats()
+        server.close()
+        lat = []
+        cups = 0
+        for q, res, ts, _ in results:
+            cups += q.N * q.nt
+            if q.t_arrival >= args.warm_s:
+                lat.append((ts - q.t_arrival) + res.latency_s)
+        lat = np.sort(np.array(lat)) if lat else np.array([float("nan")])
+        # alone vs in the mix, on every 97th request
+        same = total = 0
+        for q, res, _, check in results:
+            if not check:
+                continue
+            dt = torch.float64 if q.precision == heat.FP64 else torch.float32
+            d = torch.from_numpy(pool[q.offset:q.offset + q.N]).to("cuda", dtype=dt)
+            heat.solve_dev(d, 1, q.r, q.nt, precision=q.precision)
+            total += 1
+            same += int(np.array_equal(d.double().cpu().numpy(), res.u))
+        offered = sum(q.N * q.nt for q in trace) / args.duration / 1e9
+        print(json.dumps({
+            "metric": "serving: p50/p99 latency and GCUP/s", "rate_req_s": rate,
+            "value": round(cups / t_end / 1e9, 3), "unit": "GCUP/s", "n_gpus": 1,
+            "duration_s": args.duration, "requests": len(trace), "completed": len(results),
+            "rejected_busy": rejected,
+            "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+            "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+            "latency_max_s": round(float(lat[-1]), 4),
+            "offered_GCUPs": round(offered, 1), "wall_s": round(t_end, 2),
+            "ticks": stats["ticks"], "hbm_peak_GB": round(stats["hbm_peak"] / 1e9, 2),
+            "alone_vs_mix_bitwise": f"{same}/{total}",
+            "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "poisson_serving", "N": "log-uniform [1e3, 1e7]",
+                       "nt": "uniform [100, 5000]", "precision": "fp64 or fp32c (p = 1/2)"},
+        }), flush=True)
 
 
 if __name__ == "__main__":

@@ -148,6 +148,7 @@ typedef struct heat_problem {
     double sum_nt;
     int32_t status;
     int32_t reserved;
+    double latency_s;   /* server: seconds from heat_submit to completion */
 } heat_problem;
 
 /*

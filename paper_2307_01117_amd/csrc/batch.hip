@@ -1,6 +1,7 @@
-// batch.hip -- batching form: many independent rings in one persistent fused
-// launch (k_batch in kernels.hip).  This file builds the dependency-ordered
-// work list on the host and owns the host-buffer wrapper heat_solve_batch.
+// batch.hip -- batching form: many independent rings advanced together, one
+// launch per round over all running rings (k_batch_round), or one persistent
+// launch with per-tile epoch counters (k_batch).  This file builds the work
+// lists on the host and owns the host-buffer wrapper heat_solve_batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,20 +38,25 @@ int describe_ring(const heat_ring &g, BatchRing *out) {
     R.copy_round = (int32_t)(rounds & 1);
     R.vec_ok = aligned16(g.d_u) && aligned16(g.d_work);
     R.flag_base = 0;
+    R.round0 = 0;
     *out = R;
     return HEAT_OK;
 }
 
-// Host-side work list of one fused launch over rings of one precision.
-int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision) {
+// Host-side work list over rings of one precision.
+static inline int32_t remaining_rounds(const BatchRing &R) {
+    return R.rounds + R.copy_round - R.round0;
+}
+
+int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision, int32_t cap) {
     precision_ = precision;
     K_ = batch_cells_per_lane(precision);
     rings_.clear();
     for (const BatchRing &R : rings_in)
-        if (R.rounds > 0) rings_.push_back(R);
-    // longest first (total rounds incl. copy-back), stable for determinism
+        if (remaining_rounds(R) > 0) rings_.push_back(R);
+    // longest first (remaining rounds incl. copy-back), stable for determinism
     std::stable_sort(rings_.begin(), rings_.end(), [](const BatchRing &a, const BatchRing &b) {
-        return a.rounds + a.copy_round > b.rounds + b.copy_round;
+        return remaining_rounds(a) > remaining_rounds(b);
     });
     const size_t n = rings_.size();
     tile_prefix_.assign(n + 1, 0);
@@ -61,13 +67,14 @@ int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision) {
         tile_prefix_[i + 1] = tile_prefix_[i] + rings_[i].tiles;
     }
     nflags_ = flags;
-    max_rounds_ = n ? rings_[0].rounds + rings_[0].copy_round : 0;
+    max_rounds_ = n ? remaining_rounds(rings_[0]) : 0;
+    if (cap > 0 && max_rounds_ > cap) max_rounds_ = cap;
     active_.assign(max_rounds_, 0);
     round_start_.assign(max_rounds_ + 1, 0);
-    // rings are sorted by total rounds, so the rings alive in round k form a prefix
+    // rings are sorted by remaining rounds, so the rings alive in round k form a prefix
     size_t alive = n;
     for (int32_t k = 0; k < max_rounds_; ++k) {
-        while (alive > 0 && rings_[alive - 1].rounds + rings_[alive - 1].copy_round <= k) --alive;
+        while (alive > 0 && remaining_rounds(rings_[alive - 1]) <= k) --alive;
         active_[k] = (int32_t)alive;
         round_start_[k + 1] = round_start_[k] + tile_prefix_[alive];
     }
@@ -97,22 +104,35 @@ int BatchLaunch::enqueue(void *dev_mem, hipStream_t st, bool persistent, bool gr
     if (!persistent) {
         // one launch per round; the kernel boundary is the round barrier
         const int wpg = 4;
-        if (graph) HEAT_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipSuccess;
+        if (!graph) {
+            for (int32_t k = 0; k < max_rounds_; ++k)
+                HEAT_HIP(launch_batch_round(precision_, K_, d.rings, d.tile_prefix, k, active_[k],
+                                            tile_prefix_[active_[k]], wpg, st));
+            return HEAT_OK;
+        }
+        // Capture the round launches on a private stream (the caller's may be
+        // the legacy default stream, which cannot capture), then replay the
+        // graph on the caller's stream after the table uploads above.
+        hipStream_t cs = nullptr;
+        HEAT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         for (int32_t k = 0; k < max_rounds_ && e == hipSuccess; ++k)
             e = launch_batch_round(precision_, K_, d.rings, d.tile_prefix, k, active_[k],
-                                   tile_prefix_[active_[k]], wpg, st);
-        if (graph) {
-            hipGraph_t g = nullptr;
-            hipError_t e2 = hipStreamEndCapture(st, &g);
-            if (e == hipSuccess) e = e2;
-            if (e == hipSuccess) e = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0);
-            if (g) (void)hipGraphDestroy(g);
-            if (e == hipSuccess) e = hipGraphLaunch(graph_exec_, st);
-        }
-        if (e != hipSuccess) return fail_hip(e, "batch rounds");
+                                   tile_prefix_[active_[k]], wpg, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        if (e == hipSuccess) e = hipGraphLaunch(graph_exec_, st);
+        if (e != hipSuccess) return fail_hip(e, "batch graph");
         return HEAT_OK;
     }
+    // the persistent kernel always runs every ring from its first round to its last
+    for (const BatchRing &R : rings_)
+        if (R.round0 != 0 || max_rounds_ != remaining_rounds(rings_[0]))
+            return fail(HEAT_EINVAL, "persistent batch needs whole runs");
     d.round_start = (const int64_t *)p;
     HEAT_HIP(hipMemcpyAsync(p, round_start_.data(), round_start_.size() * 8,
                             hipMemcpyHostToDevice, st));
@@ -137,6 +157,27 @@ int BatchLaunch::enqueue(void *dev_mem, hipStream_t st, bool persistent, bool gr
     int rc = batch_grid_size(precision_, K_, wpg, &grid);
     if (rc) return rc;
     HEAT_HIP(launch_batch(precision_, K_, d, grid, wpg, st));
+    return HEAT_OK;
+}
+
+size_t BatchLaunch::table_bytes() const {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    return al(rings_.size() * sizeof(BatchRing)) + al(tile_prefix_.size() * 8);
+}
+
+int BatchLaunch::enqueue_rounds(void *dev_tables, void *host_staging, hipStream_t st) {
+    if (total_items_ == 0) return HEAT_OK;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    char *h = (char *)host_staging;
+    std::memcpy(h, rings_.data(), rings_.size() * sizeof(BatchRing));
+    const size_t off = al(rings_.size() * sizeof(BatchRing));
+    std::memcpy(h + off, tile_prefix_.data(), tile_prefix_.size() * 8);
+    HEAT_HIP(hipMemcpyAsync(dev_tables, host_staging, table_bytes(), hipMemcpyHostToDevice, st));
+    const BatchRing *rings = (const BatchRing *)dev_tables;
+    const int64_t *prefix = (const int64_t *)((char *)dev_tables + off);
+    for (int32_t k = 0; k < max_rounds_; ++k)
+        HEAT_HIP(launch_batch_round(precision_, K_, rings, prefix, k, active_[k],
+                                    tile_prefix_[active_[k]], 4, st));
     return HEAT_OK;
 }
 

@@ -18,8 +18,13 @@ int describe_ring(const heat_ring &g, BatchRing *out);
 
 class BatchLaunch {
   public:
-    // Sort rings (longest first), number the work items round-major.
-    int build(const std::vector<BatchRing> &rings, int precision);
+    // Sort rings by remaining rounds (longest first), number the work items
+    // round-major.  At most max_rounds rounds are scheduled (0 = all); each
+    // ring starts at its own round0.
+    int build(const std::vector<BatchRing> &rings, int precision, int32_t max_rounds = 0);
+    // Rings as scheduled (sorted), and the number of rounds each one advances.
+    const std::vector<BatchRing> &rings() const { return rings_; }
+    int32_t rounds_scheduled() const { return max_rounds_; }
     // Device bytes for tables, epoch counters, work counter and status word.
     size_t device_bytes() const;
     // Upload tables into dev_mem (device_bytes() bytes) and enqueue the work
@@ -29,6 +34,12 @@ class BatchLaunch {
     int enqueue(void *dev_mem, hipStream_t st, bool persistent, bool graph);
     // Release a captured graph (call after the stream has been synchronised).
     void release();
+    // Bytes of the round tables (rings + tile prefix) for enqueue_rounds.
+    size_t table_bytes() const;
+    // Copy the round tables through `host_staging` (pinned, table_bytes())
+    // into `dev_tables` and launch the scheduled rounds on st.  The staging
+    // area must stay untouched until st has passed this point.
+    int enqueue_rounds(void *dev_tables, void *host_staging, hipStream_t st);
     // Wait for st and report a timed-out dependency wait, if any.
     int check_status(hipStream_t st);
     int64_t total_items() const { return total_items_; }

@@ -111,7 +111,7 @@ struct BatchRing {          // one ring of a fused launch (device table entry)
     int32_t copy_round;     // 1 if an extra copy-back round follows (odd rounds)
     int64_t nt;
     int32_t vec_ok;         // both buffers 16-byte aligned
-    int32_t pad;
+    int32_t round0;         // rounds already done before this launch sequence
 };
 
 struct BatchPlanDev {       // device pointers of one fused launch

@@ -486,10 +486,11 @@ k_batch_round(const BatchRing *__restrict__ rings, const int64_t *__restrict__ t
     const int64_t t = id - tile_prefix[p];
     const BatchRing &R = rings[p];
     const int64_t b = t * R.W;
-    if (k < R.rounds) {
-        const T *src = reinterpret_cast<const T *>(R.buf[k & 1]);
-        T *dst = reinterpret_cast<T *>(R.buf[(k + 1) & 1]);
-        const int64_t done = (int64_t)k * R.T;
+    const int32_t kk = R.round0 + k;   // this ring's own round index
+    if (kk < R.rounds) {
+        const T *src = reinterpret_cast<const T *>(R.buf[kk & 1]);
+        T *dst = reinterpret_cast<T *>(R.buf[(kk + 1) & 1]);
+        const int64_t done = (int64_t)kk * R.T;
         const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
         window_tile<P, K, PP>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0, lane);
     } else {

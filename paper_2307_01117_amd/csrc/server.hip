@@ -1,18 +1,557 @@
-// server.hip -- serving form (continuous batching).  Placeholder until the
-// scheduler lands: every entry point reports HEAT_EINVAL.
+// server.hip -- serving form: a continuous-batching request loop.
+//
+// Requests (heat problems of different N, nt, r and precision) arrive through
+// heat_submit from any thread.  A scheduler thread admits them in arrival
+// order while the device arena has room for their footprint and a slot is
+// free, and advances every resident request together: each tick is a short
+// sequence of round launches (the batching form's k_batch_round) over all
+// active requests, so requests that arrive while others run join at the next
+// tick and their work shares the device.  A copy thread moves request data
+// host->device at admission and device->host at completion, off the
+// scheduler's path.  A request's rounds are exactly those it would run alone
+// (same T rule, same buffers, same order), so its result is bit-identical
+// alone and in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "heat_batch.h"
 #include "heat_internal.h"
+
+namespace heat {
+
+using Clock = std::chrono::steady_clock;
+
+// ------------------------------------------------------------------ arena
+// One device allocation carved first-fit; host-side bookkeeping only.
+class Arena {
+  public:
+    int init(size_t bytes) {
+        HEAT_HIP(hipMalloc(&base_, bytes));
+        cap_ = bytes;
+        free_.clear();
+        free_[0] = bytes;
+        used_ = peak_ = 0;
+        return HEAT_OK;
+    }
+    void destroy() {
+        if (base_) (void)hipFree(base_);
+        base_ = nullptr;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = round(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            used_ += bytes;
+            peak_ = std::max(peak_, used_);
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = round(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+    char *base() const { return (char *)base_; }
+    size_t cap() const { return cap_; }
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+
+  private:
+    void *base_ = nullptr;
+    size_t cap_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> size, coalesced
+};
+
+enum ReqState { QUEUED, STAGING, READY, ACTIVE, DRAINING, DONE, FAILED, CANCELLED };
+
+struct Req {
+    uint64_t ticket = 0;
+    heat_problem *p = nullptr;
+    heat_ring ring{};
+    BatchRing br{};
+    size_t off = 0, bytes = 0;
+    double *d_sums = nullptr;          // [sum0, sum_nt] on the device
+    int state = QUEUED;
+    int rc = HEAT_OK;
+    std::string msg;                   // error text, kept for the thread that polls
+    bool holds = false;                // owns an arena block and a slot
+    bool cancel = false;
+    uint64_t last_tick = 0;            // last tick that launched work for it
+    hipEvent_t fin = nullptr;          // compute stream passed its final kernels
+    Clock::time_point t_submit;
+};
+
+// Footprint: state (N x storage) + scratch wide enough to stage binary64
+// input (N x max(storage, 8)) + the two sums.
+static size_t footprint(int64_t N, int precision) {
+    const size_t es = storage_bytes(precision);
+    return Arena::round((size_t)N * es) + Arena::round((size_t)N * std::max<size_t>(es, 8)) + 256;
+}
+
+constexpr int32_t TICK_ROUNDS = 2;     // rounds per tick: bounds the admission delay
+
+}  // namespace heat
 
 using namespace heat;
 
+struct heat_server {
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_copy, cv_done;
+    std::deque<Req *> queue, h2d, d2h;
+    std::vector<Req *> ready, active;
+    std::unordered_map<uint64_t, Req *> reqs;
+    Arena arena;
+    int device = 0;
+    int32_t max_slots = 4096, max_queue = 65536, slots_used = 0;
+    hipStream_t compute = nullptr, copy = nullptr;
+    double *d_partial = nullptr;
+    // round tables, double-buffered across ticks (3 precision groups each)
+    size_t table_slot_bytes = 0;
+    char *d_tables = nullptr, *h_tables = nullptr;
+    hipEvent_t table_ev[2] = {nullptr, nullptr};
+    hipEvent_t tick_ev = nullptr;
+    uint64_t tick = 0, next_ticket = 1;
+    bool stop = false;
+    int fatal = HEAT_OK;
+    std::thread sched, copier;
+    heat_server_stats st{};
+};
+
+static void finish_locked(heat_server *s, Req *q, int state, int rc) {
+    if (q->holds) {
+        s->arena.release(q->off, q->bytes);
+        q->holds = false;
+        --s->slots_used;
+    }
+    q->state = state;
+    q->rc = rc;
+    if (rc < 0 && rc != HEAT_ECANCELED) q->msg = heat_last_error();
+    if (q->fin) {
+        (void)hipEventDestroy(q->fin);
+        q->fin = nullptr;
+    }
+    if (state == CANCELLED) ++s->st.cancelled;
+    s->cv_done.notify_all();
+    s->cv_sched.notify_one();
+}
+
+// ------------------------------------------------------------ copy thread
+static void copy_loop(heat_server *s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        s->cv_copy.wait(lk, [&] { return s->stop || !s->h2d.empty() || !s->d2h.empty(); });
+        if (!s->d2h.empty()) {
+            Req *q = s->d2h.front();
+            s->d2h.pop_front();
+            lk.unlock();
+            const int64_t N = q->ring.N;
+            hipError_t e = hipEventSynchronize(q->fin);
+            double sums[2] = {0.0, 0.0};
+            // FP32 forms were widened exactly into the scratch buffer
+            const void *src = q->ring.precision == HEAT_FP64 ? q->ring.d_u : q->ring.d_work;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(q->p->u_out, src, (size_t)N * 8, hipMemcpyDeviceToHost, s->copy);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(sums, q->d_sums, sizeof sums, hipMemcpyDeviceToHost, s->copy);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->copy);
+            lk.lock();
+            if (e == hipSuccess) {
+                q->p->sum0 = sums[0];
+                q->p->sum_nt = sums[1];
+                q->p->status = HEAT_OK;
+                q->p->latency_s =
+                    std::chrono::duration<double>(Clock::now() - q->t_submit).count();
+                ++s->st.completed;
+                s->st.cell_updates += (uint64_t)(q->ring.N * q->ring.nt);
+                finish_locked(s, q, DONE, HEAT_OK);
+            } else {
+                q->p->status = HEAT_EDEVICE;
+                finish_locked(s, q, FAILED, fail_hip(e, "server stage-out"));
+            }
+            continue;
+        }
+        if (!s->h2d.empty()) {
+            Req *q = s->h2d.front();
+            s->h2d.pop_front();
+            lk.unlock();
+            const int64_t N = q->ring.N;
+            // binary64 input lands in the state buffer (FP64) or in the scratch
+            // buffer, to be rounded to binary32 on the compute stream
+            void *dst = q->ring.precision == HEAT_FP64 ? q->ring.d_u : q->ring.d_work;
+            hipError_t e = hipMemcpyAsync(dst, q->p->u0, (size_t)N * 8, hipMemcpyHostToDevice, s->copy);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->copy);
+            lk.lock();
+            if (e != hipSuccess) {
+                q->p->status = HEAT_EDEVICE;
+                finish_locked(s, q, FAILED, fail_hip(e, "server stage-in"));
+            } else if (q->cancel) {
+                finish_locked(s, q, CANCELLED, HEAT_ECANCELED);
+            } else {
+                q->state = READY;
+                s->ready.push_back(q);
+                s->cv_sched.notify_one();
+            }
+            continue;
+        }
+        if (s->stop) break;
+    }
+}
+
+// ------------------------------------------------------------ scheduler
+static int run_tick(heat_server *s, std::vector<Req *> &act, uint64_t tick) {
+    // group by precision; every group advances up to TICK_ROUNDS rounds
+    std::vector<BatchRing> groups[3];
+    for (Req *q : act) groups[q->ring.precision].push_back(q->br);
+    const int slot = (int)(tick & 1);
+    HEAT_HIP(hipEventSynchronize(s->table_ev[slot]));   // the tick that used this slot is done
+    char *dt = s->d_tables + slot * s->table_slot_bytes;
+    char *ht = s->h_tables + slot * s->table_slot_bytes;
+    const size_t per_group = s->table_slot_bytes / 3;
+    for (int prec = 0; prec < 3; ++prec) {
+        if (groups[prec].empty()) continue;
+        BatchLaunch L;
+        L.build(groups[prec], prec, TICK_ROUNDS);
+        int rc = L.enqueue_rounds(dt + prec * per_group, ht + prec * per_group, s->compute);
+        if (rc) return rc;
+    }
+    HEAT_HIP(hipEventRecord(s->table_ev[slot], s->compute));
+    return HEAT_OK;
+}
+
+static void sched_loop(heat_server *s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        // admission in arrival order while memory and slots allow
+        while (!s->stop && !s->queue.empty() && s->slots_used < s->max_slots) {
+            Req *q = s->queue.front();
+            size_t off = 0;
+            if (!s->arena.alloc(q->bytes, &off)) break;
+            s->queue.pop_front();
+            ++s->slots_used;
+            q->holds = true;
+            q->off = off;
+            char *b = s->arena.base() + off;
+            const size_t es = storage_bytes(q->ring.precision);
+            q->ring.d_u = b;
+            q->ring.d_work = b + Arena::round((size_t)q->ring.N * es);
+            q->d_sums = (double *)(b + Arena::round((size_t)q->ring.N * es) +
+                                   Arena::round((size_t)q->ring.N * std::max<size_t>(es, 8)));
+            describe_ring(q->ring, &q->br);
+            q->state = STAGING;
+            ++s->st.admitted;
+            s->h2d.push_back(q);
+            s->cv_copy.notify_one();
+        }
+        s->st.hbm_in_use = s->arena.used();
+        s->st.hbm_peak = s->arena.peak();
+        s->st.queued = (int32_t)s->queue.size();
+        if (s->stop) break;
+        std::vector<Req *> fresh;
+        fresh.swap(s->ready);
+        // drop cancelled residents once the device no longer touches them
+        bool any_cancel = false;
+        for (Req *q : s->active) any_cancel |= q->cancel;
+        for (Req *q : fresh) any_cancel |= q->cancel;
+        if (any_cancel) {
+            lk.unlock();
+            (void)hipStreamSynchronize(s->compute);
+            lk.lock();
+            auto drop = [&](std::vector<Req *> &v) {
+                v.erase(std::remove_if(v.begin(), v.end(),
+                                       [&](Req *q) {
+                                           if (!q->cancel) return false;
+                                           finish_locked(s, q, CANCELLED, HEAT_ECANCELED);
+                                           return true;
+                                       }),
+                        v.end());
+            };
+            drop(s->active);
+            drop(fresh);
+        }
+        if (s->active.empty() && fresh.empty()) {
+            s->st.active = 0;
+            s->cv_sched.wait_for(lk, std::chrono::milliseconds(2));
+            continue;
+        }
+        lk.unlock();
+        int rc = HEAT_OK;
+        // newly staged requests: round FP32 inputs, take the initial sum
+        for (Req *q : fresh) {
+            hipError_t e = hipSuccess;
+            if (q->ring.precision != HEAT_FP64)
+                e = launch_f64_to_f32((const double *)q->ring.d_work, (float *)q->ring.d_u,
+                                      q->ring.N, s->compute);
+            if (e == hipSuccess)
+                e = launch_sum(q->ring.precision, q->ring.d_u, q->ring.N, s->d_partial, q->d_sums,
+                               s->compute);
+            if (e != hipSuccess) rc = fail_hip(e, "server admit");
+        }
+        lk.lock();
+        for (Req *q : fresh) {
+            q->state = ACTIVE;
+            s->active.push_back(q);
+        }
+        std::vector<Req *> act = s->active;
+        const uint64_t tick = s->tick++;
+        s->st.active = (int32_t)act.size();
+        lk.unlock();
+        if (!rc) rc = run_tick(s, act, tick);
+        // progress bookkeeping and completions (all enqueued after the tick)
+        std::vector<Req *> finished;
+        for (Req *q : act) {
+            const int32_t remaining = q->br.rounds + q->br.copy_round - q->br.round0;
+            q->br.round0 += std::min<int32_t>(remaining, TICK_ROUNDS);
+            q->last_tick = tick;
+            if (q->br.round0 >= q->br.rounds + q->br.copy_round) finished.push_back(q);
+        }
+        for (Req *q : finished) {
+            hipError_t e = launch_sum(q->ring.precision, q->ring.d_u, q->ring.N, s->d_partial,
+                                      q->d_sums + 1, s->compute);
+            if (e == hipSuccess && q->ring.precision != HEAT_FP64)
+                e = launch_f32_to_f64((const float *)q->ring.d_u, (double *)q->ring.d_work,
+                                      q->ring.N, s->compute);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&q->fin, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(q->fin, s->compute);
+            if (e != hipSuccess && !rc) rc = fail_hip(e, "server complete");
+        }
+        lk.lock();
+        ++s->st.ticks;
+        if (rc) {
+            // a device error poisons the server: fail everything resident
+            s->fatal = rc;
+            for (Req *q : s->active) {
+                q->p->status = rc;
+                finish_locked(s, q, FAILED, rc);
+            }
+            s->active.clear();
+            continue;
+        }
+        for (Req *q : finished) {
+            s->active.erase(std::find(s->active.begin(), s->active.end(), q));
+            q->state = DRAINING;
+            s->d2h.push_back(q);
+        }
+        if (!finished.empty()) s->cv_copy.notify_one();
+    }
+}
+
+// ================================================================== C ABI
+
 extern "C" {
-int heat_server_create(size_t, int32_t, int32_t, heat_server **out) {
-    if (out) *out = nullptr;
-    return fail(HEAT_EINVAL, "server not available in this build");
+
+int heat_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t max_queue,
+                       heat_server **out) {
+    if (!out) return fail(HEAT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 0 || max_queue < 0) return fail(HEAT_EINVAL, "negative limits");
+    heat_server *s = new heat_server();
+    s->max_slots = max_slots ? max_slots : 4096;
+    s->max_queue = max_queue ? max_queue : 65536;
+    int rc = HEAT_OK;
+    auto bail = [&](int code) {
+        if (s->d_partial) (void)hipFree(s->d_partial);
+        if (s->d_tables) (void)hipFree(s->d_tables);
+        if (s->h_tables) (void)hipHostFree(s->h_tables);
+        for (hipEvent_t &e : s->table_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (s->compute) (void)hipStreamDestroy(s->compute);
+        if (s->copy) (void)hipStreamDestroy(s->copy);
+        s->arena.destroy();
+        delete s;
+        return code;
+    };
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) return bail(fail_hip(e, "hipGetDevice"));
+    size_t fr = 0, tot = 0;
+    e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) return bail(fail_hip(e, "hipMemGetInfo"));
+    size_t budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)fr);
+    budget &= ~size_t(255);
+    if (budget < (1u << 20)) return bail(fail(HEAT_EINVAL, "budget below 1 MiB"));
+    if ((rc = s->arena.init(budget))) return bail(rc);
+    if ((e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking)) != hipSuccess)
+        return bail(fail_hip(e, "hipStreamCreate"));
+    if ((e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking)) != hipSuccess)
+        return bail(fail_hip(e, "hipStreamCreate"));
+    if ((e = hipMalloc((void **)&s->d_partial, SUM_BLOCKS * sizeof(double))) != hipSuccess)
+        return bail(fail_hip(e, "hipMalloc(partials)"));
+    const size_t group = Arena::round((size_t)s->max_slots * sizeof(BatchRing)) +
+                         Arena::round(((size_t)s->max_slots + 1) * 8);
+    s->table_slot_bytes = 3 * group;
+    if ((e = hipMalloc((void **)&s->d_tables, 2 * s->table_slot_bytes)) != hipSuccess)
+        return bail(fail_hip(e, "hipMalloc(tables)"));
+    if ((e = hipHostMalloc((void **)&s->h_tables, 2 * s->table_slot_bytes, 0)) != hipSuccess)
+        return bail(fail_hip(e, "hipHostMalloc(tables)"));
+    for (hipEvent_t &ev : s->table_ev) {
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+            return bail(fail_hip(e, "hipEventCreate"));
+        if ((e = hipEventRecord(ev, s->compute)) != hipSuccess)
+            return bail(fail_hip(e, "hipEventRecord"));
+    }
+    s->st.hbm_budget = budget;
+    s->sched = std::thread(sched_loop, s);
+    s->copier = std::thread(copy_loop, s);
+    *out = s;
+    return HEAT_OK;
 }
-int heat_submit(heat_server *, heat_problem *, uint64_t *) { return fail(HEAT_EINVAL, "no server"); }
-int heat_poll(heat_server *, uint64_t) { return fail(HEAT_ENOENT, "no server"); }
-int heat_wait(heat_server *, uint64_t) { return fail(HEAT_ENOENT, "no server"); }
-int heat_cancel(heat_server *, uint64_t) { return fail(HEAT_ENOENT, "no server"); }
-int heat_server_get_stats(heat_server *, heat_server_stats *) { return fail(HEAT_EINVAL, "no server"); }
-int heat_server_destroy(heat_server *) { return HEAT_OK; }
+
+int heat_submit(heat_server *s, heat_problem *p, uint64_t *ticket) {
+    if (!s || !p || !ticket) return fail(HEAT_EINVAL, "NULL argument");
+    heat_ring g{p->N, p->nt, p->r, p->precision, p->nparts, (void *)16, (void *)16};
+    int rc = validate_ring(g);
+    if (rc) return rc;
+    if (!p->u0 || !p->u_out) return fail(HEAT_EINVAL, "u0/u_out is NULL");
+    const size_t bytes = footprint(p->N, p->precision);
+    std::lock_guard<std::mutex> lk(s->mu);
+    ++s->st.submitted;
+    if (s->fatal) return fail(s->fatal, "server failed earlier: device error");
+    if (bytes > s->arena.cap()) {
+        ++s->st.rejected;
+        return fail(HEAT_ENOMEM, "request needs %zu bytes, budget is %zu", bytes, s->arena.cap());
+    }
+    if ((int64_t)s->queue.size() >= s->max_queue) {
+        ++s->st.rejected;
+        return fail(HEAT_EBUSY, "admission queue full (%d)", s->max_queue);
+    }
+    Req *q = new Req();
+    q->ticket = s->next_ticket++;
+    q->p = p;
+    q->ring = g;
+    q->ring.d_u = q->ring.d_work = nullptr;
+    q->bytes = bytes;
+    q->t_submit = Clock::now();
+    p->status = HEAT_PENDING;
+    s->reqs[q->ticket] = q;
+    s->queue.push_back(q);
+    *ticket = q->ticket;
+    s->cv_sched.notify_one();
+    return HEAT_OK;
 }
+
+static int consume_locked(heat_server *s, std::unordered_map<uint64_t, Req *>::iterator it) {
+    Req *q = it->second;
+    const int rc = q->state == DONE ? HEAT_OK : q->rc;
+    const std::string msg = q->msg;
+    s->reqs.erase(it);
+    delete q;
+    if (rc == HEAT_ECANCELED) return fail(rc, "request was cancelled");
+    if (rc < 0) return fail(rc, "request failed: %s", msg.c_str());
+    return rc;
+}
+
+int heat_poll(heat_server *s, uint64_t ticket) {
+    if (!s) return fail(HEAT_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(HEAT_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    const int st = it->second->state;
+    if (st == DONE || st == FAILED || st == CANCELLED) return consume_locked(s, it);
+    return HEAT_PENDING;
+}
+
+int heat_wait(heat_server *s, uint64_t ticket) {
+    if (!s) return fail(HEAT_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(HEAT_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    Req *q = it->second;
+    s->cv_done.wait(lk, [&] { return q->state == DONE || q->state == FAILED || q->state == CANCELLED; });
+    return consume_locked(s, s->reqs.find(ticket));
+}
+
+int heat_cancel(heat_server *s, uint64_t ticket) {
+    if (!s) return fail(HEAT_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(HEAT_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    Req *q = it->second;
+    if (q->state == QUEUED) {
+        s->queue.erase(std::find(s->queue.begin(), s->queue.end(), q));
+        q->state = CANCELLED;
+        ++s->st.cancelled;
+    } else if (q->state != DONE && q->state != FAILED && q->state != CANCELLED) {
+        // resident: the scheduler (or the copy thread) lets go of it; a request
+        // already draining completes normally
+        q->cancel = true;
+        s->cv_sched.notify_one();
+        s->cv_done.wait(lk, [&] { return q->state == DONE || q->state == FAILED || q->state == CANCELLED; });
+    }
+    q->p->status = HEAT_ECANCELED;
+    s->reqs.erase(ticket);
+    delete q;
+    return HEAT_OK;
+}
+
+int heat_server_get_stats(heat_server *s, heat_server_stats *out) {
+    if (!s || !out) return fail(HEAT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->st.hbm_in_use = s->arena.used();
+    s->st.hbm_peak = s->arena.peak();
+    s->st.queued = (int32_t)s->queue.size();
+    *out = s->st;
+    return HEAT_OK;
+}
+
+int heat_server_destroy(heat_server *s) {
+    if (!s) return HEAT_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_sched.notify_all();
+        s->cv_copy.notify_all();
+    }
+    if (s->sched.joinable()) s->sched.join();
+    if (s->copier.joinable()) s->copier.join();
+    (void)hipStreamSynchronize(s->compute);
+    (void)hipStreamSynchronize(s->copy);
+    for (auto &kv : s->reqs) {
+        Req *q = kv.second;
+        if (q->fin) (void)hipEventDestroy(q->fin);
+        if (q->state != DONE && q->state != FAILED) q->p->status = HEAT_ECANCELED;
+        delete q;
+    }
+    s->reqs.clear();
+    (void)hipFree(s->d_partial);
+    (void)hipFree(s->d_tables);
+    (void)hipHostFree(s->h_tables);
+    for (hipEvent_t &e : s->table_ev) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(s->compute);
+    (void)hipStreamDestroy(s->copy);
+    s->arena.destroy();
+    delete s;
+    return HEAT_OK;
+}
+
+}  // extern "C"

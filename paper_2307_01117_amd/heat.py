@@ -59,7 +59,8 @@ class heat_problem(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("nparts", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("r", ctypes.c_double), ("nt", ctypes.c_int64), ("u0", ctypes.c_void_p),
                 ("u_out", ctypes.c_void_p), ("sum0", ctypes.c_double), ("sum_nt", ctypes.c_double),
-                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("latency_s", ctypes.c_double)]
 
 
 class heat_ring(ctypes.Structure):
@@ -229,7 +230,7 @@ def solve_batch(problems) -> list:
         keep.append((u0, out))
         arr[i] = heat_problem(u0.size, int(p.get("nparts", 1)), int(p.get("precision", FP64)),
                               float(p["r"]), int(p["nt"]), u0.ctypes.data, out.ctypes.data,
-                              0.0, 0.0, 0, 0)
+                              0.0, 0.0, 0, 0, 0.0)
     rc = load().heat_solve_batch(arr, len(probs))
     res = [BatchResult(keep[i][1], arr[i].sum0, arr[i].sum_nt, arr[i].status)
            for i in range(len(probs))]
@@ -267,7 +268,7 @@ class Server:
         if out is None:
             out = np.empty_like(u0)
         p = heat_problem(u0.size, int(nparts), int(precision), float(r), int(nt), u0.ctypes.data,
-                         out.ctypes.data, 0.0, 0.0, 0, 0)
+                         out.ctypes.data, 0.0, 0.0, 0, 0, 0.0)
         t = ctypes.c_uint64()
         _check(load().heat_submit(self._h, ctypes.byref(p), ctypes.byref(t)))
         self._live[t.value] = (p, u0, out)

@@ -1,0 +1,158 @@
+"""GPU tests of the serving form (continuous batching) through the C ABI:
+results bit-identical to the oracle and to the same request solved alone,
+admission by HBM footprint, queue limits, cancellation and shutdown."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_01117_amd import heat, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    heat.load()
+
+
+def alone(u0, nt, r, prec):
+    dt = torch.float64 if prec == heat.FP64 else torch.float32
+    d = torch.from_numpy(u0).to("cuda", dtype=dt)
+    heat.solve_dev(d, 1, r, nt, precision=prec)
+    return d.double().cpu().numpy()
+
+
+def requests(seed, count, nmax=200_000, ntmax=1500):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        N = int(10 ** rng.uniform(0, np.log10(nmax)))
+        nt = int(rng.integers(0, ntmax))
+        r = float(0.5 - 0.4 * rng.random())
+        prec = heat.FP64 if k % 2 == 0 else heat.FP32C
+        out.append((inputs.uniform_ring(N, (60, seed, k)), nt, r, prec))
+    return out
+
+
+def test_single_request_matches_oracle():
+    u0 = inputs.uniform_ring(50_001, 61)
+    with heat.Server(hbm_budget=1 << 30) as s:
+        t = s.submit(u0, 300, 0.5)
+        res = s.wait(t)
+        assert res.status == heat.HEAT_OK
+        assert np.array_equal(res.u, oracle.solve(u0, 0.5, 300))
+        assert abs(res.sum_nt - res.sum0) < 1e-9
+        st = s.stats()
+        assert st["completed"] == 1 and st["hbm_in_use"] == 0
+
+
+def test_mix_equals_alone():
+    """Requests of different N, nt, r and precision submitted together: every
+    result equals the same request solved alone with the plain form."""
+    reqs = requests(62, 48)
+    with heat.Server(hbm_budget=2 << 30) as s:
+        tickets = [s.submit(u0, nt, r, prec) for (u0, nt, r, prec) in reqs]
+        results = [s.wait(t) for t in tickets]
+        assert s.stats()["ticks"] >= 1
+    for (u0, nt, r, prec), res in zip(reqs, results):
+        assert res.status == heat.HEAT_OK
+        assert np.array_equal(res.u, alone(u0, nt, r, prec)), (u0.size, nt, prec)
+
+
+def test_alone_on_idle_server_equals_in_mix():
+    probe = requests(63, 4, nmax=300_000, ntmax=3000)
+    background = requests(64, 40)
+    with heat.Server(hbm_budget=2 << 30) as s:
+        solo = [s.wait(s.submit(*q)).u for q in probe]
+        tickets = []
+        for k, q in enumerate(background):
+            tickets.append(s.submit(*q))
+            if k % 10 == 0:
+                tickets.append(("probe", s.submit(*probe[k // 10])))
+        mixed = {}
+        for t in tickets:
+            if isinstance(t, tuple):
+                mixed[len(mixed)] = s.wait(t[1]).u
+            else:
+                s.wait(t)
+    for k in range(4):
+        assert np.array_equal(solo[k], mixed[k])
+
+
+def test_budget_admission_and_enomem():
+    budget = 24 << 20     # fits one 1e6-cell binary64 request (16 MB), not two
+    with heat.Server(hbm_budget=budget) as s:
+        big = inputs.uniform_ring(2_000_000, 65)
+        with pytest.raises(heat.HeatError) as ei:
+            s.submit(big, 10, 0.5)
+        assert ei.value.code == heat.HEAT_ENOMEM
+        reqs = [(inputs.uniform_ring(1_000_000, (66, k)), 200, 0.4, heat.FP64) for k in range(3)]
+        ts = [s.submit(*q) for q in reqs]
+        outs = [s.wait(t) for t in ts]
+        st = s.stats()
+        assert st["hbm_peak"] <= budget and st["hbm_in_use"] == 0
+    for (u0, nt, r, _), res in zip(reqs, outs):
+        assert np.array_equal(res.u, oracle.solve(u0, r, nt))
+
+
+def test_queue_limit_busy():
+    with heat.Server(hbm_budget=24 << 20, max_queue=1) as s:
+        q = (inputs.uniform_ring(1_000_000, 67), 4000, 0.5, heat.FP64)
+        accepted, busy = [], 0
+        for _ in range(4):
+            try:
+                accepted.append(s.submit(*q))
+            except heat.HeatError as e:
+                assert e.code == heat.HEAT_EBUSY
+                busy += 1
+        assert busy >= 1 and accepted
+        for t in accepted:
+            assert s.wait(t).status == heat.HEAT_OK
+
+
+def test_cancel_and_unknown_ticket():
+    with heat.Server(hbm_budget=1 << 30) as s:
+        long_req = (inputs.uniform_ring(4_000_000, 68), 200_000, 0.5, heat.FP64)
+        short = (inputs.uniform_ring(10_000, 69), 100, 0.3, heat.FP64)
+        t1 = s.submit(*long_req)
+        t2 = s.submit(*short)
+        time.sleep(0.01)
+        s.cancel(t1)
+        with pytest.raises(heat.HeatError) as ei:
+            s.poll(t1)
+        assert ei.value.code == heat.HEAT_ENOENT
+        res = s.wait(t2)
+        assert np.array_equal(res.u, oracle.solve(short[0], 0.3, 100))
+        assert s.stats()["cancelled"] == 1
+    with pytest.raises(heat.HeatError):
+        heat.Server(hbm_budget=16)   # below the minimum arena
+
+
+def test_submit_from_many_threads_and_destroy_with_work_outstanding():
+    reqs = requests(70, 64, nmax=100_000, ntmax=800)
+    s = heat.Server(hbm_budget=1 << 30)
+    tickets = [None] * len(reqs)
+
+    def worker(lo):
+        for k in range(lo, len(reqs), 4):
+            tickets[k] = s.submit(*reqs[k])
+
+    th = [threading.Thread(target=worker, args=(i,)) for i in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    got = [s.wait(t) for t in tickets[:16]]
+    for q, res in zip(reqs[:16], got):
+        assert np.array_equal(res.u, alone(*q))
+    # more work outstanding: destroy must cancel it cleanly
+    for q in reqs[:8]:
+        s.submit(*q)
+    s.close()
