@@ -216,6 +216,7 @@ class BatchResult:
     sum0: float
     sum_nt: float
     status: int
+    latency_s: float = 0.0
 
 
 def solve_batch(problems) -> list:
@@ -276,7 +277,7 @@ class Server:
 
     def _result(self, t):
         p, _, out = self._live.pop(t)
-        return BatchResult(out, p.sum0, p.sum_nt, p.status)
+        return BatchResult(out, p.sum0, p.sum_nt, p.status, p.latency_s)
 
     def poll(self, ticket: int):
         rc = load().heat_poll(self._h, ctypes.c_uint64(ticket))
