@@ -250,6 +250,30 @@ int heat_server_get_stats(heat_server *s, heat_server_stats *out);
 /* Cancel all outstanding work, stop the thread, free the arena. */
 int heat_server_destroy(heat_server *s);
 
+/* ---------------------------------------------------------------- tuning */
+
+/*
+ * Autotuner: times every temporal-blocking launch shape (cells per lane,
+ * steps per round, wavefronts per workgroup, register form) on a synthetic
+ * ring of N cells of the given precision on the current device (HIP events,
+ * two rounds per shape) and returns the fastest in *best_out (host) with its
+ * rate in GCUP/s.  If `install` is nonzero the shape becomes the planner's
+ * default for rings of N's decade (log10 bucket) in this process.  Shapes
+ * never change binary64 or binary32 results; for HEAT_FP32C only shapes with
+ * the form's fixed round length are tried.  Allocates and frees 2 * N * 8
+ * bytes of device memory.  Blocking.
+ */
+int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *best_out,
+                  double *best_gcups);
+
+/*
+ * Save / load the planner's tuning table as text (one line per precision and
+ * decade: "precision bucket K T waves form").  The library also loads the
+ * file named by the environment variable HEAT_TUNE_TABLE at first use.
+ */
+int heat_tune_save(const char *path);
+int heat_tune_load(const char *path);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Thread-local text for the last negative return on this thread. */

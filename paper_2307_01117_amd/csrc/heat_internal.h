@@ -53,6 +53,8 @@ int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision);
 // Halo depth H >= steps for a window of 64*K cells (line-aligned when possible).
 int halo_cells(int64_t steps, int precision, int K);
 bool default_pingpong(int64_t N, int precision);
+// Launch shape from the tuning table for a ring of length N.
+void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, bool *pingpong);
 
 // ----------------------------------------------------------- kernels
 

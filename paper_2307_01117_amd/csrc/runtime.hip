@@ -35,11 +35,8 @@ int fail_hip(hipError_t e, const char *what) {
 
 // ================================================================ planning
 
-// Planner defaults, from a sweep on MI355X over cells per lane K in {8,16,32},
-// steps per round T in {8..128}, 1..8 waves per group and both register
-// forms (N = 1e8 ring): binary64 peaks at K = 32, T ~ 96, ping-pong form;
-// binary32 at K = 32, T ~ 96, in-place form; the compensated form at K = 32,
-// in-place form.
+// Planner defaults come from the tuning table (tune.hip): K, target T,
+// waves per group and register form per (precision, log10 N bucket).
 //
 // Steps per round.  binary64 and plain binary32 results do not depend on it
 // (only speed does), so the planner may rebalance it (see make_plan); for the
@@ -48,23 +45,32 @@ int fail_hip(hipError_t e, const char *what) {
 constexpr int FP32C_STEPS_PER_ROUND = 64;
 
 int default_steps_per_round(int64_t N, int precision) {
-    (void)N;
-    switch (precision) {
-        case HEAT_FP64: return 96;
-        case HEAT_FP32: return 96;
-        default: return FP32C_STEPS_PER_ROUND;
-    }
+    if (precision == HEAT_FP32C) return FP32C_STEPS_PER_ROUND;
+    int K, T, wpg;
+    bool pp;
+    tuned_shape(N, precision, &K, &T, &wpg, &pp);
+    return T;
 }
 
 int default_cells_per_lane(int64_t N, int precision) {
-    (void)N;
-    (void)precision;
-    return 32;
+    int K, T, wpg;
+    bool pp;
+    tuned_shape(N, precision, &K, &T, &wpg, &pp);
+    return K;
 }
 
 bool default_pingpong(int64_t N, int precision) {
-    (void)N;
-    return precision == HEAT_FP64;
+    int K, T, wpg;
+    bool pp;
+    tuned_shape(N, precision, &K, &T, &wpg, &pp);
+    return pp;
+}
+
+static int default_waves_per_group(int64_t N, int precision) {
+    int K, T, wpg;
+    bool pp;
+    tuned_shape(N, precision, &K, &T, &wpg, &pp);
+    return wpg;
 }
 
 int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision) {
@@ -114,7 +120,7 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     heat_config c{};
     if (cfg) c = *cfg;
     Plan q;
-    q.wpg = c.waves_per_group ? c.waves_per_group : 2;
+    q.wpg = c.waves_per_group ? c.waves_per_group : default_waves_per_group(N, precision);
     if (q.wpg != 1 && q.wpg != 2 && q.wpg != 4 && q.wpg != 8)
         return fail(HEAT_EINVAL, "waves_per_group must be 1, 2, 4 or 8 (got %d)", q.wpg);
     int kernel = c.kernel ? c.kernel : HEAT_KERNEL_TB;

@@ -1,0 +1,221 @@
+// tune.hip -- the planner's tuning table and the autotuner that fills it.
+//
+// The table maps (precision, ring-length bucket) to the temporal-blocking
+// launch shape: cells per lane K, target steps per round T, wavefronts per
+// workgroup and register form.  None of these change a binary64 or binary32
+// result (the update of every cell is the same whatever the tiling), and the
+// compensated form's round length is fixed outside the table, so tuning is
+// always result-neutral.  The autotuner times every candidate shape with HIP
+// events on a synthetic ring of the requested length and keeps the fastest.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "heat_internal.h"
+
+namespace heat {
+
+namespace {
+
+constexpr int NBUCKETS = 10;   // [10^b, 10^(b+1)) for b = 0..8, and >= 1e9
+
+struct TuneEntry {
+    int K, T, wpg, form;   // form: 1 in-place, 2 ping-pong
+};
+
+struct TuneTable {
+    std::mutex mu;
+    TuneEntry e[3][NBUCKETS];
+    bool env_loaded = false;
+    TuneTable() {
+        for (int p = 0; p < 3; ++p)
+            for (int b = 0; b < NBUCKETS; ++b)
+                // defaults from a sweep on MI355X at N = 1e8 (see default_* in runtime.hip)
+                e[p][b] = TuneEntry{32, p == HEAT_FP32C ? 64 : 96, 2, p == HEAT_FP64 ? 2 : 1};
+    }
+};
+
+TuneTable &table() {
+    static TuneTable t;
+    return t;
+}
+
+int bucket_of(int64_t N) {
+    int b = 0;
+    for (int64_t x = 10; b < NBUCKETS - 1 && N >= x; x *= 10) ++b;
+    return b;
+}
+
+int load_file(const char *path) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(HEAT_EINVAL, "cannot open tuning table %s", path);
+    TuneTable &t = table();
+    char line[256];
+    int n = 0, rc = HEAT_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int p, b, K, T, wpg, form;
+        if (std::sscanf(line, "%d %d %d %d %d %d", &p, &b, &K, &T, &wpg, &form) != 6 || p < 0 ||
+            p > 2 || b < 0 || b >= NBUCKETS || (K != 8 && K != 16 && K != 32) || T < 1 ||
+            (T % 4) || 3 * T > 64 * K || (wpg != 1 && wpg != 2 && wpg != 4 && wpg != 8) ||
+            (form != 1 && form != 2)) {
+            rc = fail(HEAT_EINVAL, "bad tuning table line: %s", line);
+            break;
+        }
+        std::lock_guard<std::mutex> lk(t.mu);
+        t.e[p][b] = TuneEntry{K, T, wpg, form};
+        ++n;
+    }
+    std::fclose(f);
+    return rc;
+}
+
+void load_env_once() {
+    TuneTable &t = table();
+    {
+        std::lock_guard<std::mutex> lk(t.mu);
+        if (t.env_loaded) return;
+        t.env_loaded = true;
+    }
+    const char *path = std::getenv("HEAT_TUNE_TABLE");
+    if (path && *path) (void)load_file(path);
+}
+
+}  // namespace
+
+void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, bool *pingpong) {
+    load_env_once();
+    TuneTable &t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    const TuneEntry &e = t.e[precision][bucket_of(N)];
+    *K = e.K;
+    *T = e.T;
+    *wpg = e.wpg;
+    *pingpong = e.form == 2;
+}
+
+}  // namespace heat
+
+using namespace heat;
+
+// Deterministic synthetic fill (values in [0, 1)); speed does not depend on them.
+__global__ void k_tune_fill(double *a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t x = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+        x ^= x >> 29;
+        a[i] = (double)(x >> 11) * 0x1.0p-53;
+    }
+}
+
+extern "C" {
+
+int heat_tune_load(const char *path) {
+    if (!path) return fail(HEAT_EINVAL, "path is NULL");
+    return load_file(path);
+}
+
+int heat_tune_save(const char *path) {
+    if (!path) return fail(HEAT_EINVAL, "path is NULL");
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(HEAT_EINVAL, "cannot write %s", path);
+    TuneTable &t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    std::fprintf(f, "# precision bucket(log10 N) cells_per_lane steps_per_round waves_per_group "
+                    "register_form\n");
+    for (int p = 0; p < 3; ++p)
+        for (int b = 0; b < NBUCKETS; ++b)
+            std::fprintf(f, "%d %d %d %d %d %d\n", p, b, t.e[p][b].K, t.e[p][b].T, t.e[p][b].wpg,
+                         t.e[p][b].form);
+    std::fclose(f);
+    return HEAT_OK;
+}
+
+int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *best_out,
+                  double *best_gcups) {
+    if (precision != HEAT_FP64 && precision != HEAT_FP32 && precision != HEAT_FP32C)
+        return fail(HEAT_EINVAL, "unknown precision %d", precision);
+    if (N < 1 || N > (int64_t(1) << 34)) return fail(HEAT_EINVAL, "N out of range");
+    int rc = device_pool_setup();
+    if (rc) return rc;
+    hipStream_t st = nullptr;
+    HEAT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    const size_t es = storage_bytes(precision);
+    void *a = nullptr, *w = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (a) (void)hipFreeAsync(a, st);
+        if (w) (void)hipFreeAsync(w, st);
+        (void)hipStreamSynchronize(st);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamDestroy(st);
+    };
+    hipError_t e = hipMallocAsync(&a, (size_t)N * std::max<size_t>(es, 8), st);
+    if (e == hipSuccess) e = hipMallocAsync(&w, (size_t)N * std::max<size_t>(es, 8), st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail_hip(e, "autotune setup");
+    }
+    hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(256), 0, st, (double *)w, N);
+    if (precision == HEAT_FP64)
+        e = hipMemcpyAsync(a, w, (size_t)N * 8, hipMemcpyDeviceToDevice, st);
+    else
+        e = launch_f64_to_f32((const double *)w, (float *)a, N, st);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail_hip(e, "autotune fill");
+    }
+    const int Ts_all[] = {16, 32, 48, 64, 96, 128, 160, 192};
+    double best = -1.0;
+    heat_config bc{};
+    for (int K : {8, 16, 32})
+        for (int form : {1, 2})
+            for (int wpg : {1, 2, 4})
+                for (int T : Ts_all) {
+                    if (precision == HEAT_FP32C && T != default_steps_per_round(N, precision))
+                        continue;
+                    if (3 * T > 64 * K) continue;
+                    heat_config c{HEAT_KERNEL_TB, K, T, wpg, form};
+                    const int64_t nt = 2 * (int64_t)T;
+                    rc = heat_solve_dev_cfg(a, w, N, 1, 0.25, nt, precision, &c, st, nullptr, nullptr);
+                    if (!rc) e = hipEventRecord(e0, st);
+                    if (!rc && e == hipSuccess)
+                        rc = heat_solve_dev_cfg(a, w, N, 1, 0.25, nt, precision, &c, st, nullptr,
+                                                nullptr);
+                    if (!rc && e == hipSuccess) e = hipEventRecord(e1, st);
+                    if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (rc || e != hipSuccess) {
+                        cleanup();
+                        return rc ? rc : fail_hip(e, "autotune timing");
+                    }
+                    const double g = (double)N * (double)nt / (ms * 1e-3) / 1e9;
+                    if (g > best) {
+                        best = g;
+                        bc = c;
+                    }
+                }
+    cleanup();
+    if (install) {
+        TuneTable &t = table();
+        std::lock_guard<std::mutex> lk(t.mu);
+        TuneEntry &en = t.e[precision][bucket_of(N)];
+        en = TuneEntry{bc.cells_per_lane, bc.steps_per_round, bc.waves_per_group, bc.register_form};
+        if (precision == HEAT_FP32C) en.T = default_steps_per_round(N, precision);
+    }
+    if (best_out) *best_out = bc;
+    if (best_gcups) *best_gcups = best;
+    return HEAT_OK;
+}
+
+}  // extern "C"

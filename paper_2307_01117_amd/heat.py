@@ -32,6 +32,7 @@ EXPORTS = [
     "heat_solve_batch", "heat_solve_batch_dev", "heat_server_create", "heat_submit",
     "heat_poll", "heat_wait", "heat_cancel", "heat_server_get_stats", "heat_server_destroy",
     "heat_last_error", "heat_version", "heat_device_info", "heat_copy_dev",
+    "heat_autotune", "heat_tune_save", "heat_tune_load",
 ]
 
 
@@ -112,12 +113,19 @@ def load(path: str = LIB_PATH):
         "heat_device_info": ([P(i32), P(i32), P(i32), P(i32), P(ctypes.c_size_t),
                               P(ctypes.c_size_t)], i32),
         "heat_copy_dev": ([vp, vp, ctypes.c_size_t, vp], i32),
+        "heat_autotune": ([i32, i64, i32, P(heat_config), pd], i32),
+        "heat_tune_save": ([ctypes.c_char_p], i32),
+        "heat_tune_load": ([ctypes.c_char_p], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
     _lib = lib
+    # launch shapes measured on MI355X by `python -m paper_2307_01117_amd.autotune`
+    table = os.path.join(_HERE, "tune_mi355x.txt")
+    if not os.environ.get("HEAT_TUNE_TABLE") and os.path.exists(table):
+        _check(lib.heat_tune_load(os.fsencode(table)))
     return lib
 
 
@@ -145,6 +153,23 @@ def _cfg(kernel=0, cells_per_lane=0, steps_per_round=0, waves_per_group=0, regis
         return None
     return ctypes.byref(heat_config(kernel, cells_per_lane, steps_per_round, waves_per_group,
                                     register_form))
+
+
+def autotune(precision: int, N: int, install: bool = True):
+    """Time every launch shape on an N-cell ring; returns (config dict, GCUP/s)."""
+    cfg = heat_config()
+    g = ctypes.c_double()
+    _check(load().heat_autotune(int(precision), int(N), int(bool(install)), ctypes.byref(cfg),
+                                ctypes.byref(g)))
+    return {f: getattr(cfg, f) for f, _ in heat_config._fields_}, g.value
+
+
+def tune_save(path: str) -> None:
+    _check(load().heat_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str) -> None:
+    _check(load().heat_tune_load(os.fsencode(path)))
 
 
 def version() -> str:

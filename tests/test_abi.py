@@ -108,3 +108,25 @@ def test_planner_rejects_bad_config(lib, cfg):
 def test_step_kernel_rejects_compensated(lib):
     with pytest.raises(heat.HeatError):
         heat.plan(1000, 10, heat.FP32C, kernel=heat.KERNEL_STEP)
+
+
+def test_tuning_table_roundtrip(lib, tmp_path):
+    """The planner follows a loaded tuning table; the compensated form keeps
+    its fixed round length whatever the table says; bad tables are refused."""
+    saved = tmp_path / "orig.txt"
+    heat.tune_save(str(saved))
+    try:
+        f = tmp_path / "t.txt"
+        f.write_text("# p b K T wpg form\n0 6 16 48 4 1\n2 6 8 128 1 2\n")
+        heat.tune_load(str(f))
+        p = heat.plan(5_000_000, 1000, heat.FP64)
+        assert (p["cells_per_lane"], p["waves_per_group"], p["register_form"]) == (16, 4, 1)
+        assert p["steps_per_round"] <= 48
+        c = heat.plan(5_000_000, 1000, heat.FP32C)
+        assert c["cells_per_lane"] == 8 and c["steps_per_round"] == heat.plan(10, 1000, heat.FP32C)["steps_per_round"]
+        bad = tmp_path / "bad.txt"
+        bad.write_text("0 6 12 48 4 1\n")
+        with pytest.raises(heat.HeatError):
+            heat.tune_load(str(bad))
+    finally:
+        heat.tune_load(str(saved))

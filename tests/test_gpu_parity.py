@@ -234,3 +234,19 @@ def test_ring_1e8_perturbed_fp32_forms():
         else:
             want = np.array([oracle.cone_f32(u32, int(i), r, nt) for i in idx])
             assert np.array_equal(got, want)
+
+
+def test_autotuned_shape_is_result_neutral():
+    """The autotuner's pick for a ring length runs and gives the oracle's bits."""
+    N = 100_003
+    cfg, g = heat.autotune(heat.FP64, N, install=False)
+    assert g > 0 and cfg["kernel"] == heat.KERNEL_TB
+    u0 = inputs.uniform_ring(N, 33)
+    got = run_dev(u0, 150, 0.5, **cfg)
+    assert np.array_equal(got, oracle.solve(u0, 0.5, 150))
+    cfg32, _ = heat.autotune(heat.FP32C, 20_000, install=False)
+    u32 = inputs.perturbed_ring(20_000, 34).astype(np.float32)
+    T = heat.plan(20_000, 130, heat.FP32C)["steps_per_round"]
+    assert cfg32["steps_per_round"] == heat.plan(20_000, 10**6, heat.FP32C)["steps_per_round"]
+    got = run_dev(u32, 130, 0.25, precision=heat.FP32C, **cfg32)
+    assert np.array_equal(got, oracle.solve_f32c(u32, 0.25, 130, T))
