@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--warm-s", type=float, default=5.0,
                     help="serve: arrivals before this time are excluded from latency stats")
     ap.add_argument("--batch-mode", default="rounds", choices=["rounds", "graph", "persistent"])
+    ap.add_argument("--no-plain-compare", action="store_true",
+                    help="batch: skip solving the rings one by one for comparison")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="time steps of the full ring the CPU oracle runs as its sample")
     return ap.parse_args()
@@ -247,10 +249,12 @@ def bench_batch(args):
         batch_step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    plain_step()
-    t1 = time.perf_counter()
-    plain_step()
-    plain_s = time.perf_counter() - t1
+    plain_s = float("nan")
+    if not args.no_plain_compare:
+        plain_step()
+        t1 = time.perf_counter()
+        plain_step()
+        plain_s = time.perf_counter() - t1
     value = cups * args.steps / elapsed / 1e9
     print(json.dumps({
         "metric": "GCUP/s (giga cell-updates per second), batched",
