@@ -250,3 +250,24 @@ def test_autotuned_shape_is_result_neutral():
     assert cfg32["steps_per_round"] == heat.plan(20_000, 10**6, heat.FP32C)["steps_per_round"]
     got = run_dev(u32, 130, 0.25, precision=heat.FP32C, **cfg32)
     assert np.array_equal(got, oracle.solve_f32c(u32, 0.25, 130, T))
+
+
+@pytest.mark.parametrize("nparts", [2, 20, 40])
+def test_paper_ramp_workload(nparts):
+    """The paper's benchmark run: 1,000,000 nodes, 1,000 steps, initial
+    condition u(0, x_i) = x_i, the grid cut into 2..40 segments: bit-identical
+    to the oracle for every segment count, conserved sum, bounded by the
+    initial range (maximum principle, r <= 1/2)."""
+    w = inputs.WORKLOADS["paper_ramp_1e6"]
+    u0 = inputs.make_initial(w["init"], w["N"])
+    d = dev(u0)
+    s0, s1 = heat.solve_dev(d, nparts, w["r"], w["nt"], sums=True)
+    got = d.cpu().numpy()
+    if nparts == 2:
+        assert np.array_equal(got, oracle.solve(u0, w["r"], w["nt"]))
+        test_paper_ramp_workload.ref = got
+    else:
+        assert np.array_equal(got, test_paper_ramp_workload.ref)
+    assert abs(s1 - s0) <= 1e-9 * abs(s0)
+    delta = 4 * 2.0 ** -53 * w["nt"] * (w["N"] - 1)
+    assert got.min() >= -delta and got.max() <= w["N"] - 1 + delta
