@@ -71,6 +71,26 @@ def parse():
     return ap.parse_args()
 
 
+def precision_report(heat, torch, u0, d_u, nparts, r, nt, prec, stream, passes):
+    """Error of a binary32 result against the binary64 path (bit-identical to
+    the oracle) over the whole ring, after the same number of passes:
+    max |x - y| / max |y|, against binary64 run from fl32(u0) widened
+    (arithmetic only) and from u0 itself (end to end)."""
+    import numpy as np
+    got = d_u.double()
+    out = {}
+    for label, start in (("vs_fp64_from_fl32_u0", u0.astype(np.float32).astype(np.float64)),
+                         ("vs_fp64_from_u0", u0)):
+        ref = torch.from_numpy(start).to(d_u.device)
+        for _ in range(passes):
+            heat.solve_dev(ref, nparts, r, nt, precision=heat.FP64, stream=stream)
+        torch.cuda.synchronize()
+        out[label] = float((got - ref).abs().max() / ref.abs().max())
+        del ref
+    out["steps"] = passes * nt
+    return out
+
+
 def kernel_source_digest() -> str:
     """sha256 of the kernel sources; HBM traffic taken from counters is only
     reported while the kernels are the ones that were counted."""
@@ -222,6 +242,9 @@ def main():
     roof["avg_launch_ms"] = round(k_avg_ms, 4)
     roof["launches_per_step"] = launches
 
+    err = None
+    if prec != heat.FP64:
+        err = precision_report(heat, torch, u0, d_u, nparts, r, nt, prec, stream, args.steps + args.warmup)
     out = {
         "metric": "GCUP/s (giga cell-updates per second)",
         "value": round(value, 3),
@@ -242,6 +265,8 @@ def main():
                    "waves_per_group": pl["waves_per_group"]},
         "roofline": roof,
     }
+    if err is not None:
+        out["error_vs_fp64"] = err
     del d_u, d_work
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
