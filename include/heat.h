@@ -66,11 +66,14 @@ enum heat_kernel_choice {
 /* Optional overrides for the planner; zero fields mean "choose". */
 typedef struct heat_config {
     int32_t kernel;          /* heat_kernel_choice                              */
-    int32_t cells_per_lane;  /* TB: cells held per lane, one of 8, 16, 32       */
+    int32_t cells_per_lane;  /* TB: cells held per lane, one of 8, 16, 32, 64   */
     int32_t steps_per_round; /* TB: T, a multiple of 4 with 2T < 64*cells - 8   */
     int32_t waves_per_group; /* 1, 2, 4 or 8 wavefronts per workgroup           */
-    int32_t register_form;   /* TB: 1 = in-place update (K state registers),
-                                2 = ping-pong (2K registers, no register copies) */
+    int32_t register_form;   /* TB: 1 = in-place forward sweeps (the compiler
+                                rotates the K registers every step),
+                                2 = ping-pong (2K registers, no copies),
+                                3 = alternating forward/backward in-place sweeps
+                                (K + 1 registers, no copies)                   */
 } heat_config;
 
 /* What the planner picked for a given problem (filled by heat_plan). */
@@ -79,7 +82,7 @@ typedef struct heat_plan_info {
     int32_t cells_per_lane;  /* K (TB)                                          */
     int32_t steps_per_round; /* T: steps per round (1 for STEP)                 */
     int32_t waves_per_group;
-    int32_t register_form;   /* 1 in-place, 2 ping-pong (TB)                     */
+    int32_t register_form;   /* 1 in-place, 2 ping-pong, 3 alternating (TB)      */
     int32_t reserved;
     int64_t tile_cells;      /* W = 64*K - 2T output cells per tile (TB)        */
     int64_t tiles;           /* tiles per round                                 */

@@ -112,6 +112,24 @@ __device__ __forceinline__ void window_step_pp(const T (&a)[K], T (&b)[K], T r) 
     }
 }
 
+// Backward in-place step: the same update swept from the last cell to the
+// first.  A forward step frees the register of cell j-1 when it writes cell
+// j, a backward one frees cell j+1's: alternating them leaves every value
+// where it started after two steps, so the loop needs no register copies and
+// only K + 1 registers (the alternating register form).
+template <int K, class T>
+__device__ __forceinline__ void window_step_bwd(T (&v)[K], T r) {
+    const T left = from_prev(v[K - 1]);
+    T next = from_next(v[0]);
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
+        const T c = v[j];
+        const T l = j > 0 ? v[j - 1] : left;
+        v[j] = cell_update(l, c, next, r);
+        next = c;
+    }
+}
+
 // Compensated binary32 step of the pair (u, e): the Laplacian of u + e is
 // formed from the exact-ish differences of both parts, then added to u with
 // Fast2Sum so that the rounding error of the addition is kept in e.
@@ -133,6 +151,27 @@ __device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], f
         u[j] = t;
         pu = c;
         pe = ec;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void window_step_comp_bwd(float (&u)[K], float (&e)[K], float r) {
+    const float lu = from_prev(u[K - 1]);
+    const float le = from_prev(e[K - 1]);
+    float nu = from_next(u[0]);
+    float ne = from_next(e[0]);
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
+        const float c = u[j], ec = e[j];
+        const float l = j > 0 ? u[j - 1] : lu;
+        const float el = j > 0 ? e[j - 1] : le;
+        const float d = r * (((l - c) + (nu - c)) + ((el - ec) + (ne - ec)));
+        const float y = d + ec;
+        const float t = c + y;
+        e[j] = y - (t - c);
+        u[j] = t;
+        nu = c;
+        ne = ec;
     }
 }
 

@@ -33,7 +33,7 @@ struct Plan {
     int T = 32;          // steps per round
     int H = 32;          // halo cells per side of a window (multiple of 4, >= T)
     int wpg = 4;         // wavefronts per workgroup
-    bool pingpong = true;  // TB register form: ping-pong (true) or in-place
+    int form = 3;        // TB register form: 1 in-place, 2 ping-pong, 3 alternating
     int64_t W = 0;       // output cells per tile (TB) / cells per chunk (STEP)
     int64_t tiles = 0;   // tiles (TB) or chunks (STEP) per launch
     int64_t rounds = 0;  // launches
@@ -52,9 +52,9 @@ int default_cells_per_lane(int64_t N, int precision);
 int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision);
 // Halo depth H >= steps for a window of 64*K cells (line-aligned when possible).
 int halo_cells(int64_t steps, int precision, int K);
-bool default_pingpong(int64_t N, int precision);
+int default_register_form(int64_t N, int precision);
 // Launch shape from the tuning table for a ring of length N.
-void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, bool *pingpong);
+void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form);
 
 // ----------------------------------------------------------- kernels
 
@@ -64,7 +64,7 @@ void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, bool *pingp
 struct WindowLaunch {
     int precision = HEAT_FP64;
     int K = 32;
-    bool pingpong = true;
+    int form = 3;                 // register form: 1 in-place, 2 ping-pong, 3 alternating
     const void *src = nullptr;
     void *dst = nullptr;
     int64_t N = 0;

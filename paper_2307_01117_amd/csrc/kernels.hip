@@ -40,8 +40,16 @@ __device__ __forceinline__ void window_load(const typename P::T *__restrict__ sr
             for (int k = 0; k < VEC; ++k) v[j * VEC + k] = xs[k];
         }
     } else {
+        // Windows that wrap the ring (or overhang a short ring) gather cell by
+        // cell.  Groups of 8 loads are fenced off from each other so the
+        // addresses of the whole window are never live at once: this path is
+        // rare, and its register peak would otherwise set the whole kernel's
+        // occupancy.
 #pragma unroll
-        for (int j = 0; j < K; ++j) v[j] = src[wrap_index(g0 + (int64_t)lane * K + j, N)];
+        for (int j = 0; j < K; ++j) {
+            v[j] = src[wrap_index(g0 + (int64_t)lane * K + j, N)];
+            if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
     }
 }
 
@@ -95,10 +103,13 @@ __device__ __forceinline__ double tile_sum(const T (&v)[K], int lane, int H, int
     return s;
 }
 
+// Register forms of the T-step loop.
+enum RegForm { FORM_INPLACE = 1, FORM_PINGPONG = 2, FORM_ALTERNATING = 3 };
+
 // part_in / part_out (may be NULL): per-tile binary64 sums of the state
 // before and after the round, written at index `tile` -- the conservation
 // checksum fused into the first and last rounds (no extra pass over HBM).
-template <class P, int K, bool PP>
+template <class P, int K, int FORM>
 __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ src,
                                             typename P::T *__restrict__ dst, int64_t N, int H,
                                             int steps, typename P::T r, int64_t b, int64_t W,
@@ -119,12 +130,19 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
         T e[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) e[j] = T(0);
-        if constexpr (PP) {
+        if constexpr (FORM == FORM_PINGPONG) {
             T v2[K], e2[K];
             int s = 0;
             for (; s + 2 <= steps; s += 2) {
                 window_step_comp_pp<K>(v, e, v2, e2, r);
                 window_step_comp_pp<K>(v2, e2, v, e, r);
+            }
+            if (s < steps) window_step_comp<K>(v, e, r);
+        } else if constexpr (FORM == FORM_ALTERNATING) {
+            int s = 0;
+            for (; s + 2 <= steps; s += 2) {
+                window_step_comp<K>(v, e, r);
+                window_step_comp_bwd<K>(v, e, r);
             }
             if (s < steps) window_step_comp<K>(v, e, r);
         } else {
@@ -133,12 +151,19 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
 #pragma unroll
         for (int j = 0; j < K; ++j) v[j] = v[j] + e[j];   // fold: u := fl32(u + e)
     } else {
-        if constexpr (PP) {
+        if constexpr (FORM == FORM_PINGPONG) {
             T v2[K];
             int s = 0;
             for (; s + 2 <= steps; s += 2) {
                 window_step_pp<K>(v, v2, r);
                 window_step_pp<K>(v2, v, r);
+            }
+            if (s < steps) window_step<K>(v, r);
+        } else if constexpr (FORM == FORM_ALTERNATING) {
+            int s = 0;
+            for (; s + 2 <= steps; s += 2) {
+                window_step<K>(v, r);
+                window_step_bwd<K>(v, r);
             }
             if (s < steps) window_step<K>(v, r);
         } else {
@@ -152,7 +177,7 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
     window_store<P, K>(dst, b, H, W, wlen, fast, lane, v);
 }
 
-template <class P, int K, bool PP>
+template <class P, int K, int FORM>
 __global__ void __launch_bounds__(512)
 k_window(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst, int64_t N,
          int32_t H, int32_t steps, double r, int64_t tiles, int32_t vec_ok, double *part_in,
@@ -163,8 +188,8 @@ k_window(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst,
     const int64_t tile = blk * wpg + (threadIdx.x >> 6);
     if (tile >= tiles) return;
     const int64_t W = 64 * K - 2 * (int64_t)H;
-    window_tile<P, K, PP>(src, dst, N, H, steps, (typename P::T)r, tile * W, W, vec_ok != 0, lane,
-                          part_in, part_out, tile);
+    window_tile<P, K, FORM>(src, dst, N, H, steps, (typename P::T)r, tile * W, W, vec_ok != 0,
+                            lane, part_in, part_out, tile);
 }
 
 // ==================================================================== STEP
@@ -417,8 +442,8 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
                 T *dst = reinterpret_cast<T *>(R.buf[(k + 1) & 1]);
                 const int64_t done = k * (int64_t)R.T;
                 const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
-                window_tile<P, K, sizeof(T) == 8>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0,
-                                                  lane);
+                window_tile<P, K, FORM_ALTERNATING>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W,
+                                                    R.vec_ok != 0, lane);
             } else {
                 // copy-back round: the final state sits in buf[1]
                 const T *src = reinterpret_cast<const T *>(R.buf[1]);
@@ -473,7 +498,7 @@ __global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uin
 // the round barrier, so no flags or cross-wave waits are needed.  Item ids
 // are wave-uniform, so the ring lookup runs on the scalar unit.
 
-template <class P, int K, bool PP>
+template <class P, int K, int FORM>
 __global__ void __launch_bounds__(256)
 k_batch_round(const BatchRing *__restrict__ rings, const int64_t *__restrict__ tile_prefix,
               int32_t k, int32_t active, int64_t items) {
@@ -492,7 +517,7 @@ k_batch_round(const BatchRing *__restrict__ rings, const int64_t *__restrict__ t
         T *dst = reinterpret_cast<T *>(R.buf[(kk + 1) & 1]);
         const int64_t done = (int64_t)kk * R.T;
         const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
-        window_tile<P, K, PP>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0, lane);
+        window_tile<P, K, FORM>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0, lane);
     } else {
         // copy-back round: after an odd number of rounds the state sits in buf[1]
         const T *src = reinterpret_cast<const T *>(R.buf[1]);
@@ -506,37 +531,53 @@ k_batch_round(const BatchRing *__restrict__ rings, const int64_t *__restrict__ t
 
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-template <class P, int K, bool PP>
+template <class P, int K, int FORM>
 static hipError_t launch_window_t(const WindowLaunch &a, hipStream_t st) {
     using T = typename P::T;
     const int64_t W = 64 * K - 2 * (int64_t)a.H;
     const int64_t tiles = (a.N + W - 1) / W;
     const int64_t blocks = (tiles + a.wpg - 1) / a.wpg;
     const int vec_ok = aligned16(a.src) && aligned16(a.dst);
-    hipLaunchKernelGGL((k_window<P, K, PP>), dim3((unsigned)blocks), dim3(64 * a.wpg), 0, st,
+    hipLaunchKernelGGL((k_window<P, K, FORM>), dim3((unsigned)blocks), dim3(64 * a.wpg), 0, st,
                        reinterpret_cast<const T *>(a.src), reinterpret_cast<T *>(a.dst), a.N, a.H,
                        a.steps, a.r, tiles, vec_ok, a.part_in, a.part_out);
     return hipGetLastError();
 }
 
-template <class P, bool PP>
+// Shapes that cannot hold their state in registers (they would spill).
+template <class P, int K, int FORM>
+constexpr bool shape_fits() {
+    return !(K == 64 && FORM == FORM_PINGPONG && (sizeof(typename P::T) == 8 || P::COMP));
+}
+
+template <class P, int FORM>
 static hipError_t launch_window_p(const WindowLaunch &a, hipStream_t st) {
     switch (a.K) {
-        case 8: return launch_window_t<P, 8, PP>(a, st);
-        case 16: return launch_window_t<P, 16, PP>(a, st);
-        case 32: return launch_window_t<P, 32, PP>(a, st);
+        case 8: return launch_window_t<P, 8, FORM>(a, st);
+        case 16: return launch_window_t<P, 16, FORM>(a, st);
+        case 32: return launch_window_t<P, 32, FORM>(a, st);
+        case 64:
+            if constexpr (shape_fits<P, 64, FORM>()) return launch_window_t<P, 64, FORM>(a, st);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class P>
+static hipError_t launch_window_f(const WindowLaunch &a, hipStream_t st) {
+    switch (a.form) {
+        case FORM_INPLACE: return launch_window_p<P, FORM_INPLACE>(a, st);
+        case FORM_PINGPONG: return launch_window_p<P, FORM_PINGPONG>(a, st);
+        case FORM_ALTERNATING: return launch_window_p<P, FORM_ALTERNATING>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_window(const WindowLaunch &a, hipStream_t st) {
-    switch (a.precision * 2 + (a.pingpong ? 1 : 0)) {
-        case HEAT_FP64 * 2: return launch_window_p<F64, false>(a, st);
-        case HEAT_FP64 * 2 + 1: return launch_window_p<F64, true>(a, st);
-        case HEAT_FP32 * 2: return launch_window_p<F32, false>(a, st);
-        case HEAT_FP32 * 2 + 1: return launch_window_p<F32, true>(a, st);
-        case HEAT_FP32C * 2: return launch_window_p<F32C, false>(a, st);
-        case HEAT_FP32C * 2 + 1: return launch_window_p<F32C, true>(a, st);
+    switch (a.precision) {
+        case HEAT_FP64: return launch_window_f<F64>(a, st);
+        case HEAT_FP32: return launch_window_f<F32>(a, st);
+        case HEAT_FP32C: return launch_window_f<F32C>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -621,12 +662,12 @@ static hipError_t launch_batch_t(const BatchPlanDev &plan, int grid, int wpg, hi
     return hipGetLastError();
 }
 
-template <class P, int K, bool PP>
+template <class P, int K>
 static hipError_t launch_batch_round_t(const BatchRing *rings, const int64_t *tile_prefix, int k,
                                        int active, int64_t items, int wpg, hipStream_t st) {
     const int64_t blocks = (items + wpg - 1) / wpg;
-    hipLaunchKernelGGL((k_batch_round<P, K, PP>), dim3((unsigned)blocks), dim3(64 * wpg), 0, st,
-                       rings, tile_prefix, k, active, items);
+    hipLaunchKernelGGL((k_batch_round<P, K, FORM_ALTERNATING>), dim3((unsigned)blocks),
+                       dim3(64 * wpg), 0, st, rings, tile_prefix, k, active, items);
     return hipGetLastError();
 }
 
@@ -635,11 +676,11 @@ hipError_t launch_batch_round(int precision, int K, const BatchRing *rings,
                               hipStream_t st) {
     if (items <= 0) return hipSuccess;
     if (precision == HEAT_FP64 && K == 32)
-        return launch_batch_round_t<F64, 32, true>(rings, tile_prefix, k, active, items, wpg, st);
+        return launch_batch_round_t<F64, 32>(rings, tile_prefix, k, active, items, wpg, st);
     if (precision == HEAT_FP32 && K == 32)
-        return launch_batch_round_t<F32, 32, false>(rings, tile_prefix, k, active, items, wpg, st);
+        return launch_batch_round_t<F32, 32>(rings, tile_prefix, k, active, items, wpg, st);
     if (precision == HEAT_FP32C && K == 32)
-        return launch_batch_round_t<F32C, 32, false>(rings, tile_prefix, k, active, items, wpg, st);
+        return launch_batch_round_t<F32C, 32>(rings, tile_prefix, k, active, items, wpg, st);
     return hipErrorInvalidValue;
 }
 

@@ -47,29 +47,29 @@ constexpr int FP32C_STEPS_PER_ROUND = 64;
 int default_steps_per_round(int64_t N, int precision) {
     if (precision == HEAT_FP32C) return FP32C_STEPS_PER_ROUND;
     int K, T, wpg;
-    bool pp;
-    tuned_shape(N, precision, &K, &T, &wpg, &pp);
+    int form;
+    tuned_shape(N, precision, &K, &T, &wpg, &form);
     return T;
 }
 
 int default_cells_per_lane(int64_t N, int precision) {
     int K, T, wpg;
-    bool pp;
-    tuned_shape(N, precision, &K, &T, &wpg, &pp);
+    int form;
+    tuned_shape(N, precision, &K, &T, &wpg, &form);
     return K;
 }
 
-bool default_pingpong(int64_t N, int precision) {
+int default_register_form(int64_t N, int precision) {
     int K, T, wpg;
-    bool pp;
-    tuned_shape(N, precision, &K, &T, &wpg, &pp);
-    return pp;
+    int form;
+    tuned_shape(N, precision, &K, &T, &wpg, &form);
+    return form;
 }
 
 static int default_waves_per_group(int64_t N, int precision) {
     int K, T, wpg;
-    bool pp;
-    tuned_shape(N, precision, &K, &T, &wpg, &pp);
+    int form;
+    tuned_shape(N, precision, &K, &T, &wpg, &form);
     return wpg;
 }
 
@@ -129,9 +129,9 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     if (kernel == HEAT_KERNEL_STEP && precision == HEAT_FP32C)
         return fail(HEAT_EINVAL, "compensated FP32 needs the temporal-blocked kernel");
     q.kernel = kernel;
-    if (c.register_form != 0 && c.register_form != 1 && c.register_form != 2)
-        return fail(HEAT_EINVAL, "register_form must be 1 or 2 (got %d)", c.register_form);
-    q.pingpong = c.register_form ? c.register_form == 2 : default_pingpong(N, precision);
+    if (c.register_form < 0 || c.register_form > 3)
+        return fail(HEAT_EINVAL, "register_form must be 1, 2 or 3 (got %d)", c.register_form);
+    q.form = c.register_form ? c.register_form : default_register_form(N, precision);
     if (kernel == HEAT_KERNEL_STEP) {
         q.K = 0;
         q.T = 1;
@@ -143,8 +143,10 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
         return HEAT_OK;
     }
     q.K = c.cells_per_lane ? c.cells_per_lane : default_cells_per_lane(N, precision);
-    if (q.K != 8 && q.K != 16 && q.K != 32)
-        return fail(HEAT_EINVAL, "cells_per_lane must be 8, 16 or 32 (got %d)", q.K);
+    if (q.K != 8 && q.K != 16 && q.K != 32 && q.K != 64)
+        return fail(HEAT_EINVAL, "cells_per_lane must be 8, 16, 32 or 64 (got %d)", q.K);
+    if (q.K == 64 && q.form == 2 && precision != HEAT_FP32)
+        return fail(HEAT_EINVAL, "the ping-pong form holds at most 32 cells per lane here");
     int T = c.steps_per_round ? c.steps_per_round : default_steps_per_round(N, precision);
     if (T < 1) return fail(HEAT_EINVAL, "steps_per_round must be >= 1 (got %d)", T);
     if (c.steps_per_round && (T % 4) != 0)
@@ -206,7 +208,7 @@ static int run_rounds(const Plan &pl, int precision, void *a, void *b, int64_t N
         WindowLaunch w;
         w.precision = precision;
         w.K = pl.K;
-        w.pingpong = pl.pingpong;
+        w.form = pl.form;
         w.N = N;
         w.H = pl.H;
         w.r = r;
@@ -328,7 +330,7 @@ int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
     out->cells_per_lane = pl.K;
     out->steps_per_round = pl.T;
     out->waves_per_group = pl.wpg;
-    out->register_form = pl.pingpong ? 2 : 1;
+    out->register_form = pl.form;
     out->reserved = 0;
     out->tile_cells = pl.W;
     out->tiles = pl.tiles;

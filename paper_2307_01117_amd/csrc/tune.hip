@@ -26,7 +26,7 @@ namespace {
 constexpr int NBUCKETS = 10;   // [10^b, 10^(b+1)) for b = 0..8, and >= 1e9
 
 struct TuneEntry {
-    int K, T, wpg, form;   // form: 1 in-place, 2 ping-pong
+    int K, T, wpg, form;   // form: 1 in-place, 2 ping-pong, 3 alternating
 };
 
 struct TuneTable {
@@ -37,7 +37,7 @@ struct TuneTable {
         for (int p = 0; p < 3; ++p)
             for (int b = 0; b < NBUCKETS; ++b)
                 // defaults from a sweep on MI355X at N = 1e8 (see default_* in runtime.hip)
-                e[p][b] = TuneEntry{32, p == HEAT_FP32C ? 64 : 96, 2, p == HEAT_FP64 ? 2 : 1};
+                e[p][b] = TuneEntry{32, p == HEAT_FP32C ? 64 : 96, 2, 3};
     }
 };
 
@@ -62,9 +62,10 @@ int load_file(const char *path) {
         if (line[0] == '#' || line[0] == '\n') continue;
         int p, b, K, T, wpg, form;
         if (std::sscanf(line, "%d %d %d %d %d %d", &p, &b, &K, &T, &wpg, &form) != 6 || p < 0 ||
-            p > 2 || b < 0 || b >= NBUCKETS || (K != 8 && K != 16 && K != 32) || T < 1 ||
+            p > 2 || b < 0 || b >= NBUCKETS || (K != 8 && K != 16 && K != 32 && K != 64) || T < 1 ||
             (T % 4) || 3 * T > 64 * K || (wpg != 1 && wpg != 2 && wpg != 4 && wpg != 8) ||
-            (form != 1 && form != 2)) {
+            (K == 64 && form == 2 && p != HEAT_FP32) ||
+            form < 1 || form > 3) {
             rc = fail(HEAT_EINVAL, "bad tuning table line: %s", line);
             break;
         }
@@ -89,7 +90,7 @@ void load_env_once() {
 
 }  // namespace
 
-void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, bool *pingpong) {
+void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form) {
     load_env_once();
     TuneTable &t = table();
     std::lock_guard<std::mutex> lk(t.mu);
@@ -97,7 +98,7 @@ void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, bool *pingp
     *K = e.K;
     *T = e.T;
     *wpg = e.wpg;
-    *pingpong = e.form == 2;
+    *form = e.form;
 }
 
 }  // namespace heat
@@ -174,19 +175,24 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
         cleanup();
         return fail_hip(e, "autotune fill");
     }
-    const int Ts_all[] = {16, 32, 48, 64, 96, 128, 160, 192};
+    const int Ts_all[] = {16, 32, 48, 64, 96, 128, 160, 192, 256, 320};
     double best = -1.0;
     heat_config bc{};
-    for (int K : {8, 16, 32})
-        for (int form : {1, 2})
+    for (int K : {8, 16, 32, 64})
+        for (int form : {1, 2, 3})
             for (int wpg : {1, 2, 4})
                 for (int T : Ts_all) {
                     if (precision == HEAT_FP32C && T != default_steps_per_round(N, precision))
                         continue;
                     if (3 * T > 64 * K) continue;
+                    if (K == 64 && form == 2 && precision != HEAT_FP32) continue;
                     heat_config c{HEAT_KERNEL_TB, K, T, wpg, form};
-                    const int64_t nt = 2 * (int64_t)T;
-                    rc = heat_solve_dev_cfg(a, w, N, 1, 0.25, nt, precision, &c, st, nullptr, nullptr);
+                    // whole rounds, at least 4 and at least 384 steps, so the
+                    // per-launch overheads weigh as they do in real runs
+                    int64_t R = std::max<int64_t>(4, (384 + T - 1) / T);
+                    R += R & 1;   // even: no copy-back in the timed run
+                    const int64_t nt = R * T;
+                    rc = heat_solve_dev_cfg(a, w, N, 1, 0.25, T, precision, &c, st, nullptr, nullptr);
                     if (!rc) e = hipEventRecord(e0, st);
                     if (!rc && e == hipSuccess)
                         rc = heat_solve_dev_cfg(a, w, N, 1, 0.25, nt, precision, &c, st, nullptr,

@@ -48,12 +48,18 @@ def cfgs_fp64():
         dict(kernel=heat.KERNEL_TB, cells_per_lane=16, steps_per_round=32, waves_per_group=8),
         dict(kernel=heat.KERNEL_TB, cells_per_lane=32, steps_per_round=64),
         dict(kernel=heat.KERNEL_TB, cells_per_lane=32, steps_per_round=8, waves_per_group=2),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=32, steps_per_round=96, register_form=3),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=64, steps_per_round=128, register_form=3),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=64, steps_per_round=20, register_form=1,
+             waves_per_group=1),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=16, steps_per_round=12, register_form=3,
+             waves_per_group=8),
     ]
 
 
 # ------------------------------------------------------------ tiny rings
 
-@pytest.mark.parametrize("ci", range(7))
+@pytest.mark.parametrize("ci", range(11))
 def test_tiny_rings_bitwise(ci):
     """Every ring length 1..70 (windows wrap the ring many times), run lengths
     around the round length, several r: bit-identical to the oracle."""
@@ -95,7 +101,10 @@ def test_midsize_fp32_bitwise(N):
     nt, r = 70, 0.25
     want = oracle.solve_f32(u0, r, nt)
     for cfg in (dict(), dict(kernel=heat.KERNEL_STEP), dict(cells_per_lane=8, steps_per_round=20),
-                dict(cells_per_lane=16, steps_per_round=32)):
+                dict(cells_per_lane=16, steps_per_round=32),
+                dict(cells_per_lane=64, steps_per_round=96, register_form=2),
+                dict(cells_per_lane=64, steps_per_round=96, register_form=3),
+                dict(cells_per_lane=32, steps_per_round=36, register_form=3)):
         got = run_dev(u0, nt, r, precision=heat.FP32, **cfg)
         assert np.array_equal(got, want), (cfg, N)
 
@@ -107,9 +116,9 @@ def test_midsize_fp32c_bitwise(N):
     for nt in (7, 100):
         T = heat.plan(N, nt, heat.FP32C)["steps_per_round"]
         want = oracle.solve_f32c(u0, r, nt, T)
-        for K in (8, 16, 32):
-            got = run_dev(u0, nt, r, precision=heat.FP32C, cells_per_lane=K)
-            assert np.array_equal(got, want), (K, N, nt)
+        for K, form in ((8, 1), (16, 2), (32, 3), (64, 3), (64, 1)):
+            got = run_dev(u0, nt, r, precision=heat.FP32C, cells_per_lane=K, register_form=form)
+            assert np.array_equal(got, want), (K, form, N, nt)
 
 
 # ------------------------------------------------------------ invariances on the GPU
