@@ -98,7 +98,7 @@ def kernel_source_digest() -> str:
     reported while the kernels are the ones that were counted."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "heat_device.h"):
+    for f in ("heat_device.h", "window.h", "kernels.hip"):
         with open(os.path.join(ROOT, "paper_2307_01117_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

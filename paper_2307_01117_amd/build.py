@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libheat.so")
-SOURCES = ["kernels.hip", "runtime.hip", "batch.hip", "server.hip", "tune.hip"]
+SOURCES = ["kernels.hip", "batch_kernels.hip", "runtime.hip", "batch.hip", "server.hip", "tune.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

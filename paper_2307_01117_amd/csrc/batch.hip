@@ -17,10 +17,12 @@ namespace heat {
 
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-int batch_cells_per_lane(int precision) { (void)precision; return 32; }
+int batch_cells_per_lane(int precision, int64_t N) {
+    return precision == HEAT_FP64 && N >= 65536 ? 64 : 32;
+}
 
-int describe_ring(const heat_ring &g, BatchRing *out) {
-    const int K = batch_cells_per_lane(g.precision);
+int describe_ring(const heat_ring &g, BatchRing *out, int K) {
+    if (K == 0) K = batch_cells_per_lane(g.precision, g.N);
     const int64_t Teff = planned_steps_per_round(g.N, g.nt, g.precision);
     BatchRing R{};
     R.buf[0] = g.d_u;
@@ -39,6 +41,7 @@ int describe_ring(const heat_ring &g, BatchRing *out) {
     R.vec_ok = aligned16(g.d_u) && aligned16(g.d_work);
     R.flag_base = 0;
     R.round0 = 0;
+    R.K = K;
     *out = R;
     return HEAT_OK;
 }
@@ -50,7 +53,7 @@ static inline int32_t remaining_rounds(const BatchRing &R) {
 
 int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision, int32_t cap) {
     precision_ = precision;
-    K_ = batch_cells_per_lane(precision);
+    K_ = rings_in.empty() ? 32 : rings_in[0].K;
     rings_.clear();
     for (const BatchRing &R : rings_in)
         if (remaining_rounds(R) > 0) rings_.push_back(R);
@@ -211,21 +214,25 @@ int validate_ring(const heat_ring &g) {
 int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
                       std::vector<BatchLaunch> &launches, void **dev_mem_out, int32_t flags) {
     *dev_mem_out = nullptr;
-    std::vector<BatchRing> by_prec[3];
+    // one launch sequence per (precision, K class); the persistent kernel
+    // exists for 32-cell lanes only
+    const bool persistent = (flags & HEAT_BATCH_PERSISTENT) != 0;
+    std::vector<BatchRing> groups[3][2];   // [precision][K == 64]
     for (int32_t i = 0; i < count; ++i) {
         BatchRing R;
-        int rc = describe_ring(rings[i], &R);
+        int rc = describe_ring(rings[i], &R, persistent ? 32 : 0);
         if (rc) return rc;
-        by_prec[rings[i].precision].push_back(R);
+        groups[rings[i].precision][R.K == 64].push_back(R);
     }
     launches.clear();
     size_t total = 0;
-    for (int prec = 0; prec < 3; ++prec) {
-        if (by_prec[prec].empty()) continue;
-        launches.emplace_back();
-        launches.back().build(by_prec[prec], prec);
-        total += launches.back().device_bytes();
-    }
+    for (int prec = 0; prec < 3; ++prec)
+        for (int big = 0; big < 2; ++big) {
+            if (groups[prec][big].empty()) continue;
+            launches.emplace_back();
+            launches.back().build(groups[prec][big], prec);
+            total += launches.back().device_bytes();
+        }
     if (total == 0) return HEAT_OK;
     int rc = device_pool_setup();
     if (rc) return rc;

@@ -11,16 +11,20 @@
 
 namespace heat {
 
-int batch_cells_per_lane(int precision);
+// Cells per lane of the round kernel that runs a ring: long binary64 rings
+// take 64-cell lanes (half the halo overhead), everything else 32.
+int batch_cells_per_lane(int precision, int64_t N);
 int validate_ring(const heat_ring &g);
-// Geometry of one ring in a fused launch (same T as the plain planner).
-int describe_ring(const heat_ring &g, BatchRing *out);
+// Geometry of one ring in a batch (same T rule as the plain planner);
+// K = 0 picks batch_cells_per_lane.
+int describe_ring(const heat_ring &g, BatchRing *out, int K = 0);
 
 class BatchLaunch {
   public:
-    // Sort rings by remaining rounds (longest first), number the work items
-    // round-major.  At most max_rounds rounds are scheduled (0 = all); each
-    // ring starts at its own round0.
+    // Sort rings (all of one precision and one K class) by remaining rounds,
+    // longest first, and number the work items round-major.  At most
+    // max_rounds rounds are scheduled (0 = all); each ring starts at its own
+    // round0.
     int build(const std::vector<BatchRing> &rings, int precision, int32_t max_rounds = 0);
     // Rings as scheduled (sorted), and the number of rounds each one advances.
     const std::vector<BatchRing> &rings() const { return rings_; }

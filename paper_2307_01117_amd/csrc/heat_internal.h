@@ -114,6 +114,8 @@ struct BatchRing {          // one ring of a fused launch (device table entry)
     int64_t nt;
     int32_t vec_ok;         // both buffers 16-byte aligned
     int32_t round0;         // rounds already done before this launch sequence
+    int32_t K;              // cells per lane of the kernel class that runs it
+    int32_t pad;
 };
 
 struct BatchPlanDev {       // device pointers of one fused launch

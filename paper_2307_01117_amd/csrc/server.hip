@@ -119,6 +119,7 @@ static size_t footprint(int64_t N, int precision) {
 }
 
 constexpr int32_t TICK_ROUNDS = 2;     // rounds per tick: bounds the admission delay
+constexpr int TABLE_GROUPS = 6;        // (precision, 32- or 64-cell lanes) round tables per tick
 
 }  // namespace heat
 
@@ -135,7 +136,7 @@ struct heat_server {
     int32_t max_slots = 4096, max_queue = 65536, slots_used = 0;
     hipStream_t compute = nullptr, copy = nullptr;
     double *d_partial = nullptr;
-    // round tables, double-buffered across ticks (3 precision groups each)
+    // round tables, double-buffered across ticks (TABLE_GROUPS groups each)
     size_t table_slot_bytes = 0;
     char *d_tables = nullptr, *h_tables = nullptr;
     hipEvent_t table_ev[2] = {nullptr, nullptr};
@@ -230,19 +231,20 @@ static void copy_loop(heat_server *s) {
 
 // ------------------------------------------------------------ scheduler
 static int run_tick(heat_server *s, std::vector<Req *> &act, uint64_t tick) {
-    // group by precision; every group advances up to TICK_ROUNDS rounds
-    std::vector<BatchRing> groups[3];
-    for (Req *q : act) groups[q->ring.precision].push_back(q->br);
+    // group by precision and kernel class; every group advances up to
+    // TICK_ROUNDS rounds
+    std::vector<BatchRing> groups[TABLE_GROUPS];
+    for (Req *q : act) groups[q->ring.precision * 2 + (q->br.K == 64)].push_back(q->br);
     const int slot = (int)(tick & 1);
     HEAT_HIP(hipEventSynchronize(s->table_ev[slot]));   // the tick that used this slot is done
     char *dt = s->d_tables + slot * s->table_slot_bytes;
     char *ht = s->h_tables + slot * s->table_slot_bytes;
-    const size_t per_group = s->table_slot_bytes / 3;
-    for (int prec = 0; prec < 3; ++prec) {
-        if (groups[prec].empty()) continue;
+    const size_t per_group = s->table_slot_bytes / TABLE_GROUPS;
+    for (int g = 0; g < TABLE_GROUPS; ++g) {
+        if (groups[g].empty()) continue;
         BatchLaunch L;
-        L.build(groups[prec], prec, TICK_ROUNDS);
-        int rc = L.enqueue_rounds(dt + prec * per_group, ht + prec * per_group, s->compute);
+        L.build(groups[g], g / 2, TICK_ROUNDS);
+        int rc = L.enqueue_rounds(dt + g * per_group, ht + g * per_group, s->compute);
         if (rc) return rc;
     }
     HEAT_HIP(hipEventRecord(s->table_ev[slot], s->compute));
@@ -409,7 +411,7 @@ int heat_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t max_q
         return bail(fail_hip(e, "hipMalloc(partials)"));
     const size_t group = Arena::round((size_t)s->max_slots * sizeof(BatchRing)) +
                          Arena::round(((size_t)s->max_slots + 1) * 8);
-    s->table_slot_bytes = 3 * group;
+    s->table_slot_bytes = TABLE_GROUPS * group;
     if ((e = hipMalloc((void **)&s->d_tables, 2 * s->table_slot_bytes)) != hipSuccess)
         return bail(fail_hip(e, "hipMalloc(tables)"));
     if ((e = hipHostMalloc((void **)&s->h_tables, 2 * s->table_slot_bytes, 0)) != hipSuccess)
