@@ -313,7 +313,7 @@ def bench_batch(args):
         batch_step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    plain_s = float("nan")
+    plain_s = None
     if not args.no_plain_compare:
         plain_step()
         t1 = time.perf_counter()
@@ -329,9 +329,9 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": f"batch_{args.batch_count}_rings", "rings": len(specs),
                    "cell_updates": cups, "precision": prec_name, "mode": args.batch_mode},
-        "plain_one_by_one": {"value": round(cups / plain_s / 1e9, 3), "unit": "GCUP/s",
-                             "seconds": round(plain_s, 3)},
-        "batched_vs_plain": round(value / (cups / plain_s / 1e9), 3),
+        "plain_one_by_one": None if plain_s is None else {
+            "value": round(cups / plain_s / 1e9, 3), "unit": "GCUP/s", "seconds": round(plain_s, 3)},
+        "batched_vs_plain": None if plain_s is None else round(value / (cups / plain_s / 1e9), 3),
     }), flush=True)
 
 
