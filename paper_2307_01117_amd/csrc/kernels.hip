@@ -165,7 +165,19 @@ __global__ void __launch_bounds__(256) k_sum_partial(const T *__restrict__ u, in
 __global__ void __launch_bounds__(256) k_sum_final(const double *__restrict__ partial, int64_t G,
                                                    double *__restrict__ out) {
     double s = 0.0, c = 0.0;
-    for (int64_t i = threadIdx.x; i < G; i += 256) neumaier_add(s, c, partial[i]);
+    // thread t adds partial[t], partial[t + 256], ... in that order; the loads
+    // of 8 consecutive terms are issued together so their latencies overlap
+    for (int64_t base = threadIdx.x; base < G; base += 8 * 256) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = base + u * 256;
+            x[u] = i < G ? partial[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (base + u * 256 < G) neumaier_add(s, c, x[u]);
+    }
     const double tot = block_tree_sum(s + c);
     if (threadIdx.x == 0) out[0] = tot;
 }

@@ -106,7 +106,6 @@ struct Req {
     std::string msg;                   // error text, kept for the thread that polls
     bool holds = false;                // owns an arena block and a slot
     bool cancel = false;
-    uint64_t last_tick = 0;            // last tick that launched work for it
     hipEvent_t fin = nullptr;          // compute stream passed its final kernels
     Clock::time_point t_submit;
 };
@@ -140,7 +139,6 @@ struct heat_server {
     size_t table_slot_bytes = 0;
     char *d_tables = nullptr, *h_tables = nullptr;
     hipEvent_t table_ev[2] = {nullptr, nullptr};
-    hipEvent_t tick_ev = nullptr;
     uint64_t tick = 0, next_ticket = 1;
     bool stop = false;
     int fatal = HEAT_OK;
@@ -335,7 +333,6 @@ static void sched_loop(heat_server *s) {
         for (Req *q : act) {
             const int32_t remaining = q->br.rounds + q->br.copy_round - q->br.round0;
             q->br.round0 += std::min<int32_t>(remaining, TICK_ROUNDS);
-            q->last_tick = tick;
             if (q->br.round0 >= q->br.rounds + q->br.copy_round) finished.push_back(q);
         }
         for (Req *q : finished) {

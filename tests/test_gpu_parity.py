@@ -280,3 +280,54 @@ def test_paper_ramp_workload(nparts):
     assert abs(s1 - s0) <= 1e-9 * abs(s0)
     delta = 4 * 2.0 ** -53 * w["nt"] * (w["N"] - 1)
     assert got.min() >= -delta and got.max() <= w["N"] - 1 + delta
+
+
+def test_unaligned_device_array_takes_gather_path():
+    """A device array that is not 16-byte aligned (a view one cell in) runs
+    every tile through the cell-by-cell path: same bits."""
+    N = 70_001
+    u0 = inputs.uniform_ring(N, 35)
+    base = torch.zeros(N + 1, dtype=torch.float64, device="cuda")
+    base[1:] = torch.from_numpy(u0).cuda()
+    view = base[1:]
+    assert view.data_ptr() % 16 != 0
+    heat.solve_dev(view, 1, 0.5, 90)
+    assert np.array_equal(view.cpu().numpy(), oracle.solve(u0, 0.5, 90))
+    v32 = torch.zeros(N + 1, dtype=torch.float32, device="cuda")
+    u32 = u0.astype(np.float32)
+    v32[1:] = torch.from_numpy(u32).cuda()
+    heat.solve_dev(v32[1:], 1, 0.25, 70, precision=heat.FP32C)
+    T = heat.plan(N, 70, heat.FP32C)["steps_per_round"]
+    assert np.array_equal(v32[1:].cpu().numpy(), oracle.solve_f32c(u32, 0.25, 70, T))
+
+
+def test_ring_beyond_2_pow_31_cells():
+    """Largest size class: 2^31 + 12,345 binary32 cells (64-bit tile and cell
+    indices everywhere), a few steps; sampled cells against light cones of
+    the initial state (drawn with torch on the device, copied out before the
+    solve)."""
+    N = (1 << 31) + 12_345
+    g = torch.Generator(device="cuda").manual_seed(36)
+    d = torch.rand(N, generator=g, device="cuda", dtype=torch.float32)
+    nt, r = 6, 0.25
+    rng = np.random.default_rng(37)
+    idx = sorted({0, 1, N - 1, N - 2, (1 << 31) - 1, 1 << 31, (1 << 31) + 1} |
+                 {int(x) for x in rng.integers(0, N, 16)})
+    wins = {}
+    for i in idx:
+        w = torch.arange(i - nt, i + nt + 1, device="cuda") % N
+        wins[i] = d[w].cpu().numpy()
+    heat.solve_dev(d, 1, r, nt, precision=heat.FP32)
+    for i in idx:
+        want = oracle.cone_f32(wins[i], nt, r, nt)
+        assert d[i].item() == want, i
+
+
+def test_copy_probe_and_device_info():
+    info = heat.device_info()
+    assert info["wave_size"] == 64 and info["cus"] >= 1
+    a = torch.rand(1 << 20, device="cuda", dtype=torch.float64)
+    b = torch.empty_like(a)
+    heat.copy_dev(a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
