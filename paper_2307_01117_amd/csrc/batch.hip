@@ -23,7 +23,15 @@ int batch_cells_per_lane(int precision, int64_t N) {
 
 int describe_ring(const heat_ring &g, BatchRing *out, int K) {
     if (K == 0) K = batch_cells_per_lane(g.precision, g.N);
-    const int64_t Teff = planned_steps_per_round(g.N, g.nt, g.precision);
+    int64_t Teff = planned_steps_per_round(g.N, g.nt, g.precision);
+    // a tuning table made for wider lanes may ask for rounds deeper than this
+    // kernel class's window allows; binary64/binary32 results do not depend
+    // on the round length, and the compensated form's fixed length always fits
+    const int64_t Tmax = (64 * (int64_t)K / 3) & ~int64_t(3);
+    if (Teff > Tmax) {
+        const int64_t R = (g.nt + Tmax - 1) / Tmax;
+        Teff = (g.nt + R - 1) / R;
+    }
     BatchRing R{};
     R.buf[0] = g.d_u;
     R.buf[1] = g.d_work;
@@ -36,6 +44,7 @@ int describe_ring(const heat_ring &g, BatchRing *out, int K) {
     R.nt = g.nt;
     const int64_t rounds = g.nt > 0 ? (g.nt + Teff - 1) / Teff : 0;
     if (rounds > (int64_t)1 << 30) return fail(HEAT_EINVAL, "too many rounds");
+    if (R.tiles * 64 > MAX_GRID_THREADS) return fail(HEAT_EINVAL, "ring too long for one launch");
     R.rounds = (int32_t)rounds;
     R.copy_round = (int32_t)(rounds & 1);
     R.vec_ok = aligned16(g.d_u) && aligned16(g.d_work);
@@ -82,6 +91,8 @@ int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision, in
         round_start_[k + 1] = round_start_[k] + tile_prefix_[alive];
     }
     total_items_ = max_rounds_ ? round_start_[max_rounds_] : 0;
+    if (tile_prefix_[n] * 64 > MAX_GRID_THREADS)
+        return fail(HEAT_EINVAL, "batch has more tiles than one launch can hold");
     return HEAT_OK;
 }
 
@@ -230,7 +241,8 @@ int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
         for (int big = 0; big < 2; ++big) {
             if (groups[prec][big].empty()) continue;
             launches.emplace_back();
-            launches.back().build(groups[prec][big], prec);
+            int rc = launches.back().build(groups[prec][big], prec);
+            if (rc) return rc;
             total += launches.back().device_bytes();
         }
     if (total == 0) return HEAT_OK;

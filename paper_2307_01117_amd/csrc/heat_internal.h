@@ -25,6 +25,10 @@ int fail_hip(hipError_t e, const char *what);
 
 inline size_t storage_bytes(int precision) { return precision == HEAT_FP64 ? 8 : 4; }
 
+// A launch's grid counts work-items in 32 bits: one wavefront per tile must
+// stay below this many threads.
+constexpr int64_t MAX_GRID_THREADS = (int64_t(1) << 32) - 256;
+
 // ----------------------------------------------------------- planning
 
 struct Plan {

@@ -139,6 +139,8 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
         q.W = step_chunk_cells(precision);
         q.tiles = (N + q.W - 1) / q.W;
         q.rounds = nt;
+        if (q.tiles * 64 > MAX_GRID_THREADS)
+            return fail(HEAT_EINVAL, "ring of %lld cells is too long for one launch", (long long)N);
         *p = q;
         return HEAT_OK;
     }
@@ -161,6 +163,9 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     q.W = 64 * (int64_t)q.K - 2 * (int64_t)q.H;
     q.tiles = (N + q.W - 1) / q.W;
     q.rounds = nt > 0 ? (nt + Teff - 1) / Teff : 0;
+    if (q.tiles * 64 > MAX_GRID_THREADS)
+        return fail(HEAT_EINVAL, "ring of %lld cells needs more than one launch's tiles at %d cells "
+                    "per lane", (long long)N, q.K);
     *p = q;
     return HEAT_OK;
 }

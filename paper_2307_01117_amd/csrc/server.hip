@@ -241,8 +241,8 @@ static int run_tick(heat_server *s, std::vector<Req *> &act, uint64_t tick) {
     for (int g = 0; g < TABLE_GROUPS; ++g) {
         if (groups[g].empty()) continue;
         BatchLaunch L;
-        L.build(groups[g], g / 2, TICK_ROUNDS);
-        int rc = L.enqueue_rounds(dt + g * per_group, ht + g * per_group, s->compute);
+        int rc = L.build(groups[g], g / 2, TICK_ROUNDS);
+        if (!rc) rc = L.enqueue_rounds(dt + g * per_group, ht + g * per_group, s->compute);
         if (rc) return rc;
     }
     HEAT_HIP(hipEventRecord(s->table_ev[slot], s->compute));
