@@ -18,13 +18,13 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
-#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
+#include "arena.h"
 #include "heat_batch.h"
 #include "heat_internal.h"
 
@@ -33,63 +33,29 @@ namespace heat {
 using Clock = std::chrono::steady_clock;
 
 // ------------------------------------------------------------------ arena
-// One device allocation carved first-fit; host-side bookkeeping only.
+// One device allocation; offsets are handed out by ArenaBook (arena.h).
 class Arena {
   public:
     int init(size_t bytes) {
         HEAT_HIP(hipMalloc(&base_, bytes));
-        cap_ = bytes;
-        free_.clear();
-        free_[0] = bytes;
-        used_ = peak_ = 0;
+        book_.reset(bytes);
         return HEAT_OK;
     }
     void destroy() {
         if (base_) (void)hipFree(base_);
         base_ = nullptr;
     }
-    bool alloc(size_t bytes, size_t *off) {
-        bytes = round(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            const size_t rest = it->second - bytes;
-            const size_t at = it->first + bytes;
-            free_.erase(it);
-            if (rest) free_[at] = rest;
-            used_ += bytes;
-            peak_ = std::max(peak_, used_);
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = round(bytes);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+    bool alloc(size_t bytes, size_t *off) { return book_.alloc(bytes, off); }
+    void release(size_t off, size_t bytes) { book_.release(off, bytes); }
+    static size_t round(size_t b) { return ArenaBook::round(b); }
     char *base() const { return (char *)base_; }
-    size_t cap() const { return cap_; }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
+    size_t cap() const { return book_.cap(); }
+    size_t used() const { return book_.used(); }
+    size_t peak() const { return book_.peak(); }
 
   private:
     void *base_ = nullptr;
-    size_t cap_ = 0, used_ = 0, peak_ = 0;
-    std::map<size_t, size_t> free_;   // offset -> size, coalesced
+    ArenaBook book_;
 };
 
 enum ReqState { QUEUED, STAGING, READY, ACTIVE, DRAINING, DONE, FAILED, CANCELLED };
