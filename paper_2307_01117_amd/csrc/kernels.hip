@@ -37,13 +37,13 @@ k_window(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst,
 }
 
 // ==================================================================== STEP
-// One step per launch.  Wave chunk = U vectors of 16 bytes per lane, laid out
-// so that every load instruction is fully coalesced: vector u of lane L holds
-// cells base + u*64*VEC + L*VEC + [0, VEC).  Neighbours inside the chunk come
-// from the adjacent lanes (DPP); the two cells just outside the chunk are
-// read by lanes 0 and 63.
-
-constexpr int STEP_U = 4;
+// One step per launch.  A wave owns a chunk of 64 vectors of 16 bytes, one
+// per lane, so the load and the store are each one fully coalesced
+// instruction: lane L holds cells base + L*VEC + [0, VEC).  Neighbours inside
+// the chunk come from the adjacent lanes (DPP); the two cells just outside it
+// are read by lanes 0 and 63.  Every cell is read once and written once, so
+// both accesses are marked streaming (non-temporal): measured on MI355X this
+// lifts a plain copy from about 5.8 to 6.5 TB/s.
 
 template <class P>
 __global__ void __launch_bounds__(512)
@@ -52,8 +52,7 @@ k_step(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst, i
     using T = typename P::T;
     using VT = typename Vec16<T>::type;
     constexpr int VEC = P::VEC;
-    constexpr int U = STEP_U;
-    constexpr int64_t CH = 64 * VEC * U;
+    constexpr int64_t CH = 64 * VEC;
     const int lane = threadIdx.x & 63;
     const int wpg = blockDim.x >> 6;
     const int64_t chunk = xcd_remap(blockIdx.x, gridDim.x) * wpg + (threadIdx.x >> 6);
@@ -61,48 +60,33 @@ k_step(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst, i
     const T r = (T)r_in;
     const int64_t base = chunk * CH;
     if (vec_ok && base + CH <= N) {
-        T c[U][VEC];
+        const VT x = load_stream(reinterpret_cast<const VT *>(src + base + lane * VEC));
+        T c[VEC];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            VT x = *reinterpret_cast<const VT *>(src + base + u * 64 * VEC + lane * VEC);
-            const T *xs = reinterpret_cast<const T *>(&x);
-#pragma unroll
-            for (int k = 0; k < VEC; ++k) c[u][k] = xs[k];
-        }
+        for (int k = 0; k < VEC; ++k) c[k] = x[k];
         T edge = T(0);
         if (lane == 0) edge = src[base == 0 ? N - 1 : base - 1];
         if (lane == 63) edge = src[base + CH == N ? 0 : base + CH];
-        T prev_last[U], next_first[U];
+        const T prev_last = from_prev(c[VEC - 1]);
+        const T next_first = from_next(c[0]);
+        const T left = lane == 0 ? edge : prev_last;
+        const T right = lane == 63 ? edge : next_first;
+        VT y;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            prev_last[u] = from_prev(c[u][VEC - 1]);
-            next_first[u] = from_next(c[u][0]);
+        for (int k = 0; k < VEC; ++k) {
+            const T l = k == 0 ? left : c[k - 1];
+            const T q = k == VEC - 1 ? right : c[k + 1];
+            y[k] = cell_update(l, c[k], q, r);
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const T left = lane == 0 ? (u == 0 ? edge : prev_last[u - 1]) : prev_last[u];
-            const T right = lane == 63 ? (u == U - 1 ? edge : next_first[u + 1]) : next_first[u];
-            VT y;
-            T *ys = reinterpret_cast<T *>(&y);
-#pragma unroll
-            for (int k = 0; k < VEC; ++k) {
-                const T l = k == 0 ? left : c[u][k - 1];
-                const T q = k == VEC - 1 ? right : c[u][k + 1];
-                ys[k] = cell_update(l, c[u][k], q, r);
-            }
-            *reinterpret_cast<VT *>(dst + base + u * 64 * VEC + lane * VEC) = y;
-        }
+        store_stream(y, reinterpret_cast<VT *>(dst + base + lane * VEC));
     } else {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int k = 0; k < VEC; ++k) {
-                const int64_t i = base + u * 64 * VEC + lane * VEC + k;
-                if (i < N) {
-                    const T l = src[i == 0 ? N - 1 : i - 1];
-                    const T q = src[i == N - 1 ? 0 : i + 1];
-                    dst[i] = cell_update(l, src[i], q, r);
-                }
+        for (int k = 0; k < VEC; ++k) {
+            const int64_t i = base + lane * VEC + k;
+            if (i < N) {
+                const T l = src[i == 0 ? N - 1 : i - 1];
+                const T q = src[i == N - 1 ? 0 : i + 1];
+                dst[i] = cell_update(l, src[i], q, r);
             }
         }
     }
@@ -203,26 +187,14 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
 }
 
 // ==================================================================== COPY
-// Bandwidth probe: every wave moves U 16-byte vectors per lane, coalesced,
-// exactly like the fast path of k_step without the arithmetic.
+// Bandwidth probe: every lane moves one 16-byte vector, coalesced and
+// streaming, exactly like the fast path of k_step without the arithmetic.
 
-__global__ void __launch_bounds__(256) k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+__global__ void __launch_bounds__(256) k_copy(const v4u32 *__restrict__ src, v4u32 *__restrict__ dst,
                                               int64_t nvec) {
-    constexpr int U = STEP_U;
-    const int lane = threadIdx.x & 63;
-    const int64_t chunk = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int64_t base = chunk * 64 * U;
-    uint4 x[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t i = base + u * 64 + lane;
-        if (i < nvec) x[u] = src[i];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t i = base + u * 64 + lane;
-        if (i < nvec) dst[i] = x[u];
-    }
+    const int64_t i = (xcd_remap(blockIdx.x, gridDim.x) * (int64_t)(blockDim.x >> 6) +
+                       (threadIdx.x >> 6)) * 64 + (threadIdx.x & 63);
+    if (i < nvec) store_stream(load_stream(src + i), dst + i);
 }
 
 // ================================================================ LAUNCHERS
@@ -286,7 +258,7 @@ hipError_t launch_sum_partials(const double *partial, int64_t n, double *d_out, 
 }
 
 int64_t step_chunk_cells(int precision) {
-    return 64 * STEP_U * (precision == HEAT_FP64 ? F64::VEC : F32::VEC);
+    return 64 * (precision == HEAT_FP64 ? F64::VEC : F32::VEC);
 }
 
 hipError_t launch_step(int precision, const void *src, void *dst, int64_t N, double r, int wpg,
@@ -342,10 +314,10 @@ hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st) {
     const int64_t nvec = (int64_t)(bytes / 16);
-    const int64_t chunks = (nvec + 64 * STEP_U - 1) / (64 * STEP_U);
+    const int64_t chunks = (nvec + 63) / 64;
     const int64_t blocks = (chunks + 3) / 4;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st,
-                       reinterpret_cast<const uint4 *>(src), reinterpret_cast<uint4 *>(dst), nvec);
+                       reinterpret_cast<const v4u32 *>(src), reinterpret_cast<v4u32 *>(dst), nvec);
     return hipGetLastError();
 }
 
