@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--cells-per-lane", type=int, default=0)
     ap.add_argument("--steps-per-round", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
+    ap.add_argument("--register-form", type=int, default=0, choices=[0, 1, 2, 3])
+    ap.add_argument("--exchange", default="auto", choices=["auto", "none", "lds"],
+                    help="waves of a workgroup: own tiles (none) or one shared tile with "
+                         "LDS edge exchanges (lds)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time the library's plain streaming copy of the state instead "
@@ -98,7 +102,7 @@ def kernel_source_digest() -> str:
     reported while the kernels are the ones that were counted."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("heat_device.h", "window.h", "kernels.hip"):
+    for f in ("heat_device.h", "window.h", "round.h", "kernels.hip", "kernels_xchg.hip"):
         with open(os.path.join(ROOT, "paper_2307_01117_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -117,6 +121,8 @@ def measured_traffic(kernel, workload, precision, pl):
     if t.get("kernel_source_sha256") != kernel_source_digest():
         return None
     key = f"{kernel}/{workload}/{precision}/K{pl['cells_per_lane']}/T{pl['steps_per_round']}"
+    if pl.get("exchange_steps"):
+        key += f"/G{pl['waves_per_group']}S{pl['exchange_steps']}"
     e = t.get("entries", {}).get(key)
     return None if e is None else e["bytes_per_launch"]
 
@@ -159,8 +165,10 @@ def main():
     prec_name = args.precision or ("fp64" if args.workload != "ring_1e8_perturbed" else "fp32c")
     prec = heat.PRECISIONS[prec_name]
     kernel = {"auto": 0, "tb": heat.KERNEL_TB, "step": heat.KERNEL_STEP}[args.kernel]
+    exchange = {"auto": 0, "none": heat.EXCHANGE_NONE, "lds": heat.EXCHANGE_LDS}[args.exchange]
     cfg = dict(kernel=kernel, cells_per_lane=args.cells_per_lane,
-               steps_per_round=args.steps_per_round, waves_per_group=args.waves_per_group)
+               steps_per_round=args.steps_per_round, waves_per_group=args.waves_per_group,
+               register_form=args.register_form, exchange=exchange)
     N, nparts, r, nt = w["N"], w["nparts"], w["r"], w["nt"]
     pl = heat.plan(N, nt, prec, **cfg)
 
@@ -266,7 +274,9 @@ def main():
                    "init": w["init"], "seed": w["seed"], "precision": prec_name,
                    "kernel": roof["kernel"], "cells_per_lane": pl["cells_per_lane"],
                    "steps_per_round": pl["steps_per_round"],
-                   "waves_per_group": pl["waves_per_group"]},
+                   "waves_per_group": pl["waves_per_group"],
+                   "register_form": pl["register_form"],
+                   "exchange_steps": pl["exchange_steps"]},
         "roofline": roof,
     }
     if err is not None:

@@ -63,6 +63,19 @@ enum heat_kernel_choice {
     HEAT_KERNEL_TB = 2    /* temporal blocking: T steps per round in registers  */
 };
 
+/* How the waves of a workgroup share the work of a round (TB). */
+enum heat_exchange {
+    HEAT_EXCHANGE_AUTO = 0, /* planner decides (tuned table)                      */
+    HEAT_EXCHANGE_NONE = 1, /* one tile per wavefront; windows overlap by the
+                               halo only                                          */
+    HEAT_EXCHANGE_LDS = 2   /* one tile per workgroup: its waves hold adjacent
+                               windows that overlap by S = cells_per_lane / 4
+                               cells and swap S edge cells through LDS every S
+                               steps (a deep ghost-zone exchange between
+                               segments, Section 2); needs waves_per_group >= 2
+                               and cells_per_lane >= 16                         */
+};
+
 /* Optional overrides for the planner; zero fields mean "choose". */
 typedef struct heat_config {
     int32_t kernel;          /* heat_kernel_choice                              */
@@ -74,6 +87,7 @@ typedef struct heat_config {
                                 2 = ping-pong (2K registers, no copies),
                                 3 = alternating forward/backward in-place sweeps
                                 (K + 1 registers, no copies)                   */
+    int32_t exchange;        /* TB: heat_exchange                               */
 } heat_config;
 
 /* What the planner picked for a given problem (filled by heat_plan). */
@@ -83,8 +97,11 @@ typedef struct heat_plan_info {
     int32_t steps_per_round; /* T: steps per round (1 for STEP)                 */
     int32_t waves_per_group;
     int32_t register_form;   /* 1 in-place, 2 ping-pong, 3 alternating (TB)      */
-    int32_t reserved;
-    int64_t tile_cells;      /* W = 64*K - 2T output cells per tile (TB)        */
+    int32_t exchange_steps;  /* S: steps between LDS edge exchanges of the
+                                waves of a tile; 0 = one tile per wave (TB)    */
+    int64_t tile_cells;      /* W: output cells per tile (TB): 64*K - 2H for a
+                                lone wave, G*64*K - (G-1)*2S - 2H for G waves,
+                                H >= T the halo                                 */
     int64_t tiles;           /* tiles per round                                 */
     int64_t rounds;          /* launches (STEP: nt, TB: ceil(nt / T))           */
 } heat_plan_info;

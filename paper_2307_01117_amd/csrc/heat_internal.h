@@ -38,8 +38,10 @@ struct Plan {
     int H = 32;          // halo cells per side of a window (multiple of 4, >= T)
     int wpg = 4;         // wavefronts per workgroup
     int form = 3;        // TB register form: 1 in-place, 2 ping-pong, 3 alternating
+    bool xchg = false;   // TB: the workgroup's waves share a tile (LDS edge exchange)
     int64_t W = 0;       // output cells per tile (TB) / cells per chunk (STEP)
     int64_t tiles = 0;   // tiles (TB) or chunks (STEP) per launch
+    int64_t parts = 0;   // per-wave partial sums of a fused checksum (TB)
     int64_t rounds = 0;  // launches
 };
 
@@ -58,13 +60,13 @@ int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision);
 int halo_cells(int64_t steps, int precision, int K);
 int default_register_form(int64_t N, int precision);
 // Launch shape from the tuning table for a ring of length N.
-void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form);
+void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form, int *exchange);
 
 // ----------------------------------------------------------- kernels
 
 // One round of the temporal-blocked window kernel: every tile loads 64*K
-// cells starting H cells left of its output, advances `steps` (<= H) steps
-// in registers and writes its W = 64*K - 2H output cells.
+// cells per wave starting H cells left of its output, advances `steps`
+// (<= H) steps in registers and writes its W output cells (window_tile_cells).
 struct WindowLaunch {
     int precision = HEAT_FP64;
     int K = 32;
@@ -76,10 +78,16 @@ struct WindowLaunch {
     int steps = 0;
     double r = 0.0;
     int wpg = 2;
-    double *part_in = nullptr;    // per-tile sums of the input (first round), or NULL
-    double *part_out = nullptr;   // per-tile sums of the output (last round), or NULL
+    bool xchg = false;            // the wpg waves of a workgroup share one tile
+    double *part_in = nullptr;    // per-wave sums of the input (first round), or NULL
+    double *part_out = nullptr;   // per-wave sums of the output (last round), or NULL
 };
 hipError_t launch_window(const WindowLaunch &a, hipStream_t st);
+hipError_t launch_window_lone(const WindowLaunch &a, hipStream_t st);   // kernels.hip
+hipError_t launch_window_xchg(const WindowLaunch &a, hipStream_t st);   // kernels_xchg.hip
+// Output cells of one tile: 64K - 2H for a lone wave; for wpg cooperating
+// waves, wpg windows of 64K cells overlapping by 2*(K/4), minus 2H.
+int64_t window_tile_cells(int K, int H, int wpg, bool xchg);
 // Sum n per-tile partials (fixed order) into d_out[0].
 hipError_t launch_sum_partials(const double *partial, int64_t n, double *d_out, hipStream_t st);
 

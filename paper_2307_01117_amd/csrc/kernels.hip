@@ -4,8 +4,10 @@
 // Operation: the explicit-Euler step of the paper's Eq. (heat:discrete) on a
 // periodic ring (Section 2), applied nt times with a Jacobi double buffer.
 // The paper's per-step ghost-zone exchange between segments (Section 2, last
-// paragraph) appears here at three levels:
+// paragraph) appears here at four levels:
 //   * between lanes of a wavefront: DPP rotates (no memory traffic);
+//   * between the waves of a workgroup that share a tile: edge cells
+//     swapped through LDS every K/4 steps (round.h, window.h);
 //   * between tiles of one round: overlapping windows read from HBM;
 //   * between rounds: the kernel boundary (plain form) or per-tile epoch
 //     counters (fused batch form).
@@ -13,28 +15,10 @@
 
 #include "heat_device.h"
 #include "heat_internal.h"
+#include "round.h"
 #include "window.h"
 
 namespace heat {
-
-// ================================================================ ROUNDS
-// One round of the temporal-blocked stencil: one wavefront per tile
-// (window_tile in window.h), tiles mapped XCD-contiguously.
-
-template <class P, int K, int FORM>
-__global__ void __launch_bounds__(512)
-k_window(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst, int64_t N,
-         int32_t H, int32_t steps, double r, int64_t tiles, int32_t vec_ok, double *part_in,
-         double *part_out) {
-    const int lane = threadIdx.x & 63;
-    const int wpg = blockDim.x >> 6;
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t tile = blk * wpg + (threadIdx.x >> 6);
-    if (tile >= tiles) return;
-    const int64_t W = 64 * K - 2 * (int64_t)H;
-    window_tile<P, K, FORM>(src, dst, N, H, steps, (typename P::T)r, tile * W, W, vec_ok != 0,
-                            lane, part_in, part_out, tile);
-}
 
 // ==================================================================== STEP
 // One step per launch.  A wave owns a chunk of 64 vectors of 16 bytes, one
@@ -199,57 +183,19 @@ __global__ void __launch_bounds__(256) k_copy(const v4u32 *__restrict__ src, v4u
 
 // ================================================================ LAUNCHERS
 
-static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-template <class P, int K, int FORM>
-static hipError_t launch_window_t(const WindowLaunch &a, hipStream_t st) {
-    using T = typename P::T;
-    const int64_t W = 64 * K - 2 * (int64_t)a.H;
-    const int64_t tiles = (a.N + W - 1) / W;
-    const int64_t blocks = (tiles + a.wpg - 1) / a.wpg;
-    const int vec_ok = aligned16(a.src) && aligned16(a.dst);
-    hipLaunchKernelGGL((k_window<P, K, FORM>), dim3((unsigned)blocks), dim3(64 * a.wpg), 0, st,
-                       reinterpret_cast<const T *>(a.src), reinterpret_cast<T *>(a.dst), a.N, a.H,
-                       a.steps, a.r, tiles, vec_ok, a.part_in, a.part_out);
-    return hipGetLastError();
-}
-
-// Shapes that cannot hold their state in registers (they would spill).
-template <class P, int K, int FORM>
-constexpr bool shape_fits() {
-    return !(K == 64 && FORM == FORM_PINGPONG && (sizeof(typename P::T) == 8 || P::COMP));
-}
-
-template <class P, int FORM>
-static hipError_t launch_window_p(const WindowLaunch &a, hipStream_t st) {
-    switch (a.K) {
-        case 8: return launch_window_t<P, 8, FORM>(a, st);
-        case 16: return launch_window_t<P, 16, FORM>(a, st);
-        case 32: return launch_window_t<P, 32, FORM>(a, st);
-        case 64:
-            if constexpr (shape_fits<P, 64, FORM>()) return launch_window_t<P, 64, FORM>(a, st);
-            return hipErrorInvalidValue;
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <class P>
-static hipError_t launch_window_f(const WindowLaunch &a, hipStream_t st) {
-    switch (a.form) {
-        case FORM_INPLACE: return launch_window_p<P, FORM_INPLACE>(a, st);
-        case FORM_PINGPONG: return launch_window_p<P, FORM_PINGPONG>(a, st);
-        case FORM_ALTERNATING: return launch_window_p<P, FORM_ALTERNATING>(a, st);
-        default: return hipErrorInvalidValue;
-    }
+int64_t window_tile_cells(int K, int H, int wpg, bool xchg) {
+    const int64_t win = 64 * (int64_t)K;
+    if (!xchg) return win - 2 * (int64_t)H;
+    return wpg * win - (wpg - 1) * 2 * (int64_t)(K / 4) - 2 * (int64_t)H;
 }
 
 hipError_t launch_window(const WindowLaunch &a, hipStream_t st) {
-    switch (a.precision) {
-        case HEAT_FP64: return launch_window_f<F64>(a, st);
-        case HEAT_FP32: return launch_window_f<F32>(a, st);
-        case HEAT_FP32C: return launch_window_f<F32C>(a, st);
-        default: return hipErrorInvalidValue;
-    }
+    return a.xchg ? launch_window_xchg(a, st) : launch_window_lone(a, st);
+}
+
+hipError_t launch_window_lone(const WindowLaunch &a, hipStream_t st) {
+    return launch_window_any<false>(a, st);
 }
 
 hipError_t launch_sum_partials(const double *partial, int64_t n, double *d_out, hipStream_t st) {

@@ -1,0 +1,99 @@
+// round.h -- the round kernel of the temporal-blocked stencil and its
+// launcher, as templates: kernels.hip instantiates the lone-wave variant,
+// kernels_xchg.hip the variant whose waves share a tile through LDS (kept
+// apart so that the two compile in parallel and each kernel holds one loop
+// structure, which keeps its register count at what the window needs).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "heat_device.h"
+#include "heat_internal.h"
+#include "window.h"
+
+namespace heat {
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// One round over all tiles, mapped XCD-contiguously.  XCHG = false: one
+// wavefront per tile (part = tile).  XCHG = true: the workgroup's waves share
+// one tile and swap edge cells through the launch's dynamic LDS area.
+template <class P, int K, int FORM, bool XCHG>
+__global__ void __launch_bounds__(512)
+k_window(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst, int64_t N,
+         int32_t H, int32_t steps, double r, int64_t tiles, int64_t W, int32_t vec_ok,
+         double *part_in, double *part_out) {
+    extern __shared__ __align__(16) unsigned char heat_xlds[];
+    const int lane = threadIdx.x & 63;
+    const int wpg = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t part = blk * wpg + wave;
+    const int64_t tile = XCHG ? blk : part;
+    if (tile >= tiles) return;
+    window_tile<P, K, FORM, XCHG>(src, dst, N, H, steps, (typename P::T)r, tile * W, W,
+                                  vec_ok != 0, lane, part_in, part_out, part, wpg, wave,
+                                  reinterpret_cast<typename P::T *>(heat_xlds));
+}
+
+// Shapes that cannot hold their state in registers (they would spill), and
+// shapes whose exchange depth K/4 would be below 4 cells.
+template <class P, int K, int FORM, bool XCHG>
+constexpr bool shape_fits() {
+    return !(K == 64 && FORM == FORM_PINGPONG && (sizeof(typename P::T) == 8 || P::COMP)) &&
+           !(XCHG && K < 16);
+}
+
+template <class P, int K, int FORM, bool XCHG>
+hipError_t launch_window_t(const WindowLaunch &a, hipStream_t st) {
+    using T = typename P::T;
+    if constexpr (!shape_fits<P, K, FORM, XCHG>()) {
+        return hipErrorInvalidValue;
+    } else {
+        const int64_t W = window_tile_cells(K, a.H, a.wpg, XCHG);
+        const int64_t tiles = (a.N + W - 1) / W;
+        const int64_t blocks = XCHG ? tiles : (tiles + a.wpg - 1) / a.wpg;
+        const int vec_ok = aligned16(a.src) && aligned16(a.dst);
+        const unsigned lds = XCHG ? (unsigned)exchange_lds_bytes<P>(K, a.wpg) : 0u;
+        hipLaunchKernelGGL((k_window<P, K, FORM, XCHG>), dim3((unsigned)blocks), dim3(64 * a.wpg),
+                           lds, st, reinterpret_cast<const T *>(a.src),
+                           reinterpret_cast<T *>(a.dst), a.N, a.H, a.steps, a.r, tiles, W, vec_ok,
+                           a.part_in, a.part_out);
+        return hipGetLastError();
+    }
+}
+
+template <class P, int FORM, bool XCHG>
+hipError_t launch_window_k(const WindowLaunch &a, hipStream_t st) {
+    switch (a.K) {
+        case 8: return launch_window_t<P, 8, FORM, XCHG>(a, st);
+        case 16: return launch_window_t<P, 16, FORM, XCHG>(a, st);
+        case 32: return launch_window_t<P, 32, FORM, XCHG>(a, st);
+        case 64: return launch_window_t<P, 64, FORM, XCHG>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class P, bool XCHG>
+hipError_t launch_window_f(const WindowLaunch &a, hipStream_t st) {
+    switch (a.form) {
+        case FORM_INPLACE: return launch_window_k<P, FORM_INPLACE, XCHG>(a, st);
+        case FORM_PINGPONG: return launch_window_k<P, FORM_PINGPONG, XCHG>(a, st);
+        case FORM_ALTERNATING: return launch_window_k<P, FORM_ALTERNATING, XCHG>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool XCHG>
+hipError_t launch_window_any(const WindowLaunch &a, hipStream_t st) {
+    switch (a.precision) {
+        case HEAT_FP64: return launch_window_f<F64, XCHG>(a, st);
+        case HEAT_FP32: return launch_window_f<F32, XCHG>(a, st);
+        case HEAT_FP32C: return launch_window_f<F32C, XCHG>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace heat

@@ -46,31 +46,33 @@ constexpr int FP32C_STEPS_PER_ROUND = 64;
 
 int default_steps_per_round(int64_t N, int precision) {
     if (precision == HEAT_FP32C) return FP32C_STEPS_PER_ROUND;
-    int K, T, wpg;
-    int form;
-    tuned_shape(N, precision, &K, &T, &wpg, &form);
+    int K, T, wpg, form, xchg;
+    tuned_shape(N, precision, &K, &T, &wpg, &form, &xchg);
     return T;
 }
 
 int default_cells_per_lane(int64_t N, int precision) {
-    int K, T, wpg;
-    int form;
-    tuned_shape(N, precision, &K, &T, &wpg, &form);
+    int K, T, wpg, form, xchg;
+    tuned_shape(N, precision, &K, &T, &wpg, &form, &xchg);
     return K;
 }
 
 int default_register_form(int64_t N, int precision) {
-    int K, T, wpg;
-    int form;
-    tuned_shape(N, precision, &K, &T, &wpg, &form);
+    int K, T, wpg, form, xchg;
+    tuned_shape(N, precision, &K, &T, &wpg, &form, &xchg);
     return form;
 }
 
 static int default_waves_per_group(int64_t N, int precision) {
-    int K, T, wpg;
-    int form;
-    tuned_shape(N, precision, &K, &T, &wpg, &form);
+    int K, T, wpg, form, xchg;
+    tuned_shape(N, precision, &K, &T, &wpg, &form, &xchg);
     return wpg;
+}
+
+static int default_exchange(int64_t N, int precision) {
+    int K, T, wpg, form, xchg;
+    tuned_shape(N, precision, &K, &T, &wpg, &form, &xchg);
+    return xchg;
 }
 
 int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision) {
@@ -149,6 +151,18 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
         return fail(HEAT_EINVAL, "cells_per_lane must be 8, 16, 32 or 64 (got %d)", q.K);
     if (q.K == 64 && q.form == 2 && precision != HEAT_FP32)
         return fail(HEAT_EINVAL, "the ping-pong form holds at most 32 cells per lane here");
+    if (c.exchange < 0 || c.exchange > HEAT_EXCHANGE_LDS)
+        return fail(HEAT_EINVAL, "exchange must be 0, 1 or 2 (got %d)", c.exchange);
+    int xchg = c.exchange ? c.exchange : default_exchange(N, precision);
+    // a tuned exchange that the overridden shape cannot use falls back to
+    // lone waves; an explicit request is checked
+    if (xchg == HEAT_EXCHANGE_LDS && (q.wpg < 2 || q.K < 16)) {
+        if (c.exchange == HEAT_EXCHANGE_LDS)
+            return fail(HEAT_EINVAL, "the LDS exchange needs waves_per_group >= 2 and "
+                        "cells_per_lane >= 16");
+        xchg = HEAT_EXCHANGE_NONE;
+    }
+    q.xchg = xchg == HEAT_EXCHANGE_LDS;
     int T = c.steps_per_round ? c.steps_per_round : default_steps_per_round(N, precision);
     if (T < 1) return fail(HEAT_EINVAL, "steps_per_round must be >= 1 (got %d)", T);
     if (c.steps_per_round && (T % 4) != 0)
@@ -160,10 +174,12 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
         c.steps_per_round ? (nt > 0 ? std::min<int64_t>(T, nt) : 1) : planned_steps_per_round(N, nt, precision);
     q.T = (int)Teff;
     q.H = halo_cells(Teff, precision, q.K);
-    q.W = 64 * (int64_t)q.K - 2 * (int64_t)q.H;
+    q.W = window_tile_cells(q.K, q.H, q.wpg, q.xchg);
     q.tiles = (N + q.W - 1) / q.W;
+    q.parts = q.xchg ? q.tiles * q.wpg : q.tiles;
     q.rounds = nt > 0 ? (nt + Teff - 1) / Teff : 0;
-    if (q.tiles * 64 > MAX_GRID_THREADS)
+    const int64_t threads = q.xchg ? q.tiles * q.wpg * 64 : q.tiles * 64;
+    if (threads > MAX_GRID_THREADS)
         return fail(HEAT_EINVAL, "ring of %lld cells needs more than one launch's tiles at %d cells "
                     "per lane", (long long)N, q.K);
     *p = q;
@@ -195,7 +211,7 @@ int device_pool_setup() {
 // first and last window rounds when the plan uses them, otherwise by the
 // standalone reduction.
 struct SumArea {
-    double *partial = nullptr;   // max(SUM_BLOCKS, 2 * tiles) doubles
+    double *partial = nullptr;   // max(SUM_BLOCKS, 2 * parts) doubles
     double *d_out = nullptr;     // 2 doubles
 };
 
@@ -218,20 +234,21 @@ static int run_rounds(const Plan &pl, int precision, void *a, void *b, int64_t N
         w.H = pl.H;
         w.r = r;
         w.wpg = pl.wpg;
+        w.xchg = pl.xchg;
         int64_t done = 0;
         while (done < nt) {
             w.steps = (int)std::min<int64_t>(pl.T, nt - done);
             w.src = cur;
             w.dst = oth;
             w.part_in = fused && done == 0 ? sums->partial : nullptr;
-            w.part_out = fused && done + w.steps == nt ? sums->partial + pl.tiles : nullptr;
+            w.part_out = fused && done + w.steps == nt ? sums->partial + pl.parts : nullptr;
             HEAT_HIP(launch_window(w, st));
             std::swap(cur, oth);
             done += w.steps;
         }
         if (fused) {
-            HEAT_HIP(launch_sum_partials(sums->partial, pl.tiles, sums->d_out, st));
-            HEAT_HIP(launch_sum_partials(sums->partial + pl.tiles, pl.tiles, sums->d_out + 1, st));
+            HEAT_HIP(launch_sum_partials(sums->partial, pl.parts, sums->d_out, st));
+            HEAT_HIP(launch_sum_partials(sums->partial + pl.parts, pl.parts, sums->d_out + 1, st));
         }
     }
     if (cur != a)
@@ -270,7 +287,7 @@ static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, do
     sums.st = work.st = st;
     SumArea area;
     if (want_sums) {
-        const int64_t np = std::max<int64_t>(SUM_BLOCKS, 2 * pl.tiles);
+        const int64_t np = std::max<int64_t>(SUM_BLOCKS, 2 * pl.parts);
         HEAT_HIP(hipMallocAsync(&sums.p, (size_t)(np + 2) * sizeof(double), st));
         area.partial = (double *)sums.p;
         area.d_out = area.partial + np;
@@ -336,7 +353,7 @@ int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
     out->steps_per_round = pl.T;
     out->waves_per_group = pl.wpg;
     out->register_form = pl.form;
-    out->reserved = 0;
+    out->exchange_steps = pl.kernel == HEAT_KERNEL_TB && pl.xchg ? pl.K / 4 : 0;
     out->tile_cells = pl.W;
     out->tiles = pl.tiles;
     out->rounds = pl.rounds;

@@ -2,7 +2,8 @@
 //
 // The table maps (precision, ring-length bucket) to the temporal-blocking
 // launch shape: cells per lane K, target steps per round T, wavefronts per
-// workgroup and register form.  None of these change a binary64 or binary32
+// workgroup, register form and whether the waves of a workgroup share one
+// tile through LDS edge exchanges.  None of these change a binary64 or binary32
 // result (the update of every cell is the same whatever the tiling), and the
 // compensated form's round length is fixed outside the table, so tuning is
 // always result-neutral.  The autotuner times every candidate shape with HIP
@@ -27,6 +28,7 @@ constexpr int NBUCKETS = 10;   // [10^b, 10^(b+1)) for b = 0..8, and >= 1e9
 
 struct TuneEntry {
     int K, T, wpg, form;   // form: 1 in-place, 2 ping-pong, 3 alternating
+    int xchg;              // heat_exchange: 1 lone waves, 2 LDS exchange
 };
 
 struct TuneTable {
@@ -37,7 +39,7 @@ struct TuneTable {
         for (int p = 0; p < 3; ++p)
             for (int b = 0; b < NBUCKETS; ++b)
                 // defaults from a sweep on MI355X at N = 1e8 (see default_* in runtime.hip)
-                e[p][b] = TuneEntry{32, p == HEAT_FP32C ? 64 : 96, 2, 3};
+                e[p][b] = TuneEntry{32, p == HEAT_FP32C ? 64 : 96, 2, 3, HEAT_EXCHANGE_NONE};
     }
 };
 
@@ -60,17 +62,19 @@ int load_file(const char *path) {
     int n = 0, rc = HEAT_OK;
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
-        int p, b, K, T, wpg, form;
-        if (std::sscanf(line, "%d %d %d %d %d %d", &p, &b, &K, &T, &wpg, &form) != 6 || p < 0 ||
-            p > 2 || b < 0 || b >= NBUCKETS || (K != 8 && K != 16 && K != 32 && K != 64) || T < 1 ||
-            (T % 4) || 3 * T > 64 * K || (wpg != 1 && wpg != 2 && wpg != 4 && wpg != 8) ||
-            (K == 64 && form == 2 && p != HEAT_FP32) ||
-            form < 1 || form > 3) {
+        int p, b, K, T, wpg, form, xchg = HEAT_EXCHANGE_NONE;
+        const int got = std::sscanf(line, "%d %d %d %d %d %d %d", &p, &b, &K, &T, &wpg, &form, &xchg);
+        if ((got != 6 && got != 7) || p < 0 || p > 2 || b < 0 || b >= NBUCKETS ||
+            (K != 8 && K != 16 && K != 32 && K != 64) || T < 1 || (T % 4) || 3 * T > 64 * K ||
+            (wpg != 1 && wpg != 2 && wpg != 4 && wpg != 8) ||
+            (K == 64 && form == 2 && p != HEAT_FP32) || form < 1 || form > 3 ||
+            (xchg != HEAT_EXCHANGE_NONE && xchg != HEAT_EXCHANGE_LDS) ||
+            (xchg == HEAT_EXCHANGE_LDS && (wpg < 2 || K < 16))) {
             rc = fail(HEAT_EINVAL, "bad tuning table line: %s", line);
             break;
         }
         std::lock_guard<std::mutex> lk(t.mu);
-        t.e[p][b] = TuneEntry{K, T, wpg, form};
+        t.e[p][b] = TuneEntry{K, T, wpg, form, xchg};
         ++n;
     }
     std::fclose(f);
@@ -90,7 +94,7 @@ void load_env_once() {
 
 }  // namespace
 
-void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form) {
+void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form, int *exchange) {
     load_env_once();
     TuneTable &t = table();
     std::lock_guard<std::mutex> lk(t.mu);
@@ -99,6 +103,7 @@ void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form) 
     *T = e.T;
     *wpg = e.wpg;
     *form = e.form;
+    *exchange = e.xchg;
 }
 
 }  // namespace heat
@@ -129,11 +134,11 @@ int heat_tune_save(const char *path) {
     TuneTable &t = table();
     std::lock_guard<std::mutex> lk(t.mu);
     std::fprintf(f, "# precision bucket(log10 N) cells_per_lane steps_per_round waves_per_group "
-                    "register_form\n");
+                    "register_form exchange\n");
     for (int p = 0; p < 3; ++p)
         for (int b = 0; b < NBUCKETS; ++b)
-            std::fprintf(f, "%d %d %d %d %d %d\n", p, b, t.e[p][b].K, t.e[p][b].T, t.e[p][b].wpg,
-                         t.e[p][b].form);
+            std::fprintf(f, "%d %d %d %d %d %d %d\n", p, b, t.e[p][b].K, t.e[p][b].T, t.e[p][b].wpg,
+                         t.e[p][b].form, t.e[p][b].xchg);
     std::fclose(f);
     return HEAT_OK;
 }
@@ -181,42 +186,46 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
     for (int K : {8, 16, 32, 64})
         for (int form : {1, 2, 3})
             for (int wpg : {1, 2, 4})
-                for (int T : Ts_all) {
-                    if (precision == HEAT_FP32C && T != default_steps_per_round(N, precision))
-                        continue;
-                    if (3 * T > 64 * K) continue;
-                    if (K == 64 && form == 2 && precision != HEAT_FP32) continue;
-                    heat_config c{HEAT_KERNEL_TB, K, T, wpg, form};
-                    // whole rounds, at least 4 and at least 384 steps, so the
-                    // per-launch overheads weigh as they do in real runs
-                    int64_t R = std::max<int64_t>(4, (384 + T - 1) / T);
-                    R += R & 1;   // even: no copy-back in the timed run
-                    const int64_t nt = R * T;
-                    rc = heat_solve_dev_cfg(a, w, N, 1, 0.25, T, precision, &c, st, nullptr, nullptr);
-                    if (!rc) e = hipEventRecord(e0, st);
-                    if (!rc && e == hipSuccess)
-                        rc = heat_solve_dev_cfg(a, w, N, 1, 0.25, nt, precision, &c, st, nullptr,
+                for (int xchg : {HEAT_EXCHANGE_NONE, HEAT_EXCHANGE_LDS})
+                    for (int T : Ts_all) {
+                        if (precision == HEAT_FP32C && T != default_steps_per_round(N, precision))
+                            continue;
+                        if (3 * T > 64 * K) continue;
+                        if (K == 64 && form == 2 && precision != HEAT_FP32) continue;
+                        if (xchg == HEAT_EXCHANGE_LDS && (wpg < 2 || K < 16)) continue;
+                        heat_config c{HEAT_KERNEL_TB, K, T, wpg, form, xchg};
+                        // whole rounds, at least 4 and at least 384 steps, so the
+                        // per-launch overheads weigh as they do in real runs
+                        int64_t R = std::max<int64_t>(4, (384 + T - 1) / T);
+                        R += R & 1;   // even: no copy-back in the timed run
+                        const int64_t nt = R * T;
+                        rc = heat_solve_dev_cfg(a, w, N, 1, 0.25, T, precision, &c, st, nullptr,
                                                 nullptr);
-                    if (!rc && e == hipSuccess) e = hipEventRecord(e1, st);
-                    if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    if (rc || e != hipSuccess) {
-                        cleanup();
-                        return rc ? rc : fail_hip(e, "autotune timing");
+                        if (!rc) e = hipEventRecord(e0, st);
+                        if (!rc && e == hipSuccess)
+                            rc = heat_solve_dev_cfg(a, w, N, 1, 0.25, nt, precision, &c, st,
+                                                    nullptr, nullptr);
+                        if (!rc && e == hipSuccess) e = hipEventRecord(e1, st);
+                        if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+                        float ms = 0.f;
+                        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                        if (rc || e != hipSuccess) {
+                            cleanup();
+                            return rc ? rc : fail_hip(e, "autotune timing");
+                        }
+                        const double g = (double)N * (double)nt / (ms * 1e-3) / 1e9;
+                        if (g > best) {
+                            best = g;
+                            bc = c;
+                        }
                     }
-                    const double g = (double)N * (double)nt / (ms * 1e-3) / 1e9;
-                    if (g > best) {
-                        best = g;
-                        bc = c;
-                    }
-                }
     cleanup();
     if (install) {
         TuneTable &t = table();
         std::lock_guard<std::mutex> lk(t.mu);
         TuneEntry &en = t.e[precision][bucket_of(N)];
-        en = TuneEntry{bc.cells_per_lane, bc.steps_per_round, bc.waves_per_group, bc.register_form};
+        en = TuneEntry{bc.cells_per_lane, bc.steps_per_round, bc.waves_per_group, bc.register_form,
+                       bc.exchange};
         if (precision == HEAT_FP32C) en.T = default_steps_per_round(N, precision);
     }
     if (best_out) *best_out = bc;

@@ -22,6 +22,7 @@ HEAT_OK, HEAT_PENDING = 0, 1
 HEAT_EINVAL, HEAT_ENOMEM, HEAT_EBUSY, HEAT_ENOENT, HEAT_EDEVICE, HEAT_ECANCELED = -1, -2, -3, -4, -5, -6
 FP64, FP32, FP32C = 0, 1, 2
 KERNEL_AUTO, KERNEL_STEP, KERNEL_TB = 0, 1, 2
+EXCHANGE_AUTO, EXCHANGE_NONE, EXCHANGE_LDS = 0, 1, 2
 BATCH_WAIT, BATCH_PERSISTENT, BATCH_GRAPH = 1, 2, 4
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32c": FP32C}
@@ -45,13 +46,13 @@ class HeatError(RuntimeError):
 class heat_config(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("cells_per_lane", ctypes.c_int32),
                 ("steps_per_round", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
-                ("register_form", ctypes.c_int32)]
+                ("register_form", ctypes.c_int32), ("exchange", ctypes.c_int32)]
 
 
 class heat_plan_info(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("cells_per_lane", ctypes.c_int32),
                 ("steps_per_round", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
-                ("register_form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("register_form", ctypes.c_int32), ("exchange_steps", ctypes.c_int32),
                 ("tile_cells", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("rounds", ctypes.c_int64)]
 
@@ -148,11 +149,13 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
-def _cfg(kernel=0, cells_per_lane=0, steps_per_round=0, waves_per_group=0, register_form=0):
-    if not (kernel or cells_per_lane or steps_per_round or waves_per_group or register_form):
+def _cfg(kernel=0, cells_per_lane=0, steps_per_round=0, waves_per_group=0, register_form=0,
+         exchange=0):
+    if not (kernel or cells_per_lane or steps_per_round or waves_per_group or register_form
+            or exchange):
         return None
     return ctypes.byref(heat_config(kernel, cells_per_lane, steps_per_round, waves_per_group,
-                                    register_form))
+                                    register_form, exchange))
 
 
 def autotune(precision: int, N: int, install: bool = True):

@@ -99,11 +99,55 @@ def test_compensated_round_length_is_fixed(lib):
     dict(kernel=7), dict(cells_per_lane=12), dict(steps_per_round=6), dict(register_form=4),
     dict(cells_per_lane=64, register_form=2),
     dict(cells_per_lane=8, steps_per_round=256), dict(waves_per_group=3),
+    dict(exchange=3), dict(exchange=-1),
+    dict(exchange=2, waves_per_group=1, cells_per_lane=32),
+    dict(exchange=2, waves_per_group=4, cells_per_lane=8),
 ])
 def test_planner_rejects_bad_config(lib, cfg):
     with pytest.raises(heat.HeatError) as ei:
         heat.plan(10**6, 100, heat.FP64, **cfg)
     assert ei.value.code == heat.HEAT_EINVAL
+
+
+@pytest.mark.parametrize("K,G", [(16, 2), (32, 4), (64, 4), (64, 8)])
+def test_plan_exchange_geometry(lib, K, G):
+    """Waves sharing a tile: G windows of 64K cells overlapping by 2S, S = K/4,
+    minus the outer halo H >= T on each side; one lone-wave tile is
+    64K - 2H.  The tile count covers the ring."""
+    N, nt = 10**7, 1000
+    x = heat.plan(N, nt, heat.FP64, cells_per_lane=K, waves_per_group=G, steps_per_round=16,
+                  exchange=heat.EXCHANGE_LDS)
+    one = heat.plan(N, nt, heat.FP64, cells_per_lane=K, waves_per_group=G, steps_per_round=16,
+                    exchange=heat.EXCHANGE_NONE)
+    S = K // 4
+    assert x["exchange_steps"] == S and one["exchange_steps"] == 0
+    H = (64 * K - one["tile_cells"]) // 2
+    assert H >= x["steps_per_round"] and H % 4 == 0
+    assert x["tile_cells"] == G * 64 * K - (G - 1) * 2 * S - 2 * H
+    for p in (x, one):
+        assert (p["tiles"] - 1) * p["tile_cells"] < N <= p["tiles"] * p["tile_cells"]
+
+
+def test_tuned_exchange_falls_back_for_lone_shapes(lib, tmp_path):
+    """A tuned exchange entry is dropped (not refused) when an override makes
+    the shape unable to use it; an explicit request is refused."""
+    saved = tmp_path / "orig.txt"
+    heat.tune_save(str(saved))
+    try:
+        f = tmp_path / "x.txt"
+        f.write_text("0 6 32 64 4 3 2\n")
+        heat.tune_load(str(f))
+        assert heat.plan(5_000_000, 1000, heat.FP64)["exchange_steps"] == 8
+        assert heat.plan(5_000_000, 1000, heat.FP64, waves_per_group=1)["exchange_steps"] == 0
+        assert heat.plan(5_000_000, 1000, heat.FP64, cells_per_lane=8)["exchange_steps"] == 0
+        with pytest.raises(heat.HeatError):
+            heat.plan(5_000_000, 1000, heat.FP64, waves_per_group=1, exchange=heat.EXCHANGE_LDS)
+        for bad in ("0 6 32 64 1 3 2\n", "0 6 8 64 4 3 2\n", "0 6 32 64 4 3 5\n"):
+            f.write_text(bad)
+            with pytest.raises(heat.HeatError):
+                heat.tune_load(str(f))
+    finally:
+        heat.tune_load(str(saved))
 
 
 def test_step_kernel_rejects_compensated(lib):

@@ -54,12 +54,24 @@ def cfgs_fp64():
              waves_per_group=1),
         dict(kernel=heat.KERNEL_TB, cells_per_lane=16, steps_per_round=12, register_form=3,
              waves_per_group=8),
+        # waves of a workgroup sharing one tile (LDS edge exchange every K/4 steps)
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=16, steps_per_round=12, waves_per_group=2,
+             exchange=heat.EXCHANGE_LDS),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=32, steps_per_round=36, waves_per_group=4,
+             register_form=1, exchange=heat.EXCHANGE_LDS),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=32, steps_per_round=20, waves_per_group=8,
+             register_form=2, exchange=heat.EXCHANGE_LDS),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=64, steps_per_round=124, waves_per_group=4,
+             register_form=3, exchange=heat.EXCHANGE_LDS),
     ]
+
+
+N_CFGS = len(cfgs_fp64())
 
 
 # ------------------------------------------------------------ tiny rings
 
-@pytest.mark.parametrize("ci", range(11))
+@pytest.mark.parametrize("ci", range(N_CFGS))
 def test_tiny_rings_bitwise(ci):
     """Every ring length 1..70 (windows wrap the ring many times), run lengths
     around the round length, several r: bit-identical to the oracle."""
@@ -104,7 +116,11 @@ def test_midsize_fp32_bitwise(N):
                 dict(cells_per_lane=16, steps_per_round=32),
                 dict(cells_per_lane=64, steps_per_round=96, register_form=2),
                 dict(cells_per_lane=64, steps_per_round=96, register_form=3),
-                dict(cells_per_lane=32, steps_per_round=36, register_form=3)):
+                dict(cells_per_lane=32, steps_per_round=36, register_form=3),
+                dict(cells_per_lane=32, steps_per_round=36, waves_per_group=4, register_form=1,
+                     exchange=heat.EXCHANGE_LDS),
+                dict(cells_per_lane=16, steps_per_round=16, waves_per_group=2, register_form=3,
+                     exchange=heat.EXCHANGE_LDS)):
         got = run_dev(u0, nt, r, precision=heat.FP32, **cfg)
         assert np.array_equal(got, want), (cfg, N)
 
@@ -116,9 +132,13 @@ def test_midsize_fp32c_bitwise(N):
     for nt in (7, 100):
         T = heat.plan(N, nt, heat.FP32C)["steps_per_round"]
         want = oracle.solve_f32c(u0, r, nt, T)
-        for K, form in ((8, 1), (16, 2), (32, 3), (64, 3), (64, 1)):
-            got = run_dev(u0, nt, r, precision=heat.FP32C, cells_per_lane=K, register_form=form)
-            assert np.array_equal(got, want), (K, form, N, nt)
+        for K, form, wpg, x in ((8, 1, 0, 0), (16, 2, 0, 0), (32, 3, 0, 0), (64, 3, 0, 0),
+                                (64, 1, 0, 0), (16, 3, 2, heat.EXCHANGE_LDS),
+                                (32, 2, 4, heat.EXCHANGE_LDS), (32, 3, 8, heat.EXCHANGE_LDS),
+                                (64, 3, 4, heat.EXCHANGE_LDS)):
+            got = run_dev(u0, nt, r, precision=heat.FP32C, cells_per_lane=K, register_form=form,
+                          waves_per_group=wpg, exchange=x)
+            assert np.array_equal(got, want), (K, form, wpg, x, N, nt)
 
 
 # ------------------------------------------------------------ invariances on the GPU
@@ -167,12 +187,22 @@ def test_device_errors():
 
 # ------------------------------------------------------------ full-size workloads
 
-def sample_cells(N, W, rng, n=48):
-    """Cells at and around tile edges, the ring's wrap and random places."""
+def sample_cells(N, plan, rng, n=48):
+    """Cells at and around tile edges, the edges between the waves of a tile
+    (when they share it), the ring's wrap and random places."""
+    W = plan["tile_cells"]
     s = {0, 1, N - 1, N - 2, N // 2}
     for t in (1, 2, N // W // 2, N // W - 1):
         for d in (-1, 0, 1):
             s.add((t * W + d) % N)
+        S = plan["exchange_steps"]
+        if S:
+            K = plan["cells_per_lane"]
+            H = (plan["waves_per_group"] * 64 * K - (plan["waves_per_group"] - 1) * 2 * S - W) // 2
+            for w in range(1, plan["waves_per_group"]):
+                edge = t * W + w * (64 * K - 2 * S) + S - H
+                for d in (-1, 0, 1):
+                    s.add((edge + d) % N)
     s.update(int(x) for x in rng.integers(0, N, n))
     return np.array(sorted(s), dtype=np.int64)
 
@@ -200,23 +230,49 @@ def test_sine_mode_decay_on_gpu():
     assert np.abs(got - g ** nt * u0).max() <= 1e-13
 
 
-@pytest.mark.parametrize("kernel", [heat.KERNEL_TB, heat.KERNEL_STEP])
-def test_ring_1e8_sampled(kernel):
+@pytest.mark.parametrize("cfg", [
+    dict(kernel=heat.KERNEL_TB),
+    dict(kernel=heat.KERNEL_STEP),
+    dict(kernel=heat.KERNEL_TB, cells_per_lane=64, waves_per_group=4, register_form=3,
+         exchange=heat.EXCHANGE_LDS),
+    dict(kernel=heat.KERNEL_TB, cells_per_lane=64, waves_per_group=2, register_form=3,
+         exchange=heat.EXCHANGE_NONE),
+], ids=["tuned", "step", "k64-lds-exchange", "k64-lone-waves"])
+def test_ring_1e8_sampled(cfg):
     """100 partitions x 1,000,000 cells, r = 1/2, 1,000 steps, Uniform[0,1)
-    seed 1, in the launch configuration the benchmark times: sampled cells
-    bit for bit against light cones, and the binary64 sum conserved."""
+    seed 1, in the launch configuration the benchmark times (the tuned one)
+    and in explicit shapes: sampled cells bit for bit against light cones,
+    and the binary64 sum conserved."""
     w = inputs.WORKLOADS["ring_1e8"]
     N = w["N"]
     u0 = inputs.make_initial(w["init"], N, w["seed"])
     d = dev(u0)
-    s0, s1 = heat.solve_dev(d, w["nparts"], w["r"], w["nt"], sums=True, kernel=kernel)
-    W = heat.plan(N, w["nt"], heat.FP64)["tile_cells"]
-    idx = sample_cells(N, W, np.random.default_rng(31), n=24 if kernel == heat.KERNEL_TB else 8)
+    s0, s1 = heat.solve_dev(d, w["nparts"], w["r"], w["nt"], sums=True, **cfg)
+    pl = heat.plan(N, w["nt"], heat.FP64, **cfg)
+    step = cfg["kernel"] == heat.KERNEL_STEP
+    idx = sample_cells(N, pl, np.random.default_rng(31), n=8 if step else 24)
     got = d[torch.from_numpy(idx).cuda()].cpu().numpy()
     del d
     want = np.array([oracle.cone(u0, int(i), w["r"], w["nt"]) for i in idx])
     assert np.array_equal(got, want), idx[got != want][:10]
+    assert abs(s0 - math.fsum(u0)) <= 1e-13 * abs(s0)
     assert abs(s1 - s0) <= 8 * 2.0 ** -53 * N * w["nt"]
+
+
+@pytest.mark.parametrize("ci", range(N_CFGS))
+def test_fused_checksums(ci):
+    """The conservation checksum (fused into the first and last rounds of the
+    temporal-blocked kernel, per wave): the sums of the state before and after
+    equal the exact sums of the oracle's states to 1e-13."""
+    cfg = cfgs_fp64()[ci]
+    for N, nt in ((1, 3), (1000, 75), (100_003, 150)):
+        u0 = inputs.uniform_ring(N, (29, N))
+        d = dev(u0)
+        s0, s1 = heat.solve_dev(d, 1, 0.5, nt, sums=True, **cfg)
+        want = oracle.solve(u0, 0.5, nt)
+        assert np.array_equal(d.cpu().numpy(), want), (cfg, N)
+        assert abs(s0 - math.fsum(u0)) <= 1e-13 * max(abs(s0), 1.0), (cfg, N)
+        assert abs(s1 - math.fsum(want)) <= 1e-13 * max(abs(s1), 1.0), (cfg, N)
 
 
 def test_ring_1e8_perturbed_fp32_forms():
@@ -228,10 +284,11 @@ def test_ring_1e8_perturbed_fp32_forms():
     N, r, nt = w["N"], w["r"], w["nt"]
     u0 = inputs.make_initial(w["init"], N, w["seed"])
     u32 = u0.astype(np.float32)
-    idx = sample_cells(N, 1984, np.random.default_rng(32), n=12)
     T = heat.plan(N, nt, heat.FP32C)["steps_per_round"]
-    ref64 = np.array([oracle.cone(u32.astype(np.float64), int(i), r, nt) for i in idx])
     for prec in (heat.FP32C, heat.FP32):
+        idx = sample_cells(N, heat.plan(N, nt, prec), np.random.default_rng(32), n=12)
+        if prec == heat.FP32C:
+            ref64 = np.array([oracle.cone(u32.astype(np.float64), int(i), r, nt) for i in idx])
         d = dev(u32, torch.float32)
         heat.solve_dev(d, w["nparts"], r, nt, precision=prec)
         got = d[torch.from_numpy(idx).cuda()].cpu().numpy()
@@ -291,8 +348,11 @@ def test_unaligned_device_array_takes_gather_path():
     base[1:] = torch.from_numpy(u0).cuda()
     view = base[1:]
     assert view.data_ptr() % 16 != 0
-    heat.solve_dev(view, 1, 0.5, 90)
-    assert np.array_equal(view.cpu().numpy(), oracle.solve(u0, 0.5, 90))
+    want = oracle.solve(u0, 0.5, 90)
+    for cfg in (dict(), dict(cells_per_lane=32, waves_per_group=4, exchange=heat.EXCHANGE_LDS)):
+        view.copy_(torch.from_numpy(u0).cuda())
+        heat.solve_dev(view, 1, 0.5, 90, **cfg)
+        assert np.array_equal(view.cpu().numpy(), want), cfg
     v32 = torch.zeros(N + 1, dtype=torch.float32, device="cuda")
     u32 = u0.astype(np.float32)
     v32[1:] = torch.from_numpy(u32).cuda()
@@ -309,7 +369,7 @@ def test_ring_beyond_2_pow_31_cells():
     N = (1 << 31) + 12_345
     g = torch.Generator(device="cuda").manual_seed(36)
     d = torch.rand(N, generator=g, device="cuda", dtype=torch.float32)
-    nt, r = 6, 0.25
+    nt, r = 20, 0.25
     rng = np.random.default_rng(37)
     idx = sorted({0, 1, N - 1, N - 2, (1 << 31) - 1, 1 << 31, (1 << 31) + 1} |
                  {int(x) for x in rng.integers(0, N, 16)})
@@ -317,10 +377,15 @@ def test_ring_beyond_2_pow_31_cells():
     for i in idx:
         w = torch.arange(i - nt, i + nt + 1, device="cuda") % N
         wins[i] = d[w].cpu().numpy()
+    d2 = d.clone()
     heat.solve_dev(d, 1, r, nt, precision=heat.FP32)
+    # and with the waves of a workgroup sharing tiles
+    heat.solve_dev(d2, 1, r, nt, precision=heat.FP32, cells_per_lane=32, waves_per_group=4,
+                   exchange=heat.EXCHANGE_LDS)
     for i in idx:
         want = oracle.cone_f32(wins[i], nt, r, nt)
         assert d[i].item() == want, i
+        assert d2[i].item() == want, i
 
 
 def test_copy_probe_and_device_info():
