@@ -8,7 +8,9 @@ Two independent implementations of the same definition live here:
 
 * ``heat_oracle.c`` (plain C, built with ``-O2 -ffp-contract=off``), loaded
   through ctypes: ``solve``, ``solve_parts``, ``cone``, ``solve_f32``,
-  ``cone_f32``, ``solve_f32c``, ``cone_f32c``;
+  ``cone_f32``, ``solve_f32c``, ``cone_f32c`` (and, composed around the
+  binary32 ones in NumPy, the mean-shifted storage ``solve_f32_shifted``,
+  ``solve_f32c_shifted``);
 * NumPy ring shifts (``np_solve``, ``np_solve_f32``, ``np_solve_f32c``), one
   ufunc per arithmetic operation, so every operation is rounded on its own
   exactly as in the C code.
@@ -151,6 +153,37 @@ def solve_f32c(u0, r: float, nt: int, T: int, return_pair: bool = False):
 def cone_f32c(u0, i: int, r: float, nt: int, T: int) -> np.float32:
     w = _f32(cone_window(np.asarray(u0), int(i), int(nt)))
     return np.float32(_load().heat_oracle_cone_f32c(_ptr(w), int(nt), np.float32(r), int(T)))
+
+
+# -------------------------------------------------------- mean-shifted storage
+# The binary32 forms applied to offsets from a constant s: v0 = fl32(u0 - s)
+# (difference in binary64, then rounded to nearest even), the binary32 form
+# on v, and u = s + v in binary64.  A constant is a fixed point of the update
+# (its second difference is zero), so in exact arithmetic s + v evolves
+# exactly as u does; s = 0 is the plain rounding and widening.
+
+def to_offsets(u0, shift: float) -> np.ndarray:
+    a = _f64(u0)
+    if shift == 0:
+        return a.astype(np.float32)
+    return (a - np.float64(shift)).astype(np.float32)
+
+
+def from_offsets(v, shift: float) -> np.ndarray:
+    w = np.asarray(v, dtype=np.float32).astype(np.float64)
+    if shift == 0:
+        return w
+    return np.float64(shift) + w
+
+
+def solve_f32_shifted(u0, r: float, nt: int, shift: float) -> np.ndarray:
+    """Plain binary32 form on offsets from ``shift``; binary64 result."""
+    return from_offsets(solve_f32(to_offsets(u0, shift), r, nt), shift)
+
+
+def solve_f32c_shifted(u0, r: float, nt: int, T: int, shift: float) -> np.ndarray:
+    """Compensated binary32 form on offsets from ``shift``; binary64 result."""
+    return from_offsets(solve_f32c(to_offsets(u0, shift), r, nt, T), shift)
 
 
 # -------------------------------------------------------- NumPy second oracle

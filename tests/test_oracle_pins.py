@@ -291,3 +291,63 @@ def test_compensated_rounds_beat_plain_fp32():
     for T in (16, 32, 64):
         err = np.abs(oracle.solve_f32c(u0, r, nt, T) - want).max()
         assert err <= 1e-6 and err < plain / 50, (T, err, plain)
+
+
+# ------------------------------------------------------------ mean-shifted binary32 storage
+
+def test_shifted_zero_is_plain():
+    """Shift 0 is the plain rounding of u0 and the plain widening of the result."""
+    u0 = inputs.perturbed_ring(777, 9)
+    u32 = u0.astype(np.float32)
+    for nt in (0, 1, 37):
+        assert np.array_equal(oracle.solve_f32_shifted(u0, 0.25, nt, 0.0),
+                              oracle.solve_f32(u32, 0.25, nt).astype(np.float64))
+        assert np.array_equal(oracle.solve_f32c_shifted(u0, 0.25, nt, 16, 0.0),
+                              oracle.solve_f32c(u32, 0.25, nt, 16).astype(np.float64))
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 8, 12])
+def test_shifted_exact_brute_force(N):
+    """Small integers on a large offset C = 2^20.  With shift C the offsets are
+    the small integers, every binary32 operation on them is exact for nt <= 6,
+    and C + v is the exact rational result; plain binary32 on C + u0 cannot
+    hold the fractional parts the steps create."""
+    C = 2.0 ** 20
+    lost = 0
+    for r in DYADIC_R[1:]:
+        for nt in (1, 2, 6):
+            u0 = inputs.small_integer_ring(N, (9, N, nt)) + C
+            want = exact_solution(u0, r, nt)
+            assert as_fractions(oracle.solve_f32_shifted(u0, float(r), nt, C)) == want
+            for T in (1, 4, 100):
+                assert as_fractions(oracle.solve_f32c_shifted(u0, float(r), nt, T, C)) == want
+            plain = oracle.solve_f32(u0.astype(np.float32), float(r), nt)
+            lost += as_fractions(plain) != want
+    assert lost > 0 or N == 1
+
+
+def test_shifted_storage_error():
+    """Perturbations of 1e-3 on a mean of 1 (the precision workload's
+    distribution): binary32 offsets from the mean resolve the perturbations,
+    so the error against binary64 drops from ~1e-7 (compensated) and ~3e-5
+    (plain) to ~1e-10.  Rounding u0 to binary32 before the subtraction, or a
+    shift applied with the wrong sign on either side, would stay at the plain
+    binary32 level (or be off by 2 shift) and fail these bounds."""
+    N, r, nt = 8192, 0.25, 1000
+    u0 = inputs.perturbed_ring(N, 2)
+    want = oracle.solve(u0, r, nt)
+    s = math.fsum(u0) / N
+
+    def rel(x):
+        return float(np.abs(np.asarray(x, dtype=np.float64) - want).max() / np.abs(want).max())
+
+    u32 = u0.astype(np.float32)
+    e_plain = rel(oracle.solve_f32(u32, r, nt))
+    e_comp = rel(oracle.solve_f32c(u32, r, nt, 64))
+    e_s = rel(oracle.solve_f32_shifted(u0, r, nt, s))
+    e_sc = rel(oracle.solve_f32c_shifted(u0, r, nt, 64, s))
+    assert e_s <= 1e-9 and e_s < e_comp / 100 < e_plain / 100
+    assert e_sc <= 1e-10 and e_sc < e_s
+    # the offsets really are small: about the perturbation, not the mean
+    v = oracle.to_offsets(u0, s)
+    assert np.abs(v).max() <= 1.1e-3
