@@ -79,7 +79,11 @@ def precision_report(heat, torch, u0, nparts, r, nt, prec, stream):
     """Error of one pass of a binary32 form against the binary64 path
     (bit-identical to the oracle) over the whole ring: max |x - y| / max |y|,
     against binary64 run from fl32(u0) widened (arithmetic only) and from u0
-    itself (end to end)."""
+    itself (end to end); and the same form with the state stored as binary32
+    offsets from the ring's mean (the library's host-buffer path with
+    ``shift``), end to end."""
+    import math
+
     import numpy as np
     d = torch.from_numpy(u0).to("cuda").float()
     heat.solve_dev(d, nparts, r, nt, precision=prec, stream=stream)
@@ -92,6 +96,15 @@ def precision_report(heat, torch, u0, nparts, r, nt, prec, stream):
         heat.solve_dev(ref, nparts, r, nt, precision=heat.FP64, stream=stream)
         torch.cuda.synchronize()
         out[label] = float((got - ref).abs().max() / ref.abs().max())
+        if label == "vs_fp64_from_u0":
+            del got
+            shift = math.fsum(u0) / u0.size
+            res = heat.solve_batch([dict(u0=u0, nparts=nparts, r=r, nt=nt, precision=prec,
+                                         shift=shift)])[0]
+            sh = torch.from_numpy(res.u).to("cuda")
+            out["mean_shifted_vs_fp64_from_u0"] = float((sh - ref).abs().max() / ref.abs().max())
+            out["shift"] = shift
+            del sh, res
         del ref
     out["steps"] = nt
     return out

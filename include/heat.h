@@ -155,6 +155,15 @@ int heat_checksum_dev(const void *d_u, int64_t N, int32_t precision, void *hip_s
  * and widen the result back exactly.  sum0 / sum_nt: binary64 sums of the
  * state (in its storage precision) before and after; status: per-problem
  * heat_status.
+ *
+ * shift (FP32 forms; ignored for HEAT_FP64; must be finite): the device holds
+ * the binary32 offsets v = fl32(u0 - shift) (difference taken in binary64,
+ * rounded to nearest even) and the result is u = shift + v (binary64).  A
+ * constant is a fixed point of the update (its Laplacian is zero), so in
+ * exact arithmetic the offsets evolve exactly as the state does; stored
+ * relative to a shift near the state's mean, binary32 resolves the
+ * fluctuations instead of the mean (mean-shifted storage).  0 = no offset.
+ * The sums then are N*shift + sum(v).
  */
 typedef struct heat_problem {
     int64_t N;
@@ -169,6 +178,7 @@ typedef struct heat_problem {
     int32_t status;
     int32_t reserved;
     double latency_s;   /* server: seconds from heat_submit to completion */
+    double shift;       /* FP32 forms: state stored as binary32 offsets from it */
 } heat_problem;
 
 /*

@@ -302,6 +302,7 @@ int heat_solve_batch(heat_problem *probs, int32_t count) {
         heat_ring g{p.N, p.nt, p.r, p.precision, p.nparts, (void *)1, (void *)1};
         int rc = validate_ring(g);
         if (!rc && (!p.u0 || !p.u_out)) rc = fail(HEAT_EINVAL, "u0/u_out is NULL");
+        if (!rc && !std::isfinite(p.shift)) rc = fail(HEAT_EINVAL, "shift must be finite");
         p.status = rc;
         if (rc && first == HEAT_OK) first = rc;
         ok[i] = rc == HEAT_OK;
@@ -342,7 +343,8 @@ int heat_solve_batch(heat_problem *probs, int32_t count) {
             e = hipMemcpyAsync(a, p.u0, (size_t)p.N * 8, hipMemcpyHostToDevice, st);
         } else {
             e = hipMemcpyAsync(b, p.u0, (size_t)p.N * 8, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess) e = launch_f64_to_f32((const double *)b, (float *)a, p.N, st);
+            if (e == hipSuccess)
+                e = launch_f64_to_f32((const double *)b, (float *)a, p.N, st, p.shift);
         }
         if (e != hipSuccess) {
             rc = fail_hip(e, "stage-in");
@@ -379,7 +381,8 @@ int heat_solve_batch(heat_problem *probs, int32_t count) {
         if (p.precision == HEAT_FP64) {
             e = hipMemcpyAsync(p.u_out, rings[j].d_u, (size_t)p.N * 8, hipMemcpyDeviceToHost, st);
         } else {
-            e = launch_f32_to_f64((const float *)rings[j].d_u, (double *)rings[j].d_work, p.N, st);
+            e = launch_f32_to_f64((const float *)rings[j].d_u, (double *)rings[j].d_work, p.N, st,
+                                  p.shift);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(p.u_out, rings[j].d_work, (size_t)p.N * 8,
                                    hipMemcpyDeviceToHost, st);
@@ -404,8 +407,10 @@ int heat_solve_batch(heat_problem *probs, int32_t count) {
         heat_problem &p = probs[idx[j]];
         p.status = rc;
         if (!rc) {
-            p.sum0 = hs[2 * j];
-            p.sum_nt = hs[2 * j + 1];
+            // sums of the stored offsets, plus N*shift for the shifted forms
+            const double base = p.precision == HEAT_FP64 ? 0.0 : (double)p.N * p.shift;
+            p.sum0 = base + hs[2 * j];
+            p.sum_nt = base + hs[2 * j + 1];
         }
     }
     cleanup();

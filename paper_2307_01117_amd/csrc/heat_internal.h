@@ -104,8 +104,12 @@ constexpr int SUM_BLOCKS = 4096;
 hipError_t launch_sum(int precision, const void *u, int64_t N, double *partial, double *d_out,
                       hipStream_t st);
 
-hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
-hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t st);
+// binary64 <-> binary32 state conversions, relative to `shift` (0 = none):
+// dst = fl32(src - shift) and dst = shift + src.
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st,
+                             double shift = 0.0);
+hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t st,
+                             double shift = 0.0);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 // Streaming 16-byte copy (bandwidth probe), same launch shape as k_step.
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);

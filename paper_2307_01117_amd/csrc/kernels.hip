@@ -152,16 +152,23 @@ __global__ void __launch_bounds__(256) k_sum_final(const double *__restrict__ pa
 
 // ================================================================= CONVERT
 
-__global__ void k_f64_to_f32(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
+// Stage-in and stage-out of the binary32 forms, optionally relative to a
+// shift s: v = fl32(u - s) (binary64 difference, then round to nearest
+// even) and u = s + v (binary64).  s = 0 takes the plain conversions, which
+// keep the sign of zero.
+
+__global__ void k_f64_to_f32(const double *__restrict__ a, float *__restrict__ b, int64_t n,
+                             double s) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        b[i] = (float)a[i];   // round to nearest even
+        b[i] = s != 0.0 ? (float)(a[i] - s) : (float)a[i];
 }
 
-__global__ void k_f32_to_f64(const float *__restrict__ a, double *__restrict__ b, int64_t n) {
+__global__ void k_f32_to_f64(const float *__restrict__ a, double *__restrict__ b, int64_t n,
+                             double s) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        b[i] = (double)a[i];  // exact
+        b[i] = s != 0.0 ? s + (double)a[i] : (double)a[i];   // widening is exact
 }
 
 __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
@@ -248,13 +255,13 @@ static unsigned grid_for(int64_t n) {
     return (unsigned)b;
 }
 
-hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t st, double shift) {
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n, shift);
     return hipGetLastError();
 }
 
-hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t n, hipStream_t st, double shift) {
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n, shift);
     return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -67,6 +68,7 @@ struct Req {
     BatchRing br{};
     size_t off = 0, bytes = 0;
     double *d_sums = nullptr;          // [sum0, sum_nt] on the device
+    double shift = 0.0;                // FP32 forms: state held as offsets from it
     int state = QUEUED;
     int rc = HEAT_OK;
     std::string msg;                   // error text, kept for the thread that polls
@@ -152,8 +154,10 @@ static void copy_loop(heat_server *s) {
             if (e == hipSuccess) e = hipStreamSynchronize(s->copy);
             lk.lock();
             if (e == hipSuccess) {
-                q->p->sum0 = sums[0];
-                q->p->sum_nt = sums[1];
+                // sums of the stored offsets, plus N*shift for the shifted forms
+                const double base = q->ring.precision == HEAT_FP64 ? 0.0 : (double)N * q->shift;
+                q->p->sum0 = base + sums[0];
+                q->p->sum_nt = base + sums[1];
                 q->p->status = HEAT_OK;
                 q->p->latency_s =
                     std::chrono::duration<double>(Clock::now() - q->t_submit).count();
@@ -278,7 +282,7 @@ static void sched_loop(heat_server *s) {
             hipError_t e = hipSuccess;
             if (q->ring.precision != HEAT_FP64)
                 e = launch_f64_to_f32((const double *)q->ring.d_work, (float *)q->ring.d_u,
-                                      q->ring.N, s->compute);
+                                      q->ring.N, s->compute, q->shift);
             if (e == hipSuccess)
                 e = launch_sum(q->ring.precision, q->ring.d_u, q->ring.N, s->d_partial, q->d_sums,
                                s->compute);
@@ -306,7 +310,7 @@ static void sched_loop(heat_server *s) {
                                       q->d_sums + 1, s->compute);
             if (e == hipSuccess && q->ring.precision != HEAT_FP64)
                 e = launch_f32_to_f64((const float *)q->ring.d_u, (double *)q->ring.d_work,
-                                      q->ring.N, s->compute);
+                                      q->ring.N, s->compute, q->shift);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&q->fin, hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventRecord(q->fin, s->compute);
             if (e != hipSuccess && !rc) rc = fail_hip(e, "server complete");
@@ -398,6 +402,7 @@ int heat_submit(heat_server *s, heat_problem *p, uint64_t *ticket) {
     int rc = validate_ring(g);
     if (rc) return rc;
     if (!p->u0 || !p->u_out) return fail(HEAT_EINVAL, "u0/u_out is NULL");
+    if (!std::isfinite(p->shift)) return fail(HEAT_EINVAL, "shift must be finite");
     const size_t bytes = footprint(p->N, p->precision);
     std::lock_guard<std::mutex> lk(s->mu);
     ++s->st.submitted;
@@ -413,6 +418,7 @@ int heat_submit(heat_server *s, heat_problem *p, uint64_t *ticket) {
     Req *q = new Req();
     q->ticket = s->next_ticket++;
     q->p = p;
+    q->shift = p->precision == HEAT_FP64 ? 0.0 : p->shift;
     q->ring = g;
     q->ring.d_u = q->ring.d_work = nullptr;
     q->bytes = bytes;

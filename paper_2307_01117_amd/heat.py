@@ -62,7 +62,7 @@ class heat_problem(ctypes.Structure):
                 ("r", ctypes.c_double), ("nt", ctypes.c_int64), ("u0", ctypes.c_void_p),
                 ("u_out", ctypes.c_void_p), ("sum0", ctypes.c_double), ("sum_nt", ctypes.c_double),
                 ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("latency_s", ctypes.c_double)]
+                ("latency_s", ctypes.c_double), ("shift", ctypes.c_double)]
 
 
 class heat_ring(ctypes.Structure):
@@ -249,7 +249,8 @@ class BatchResult:
 
 def solve_batch(problems) -> list:
     """Batching form on host arrays.  ``problems``: iterable of dicts with
-    u0, nparts, r, nt and optional precision.  Returns BatchResult list."""
+    u0, nparts, r, nt and optional precision and shift (binary32 forms: the
+    state is stored as offsets from it).  Returns BatchResult list."""
     probs = list(problems)
     arr = (heat_problem * len(probs))()
     keep = []
@@ -259,7 +260,7 @@ def solve_batch(problems) -> list:
         keep.append((u0, out))
         arr[i] = heat_problem(u0.size, int(p.get("nparts", 1)), int(p.get("precision", FP64)),
                               float(p["r"]), int(p["nt"]), u0.ctypes.data, out.ctypes.data,
-                              0.0, 0.0, 0, 0, 0.0)
+                              0.0, 0.0, 0, 0, 0.0, float(p.get("shift", 0.0)))
     rc = load().heat_solve_batch(arr, len(probs))
     res = [BatchResult(keep[i][1], arr[i].sum0, arr[i].sum_nt, arr[i].status)
            for i in range(len(probs))]
@@ -292,12 +293,12 @@ class Server:
         self._live = {}
 
     def submit(self, u0: np.ndarray, nt: int, r: float, precision: int = FP64, nparts: int = 1,
-               out: np.ndarray | None = None) -> int:
+               out: np.ndarray | None = None, shift: float = 0.0) -> int:
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         if out is None:
             out = np.empty_like(u0)
         p = heat_problem(u0.size, int(nparts), int(precision), float(r), int(nt), u0.ctypes.data,
-                         out.ctypes.data, 0.0, 0.0, 0, 0, 0.0)
+                         out.ctypes.data, 0.0, 0.0, 0, 0, 0.0, float(shift))
         t = ctypes.c_uint64()
         _check(load().heat_submit(self._h, ctypes.byref(p), ctypes.byref(t)))
         self._live[t.value] = (p, u0, out)

@@ -66,8 +66,12 @@ def test_null_pointers(lib):
 def test_planner_geometry(lib):
     p = heat.plan(100_000_000, 1000, heat.FP64)
     assert p["kernel"] == heat.KERNEL_TB
-    K, T = p["cells_per_lane"], p["steps_per_round"]
-    H = (64 * K - p["tile_cells"]) // 2          # halo: >= T, whole 128-byte lines
+    K, T, G, S = (p["cells_per_lane"], p["steps_per_round"], p["waves_per_group"],
+                  p["exchange_steps"])
+    # the tile's span: one window, or G windows overlapping by 2S (S = K/4)
+    span = G * 64 * K - (G - 1) * 2 * S if S else 64 * K
+    assert S in (0, K // 4)
+    H = (span - p["tile_cells"]) // 2            # halo: >= T, whole 128-byte lines
     assert H >= T and H % 16 == 0 and 3 * H <= 64 * K
     assert p["tiles"] == -(-100_000_000 // p["tile_cells"])
     assert p["rounds"] == -(-1000 // T)

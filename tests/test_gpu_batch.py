@@ -61,6 +61,46 @@ def test_host_batch_matches_oracle(precs):
         assert abs(q.sum_nt - math.fsum(want)) <= 1e-13 * max(abs(s0), 1.0)
 
 
+@pytest.mark.parametrize("prec", [heat.FP32, heat.FP32C])
+def test_host_batch_mean_shifted_storage(prec):
+    """binary32 forms stored as offsets from a shift (the ring's mean, or any
+    constant): bit-identical to the oracle's shifted composition, sums of the
+    state reported as N*shift + sum of the offsets, and binary64 problems in
+    the same batch ignore the shift."""
+    rng = np.random.default_rng(46)
+    probs, want = [], []
+    for k in range(12):
+        N = int(rng.integers(1, 40_000))
+        nt = int(rng.integers(0, 400))
+        r = float(0.5 - 0.4 * rng.random())
+        u0 = inputs.perturbed_ring(N, (47, k)) * 3.0 + 5.0
+        shift = (math.fsum(u0) / N) if k % 3 else float(rng.normal())
+        p = dict(u0=u0, nparts=1, r=r, nt=nt, precision=prec, shift=shift)
+        if prec == heat.FP32:
+            w = oracle.solve_f32_shifted(u0, r, nt, shift)
+        else:
+            T = heat.plan(N, nt, heat.FP32C)["steps_per_round"]
+            w = oracle.solve_f32c_shifted(u0, r, nt, T, shift)
+        probs.append(p)
+        want.append(w)
+    u64 = inputs.uniform_ring(5000, 48)
+    probs.append(dict(u0=u64, nparts=1, r=0.5, nt=77, precision=heat.FP64, shift=123.0))
+    want.append(oracle.solve(u64, 0.5, 77))
+    res = heat.solve_batch(probs)
+    for p, w, q in zip(probs, want, res):
+        assert q.status == heat.HEAT_OK
+        assert np.array_equal(q.u, w), (p["u0"].size, p["nt"], p["precision"])
+        if p["precision"] == heat.FP64:
+            continue
+        N, s = p["u0"].size, p["shift"]
+        s0 = N * s + math.fsum(oracle.to_offsets(p["u0"], s).astype(np.float64))
+        assert abs(q.sum0 - s0) <= 1e-12 * max(abs(s0), 1.0)
+        assert abs(q.sum_nt - math.fsum(w)) <= 1e-9 * max(abs(s0), 1.0)
+    with pytest.raises(heat.HeatError) as ei:
+        heat.solve_batch([dict(u0=u64, nparts=1, r=0.5, nt=3, precision=prec, shift=math.inf)])
+    assert ei.value.code == heat.HEAT_EINVAL
+
+
 def test_host_batch_reports_bad_problem():
     good = dict(u0=inputs.uniform_ring(500, 1), nparts=1, r=0.4, nt=50)
     bad = dict(u0=inputs.uniform_ring(10, 2), nparts=1, r=0.7, nt=5)

@@ -86,6 +86,29 @@ def test_alone_on_idle_server_equals_in_mix():
         assert np.array_equal(solo[k], mixed[k])
 
 
+def test_mean_shifted_requests():
+    """binary32 requests stored as offsets from a shift, mixed with unshifted
+    ones: each equals the oracle's shifted composition bit for bit."""
+    reqs = []
+    for k in range(8):
+        N = 20_000 + 997 * k
+        u0 = inputs.perturbed_ring(N, (71, k))
+        prec = heat.FP32 if k % 2 else heat.FP32C
+        shift = 0.0 if k % 4 == 3 else float(np.mean(u0))
+        reqs.append((u0, 300 + 11 * k, 0.25, prec, shift))
+    with heat.Server(hbm_budget=1 << 30) as s:
+        ts = [s.submit(u0, nt, r, prec, shift=sh) for (u0, nt, r, prec, sh) in reqs]
+        outs = [s.wait(t) for t in ts]
+    for (u0, nt, r, prec, sh), res in zip(reqs, outs):
+        assert res.status == heat.HEAT_OK
+        if prec == heat.FP32:
+            want = oracle.solve_f32_shifted(u0, r, nt, sh)
+        else:
+            T = heat.plan(u0.size, nt, heat.FP32C)["steps_per_round"]
+            want = oracle.solve_f32c_shifted(u0, r, nt, T, sh)
+        assert np.array_equal(res.u, want), (u0.size, nt, prec, sh)
+
+
 def test_budget_admission_and_enomem():
     budget = 24 << 20     # fits one 1e6-cell binary64 request (16 MB), not two
     with heat.Server(hbm_budget=budget) as s:
