@@ -81,7 +81,7 @@ typedef struct heat_config {
     int32_t kernel;          /* heat_kernel_choice                              */
     int32_t cells_per_lane;  /* TB: cells held per lane, one of 8, 16, 32, 64   */
     int32_t steps_per_round; /* TB: T, a multiple of 4 with 2T < 64*cells - 8   */
-    int32_t waves_per_group; /* 1, 2, 4 or 8 wavefronts per workgroup           */
+    int32_t waves_per_group; /* wavefronts per workgroup, 1 to 8                */
     int32_t register_form;   /* TB: 1 = in-place forward sweeps (the compiler
                                 rotates the K registers every step),
                                 2 = ping-pong (2K registers, no copies),

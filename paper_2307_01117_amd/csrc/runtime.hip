@@ -123,8 +123,8 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     if (cfg) c = *cfg;
     Plan q;
     q.wpg = c.waves_per_group ? c.waves_per_group : default_waves_per_group(N, precision);
-    if (q.wpg != 1 && q.wpg != 2 && q.wpg != 4 && q.wpg != 8)
-        return fail(HEAT_EINVAL, "waves_per_group must be 1, 2, 4 or 8 (got %d)", q.wpg);
+    if (q.wpg < 1 || q.wpg > 8)
+        return fail(HEAT_EINVAL, "waves_per_group must be in [1, 8] (got %d)", q.wpg);
     int kernel = c.kernel ? c.kernel : HEAT_KERNEL_TB;
     if (kernel != HEAT_KERNEL_STEP && kernel != HEAT_KERNEL_TB)
         return fail(HEAT_EINVAL, "unknown kernel choice %d", c.kernel);

@@ -66,7 +66,7 @@ int load_file(const char *path) {
         const int got = std::sscanf(line, "%d %d %d %d %d %d %d", &p, &b, &K, &T, &wpg, &form, &xchg);
         if ((got != 6 && got != 7) || p < 0 || p > 2 || b < 0 || b >= NBUCKETS ||
             (K != 8 && K != 16 && K != 32 && K != 64) || T < 1 || (T % 4) || 3 * T > 64 * K ||
-            (wpg != 1 && wpg != 2 && wpg != 4 && wpg != 8) ||
+            wpg < 1 || wpg > 8 ||
             (K == 64 && form == 2 && p != HEAT_FP32) || form < 1 || form > 3 ||
             (xchg != HEAT_EXCHANGE_NONE && xchg != HEAT_EXCHANGE_LDS) ||
             (xchg == HEAT_EXCHANGE_LDS && (wpg < 2 || K < 16))) {

@@ -102,7 +102,7 @@ def test_compensated_round_length_is_fixed(lib):
 @pytest.mark.parametrize("cfg", [
     dict(kernel=7), dict(cells_per_lane=12), dict(steps_per_round=6), dict(register_form=4),
     dict(cells_per_lane=64, register_form=2),
-    dict(cells_per_lane=8, steps_per_round=256), dict(waves_per_group=3),
+    dict(cells_per_lane=8, steps_per_round=256), dict(waves_per_group=9), dict(waves_per_group=-1),
     dict(exchange=3), dict(exchange=-1),
     dict(exchange=2, waves_per_group=1, cells_per_lane=32),
     dict(exchange=2, waves_per_group=4, cells_per_lane=8),

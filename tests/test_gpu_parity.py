@@ -63,6 +63,11 @@ def cfgs_fp64():
              register_form=2, exchange=heat.EXCHANGE_LDS),
         dict(kernel=heat.KERNEL_TB, cells_per_lane=64, steps_per_round=124, waves_per_group=4,
              register_form=3, exchange=heat.EXCHANGE_LDS),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=64, steps_per_round=60, waves_per_group=6,
+             register_form=3, exchange=heat.EXCHANGE_LDS),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=16, steps_per_round=12, waves_per_group=3,
+             register_form=2, exchange=heat.EXCHANGE_LDS),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=8, steps_per_round=8, waves_per_group=5),
     ]
 
 
