@@ -21,17 +21,24 @@ int batch_cells_per_lane(int precision, int64_t N) {
     return precision == HEAT_FP64 && N >= 65536 ? 64 : 32;
 }
 
+// Shortest target round length of a batch kernel class.  The tuning table's
+// round length belongs to the plain kernel's shape for that ring length
+// (often narrower lanes); a batch class runs its own lane width, and rounds
+// much shorter than its window's natural depth only multiply launches and
+// scheduling steps (measured on MI355X: the long binary64 rings of the
+// serving mix at 64-step rounds doubled its latency at 1,000 requests/s).
+static int64_t batch_min_steps_per_round(int K) { return K >= 64 ? 160 : 96; }
+
 int describe_ring(const heat_ring &g, BatchRing *out, int K) {
     if (K == 0) K = batch_cells_per_lane(g.precision, g.N);
-    int64_t Teff = planned_steps_per_round(g.N, g.nt, g.precision);
-    // a tuning table made for wider lanes may ask for rounds deeper than this
-    // kernel class's window allows; binary64/binary32 results do not depend
-    // on the round length, and the compensated form's fixed length always fits
+    // the deepest rounds this class's window allows
     const int64_t Tmax = (64 * (int64_t)K / 3) & ~int64_t(3);
-    if (Teff > Tmax) {
-        const int64_t R = (g.nt + Tmax - 1) / Tmax;
-        Teff = (g.nt + R - 1) / R;
-    }
+    int64_t Ttarget = default_steps_per_round(g.N, g.precision);
+    // binary64/binary32 results do not depend on the round length; the
+    // compensated form's fixed length is kept (and always fits)
+    if (g.precision != HEAT_FP32C)
+        Ttarget = std::min(std::max(Ttarget, batch_min_steps_per_round(K)), Tmax);
+    const int64_t Teff = balanced_steps_per_round(g.nt, Ttarget, g.precision);
     BatchRing R{};
     R.buf[0] = g.d_u;
     R.buf[1] = g.d_work;
@@ -60,15 +67,25 @@ static inline int32_t remaining_rounds(const BatchRing &R) {
     return R.rounds + R.copy_round - R.round0;
 }
 
-int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision, int32_t cap) {
+int32_t scheduled_rounds(const BatchRing &R, int32_t cap, int32_t tick_steps) {
+    const int32_t n = remaining_rounds(R);
+    int32_t c = cap;
+    if (tick_steps > 0) c = std::max<int32_t>(1, (tick_steps + R.T - 1) / std::max<int32_t>(R.T, 1));
+    return c > 0 ? std::min(n, c) : n;
+}
+
+int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision, int32_t cap,
+                       int32_t tick_steps) {
     precision_ = precision;
     K_ = rings_in.empty() ? 32 : rings_in[0].K;
     rings_.clear();
     for (const BatchRing &R : rings_in)
         if (remaining_rounds(R) > 0) rings_.push_back(R);
-    // longest first (remaining rounds incl. copy-back), stable for determinism
-    std::stable_sort(rings_.begin(), rings_.end(), [](const BatchRing &a, const BatchRing &b) {
-        return remaining_rounds(a) > remaining_rounds(b);
+    // most scheduled rounds first (remaining rounds incl. copy-back, capped),
+    // stable for determinism
+    auto sched = [&](const BatchRing &R) { return scheduled_rounds(R, cap, tick_steps); };
+    std::stable_sort(rings_.begin(), rings_.end(), [&](const BatchRing &a, const BatchRing &b) {
+        return sched(a) > sched(b);
     });
     const size_t n = rings_.size();
     tile_prefix_.assign(n + 1, 0);
@@ -79,14 +96,13 @@ int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision, in
         tile_prefix_[i + 1] = tile_prefix_[i] + rings_[i].tiles;
     }
     nflags_ = flags;
-    max_rounds_ = n ? remaining_rounds(rings_[0]) : 0;
-    if (cap > 0 && max_rounds_ > cap) max_rounds_ = cap;
+    max_rounds_ = n ? sched(rings_[0]) : 0;
     active_.assign(max_rounds_, 0);
     round_start_.assign(max_rounds_ + 1, 0);
-    // rings are sorted by remaining rounds, so the rings alive in round k form a prefix
+    // rings are sorted by scheduled rounds, so the rings alive in round k form a prefix
     size_t alive = n;
     for (int32_t k = 0; k < max_rounds_; ++k) {
-        while (alive > 0 && remaining_rounds(rings_[alive - 1]) <= k) --alive;
+        while (alive > 0 && sched(rings_[alive - 1]) <= k) --alive;
         active_[k] = (int32_t)alive;
         round_start_[k + 1] = round_start_[k] + tile_prefix_[alive];
     }

@@ -11,21 +11,28 @@
 
 namespace heat {
 
-// Cells per lane of the round kernel that runs a ring: long binary64 rings
-// take 64-cell lanes (half the halo overhead), everything else 32.
+// Cells per lane of the round kernel that runs a ring in the batching form:
+// long binary64 rings take 64-cell lanes (half the halo overhead),
+// everything else 32.  (The server runs all rings with 32-cell lanes.)
 int batch_cells_per_lane(int precision, int64_t N);
 int validate_ring(const heat_ring &g);
-// Geometry of one ring in a batch (same T rule as the plain planner);
-// K = 0 picks batch_cells_per_lane.
+// Geometry of one ring in a batch: the tuned round length for its size,
+// raised to the kernel class's minimum (binary64/binary32) and balanced into
+// equal rounds like the plain planner; K = 0 picks batch_cells_per_lane.
 int describe_ring(const heat_ring &g, BatchRing *out, int K = 0);
+
+// Rounds a ring advances in one scheduling step: its remaining rounds
+// (copy-back included), at most `cap` (0 = no cap) or, with tick_steps > 0,
+// at most the rounds that cover tick_steps steps (at least one).
+int32_t scheduled_rounds(const BatchRing &R, int32_t cap, int32_t tick_steps);
 
 class BatchLaunch {
   public:
-    // Sort rings (all of one precision and one K class) by remaining rounds,
-    // longest first, and number the work items round-major.  At most
-    // max_rounds rounds are scheduled (0 = all); each ring starts at its own
-    // round0.
-    int build(const std::vector<BatchRing> &rings, int precision, int32_t max_rounds = 0);
+    // Sort rings (all of one precision and one K class) by the rounds they
+    // are scheduled for (scheduled_rounds), most first, and number the work
+    // items round-major; each ring starts at its own round0.
+    int build(const std::vector<BatchRing> &rings, int precision, int32_t max_rounds = 0,
+              int32_t tick_steps = 0);
     // Rings as scheduled (sorted), and the number of rounds each one advances.
     const std::vector<BatchRing> &rings() const { return rings_; }
     int32_t rounds_scheduled() const { return max_rounds_; }

@@ -76,7 +76,10 @@ static int default_exchange(int64_t N, int precision) {
 }
 
 int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision) {
-    const int T = default_steps_per_round(N, precision);
+    return balanced_steps_per_round(nt, default_steps_per_round(N, precision), precision);
+}
+
+int64_t balanced_steps_per_round(int64_t nt, int64_t T, int precision) {
     // a run shorter than one round is a single round of nt steps
     int64_t Teff = nt > 0 ? std::min<int64_t>(T, nt) : 1;
     if (precision != HEAT_FP32C && nt >= 2) {

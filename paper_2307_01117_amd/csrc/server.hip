@@ -17,6 +17,7 @@
 #include <cmath>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -85,7 +86,22 @@ static size_t footprint(int64_t N, int precision) {
     return Arena::round((size_t)N * es) + Arena::round((size_t)N * std::max<size_t>(es, 8)) + 256;
 }
 
-constexpr int32_t TICK_ROUNDS = 2;     // rounds per tick: bounds the admission delay
+// Rounds per tick: every active request advances this many rounds (or what
+// it has left).  Short ticks bound the admission delay, and every round of a
+// tick is a launch per kernel class, so later rounds that hold only a few
+// rings leave the GPU partly idle: on MI355X with the serving mix, ticks of
+// 320+ steps fell behind 1,000 requests/s that 2-round ticks sustain.
+// HEAT_SERVER_TICK_STEPS (optional) instead sizes ticks in steps.
+constexpr int32_t TICK_ROUNDS = 2;
+
+// Cells per lane of every served ring.  A tick's rounds are launches that a
+// mix of requests fills only partly, so a round lasts about as long as its
+// slowest tile, and a 64-cell tile takes twice as long as a 32-cell one; the
+// batching form, which fills the GPU, uses 64-cell lanes for long binary64
+// rings instead.  Measured on MI355X with the serving mix at 1,000
+// requests/s: p50 / p99 13.4 / 63.7 ms with 32-cell lanes against 25.6 /
+// 75.9 ms with the batching form's classes, at the same throughput.
+constexpr int SERVER_CELLS_PER_LANE = 32;
 constexpr int TABLE_GROUPS = 6;        // (precision, 32- or 64-cell lanes) round tables per tick
 
 }  // namespace heat
@@ -101,6 +117,7 @@ struct heat_server {
     Arena arena;
     int device = 0;
     int32_t max_slots = 4096, max_queue = 65536, slots_used = 0;
+    int32_t tick_steps = 0;   // 0: TICK_ROUNDS rounds per tick
     hipStream_t compute = nullptr, copy = nullptr;
     double *d_partial = nullptr;
     // round tables, double-buffered across ticks (TABLE_GROUPS groups each)
@@ -199,8 +216,8 @@ static void copy_loop(heat_server *s) {
 
 // ------------------------------------------------------------ scheduler
 static int run_tick(heat_server *s, std::vector<Req *> &act, uint64_t tick) {
-    // group by precision and kernel class; every group advances up to
-    // TICK_ROUNDS rounds
+    // group by precision and kernel class; every ring advances the rounds
+    // that cover the tick's steps
     std::vector<BatchRing> groups[TABLE_GROUPS];
     for (Req *q : act) groups[q->ring.precision * 2 + (q->br.K == 64)].push_back(q->br);
     const int slot = (int)(tick & 1);
@@ -211,7 +228,7 @@ static int run_tick(heat_server *s, std::vector<Req *> &act, uint64_t tick) {
     for (int g = 0; g < TABLE_GROUPS; ++g) {
         if (groups[g].empty()) continue;
         BatchLaunch L;
-        int rc = L.build(groups[g], g / 2, TICK_ROUNDS);
+        int rc = L.build(groups[g], g / 2, s->tick_steps ? 0 : TICK_ROUNDS, s->tick_steps);
         if (!rc) rc = L.enqueue_rounds(dt + g * per_group, ht + g * per_group, s->compute);
         if (rc) return rc;
     }
@@ -238,7 +255,7 @@ static void sched_loop(heat_server *s) {
             q->ring.d_work = b + Arena::round((size_t)q->ring.N * es);
             q->d_sums = (double *)(b + Arena::round((size_t)q->ring.N * es) +
                                    Arena::round((size_t)q->ring.N * std::max<size_t>(es, 8)));
-            describe_ring(q->ring, &q->br);
+            describe_ring(q->ring, &q->br, SERVER_CELLS_PER_LANE);
             q->state = STAGING;
             ++s->st.admitted;
             s->h2d.push_back(q);
@@ -301,8 +318,7 @@ static void sched_loop(heat_server *s) {
         // progress bookkeeping and completions (all enqueued after the tick)
         std::vector<Req *> finished;
         for (Req *q : act) {
-            const int32_t remaining = q->br.rounds + q->br.copy_round - q->br.round0;
-            q->br.round0 += std::min<int32_t>(remaining, TICK_ROUNDS);
+            q->br.round0 += scheduled_rounds(q->br, s->tick_steps ? 0 : TICK_ROUNDS, s->tick_steps);
             if (q->br.round0 >= q->br.rounds + q->br.copy_round) finished.push_back(q);
         }
         for (Req *q : finished) {
@@ -348,6 +364,10 @@ int heat_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t max_q
     heat_server *s = new heat_server();
     s->max_slots = max_slots ? max_slots : 4096;
     s->max_queue = max_queue ? max_queue : 65536;
+    if (const char *ts = std::getenv("HEAT_SERVER_TICK_STEPS")) {
+        const long v = std::strtol(ts, nullptr, 10);
+        if (v >= 1 && v <= (1 << 20)) s->tick_steps = (int32_t)v;
+    }
     int rc = HEAT_OK;
     auto bail = [&](int code) {
         if (s->d_partial) (void)hipFree(s->d_partial);
