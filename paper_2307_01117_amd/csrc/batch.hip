@@ -27,17 +27,24 @@ int batch_cells_per_lane(int precision, int64_t N) {
 // much shorter than its window's natural depth only multiply launches and
 // scheduling steps (measured on MI355X: the long binary64 rings of the
 // serving mix at 64-step rounds doubled its latency at 1,000 requests/s).
-static int64_t batch_min_steps_per_round(int K) { return K >= 64 ? 160 : 96; }
+// Tiles of 4 cooperating waves share the outer halo, so deeper rounds pay
+// (as for the plain kernel, whose tuned binary64 shape is 4 waves and
+// 250-step rounds).
+static int64_t batch_min_steps_per_round(int K, int G) {
+    if (G > 1) return 240;
+    return K >= 64 ? 160 : 96;
+}
 
-int describe_ring(const heat_ring &g, BatchRing *out, int K) {
+int describe_ring(const heat_ring &g, BatchRing *out, int K, int G) {
     if (K == 0) K = batch_cells_per_lane(g.precision, g.N);
+    if (G < 1 || G > 8 || (G > 1 && K < 16)) return fail(HEAT_EINVAL, "bad batch tile shape");
     // the deepest rounds this class's window allows
     const int64_t Tmax = (64 * (int64_t)K / 3) & ~int64_t(3);
     int64_t Ttarget = default_steps_per_round(g.N, g.precision);
     // binary64/binary32 results do not depend on the round length; the
     // compensated form's fixed length is kept (and always fits)
     if (g.precision != HEAT_FP32C)
-        Ttarget = std::min(std::max(Ttarget, batch_min_steps_per_round(K)), Tmax);
+        Ttarget = std::min(std::max(Ttarget, batch_min_steps_per_round(K, G)), Tmax);
     const int64_t Teff = balanced_steps_per_round(g.nt, Ttarget, g.precision);
     BatchRing R{};
     R.buf[0] = g.d_u;
@@ -45,20 +52,39 @@ int describe_ring(const heat_ring &g, BatchRing *out, int K) {
     R.N = g.N;
     R.H = (int32_t)halo_cells(Teff, g.precision, K);
     R.T = (int32_t)Teff;
-    R.W = 64 * (int64_t)K - 2 * (int64_t)R.H;
+    R.W = window_tile_cells(K, R.H, G, G > 1);
     R.tiles = (g.N + R.W - 1) / R.W;
     R.r = g.r;
     R.nt = g.nt;
     const int64_t rounds = g.nt > 0 ? (g.nt + Teff - 1) / Teff : 0;
     if (rounds > (int64_t)1 << 30) return fail(HEAT_EINVAL, "too many rounds");
-    if (R.tiles * 64 > MAX_GRID_THREADS) return fail(HEAT_EINVAL, "ring too long for one launch");
+    if (R.tiles * 64 * G > MAX_GRID_THREADS) return fail(HEAT_EINVAL, "ring too long for one launch");
     R.rounds = (int32_t)rounds;
     R.copy_round = (int32_t)(rounds & 1);
     R.vec_ok = aligned16(g.d_u) && aligned16(g.d_work);
     R.flag_base = 0;
     R.round0 = 0;
     R.K = K;
+    R.G = G;
     *out = R;
+    return HEAT_OK;
+}
+
+int describe_ring_batch(const heat_ring &g, BatchRing *out) {
+    const int K = batch_cells_per_lane(g.precision, g.N);
+    int rc = describe_ring(g, out, K, 1);
+    if (rc || K != 64 || g.nt == 0) return rc;
+    // Cost in wave-steps: every tile costs its waves x (steps + a per-round
+    // overhead for loading and storing the window, about 4 steps' worth);
+    // the exchange's own steps cost about 1 % more.
+    BatchRing X;
+    if (describe_ring(g, &X, K, 4)) return HEAT_OK;   // keep the lone shape
+    const double over = 4.0;
+    auto cost = [&](const BatchRing &R) {
+        const double rounds = std::ceil((double)g.nt / R.T);
+        return (double)R.tiles * R.G * ((double)g.nt + over * rounds) * (R.G > 1 ? 1.01 : 1.0);
+    };
+    if (cost(X) < cost(*out)) *out = X;
     return HEAT_OK;
 }
 
@@ -78,6 +104,7 @@ int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision, in
                        int32_t tick_steps) {
     precision_ = precision;
     K_ = rings_in.empty() ? 32 : rings_in[0].K;
+    G_ = rings_in.empty() ? 1 : rings_in[0].G;
     rings_.clear();
     for (const BatchRing &R : rings_in)
         if (remaining_rounds(R) > 0) rings_.push_back(R);
@@ -107,7 +134,7 @@ int BatchLaunch::build(const std::vector<BatchRing> &rings_in, int precision, in
         round_start_[k + 1] = round_start_[k] + tile_prefix_[alive];
     }
     total_items_ = max_rounds_ ? round_start_[max_rounds_] : 0;
-    if (tile_prefix_[n] * 64 > MAX_GRID_THREADS)
+    if (tile_prefix_[n] * 64 * G_ > MAX_GRID_THREADS)
         return fail(HEAT_EINVAL, "batch has more tiles than one launch can hold");
     return HEAT_OK;
 }
@@ -136,7 +163,7 @@ int BatchLaunch::enqueue(void *dev_mem, hipStream_t st, bool persistent, bool gr
         const int wpg = 4;
         if (!graph) {
             for (int32_t k = 0; k < max_rounds_; ++k)
-                HEAT_HIP(launch_batch_round(precision_, K_, d.rings, d.tile_prefix, k, active_[k],
+                HEAT_HIP(launch_batch_round(precision_, K_, G_, d.rings, d.tile_prefix, k, active_[k],
                                             tile_prefix_[active_[k]], wpg, st));
             return HEAT_OK;
         }
@@ -147,7 +174,7 @@ int BatchLaunch::enqueue(void *dev_mem, hipStream_t st, bool persistent, bool gr
         HEAT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         for (int32_t k = 0; k < max_rounds_ && e == hipSuccess; ++k)
-            e = launch_batch_round(precision_, K_, d.rings, d.tile_prefix, k, active_[k],
+            e = launch_batch_round(precision_, K_, G_, d.rings, d.tile_prefix, k, active_[k],
                                    tile_prefix_[active_[k]], wpg, cs);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -206,7 +233,7 @@ int BatchLaunch::enqueue_rounds(void *dev_tables, void *host_staging, hipStream_
     const BatchRing *rings = (const BatchRing *)dev_tables;
     const int64_t *prefix = (const int64_t *)((char *)dev_tables + off);
     for (int32_t k = 0; k < max_rounds_; ++k)
-        HEAT_HIP(launch_batch_round(precision_, K_, rings, prefix, k, active_[k],
+        HEAT_HIP(launch_batch_round(precision_, K_, G_, rings, prefix, k, active_[k],
                                     tile_prefix_[active_[k]], 4, st));
     return HEAT_OK;
 }
@@ -244,20 +271,21 @@ int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
     // one launch sequence per (precision, K class); the persistent kernel
     // exists for 32-cell lanes only
     const bool persistent = (flags & HEAT_BATCH_PERSISTENT) != 0;
-    std::vector<BatchRing> groups[3][2];   // [precision][K == 64]
+    // classes: [precision][32-cell lanes, 64-cell lanes, 64-cell lanes x 4 waves per tile]
+    std::vector<BatchRing> groups[3][3];
     for (int32_t i = 0; i < count; ++i) {
         BatchRing R;
-        int rc = describe_ring(rings[i], &R, persistent ? 32 : 0);
+        int rc = persistent ? describe_ring(rings[i], &R, 32) : describe_ring_batch(rings[i], &R);
         if (rc) return rc;
-        groups[rings[i].precision][R.K == 64].push_back(R);
+        groups[rings[i].precision][R.G > 1 ? 2 : (R.K == 64)].push_back(R);
     }
     launches.clear();
     size_t total = 0;
     for (int prec = 0; prec < 3; ++prec)
-        for (int big = 0; big < 2; ++big) {
-            if (groups[prec][big].empty()) continue;
+        for (int cls = 0; cls < 3; ++cls) {
+            if (groups[prec][cls].empty()) continue;
             launches.emplace_back();
-            int rc = launches.back().build(groups[prec][big], prec);
+            int rc = launches.back().build(groups[prec][cls], prec);
             if (rc) return rc;
             total += launches.back().device_bytes();
         }

@@ -167,6 +167,40 @@ k_batch_round(const BatchRing *__restrict__ rings, const int64_t *__restrict__ t
     }
 }
 
+// Same round over tiles shared by the G waves of a workgroup (one tile per
+// workgroup, edge cells swapped through LDS; see window.h).
+template <class P, int K, int FORM>
+__global__ void __launch_bounds__(256)
+k_batch_round_x(const BatchRing *__restrict__ rings, const int64_t *__restrict__ tile_prefix,
+                int32_t k, int32_t active, int64_t items) {
+    using T = typename P::T;
+    extern __shared__ __align__(16) unsigned char heat_batch_xlds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int G = blockDim.x >> 6;
+    const int64_t id = xcd_remap(blockIdx.x, gridDim.x);   // one tile per workgroup
+    if (id >= items) return;
+    const int64_t p = upper_bound_i64(tile_prefix, (int64_t)active + 1, id) - 1;
+    const int64_t t = id - tile_prefix[p];
+    const BatchRing &R = rings[p];
+    const int64_t b = t * R.W;
+    const int32_t kk = R.round0 + k;
+    if (kk < R.rounds) {
+        const T *src = reinterpret_cast<const T *>(R.buf[kk & 1]);
+        T *dst = reinterpret_cast<T *>(R.buf[(kk + 1) & 1]);
+        const int64_t done = (int64_t)kk * R.T;
+        const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
+        window_tile<P, K, FORM, true>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0,
+                                      lane, nullptr, nullptr, 0, G, wave,
+                                      reinterpret_cast<T *>(heat_batch_xlds));
+    } else {
+        const T *src = reinterpret_cast<const T *>(R.buf[1]);
+        T *dst = reinterpret_cast<T *>(R.buf[0]);
+        const int64_t wlen = (R.N - b) < R.W ? (R.N - b) : R.W;
+        for (int64_t i = threadIdx.x; i < wlen; i += blockDim.x) dst[b + i] = src[b + i];
+    }
+}
+
 template <class P, int K>
 static hipError_t launch_batch_t(const BatchPlanDev &plan, int grid, int wpg, hipStream_t st) {
     hipLaunchKernelGGL((k_batch<P, K>), dim3(grid), dim3(64 * wpg), 0, st, plan);
@@ -182,11 +216,27 @@ static hipError_t launch_batch_round_t(const BatchRing *rings, const int64_t *ti
     return hipGetLastError();
 }
 
+template <class P, int K, int FORM>
+static hipError_t launch_batch_round_x(const BatchRing *rings, const int64_t *tile_prefix, int k,
+                                       int active, int64_t items, int G, hipStream_t st) {
+    const unsigned lds = (unsigned)exchange_lds_bytes<P>(K, G);
+    hipLaunchKernelGGL((k_batch_round_x<P, K, FORM>), dim3((unsigned)items), dim3(64 * G), lds, st,
+                       rings, tile_prefix, k, active, items);
+    return hipGetLastError();
+}
+
 // Kernel classes of the batch (the fastest register form of each, measured).
-hipError_t launch_batch_round(int precision, int K, const BatchRing *rings,
+hipError_t launch_batch_round(int precision, int K, int G, const BatchRing *rings,
                               const int64_t *tile_prefix, int k, int active, int64_t items, int wpg,
                               hipStream_t st) {
     if (items <= 0) return hipSuccess;
+    if (G > 1) {
+        if (G > 4) return hipErrorInvalidValue;
+        if (precision == HEAT_FP64 && K == 64)
+            return launch_batch_round_x<F64, 64, FORM_ALTERNATING>(rings, tile_prefix, k, active,
+                                                                   items, G, st);
+        return hipErrorInvalidValue;
+    }
     if (precision == HEAT_FP64 && K == 64)
         return launch_batch_round_t<F64, 64, FORM_ALTERNATING>(rings, tile_prefix, k, active, items,
                                                                wpg, st);

@@ -19,7 +19,11 @@ int validate_ring(const heat_ring &g);
 // Geometry of one ring in a batch: the tuned round length for its size,
 // raised to the kernel class's minimum (binary64/binary32) and balanced into
 // equal rounds like the plain planner; K = 0 picks batch_cells_per_lane.
-int describe_ring(const heat_ring &g, BatchRing *out, int K = 0);
+// G > 1: G waves share each tile and swap edges through LDS (K >= 16).
+int describe_ring(const heat_ring &g, BatchRing *out, int K = 0, int G = 1);
+// Batching form's shape for a ring: 32- or 64-cell lanes, and for long
+// binary64 rings 4 waves per tile when that costs fewer wave-steps.
+int describe_ring_batch(const heat_ring &g, BatchRing *out);
 
 // Rounds a ring advances in one scheduling step: its remaining rounds
 // (copy-back included), at most `cap` (0 = no cap) or, with tick_steps > 0,
@@ -58,6 +62,7 @@ class BatchLaunch {
   private:
     int precision_ = 0;
     int K_ = 16;
+    int G_ = 1;
     std::vector<BatchRing> rings_;
     std::vector<int64_t> tile_prefix_;
     std::vector<int64_t> round_start_;

@@ -134,7 +134,7 @@ struct BatchRing {          // one ring of a fused launch (device table entry)
     int32_t vec_ok;         // both buffers 16-byte aligned
     int32_t round0;         // rounds already done before this launch sequence
     int32_t K;              // cells per lane of the kernel class that runs it
-    int32_t pad;
+    int32_t G;              // waves sharing one tile (1: a wave per tile; >1: LDS exchange)
 };
 
 struct BatchPlanDev {       // device pointers of one fused launch
@@ -154,7 +154,9 @@ struct BatchPlanDev {       // device pointers of one fused launch
 hipError_t launch_batch(int precision, int K, const BatchPlanDev &plan, int grid, int wpg,
                         hipStream_t st);
 // One round of every active ring (rings[0, active) in the sorted table).
-hipError_t launch_batch_round(int precision, int K, const BatchRing *rings,
+// G = 1: one wave per tile, wpg waves per workgroup; G > 1: one workgroup of
+// G waves per tile (LDS edge exchange; wpg ignored).
+hipError_t launch_batch_round(int precision, int K, int G, const BatchRing *rings,
                               const int64_t *tile_prefix, int k, int active, int64_t items, int wpg,
                               hipStream_t st);
 int batch_grid_size(int precision, int K, int wpg, int *grid);

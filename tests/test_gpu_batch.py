@@ -152,6 +152,39 @@ def test_device_batch_large_rings_sampled():
                 assert u[i].item() == oracle.cone(u0, i, s.r, s.nt), (s.N, s.nt, i)
 
 
+def test_device_batch_long_rings_all_classes():
+    """Long binary64 rings (64K to 3M cells; the longest run as tiles of 4
+    waves that swap edges through LDS, the others as one wave per tile) with
+    short and odd step counts, in one batch with short rings: every ring bit
+    for bit equal to the ring solved alone, and sampled cells (tile edges,
+    edges between the waves of a tile) equal to the oracle's light cones."""
+    rng = np.random.default_rng(49)
+    Ns = [65_536, 100_003, 250_000, 1_000_001, 3_000_017, 777, 20_000]
+    nts = [301, 77, 600, 451, 128, 999, 64]
+    us, u0s = [], []
+    for k, N in enumerate(Ns):
+        u0 = inputs.uniform_ring(N, (50, k))
+        u0s.append(u0)
+        us.append(torch.from_numpy(u0).cuda())
+    work = [torch.empty_like(u) for u in us]
+    rs = [float(0.5 - 0.4 * rng.random()) for _ in Ns]
+    heat.solve_batch_dev([(u, w, nt, r, heat.FP64) for u, w, nt, r in zip(us, work, nts, rs)])
+    torch.cuda.synchronize()
+    for k, (N, nt, r, u0, u) in enumerate(zip(Ns, nts, rs, u0s, us)):
+        a = torch.from_numpy(u0).cuda()
+        heat.solve_dev(a, 1, r, nt)
+        assert torch.equal(u, a), (N, nt)
+        # tile and wave edges of both tile shapes the batch may have used
+        cells = {0, N - 1, int(rng.integers(0, N))}
+        for W, step in ((64 * 64 - 2 * 256, 0), (4 * 4096 - 3 * 32 - 2 * 256, 4096 - 32)):
+            for t in (1, 2):
+                cells.update({(t * W + d) % N for d in (-1, 0, 1)})
+                if step:
+                    cells.update({(t * W + step + 16 - 256 + d) % N for d in (-1, 0, 1)})
+        for i in sorted(cells):
+            assert u[i].item() == oracle.cone(u0, i, r, nt), (N, nt, i)
+
+
 def test_device_batch_empty_and_zero_steps():
     heat.solve_batch_dev([])
     u = torch.rand(1000, device="cuda", dtype=torch.float64)
