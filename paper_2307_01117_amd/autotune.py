@@ -23,9 +23,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--sizes", default="1e3,1e4,1e5,1e6,1e7,1e8")
+    ap.add_argument("--precisions", default="fp64,fp32,fp32c",
+                    help="precisions to tune; the others keep the loaded table's entries")
     args = ap.parse_args()
     heat.load()
-    for name, prec in heat.PRECISIONS.items():
+    for name in args.precisions.split(","):
+        prec = heat.PRECISIONS[name]
         for n in args.sizes.split(","):
             N = int(float(n))
             cfg, g = heat.autotune(prec, N, install=True)

@@ -102,14 +102,40 @@ __device__ __forceinline__ float cell_update(float l, float c, float q, float r)
 // corrupt the window's outer cells (the trapezoid shrinks by one per step).
 template <int K, class T>
 __device__ __forceinline__ void window_step(T (&v)[K], T r) {
-    T prev = from_prev(v[K - 1]);
-    const T right = from_next(v[0]);
+    if constexpr (sizeof(T) == 4 && K >= 16) {
+        // binary32: two interleaved sweeps, chain a over [0, M) and chain b
+        // over [M, K), M = K/2 + 1.  Same per-cell arithmetic (bit-identical);
+        // measured on MI355X 2 % faster for the in-place form, whose issue
+        // rate is set by how often two VALU instructions pair in a cycle.
+        constexpr int M = K / 2 + 1;
+        constexpr int NB = K - M;
+        T pa = from_prev(v[K - 1]);
+        const T right = from_next(v[0]);
+        T pb = v[M - 1];
+        const T ra = v[M];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const T c = v[j];
-        const T q = (j + 1 < K) ? v[j + 1] : right;
-        v[j] = cell_update(prev, c, q, r);
-        prev = c;
+        for (int j = 0; j < M; ++j) {
+            const T ca = v[j];
+            const T qa = (j + 1 < M) ? v[j + 1] : ra;
+            v[j] = cell_update(pa, ca, qa, r);
+            pa = ca;
+            if (j < NB) {
+                const T cb = v[M + j];
+                const T qb = (M + j + 1 < K) ? v[M + j + 1] : right;
+                v[M + j] = cell_update(pb, cb, qb, r);
+                pb = cb;
+            }
+        }
+    } else {
+        T prev = from_prev(v[K - 1]);
+        const T right = from_next(v[0]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const T c = v[j];
+            const T q = (j + 1 < K) ? v[j + 1] : right;
+            v[j] = cell_update(prev, c, q, r);
+            prev = c;
+        }
     }
 }
 
@@ -136,14 +162,40 @@ __device__ __forceinline__ void window_step_pp(const T (&a)[K], T (&b)[K], T r) 
 // only K + 1 registers (the alternating register form).
 template <int K, class T>
 __device__ __forceinline__ void window_step_bwd(T (&v)[K], T r) {
-    const T left = from_prev(v[K - 1]);
-    T next = from_next(v[0]);
+    if constexpr (sizeof(T) == 4 && K >= 16) {
+        // chain a: cells K-1 .. M (NB cells); chain b: cells M-1 .. 0 (M
+        // cells), M = K/2 + 1, as in the forward sweep
+        constexpr int M = K / 2 + 1;
+        constexpr int NB = K - M;
+        const T left = from_prev(v[K - 1]);
+        T na = from_next(v[0]);
+        T nb = v[M];
+        const T lb = v[M - 1];
 #pragma unroll
-    for (int j = K - 1; j >= 0; --j) {
-        const T c = v[j];
-        const T l = j > 0 ? v[j - 1] : left;
-        v[j] = cell_update(l, c, next, r);
-        next = c;
+        for (int j = 0; j < M; ++j) {
+            if (j < NB) {
+                const int ia = K - 1 - j;
+                const T ca = v[ia];
+                const T la = ia > M ? v[ia - 1] : lb;
+                v[ia] = cell_update(la, ca, na, r);
+                na = ca;
+            }
+            const int ib = M - 1 - j;
+            const T cb = v[ib];
+            const T l2 = ib > 0 ? v[ib - 1] : left;
+            v[ib] = cell_update(l2, cb, nb, r);
+            nb = cb;
+        }
+    } else {
+        const T left = from_prev(v[K - 1]);
+        T next = from_next(v[0]);
+#pragma unroll
+        for (int j = K - 1; j >= 0; --j) {
+            const T c = v[j];
+            const T l = j > 0 ? v[j - 1] : left;
+            v[j] = cell_update(l, c, next, r);
+            next = c;
+        }
     }
 }
 
