@@ -248,6 +248,17 @@ def main():
         achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+        # the achievable bandwidth: the library's streaming copy of the same
+        # bytes, timed here on the same stream
+        heat.copy_dev(d_u, d_work, stream)
+        ev[0].record(stream)
+        for _ in range(20):
+            heat.copy_dev(d_u, d_work, stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = alg_bytes / (ev[0].elapsed_time(ev[1]) / 20 * 1e-3) / 1e9
+        roof["copy_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
     else:
         # temporal blocking moves 2*es bytes per cell per T steps; it is
         # limited by the vector ALU: achieved = minimal lane operations of the
@@ -259,7 +270,12 @@ def main():
         roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "Tops/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
                 "hbm_algorithmic_GBs": round(hbm, 1),
-                "hbm_frac": round(hbm / HBM_PEAK_GBS, 4)}
+                "hbm_frac": round(hbm / HBM_PEAK_GBS, 4),
+                # cell updates per second against the roofline of one step per
+                # launch (every step reads and writes the state: 2*es bytes per
+                # cell update at 8 TB/s); temporal blocking exceeds it T-fold
+                "vs_one_step_hbm_roofline": round(N * steps_per_launch / (k_avg_ms * 1e-3)
+                                                  / (HBM_PEAK_GBS * 1e9 / (2 * es)), 2)}
     roof["kernel"] = ("k_step" if pl["kernel"] == heat.KERNEL_STEP else "k_window")
     roof["traffic"] = measured_traffic(roof["kernel"], args.workload, prec_name, pl)
     roof["avg_launch_ms"] = round(k_avg_ms, 4)

@@ -152,6 +152,29 @@ def test_device_batch_large_rings_sampled():
                 assert u[i].item() == oracle.cone(u0, i, s.r, s.nt), (s.N, s.nt, i)
 
 
+def test_device_batch_seeded_256_ring_subset():
+    """A seeded subset of 256 rings of the full batching workload (4,096 rings,
+    N log-uniform in [1e3, 1e6], nt uniform in [100, 10,000], r in (0.1, 0.5]),
+    batched in binary64 in the benchmark's configuration: every ring bit for
+    bit equal to the same ring solved alone, and one sampled cell of every
+    ring equal to the oracle's light cone of that cell."""
+    specs = inputs.batch_specs(count=4096, seed=4)
+    pick = np.random.default_rng(51).choice(len(specs), size=256, replace=False)
+    specs = [specs[j] for j in sorted(pick)]
+    u0s = [inputs.ring_initial(s) for s in specs]
+    us = [torch.from_numpy(u).cuda() for u in u0s]
+    work = [torch.empty_like(u) for u in us]
+    heat.solve_batch_dev([(u, w, s.nt, s.r, heat.FP64) for u, w, s in zip(us, work, specs)])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(52)
+    for s, u0, u in zip(specs, u0s, us):
+        a = torch.from_numpy(u0).cuda()
+        heat.solve_dev(a, s.nparts, s.r, s.nt)
+        assert torch.equal(u, a), (s.N, s.nt)
+        i = int(rng.integers(0, s.N))
+        assert u[i].item() == oracle.cone(u0, i, s.r, s.nt), (s.N, s.nt, i)
+
+
 def test_device_batch_long_rings_all_classes():
     """Long binary64 rings (64K to 3M cells; the longest run as tiles of 4
     waves that swap edges through LDS, the others as one wave per tile) with
