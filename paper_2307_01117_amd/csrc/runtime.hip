@@ -269,6 +269,36 @@ struct DevBuf {   // stream-ordered scratch, freed on the same stream
     }
 };
 
+// Checksum scratch per thread and device: device partials and results, and
+// a pinned host landing spot for the two sums.  A call that asks for sums
+// waits for its stream before it returns, so the next call from the same
+// thread always finds the buffers idle.  Grown on demand and kept until the
+// process ends (never freed: the runtime may be gone by thread exit), so a
+// small ring's pass makes no allocation call.
+struct SumCache {
+    double *d = nullptr;   // device: partials + 2 results
+    size_t cap = 0;        // doubles held by d
+    double *h = nullptr;   // pinned host: 2 doubles
+};
+static thread_local SumCache g_sum_cache[64];
+
+static int sum_scratch(size_t doubles, SumCache **out) {
+    int dev = 0;
+    HEAT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(HEAT_EDEVICE, "device %d out of range", dev);
+    SumCache &c = g_sum_cache[dev];
+    if (!c.h) HEAT_HIP(hipHostMalloc((void **)&c.h, 2 * sizeof(double), hipHostMallocDefault));
+    if (c.cap < doubles) {
+        if (c.d) HEAT_HIP(hipFree(c.d));   // idle: the last call waited for its stream
+        c.d = nullptr;
+        c.cap = 0;
+        HEAT_HIP(hipMalloc((void **)&c.d, doubles * sizeof(double)));
+        c.cap = doubles;
+    }
+    *out = &c;
+    return HEAT_OK;
+}
+
 static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, double r, int64_t nt,
                           int32_t precision, const heat_config *cfg, hipStream_t st,
                           double *sum0_out, double *sum_out) {
@@ -286,13 +316,15 @@ static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, do
     rc = device_pool_setup();
     if (rc) return rc;
     const bool want_sums = sum0_out || sum_out;
-    DevBuf sums, work;
-    sums.st = work.st = st;
+    DevBuf work;
+    work.st = st;
     SumArea area;
+    SumCache *cache = nullptr;
     if (want_sums) {
         const int64_t np = std::max<int64_t>(SUM_BLOCKS, 2 * pl.parts);
-        HEAT_HIP(hipMallocAsync(&sums.p, (size_t)(np + 2) * sizeof(double), st));
-        area.partial = (double *)sums.p;
+        rc = sum_scratch((size_t)(np + 2), &cache);
+        if (rc) return rc;
+        area.partial = cache->d;
         area.d_out = area.partial + np;
     }
     void *b = d_work;
@@ -301,13 +333,16 @@ static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, do
         b = work.p;
     }
     rc = run_rounds(pl, precision, d_u, b, N, r, nt, st, want_sums ? &area : nullptr);
-    if (rc) return rc;
+    if (rc) {
+        // the cached scratch must be idle when this thread calls again
+        if (want_sums) (void)hipStreamSynchronize(st);
+        return rc;
+    }
     if (want_sums) {
-        double h[2];
-        HEAT_HIP(hipMemcpyAsync(h, area.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HEAT_HIP(hipMemcpyAsync(cache->h, area.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         HEAT_HIP(hipStreamSynchronize(st));
-        if (sum0_out) *sum0_out = h[0];
-        if (sum_out) *sum_out = h[1];
+        if (sum0_out) *sum0_out = cache->h[0];
+        if (sum_out) *sum_out = cache->h[1];
     }
     return HEAT_OK;
 }
