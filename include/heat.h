@@ -248,6 +248,10 @@ typedef struct heat_server_stats {
  * device arena of hbm_budget_bytes (0 = 80 % of the free device memory), a
  * scheduler thread and its streams.  At most max_slots requests (0 = 4096)
  * are resident at once; max_queue (0 = 65536) may wait for admission.
+ * Every scheduling step (tick) advances each resident request by 2 rounds;
+ * the environment variable HEAT_SERVER_TICK_STEPS, read here, instead sizes
+ * ticks in steps (each request advances the whole rounds that cover that
+ * many steps).  Ticks never change a result.
  */
 int heat_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t max_queue,
                        heat_server **out);

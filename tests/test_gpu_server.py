@@ -109,6 +109,20 @@ def test_mean_shifted_requests():
         assert np.array_equal(res.u, want), (u0.size, nt, prec, sh)
 
 
+def test_tick_size_does_not_change_results(monkeypatch):
+    """Ticks sized in steps (HEAT_SERVER_TICK_STEPS) regroup the rounds of
+    the resident requests; every result stays bit-identical to the request
+    solved alone."""
+    reqs = requests(72, 24, nmax=150_000, ntmax=1200)
+    for steps in ("64", "500"):
+        monkeypatch.setenv("HEAT_SERVER_TICK_STEPS", steps)
+        with heat.Server(hbm_budget=1 << 30) as s:
+            outs = [s.wait(t) for t in [s.submit(*q) for q in reqs]]
+        for q, res in zip(reqs, outs):
+            assert res.status == heat.HEAT_OK
+            assert np.array_equal(res.u, alone(*q)), (steps, q[0].size, q[1], q[3])
+
+
 def test_budget_admission_and_enomem():
     budget = 24 << 20     # fits one 1e6-cell binary64 request (16 MB), not two
     with heat.Server(hbm_budget=budget) as s:
