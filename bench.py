@@ -72,6 +72,10 @@ def parse():
                     help="batch: skip solving the rings one by one for comparison")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="time steps of the full ring the CPU oracle runs as its sample")
+    ap.add_argument("--no-cpu-threads", action="store_true",
+                    help="skip the thread axis of the threaded CPU oracle (binary64 ring only)")
+    ap.add_argument("--cpu-thread-steps", type=int, default=5,
+                    help="time steps of the full ring per thread count on the thread axis")
     return ap.parse_args()
 
 
@@ -156,6 +160,52 @@ def cpu_baseline(u0, r, steps, precision, T):
     return {"value": round(u0.size * steps / dt / 1e9, 4), "unit": "GCUP/s", "cores": 1,
             "kind": "oracle",
             "sample": f"full ring of {u0.size} cells, {steps} steps ({dt:.1f} s, single thread)"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_threads(u0, r, steps, workload, max_threads=16):
+    """The paper's own CPU method, timed along its thread axis: one thread per
+    segment, ghost cells through single-producer single-consumer queues (the
+    threaded oracle; every thread count gives the same bits).  Two samples:
+    the paper's workload (ramp, 1e6 cells, 1,000 steps) and a few steps of the
+    full ring timed above."""
+    import numpy as np
+
+    import oracle
+    from paper_2307_01117_amd import inputs
+    avail = len(os.sched_getaffinity(0))
+    threads = [t for t in (1, 2, 4, 8, 16) if t <= min(avail, max_threads)]
+    ramp = inputs.WORKLOADS["paper_ramp_1e6"]
+    samples = [("paper_ramp_1e6", inputs.make_initial(ramp["init"], ramp["N"], ramp["seed"]),
+                ramp["r"], ramp["nt"]),
+               (f"{workload}, {steps} steps", u0, r, steps)]
+    res = {}
+    for name, u, rr, nt in samples:
+        rates, ref, same = [], None, True
+        for t in threads:
+            t0 = time.perf_counter()
+            out = oracle.solve_threads(u, t, rr, nt)
+            dt = time.perf_counter() - t0
+            rates.append(round(u.size * nt / dt / 1e9, 4))
+            if ref is None:
+                ref = out
+            else:
+                same = same and bool(np.array_equal(out, ref))
+            del out
+        res[name] = {"N": int(u.size), "nt": int(nt), "value": rates,
+                     "bitwise_equal_across_threads": same}
+    return {"kind": "oracle_threads", "unit": "GCUP/s", "threads": threads,
+            "cores_available": avail, "cpu": cpu_model(), "samples": res}
 
 
 def main():
@@ -316,6 +366,8 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u0, r, args.cpu_steps, prec_name,
                                            heat.plan(N, nt, prec)["steps_per_round"])
+    if not args.no_cpu_threads and prec_name == "fp64" and args.cpu_thread_steps > 0:
+        out["cpu_threads"] = cpu_threads(u0, r, args.cpu_thread_steps, args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -7,7 +7,8 @@ calls it and shares no code with it.
 Two independent implementations of the same definition live here:
 
 * ``heat_oracle.c`` (plain C, built with ``-O2 -ffp-contract=off``), loaded
-  through ctypes: ``solve``, ``solve_parts``, ``cone``, ``solve_f32``,
+  through ctypes: ``solve``, ``solve_parts``, ``solve_threads`` (one POSIX
+  thread per segment, ghost cells through queues), ``cone``, ``solve_f32``,
   ``cone_f32``, ``solve_f32c``, ``cone_f32c`` (and, composed around the
   binary32 ones in NumPy, the mean-shifted storage ``solve_f32_shifted``,
   ``solve_f32c_shifted``);
@@ -42,7 +43,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB + ".tmp"
         subprocess.check_call([
             "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-            "-fexcess-precision=standard", "-shared", "-fPIC", "-o", tmp, _SRC,
+            "-fexcess-precision=standard", "-pthread", "-shared", "-fPIC", "-o", tmp, _SRC,
         ])
         os.replace(tmp, _LIB)
     return _LIB
@@ -61,6 +62,8 @@ def _load():
     lib.heat_oracle_solve.restype = None
     lib.heat_oracle_solve_parts.argtypes = [p, p, i64, i64, d, i64]
     lib.heat_oracle_solve_parts.restype = None
+    lib.heat_oracle_solve_threads.argtypes = [p, p, i64, i64, d, i64]
+    lib.heat_oracle_solve_threads.restype = ctypes.c_int
     lib.heat_oracle_cone.argtypes = [p, i64, d]
     lib.heat_oracle_cone.restype = d
     lib.heat_oracle_solve_f32.argtypes = [p, p, i64, f, i64]
@@ -105,6 +108,21 @@ def solve_parts(u0, nparts: int, r: float, nt: int) -> np.ndarray:
         raise ValueError("need 1 <= nparts <= N")
     out = np.empty_like(a)
     _load().heat_oracle_solve_parts(_ptr(a), _ptr(out), a.size, int(nparts), float(r), int(nt))
+    return out
+
+
+def solve_threads(u0, nparts: int, r: float, nt: int) -> np.ndarray:
+    """The same segmented solver with one thread per segment and the ghost
+    cells passed through single-producer single-consumer queues, as the
+    paper's CPU codes run it (Section 2, last paragraph)."""
+    a = _f64(u0)
+    if not 1 <= nparts <= min(a.size, 4096) or nt < 0:
+        raise ValueError("need 1 <= nparts <= min(N, 4096) and nt >= 0")
+    out = np.empty_like(a)
+    rc = _load().heat_oracle_solve_threads(_ptr(a), _ptr(out), a.size, int(nparts),
+                                           float(r), int(nt))
+    if rc != 0:
+        raise MemoryError(f"threaded oracle failed ({rc}): no memory or threads")
     return out
 
 

@@ -44,6 +44,7 @@
  * (N < 1 or nt < 0 do nothing); r is NOT range-checked, so unstable r can be
  * exercised as a negative control.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -128,6 +129,173 @@ void heat_oracle_solve_parts(const double *u0, double *out, int64_t N, int64_t n
     free(seg);
     free(nxt);
     free(start);
+}
+
+/*
+ * Threaded partitioned solver: the parallel algorithm of Section 2 as the
+ * paper runs it on a CPU.  One thread per segment applies the update to its
+ * own segment, step after step; ghost cells travel between neighbouring
+ * segments through single-producer single-consumer queues (a mutex and a
+ * condition variable guard each queue, as in the paper's hand-written C++17
+ * queue).  Segment p pushes its last cell to p+1 (which uses it as its left
+ * ghost) and its first cell to p-1 (its right ghost), then pops its own two
+ * ghosts.  Every queue is FIFO, so a ghost popped at step n is the
+ * neighbour's value at step n however far the threads drift apart, and the
+ * result equals heat_oracle_solve exactly.
+ *
+ * Each thread allocates and fills its own segment (first touch on its own
+ * NUMA node).  A start gate holds every thread until all have allocated, so
+ * a failed allocation or thread creation aborts them all before any queue is
+ * used.  Returns 0, -1 for bad arguments (N < 1, nparts outside
+ * [1, min(N, 4096)], nt < 0), -2 if memory or a thread could not be had.
+ */
+#define GHOST_QUEUE_CAP 4
+
+typedef struct {
+    pthread_mutex_t m;
+    pthread_cond_t cv;
+    double slot[GHOST_QUEUE_CAP];
+    int64_t pushed, popped;
+} ghost_queue;
+
+static void ghost_push(ghost_queue *q, double v)
+{
+    pthread_mutex_lock(&q->m);
+    while (q->pushed - q->popped == GHOST_QUEUE_CAP) pthread_cond_wait(&q->cv, &q->m);
+    q->slot[q->pushed % GHOST_QUEUE_CAP] = v;
+    q->pushed++;
+    pthread_cond_broadcast(&q->cv);
+    pthread_mutex_unlock(&q->m);
+}
+
+static double ghost_pop(ghost_queue *q)
+{
+    pthread_mutex_lock(&q->m);
+    while (q->pushed == q->popped) pthread_cond_wait(&q->cv, &q->m);
+    double v = q->slot[q->popped % GHOST_QUEUE_CAP];
+    q->popped++;
+    pthread_cond_broadcast(&q->cv);
+    pthread_mutex_unlock(&q->m);
+    return v;
+}
+
+typedef struct {
+    pthread_mutex_t m;
+    pthread_cond_t cv;
+    int64_t ready;  /* threads that finished allocating (successfully or not) */
+    int failed;     /* some thread could not allocate, or a thread was not created */
+    int state;      /* 0 wait, 1 run, -1 abort */
+} start_gate;
+
+typedef struct {
+    const double *u0;
+    double *out;
+    int64_t start, len, nt;
+    double r;
+    ghost_queue *from_left, *from_right;  /* my ghosts arrive here */
+    ghost_queue *to_right, *to_left;      /* my edge cells leave here */
+    start_gate *gate;
+} segment_task;
+
+static void *segment_worker(void *arg)
+{
+    segment_task *t = (segment_task *)arg;
+    int64_t len = t->len;
+    double *a = (double *)malloc((size_t)(len + 2) * sizeof(double));
+    double *b = (double *)malloc((size_t)(len + 2) * sizeof(double));
+    if (a) memcpy(a + 1, t->u0 + t->start, (size_t)len * sizeof(double));
+
+    start_gate *g = t->gate;
+    pthread_mutex_lock(&g->m);
+    if (!a || !b) g->failed = 1;
+    g->ready++;
+    pthread_cond_broadcast(&g->cv);
+    while (g->state == 0) pthread_cond_wait(&g->cv, &g->m);
+    int run = g->state == 1;
+    pthread_mutex_unlock(&g->m);
+
+    if (run) {
+        double r = t->r;
+        for (int64_t n = 0; n < t->nt; ++n) {
+            ghost_push(t->to_right, a[len]);
+            ghost_push(t->to_left, a[1]);
+            a[0] = ghost_pop(t->from_left);
+            a[len + 1] = ghost_pop(t->from_right);
+            for (int64_t j = 1; j <= len; ++j) {
+                double l = a[j - 1], c = a[j], q = a[j + 1];
+                b[j] = c + r * ((l - 2.0 * c) + q);
+            }
+            double *s = a; a = b; b = s;
+        }
+        memcpy(t->out + t->start, a + 1, (size_t)len * sizeof(double));
+    }
+    free(a);
+    free(b);
+    return NULL;
+}
+
+int heat_oracle_solve_threads(const double *u0, double *out, int64_t N, int64_t nparts,
+                              double r, int64_t nt)
+{
+    if (N < 1 || nparts < 1 || nparts > N || nparts > 4096 || nt < 0) return -1;
+    int64_t P = nparts;
+    ghost_queue *from_left = (ghost_queue *)calloc((size_t)P, sizeof(ghost_queue));
+    ghost_queue *from_right = (ghost_queue *)calloc((size_t)P, sizeof(ghost_queue));
+    segment_task *task = (segment_task *)calloc((size_t)P, sizeof(segment_task));
+    pthread_t *tid = (pthread_t *)calloc((size_t)P, sizeof(pthread_t));
+    if (!from_left || !from_right || !task || !tid) {
+        free(from_left); free(from_right); free(task); free(tid);
+        return -2;
+    }
+    start_gate gate;
+    pthread_mutex_init(&gate.m, NULL);
+    pthread_cond_init(&gate.cv, NULL);
+    gate.ready = 0;
+    gate.failed = 0;
+    gate.state = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        pthread_mutex_init(&from_left[p].m, NULL);
+        pthread_cond_init(&from_left[p].cv, NULL);
+        pthread_mutex_init(&from_right[p].m, NULL);
+        pthread_cond_init(&from_right[p].cv, NULL);
+    }
+    for (int64_t p = 0; p < P; ++p) {
+        segment_task *t = &task[p];
+        t->u0 = u0;
+        t->out = out;
+        t->start = (p * N) / P;
+        t->len = ((p + 1) * N) / P - t->start;
+        t->nt = nt;
+        t->r = r;
+        t->from_left = &from_left[p];
+        t->from_right = &from_right[p];
+        t->to_right = &from_left[(p + 1) % P];
+        t->to_left = &from_right[(p - 1 + P) % P];
+        t->gate = &gate;
+    }
+    int64_t created = 0;
+    while (created < P && pthread_create(&tid[created], NULL, segment_worker, &task[created]) == 0)
+        ++created;
+
+    pthread_mutex_lock(&gate.m);
+    if (created < P) gate.failed = 1;
+    while (gate.ready < created) pthread_cond_wait(&gate.cv, &gate.m);
+    int ok = !gate.failed;
+    gate.state = ok ? 1 : -1;
+    pthread_cond_broadcast(&gate.cv);
+    pthread_mutex_unlock(&gate.m);
+    for (int64_t p = 0; p < created; ++p) pthread_join(tid[p], NULL);
+
+    for (int64_t p = 0; p < P; ++p) {
+        pthread_mutex_destroy(&from_left[p].m);
+        pthread_cond_destroy(&from_left[p].cv);
+        pthread_mutex_destroy(&from_right[p].m);
+        pthread_cond_destroy(&from_right[p].cv);
+    }
+    pthread_mutex_destroy(&gate.m);
+    pthread_cond_destroy(&gate.cv);
+    free(from_left); free(from_right); free(task); free(tid);
+    return ok ? 0 : -2;
 }
 
 /*

@@ -17,3 +17,26 @@ def test_arena_bookkeeping(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr
     assert "arena ok" in out.stdout
+
+
+# ------------------------------------------------------------ bench.py host legs
+
+def test_bench_refuses_more_than_one_gpu():
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stdout
+
+
+def test_bench_thread_axis_is_bitwise_stable():
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2307_01117_amd import inputs
+    u0 = inputs.make_initial("uniform", 50_001, 1)
+    rep = bench.cpu_threads(u0, 0.5, 3, "ring_50001", max_threads=2)
+    assert rep["kind"] == "oracle_threads" and rep["threads"][0] == 1
+    for name, s in rep["samples"].items():
+        assert s["bitwise_equal_across_threads"], name
+        assert len(s["value"]) == len(rep["threads"]) and min(s["value"]) > 0

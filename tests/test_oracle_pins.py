@@ -66,6 +66,8 @@ def test_brute_force_exact_fp64(N):
         for P in range(1, N + 1):
             gp = oracle.solve_parts(u0, P, float(r), nt)
             assert as_fractions(gp) == want, (N, P, r, nt)
+            gt = oracle.solve_threads(u0, P, float(r), nt)
+            assert as_fractions(gt) == want, ("threads", N, P, r, nt)
         assert as_fractions(oracle.np_solve(u0, float(r), nt)) == want
 
 
@@ -208,6 +210,31 @@ def test_partition_invariance():
     want = oracle.solve(u0, 0.5, 37)
     for P in (1, 2, 3, 10, 40, 1000, N):
         assert np.array_equal(oracle.solve_parts(u0, P, 0.5, 37), want), P
+    for P in (1, 2, 3, 16, 64):
+        assert np.array_equal(oracle.solve_threads(u0, P, 0.5, 37), want), ("threads", P)
+
+
+def test_threaded_segments_ragged_and_long():
+    """One thread per segment with queued ghost cells: ragged segments (P does
+    not divide N), more steps than the ghost queues hold, every thread count
+    bitwise equal to the unpartitioned ring."""
+    N = 20_011
+    u0 = inputs.uniform_ring(N, 12)
+    want = oracle.solve(u0, 0.375, 301)
+    for P in (1, 2, 5, 7, 33):
+        assert np.array_equal(oracle.solve_threads(u0, P, 0.375, 301), want), P
+    assert np.array_equal(oracle.solve_threads(u0, 7, 0.375, 0), u0)
+
+
+def test_threaded_rejects_bad_arguments():
+    u0 = inputs.uniform_ring(8, 13)
+    for P, nt in ((0, 1), (9, 1), (2, -1)):
+        with pytest.raises(ValueError):
+            oracle.solve_threads(u0, P, 0.5, nt)
+    lib = oracle._load()
+    out = np.empty_like(u0)
+    assert lib.heat_oracle_solve_threads(u0.ctypes.data, out.ctypes.data, 8, 9, 0.5, 1) == -1
+    assert lib.heat_oracle_solve_threads(u0.ctypes.data, out.ctypes.data, 0, 1, 0.5, 1) == -1
 
 
 def test_shift_composition_scaling():
