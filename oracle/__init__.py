@@ -140,7 +140,7 @@ def cone(u0, i: int, r: float, nt: int) -> float:
 
 
 def solve_f32(u0, r: float, nt: int) -> np.ndarray:
-    """Plain binary32 form: c + r*((l - c) + (q - c))."""
+    """Plain binary32 form: c + r*((q - c) - (c - l))."""
     a = _f32(u0)
     out = np.empty_like(a)
     if a.size:
@@ -223,7 +223,7 @@ def np_solve_f32(u0, r: float, nt: int) -> np.ndarray:
     for _ in range(int(nt)):
         left = np.roll(a, 1)
         right = np.roll(a, -1)
-        a = a + r * ((left - a) + (right - a))
+        a = a + r * ((right - a) - (a - left))
     return a
 
 
@@ -237,7 +237,7 @@ def np_solve_f32c(u0, r: float, nt: int, T: int) -> np.ndarray:
         for _ in range(s):
             l, q = np.roll(u, 1), np.roll(u, -1)
             el, eq = np.roll(e, 1), np.roll(e, -1)
-            d = r * (((l - u) + (q - u)) + ((el - e) + (eq - e)))
+            d = r * (((q - u) - (u - l)) + ((eq - e) - (e - el)))
             y = d + e
             t = u + y
             e = y - (t - u)

@@ -27,12 +27,14 @@
  * 2.0*c is exact, so (l - 2.0*c) + q is the left-to-right reading of the
  * paper's numerator.
  *
- * The FP32 forms are not in the paper; they are the reduced-precision forms of
- * the same update that the GPU library offers:
- *   - plain FP32:  new = c + r * ((l - c) + (q - c))   (all in binary32)
+ * The FP32 forms are not in the paper (it computes in binary64); they are the
+ * reduced-precision forms of the same update that the GPU library offers.
+ * Their second difference is written as the difference of the two one-sided
+ * differences (the flux form of the numerator of Eq. (heat:discrete)):
+ *   - plain FP32:  new = c + r * ((q - c) - (c - l))   (all in binary32)
  *   - compensated FP32: the state is the unevaluated sum u + e of two binary32
  *     numbers.  One step is
- *         d  = r * (((l - c) + (q - c)) + ((el - ec) + (eq - ec)))
+ *         d  = r * (((q - c) - (c - l)) + ((eq - ec) - (ec - el)))
  *         y  = d + ec
  *         t  = c + y
  *         e' = y - (t - c)          (Fast2Sum error term of c + y)
@@ -337,7 +339,7 @@ void heat_oracle_solve_f32(const float *u0, float *out, int64_t N, float r, int6
             float l = a[(i - 1 + N) % N];
             float c = a[i];
             float q = a[(i + 1) % N];
-            b[i] = c + r * ((l - c) + (q - c));
+            b[i] = c + r * ((q - c) - (c - l));
         }
         float *t = a; a = b; b = t;
     }
@@ -355,7 +357,7 @@ float heat_oracle_cone_f32(const float *w, int64_t nt, float r)
     for (int64_t s = 1; s <= nt; ++s) {
         for (int64_t j = s; j <= len - 1 - s; ++j) {
             float l = a[j - 1], c = a[j], q = a[j + 1];
-            b[j] = c + r * ((l - c) + (q - c));
+            b[j] = c + r * ((q - c) - (c - l));
         }
         float *t = a; a = b; b = t;
     }
@@ -375,7 +377,7 @@ static void step_ring_f32c(const float *u, const float *e, float *un, float *en,
         int64_t il = (i - 1 + N) % N, iq = (i + 1) % N;
         float l = u[il], c = u[i], q = u[iq];
         float el = e[il], ec = e[i], eq = e[iq];
-        float d = r * (((l - c) + (q - c)) + ((el - ec) + (eq - ec)));
+        float d = r * (((q - c) - (c - l)) + ((eq - ec) - (ec - el)));
         float y = d + ec;
         float t = c + y;
         en[i] = y - (t - c);
@@ -444,7 +446,7 @@ float heat_oracle_cone_f32c(const float *w, int64_t nt, float r, int64_t T)
             for (int64_t j = s; j <= len - 1 - s; ++j) {
                 float l = u[j - 1], c = u[j], q = u[j + 1];
                 float el = e[j - 1], ec = e[j], eq = e[j + 1];
-                float d = r * (((l - c) + (q - c)) + ((el - ec) + (eq - ec)));
+                float d = r * (((q - c) - (c - l)) + ((eq - ec) - (ec - el)));
                 float y = d + ec;
                 float t = c + y;
                 en[j] = y - (t - c);
