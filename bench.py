@@ -32,9 +32,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # FP32 ops/s (FP32 issues at twice the FP64 rate).
 VALU_PEAK_TOPS = {"fp64": 39.3, "fp32": 78.65, "fp32c": 78.65}
 # Minimal VALU operations per cell update of each form (the update formula,
-# nothing else): binary64 fma(-2,c,l), +q, *r, +c = 4; binary32 (l-c), (q-c),
-# +, *r, +c = 5; compensated 12 (two Laplacians 6, sum 1, *r 1, Fast2Sum 4).
-OPS_PER_CUP = {"fp64": 4, "fp32": 5, "fp32c": 12}
+# nothing else): binary64 fma(-2,c,l), +q, *r, +c = 4; binary32 in flux form
+# (q-c) - (c-l), whose one-sided difference serves two cells: one difference,
+# the difference of differences, *r, +c = 4; compensated 10 (the same two
+# steps for u and for e 4, sum 1, *r 1, Fast2Sum 4).
+OPS_PER_CUP = {"fp64": 4, "fp32": 4, "fp32c": 10}
 
 
 def parse():

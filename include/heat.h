@@ -18,7 +18,10 @@
  *   HEAT_FP64  -- binary64 storage and arithmetic in the order written above
  *                 (2 u[i] is exact; no other contraction).  Bit-identical to a
  *                 plain sequential evaluation.
- *   HEAT_FP32  -- binary32 storage and arithmetic: c + r*((l - c) + (q - c)).
+ *   HEAT_FP32  -- binary32 storage and arithmetic: c + r*((q - c) - (c - l))
+ *                 (the second difference as the difference of the two
+ *                 one-sided differences; each is exact for neighbours within
+ *                 a factor of 2).
  *   HEAT_FP32C -- binary32 storage; inside the kernels the state is the pair
  *                 (u, e) of binary32 numbers whose sum is the value, advanced
  *                 with a Fast2Sum (Kahan-style) compensated update in which e
@@ -82,8 +85,9 @@ typedef struct heat_config {
     int32_t cells_per_lane;  /* TB: cells held per lane, one of 8, 16, 32, 64   */
     int32_t steps_per_round; /* TB: T, a multiple of 4 with 2T < 64*cells - 8   */
     int32_t waves_per_group; /* wavefronts per workgroup, 1 to 8                */
-    int32_t register_form;   /* TB: 1 = in-place forward sweeps (the compiler
-                                rotates the K registers every step),
+    int32_t register_form;   /* TB: 1 = in-place forward sweeps (in binary64
+                                the compiler rotates the K registers every
+                                step; binary32 needs no copies),
                                 2 = ping-pong (2K registers, no copies),
                                 3 = alternating forward/backward in-place sweeps
                                 (K + 1 registers, no copies)                   */

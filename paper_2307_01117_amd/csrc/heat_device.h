@@ -91,9 +91,16 @@ __device__ __forceinline__ double from_next(double x) {
 __device__ __forceinline__ double cell_update(double l, double c, double q, double r) {
     return c + r * (__builtin_fma(-2.0, c, l) + q);
 }
-// binary32: both differences are exact when neighbours are within a factor 2.
+// binary32: the second difference as the difference of the two one-sided
+// differences, (q - c) - (c - l) (flux form).  Both are exact when neighbours
+// are within a factor 2.  A sweep over consecutive cells forms each one-sided
+// difference once: the right difference of cell j is the left difference of
+// cell j + 1 (see the window steps below).
 __device__ __forceinline__ float cell_update(float l, float c, float q, float r) {
-    return c + r * ((l - c) + (q - c));
+    return c + r * ((q - c) - (c - l));
+}
+__device__ __forceinline__ float flux_update(float c, float dl, float dr, float r) {
+    return c + r * (dr - dl);
 }
 
 // One step on K consecutive cells held by each lane (lane L holds cells
@@ -104,27 +111,38 @@ template <int K, class T>
 __device__ __forceinline__ void window_step(T (&v)[K], T r) {
     if constexpr (sizeof(T) == 4 && K >= 16) {
         // binary32: two interleaved sweeps, chain a over [0, M) and chain b
-        // over [M, K), M = K/2 + 1.  Same per-cell arithmetic (bit-identical);
-        // measured on MI355X 2 % faster for the in-place form, whose issue
-        // rate is set by how often two VALU instructions pair in a cycle.
+        // over [M, K), M = K/2 + 1, each carrying its last right difference
+        // as the next cell's left difference.  The difference across the
+        // chain boundary is formed once, before either chain writes.
         constexpr int M = K / 2 + 1;
         constexpr int NB = K - M;
-        T pa = from_prev(v[K - 1]);
+        T dla = v[0] - from_prev(v[K - 1]);
         const T right = from_next(v[0]);
-        T pb = v[M - 1];
-        const T ra = v[M];
+        T dlb = v[M] - v[M - 1];
+        const T dra_last = dlb;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             const T ca = v[j];
-            const T qa = (j + 1 < M) ? v[j + 1] : ra;
-            v[j] = cell_update(pa, ca, qa, r);
-            pa = ca;
+            const T dra = (j + 1 < M) ? v[j + 1] - ca : dra_last;
+            v[j] = flux_update(ca, dla, dra, r);
+            dla = dra;
             if (j < NB) {
                 const T cb = v[M + j];
                 const T qb = (M + j + 1 < K) ? v[M + j + 1] : right;
-                v[M + j] = cell_update(pb, cb, qb, r);
-                pb = cb;
+                const T drb = qb - cb;
+                v[M + j] = flux_update(cb, dlb, drb, r);
+                dlb = drb;
             }
+        }
+    } else if constexpr (sizeof(T) == 4) {
+        T dl = v[0] - from_prev(v[K - 1]);
+        const T right = from_next(v[0]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const T c = v[j];
+            const T dr = ((j + 1 < K) ? v[j + 1] : right) - c;
+            v[j] = flux_update(c, dl, dr, r);
+            dl = dr;
         }
     } else {
         T prev = from_prev(v[K - 1]);
@@ -140,51 +158,74 @@ __device__ __forceinline__ void window_step(T (&v)[K], T r) {
 }
 
 // Ping-pong form of the same step: reads a[], writes b[].  Two of them in a
-// row return the state to a[] with no register copies (the in-place form
-// makes the compiler rotate the whole array through the registers once per
-// step).  Costs K more registers.
+// row return the state to a[] with no register copies (the binary64 in-place
+// form keeps the old left value past the write of each cell, which makes the
+// compiler rotate the whole array through the registers once per step; the
+// binary32 flux form carries a difference instead and needs no copies).
+// Costs K more registers.
 template <int K, class T>
 __device__ __forceinline__ void window_step_pp(const T (&a)[K], T (&b)[K], T r) {
     const T left = from_prev(a[K - 1]);
     const T right = from_next(a[0]);
+    if constexpr (sizeof(T) == 4) {
+        T dl = a[0] - left;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const T l = j == 0 ? left : a[j - 1];
-        const T q = (j + 1 < K) ? a[j + 1] : right;
-        b[j] = cell_update(l, a[j], q, r);
+        for (int j = 0; j < K; ++j) {
+            const T dr = ((j + 1 < K) ? a[j + 1] : right) - a[j];
+            b[j] = flux_update(a[j], dl, dr, r);
+            dl = dr;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const T l = j == 0 ? left : a[j - 1];
+            const T q = (j + 1 < K) ? a[j + 1] : right;
+            b[j] = cell_update(l, a[j], q, r);
+        }
     }
 }
 
 // Backward in-place step: the same update swept from the last cell to the
-// first.  A forward step frees the register of cell j-1 when it writes cell
-// j, a backward one frees cell j+1's: alternating them leaves every value
-// where it started after two steps, so the loop needs no register copies and
-// only K + 1 registers (the alternating register form).
+// first.  A binary64 forward step frees the register of cell j-1 when it
+// writes cell j, a backward one frees cell j+1's: alternating them leaves
+// every value where it started after two steps, so the loop needs no register
+// copies and only K + 1 registers (the alternating register form).
 template <int K, class T>
 __device__ __forceinline__ void window_step_bwd(T (&v)[K], T r) {
     if constexpr (sizeof(T) == 4 && K >= 16) {
         // chain a: cells K-1 .. M (NB cells); chain b: cells M-1 .. 0 (M
-        // cells), M = K/2 + 1, as in the forward sweep
+        // cells), M = K/2 + 1, as in the forward sweep; each carries its last
+        // left difference as the next cell's right difference
         constexpr int M = K / 2 + 1;
         constexpr int NB = K - M;
         const T left = from_prev(v[K - 1]);
-        T na = from_next(v[0]);
-        T nb = v[M];
-        const T lb = v[M - 1];
+        T dra = from_next(v[0]) - v[K - 1];
+        T drb = v[M] - v[M - 1];
+        const T dla_last = drb;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             if (j < NB) {
                 const int ia = K - 1 - j;
                 const T ca = v[ia];
-                const T la = ia > M ? v[ia - 1] : lb;
-                v[ia] = cell_update(la, ca, na, r);
-                na = ca;
+                const T dla = ia > M ? ca - v[ia - 1] : dla_last;
+                v[ia] = flux_update(ca, dla, dra, r);
+                dra = dla;
             }
             const int ib = M - 1 - j;
             const T cb = v[ib];
-            const T l2 = ib > 0 ? v[ib - 1] : left;
-            v[ib] = cell_update(l2, cb, nb, r);
-            nb = cb;
+            const T dlb = cb - (ib > 0 ? v[ib - 1] : left);
+            v[ib] = flux_update(cb, dlb, drb, r);
+            drb = dlb;
+        }
+    } else if constexpr (sizeof(T) == 4) {
+        const T left = from_prev(v[K - 1]);
+        T dr = from_next(v[0]) - v[K - 1];
+#pragma unroll
+        for (int j = K - 1; j >= 0; --j) {
+            const T c = v[j];
+            const T dl = c - (j > 0 ? v[j - 1] : left);
+            v[j] = flux_update(c, dl, dr, r);
+            dr = dl;
         }
     } else {
         const T left = from_prev(v[K - 1]);
@@ -200,26 +241,32 @@ __device__ __forceinline__ void window_step_bwd(T (&v)[K], T r) {
 }
 
 // Compensated binary32 step of the pair (u, e): the Laplacian of u + e is
-// formed from the exact-ish differences of both parts, then added to u with
-// Fast2Sum so that the rounding error of the addition is kept in e.
+// formed from the flux-form differences of both parts (each one-sided
+// difference formed once per sweep), then added to u with Fast2Sum so that
+// the rounding error of the addition is kept in e.
+__device__ __forceinline__ void comp_update(float &u, float &e, float dlu, float dru, float dle,
+                                            float dre, float r) {
+    const float c = u;
+    const float d = r * ((dru - dlu) + (dre - dle));
+    const float y = d + e;
+    const float t = c + y;
+    e = y - (t - c);
+    u = t;
+}
+
 template <int K>
 __device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], float r) {
-    float pu = from_prev(u[K - 1]);
-    float pe = from_prev(e[K - 1]);
+    float dlu = u[0] - from_prev(u[K - 1]);
+    float dle = e[0] - from_prev(e[K - 1]);
     const float ru = from_next(u[0]);
     const float re = from_next(e[0]);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const float c = u[j], ec = e[j];
-        const float q = (j + 1 < K) ? u[j + 1] : ru;
-        const float eq = (j + 1 < K) ? e[j + 1] : re;
-        const float d = r * (((pu - c) + (q - c)) + ((pe - ec) + (eq - ec)));
-        const float y = d + ec;
-        const float t = c + y;
-        e[j] = y - (t - c);
-        u[j] = t;
-        pu = c;
-        pe = ec;
+        const float dru = ((j + 1 < K) ? u[j + 1] : ru) - u[j];
+        const float dre = ((j + 1 < K) ? e[j + 1] : re) - e[j];
+        comp_update(u[j], e[j], dlu, dru, dle, dre, r);
+        dlu = dru;
+        dle = dre;
     }
 }
 
@@ -227,42 +274,35 @@ template <int K>
 __device__ __forceinline__ void window_step_comp_bwd(float (&u)[K], float (&e)[K], float r) {
     const float lu = from_prev(u[K - 1]);
     const float le = from_prev(e[K - 1]);
-    float nu = from_next(u[0]);
-    float ne = from_next(e[0]);
+    float dru = from_next(u[0]) - u[K - 1];
+    float dre = from_next(e[0]) - e[K - 1];
 #pragma unroll
     for (int j = K - 1; j >= 0; --j) {
-        const float c = u[j], ec = e[j];
-        const float l = j > 0 ? u[j - 1] : lu;
-        const float el = j > 0 ? e[j - 1] : le;
-        const float d = r * (((l - c) + (nu - c)) + ((el - ec) + (ne - ec)));
-        const float y = d + ec;
-        const float t = c + y;
-        e[j] = y - (t - c);
-        u[j] = t;
-        nu = c;
-        ne = ec;
+        const float dlu = u[j] - (j > 0 ? u[j - 1] : lu);
+        const float dle = e[j] - (j > 0 ? e[j - 1] : le);
+        comp_update(u[j], e[j], dlu, dru, dle, dre, r);
+        dru = dlu;
+        dre = dle;
     }
 }
 
 template <int K>
 __device__ __forceinline__ void window_step_comp_pp(const float (&u)[K], const float (&e)[K],
                                                     float (&un)[K], float (&en)[K], float r) {
-    const float lu = from_prev(u[K - 1]);
-    const float le = from_prev(e[K - 1]);
     const float ru = from_next(u[0]);
     const float re = from_next(e[0]);
+    float dlu = u[0] - from_prev(u[K - 1]);
+    float dle = e[0] - from_prev(e[K - 1]);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const float c = u[j], ec = e[j];
-        const float l = j == 0 ? lu : u[j - 1];
-        const float el = j == 0 ? le : e[j - 1];
-        const float q = (j + 1 < K) ? u[j + 1] : ru;
-        const float eq = (j + 1 < K) ? e[j + 1] : re;
-        const float d = r * (((l - c) + (q - c)) + ((el - ec) + (eq - ec)));
-        const float y = d + ec;
-        const float t = c + y;
-        en[j] = y - (t - c);
-        un[j] = t;
+        const float dru = ((j + 1 < K) ? u[j + 1] : ru) - u[j];
+        const float dre = ((j + 1 < K) ? e[j + 1] : re) - e[j];
+        float a = u[j], b = e[j];
+        comp_update(a, b, dlu, dru, dle, dre, r);
+        un[j] = a;
+        en[j] = b;
+        dlu = dru;
+        dle = dre;
     }
 }
 

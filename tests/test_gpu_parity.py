@@ -20,6 +20,22 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+def same_bits(a, b):
+    """Bit-for-bit equality of two arrays (np.array_equal takes -0.0 == +0.0).
+    A binary32 array compared with a binary64 one is widened first, which is
+    exact and keeps the sign of zero."""
+    a, b = np.asarray(a), np.asarray(b)
+    if a.shape != b.shape:
+        return False
+    if a.dtype != b.dtype and a.dtype.kind == "f" and b.dtype.kind == "f":
+        a, b = a.astype(np.float64), b.astype(np.float64)
+    if a.dtype.kind == "f":
+        it = {4: np.uint32, 8: np.uint64}[a.dtype.itemsize]
+        return bool(np.array_equal(np.ascontiguousarray(a).view(it),
+                                   np.ascontiguousarray(b).view(it)))
+    return bool(np.array_equal(a, b))
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     if not torch.cuda.is_available():
@@ -86,7 +102,7 @@ def test_tiny_rings_bitwise(ci):
         for nt, r in ((0, 0.5), (1, 0.5), (3, 0.25), (33, 0.5), (70, 0.3)):
             got = run_dev(u0, nt, r, **cfg)
             want = oracle.solve(u0, r, nt)
-            assert np.array_equal(got, want), (cfg, N, nt, r)
+            assert same_bits(got, want), (cfg, N, nt, r)
 
 
 def test_exact_small_integer_cases():
@@ -96,7 +112,7 @@ def test_exact_small_integer_cases():
         u0 = inputs.small_integer_ring(N, (21, N))
         for r in (0.0, 0.125, 0.25, 0.375, 0.5):
             for cfg in cfgs_fp64()[:3]:
-                assert np.array_equal(run_dev(u0, 12, r, **cfg), oracle.solve(u0, r, 12))
+                assert same_bits(run_dev(u0, 12, r, **cfg), oracle.solve(u0, r, 12))
 
 
 # ------------------------------------------------------------ mid-size, ragged
@@ -127,7 +143,7 @@ def test_midsize_fp32_bitwise(N):
                 dict(cells_per_lane=16, steps_per_round=16, waves_per_group=2, register_form=3,
                      exchange=heat.EXCHANGE_LDS)):
         got = run_dev(u0, nt, r, precision=heat.FP32, **cfg)
-        assert np.array_equal(got, want), (cfg, N)
+        assert same_bits(got, want), (cfg, N)
 
 
 @pytest.mark.parametrize("N", [1, 5, 999, 65_536 + 13, 300_001])
@@ -143,7 +159,37 @@ def test_midsize_fp32c_bitwise(N):
                                 (64, 3, 4, heat.EXCHANGE_LDS)):
             got = run_dev(u0, nt, r, precision=heat.FP32C, cells_per_lane=K, register_form=form,
                           waves_per_group=wpg, exchange=x)
-            assert np.array_equal(got, want), (K, form, wpg, x, N, nt)
+            assert same_bits(got, want), (K, form, wpg, x, N, nt)
+
+
+def test_signed_zeros_fp32_forms():
+    """A state of +0 and -0 cells among small dyadic values: both binary32
+    forms reach the oracle's bits, the signs of zeros included, on the
+    one-step kernel and in every register form with lone and cooperating
+    waves."""
+    N = 70_001
+    rng = np.random.default_rng([25, N])
+    u0 = (rng.integers(-2, 3, N) * 2.0 ** -20).astype(np.float32)
+    z = u0 == 0
+    u0[z] = np.where(rng.random(int(z.sum())) < 0.5, np.float32(0.0), np.float32(-0.0))
+    assert np.signbit(u0[z]).any() and (~np.signbit(u0[z])).any()
+    shapes = [dict(kernel=heat.KERNEL_STEP)] + [
+        dict(cells_per_lane=K, register_form=f, waves_per_group=g, exchange=x)
+        for K in (8, 32, 64) for f in (1, 2, 3)
+        for (g, x) in ((1, heat.EXCHANGE_NONE), (4, heat.EXCHANGE_LDS))
+        if not (x == heat.EXCHANGE_LDS and K < 16) and not (K == 64 and f == 2)]
+    for r in (0.25, 0.375):
+        for nt in (1, 9, 130):
+            want = oracle.solve_f32(u0, r, nt)
+            T = heat.plan(N, nt, heat.FP32C)["steps_per_round"]
+            want_c = oracle.solve_f32c(u0, r, nt, T)
+            for cfg in shapes:
+                got = run_dev(u0, nt, r, precision=heat.FP32, **cfg)
+                assert same_bits(got, want), ("fp32", cfg, r, nt)
+                if cfg.get("kernel") == heat.KERNEL_STEP:
+                    continue
+                got = run_dev(u0, nt, r, precision=heat.FP32C, **cfg)
+                assert same_bits(got, want_c), ("fp32c", cfg, r, nt)
 
 
 # ------------------------------------------------------------ invariances on the GPU
@@ -153,7 +199,7 @@ def test_partition_count_does_not_change_result():
     u0 = inputs.uniform_ring(N, 25)
     base = run_dev(u0, 40, 0.5, nparts=1)
     for P in (2, 10, 100, N):
-        assert np.array_equal(run_dev(u0, 40, 0.5, nparts=P), base)
+        assert same_bits(run_dev(u0, 40, 0.5, nparts=P), base)
 
 
 def test_shift_and_composition():
@@ -161,9 +207,9 @@ def test_shift_and_composition():
     u0 = inputs.uniform_ring(N, 26)
     base = run_dev(u0, 64, 0.37)
     for s in (1, 959, 960, 961, 65_536):
-        assert np.array_equal(run_dev(np.roll(u0, s), 64, 0.37), np.roll(base, s))
+        assert same_bits(run_dev(np.roll(u0, s), 64, 0.37), np.roll(base, s))
     mid = run_dev(u0, 23, 0.37)
-    assert np.array_equal(run_dev(mid, 41, 0.37), base)
+    assert same_bits(run_dev(mid, 41, 0.37), base)
 
 
 def test_checksum_matches_exact_sum():
@@ -187,7 +233,7 @@ def test_device_errors():
                        kernel=heat.KERNEL_STEP)
     # host form agrees with the device form
     u0 = inputs.uniform_ring(1000, 28)
-    assert np.array_equal(heat.solve(u0, 4, 0.5, 30), oracle.solve(u0, 0.5, 30))
+    assert same_bits(heat.solve(u0, 4, 0.5, 30), oracle.solve(u0, 0.5, 30))
 
 
 # ------------------------------------------------------------ full-size workloads
@@ -221,10 +267,10 @@ def test_ring_1e6_full_compare():
     s0, s1 = heat.solve_dev(d, w["nparts"], w["r"], w["nt"], sums=True)
     got = d.cpu().numpy()
     want = oracle.solve(u0, w["r"], w["nt"])
-    assert np.array_equal(got, want)
+    assert same_bits(got, want)
     assert abs(s1 - s0) <= 8 * 2.0 ** -53 * w["N"] * w["nt"]
     # the step kernel as well
-    assert np.array_equal(run_dev(u0, w["nt"], w["r"], kernel=heat.KERNEL_STEP), want)
+    assert same_bits(run_dev(u0, w["nt"], w["r"], kernel=heat.KERNEL_STEP), want)
 
 
 def test_sine_mode_decay_on_gpu():
@@ -259,7 +305,7 @@ def test_ring_1e8_sampled(cfg):
     got = d[torch.from_numpy(idx).cuda()].cpu().numpy()
     del d
     want = np.array([oracle.cone(u0, int(i), w["r"], w["nt"]) for i in idx])
-    assert np.array_equal(got, want), idx[got != want][:10]
+    assert same_bits(got, want), idx[got != want][:10]
     assert abs(s0 - math.fsum(u0)) <= 1e-13 * abs(s0)
     assert abs(s1 - s0) <= 8 * 2.0 ** -53 * N * w["nt"]
 
@@ -275,7 +321,7 @@ def test_fused_checksums(ci):
         d = dev(u0)
         s0, s1 = heat.solve_dev(d, 1, 0.5, nt, sums=True, **cfg)
         want = oracle.solve(u0, 0.5, nt)
-        assert np.array_equal(d.cpu().numpy(), want), (cfg, N)
+        assert same_bits(d.cpu().numpy(), want), (cfg, N)
         assert abs(s0 - math.fsum(u0)) <= 1e-13 * max(abs(s0), 1.0), (cfg, N)
         assert abs(s1 - math.fsum(want)) <= 1e-13 * max(abs(s1), 1.0), (cfg, N)
 
@@ -300,11 +346,11 @@ def test_ring_1e8_perturbed_fp32_forms():
         del d
         if prec == heat.FP32C:
             want = np.array([oracle.cone_f32c(u32, int(i), r, nt, T) for i in idx])
-            assert np.array_equal(got, want)
+            assert same_bits(got, want)
             assert np.abs(got - ref64).max() / np.abs(ref64).max() <= 1e-6
         else:
             want = np.array([oracle.cone_f32(u32, int(i), r, nt) for i in idx])
-            assert np.array_equal(got, want)
+            assert same_bits(got, want)
 
 
 def test_autotuned_shape_is_result_neutral():
@@ -314,13 +360,13 @@ def test_autotuned_shape_is_result_neutral():
     assert g > 0 and cfg["kernel"] == heat.KERNEL_TB
     u0 = inputs.uniform_ring(N, 33)
     got = run_dev(u0, 150, 0.5, **cfg)
-    assert np.array_equal(got, oracle.solve(u0, 0.5, 150))
+    assert same_bits(got, oracle.solve(u0, 0.5, 150))
     cfg32, _ = heat.autotune(heat.FP32C, 20_000, install=False)
     u32 = inputs.perturbed_ring(20_000, 34).astype(np.float32)
     T = heat.plan(20_000, 130, heat.FP32C)["steps_per_round"]
     assert cfg32["steps_per_round"] == heat.plan(20_000, 10**6, heat.FP32C)["steps_per_round"]
     got = run_dev(u32, 130, 0.25, precision=heat.FP32C, **cfg32)
-    assert np.array_equal(got, oracle.solve_f32c(u32, 0.25, 130, T))
+    assert same_bits(got, oracle.solve_f32c(u32, 0.25, 130, T))
 
 
 @pytest.mark.parametrize("nparts", [2, 20, 40])
@@ -335,10 +381,10 @@ def test_paper_ramp_workload(nparts):
     s0, s1 = heat.solve_dev(d, nparts, w["r"], w["nt"], sums=True)
     got = d.cpu().numpy()
     if nparts == 2:
-        assert np.array_equal(got, oracle.solve(u0, w["r"], w["nt"]))
+        assert same_bits(got, oracle.solve(u0, w["r"], w["nt"]))
         test_paper_ramp_workload.ref = got
     else:
-        assert np.array_equal(got, test_paper_ramp_workload.ref)
+        assert same_bits(got, test_paper_ramp_workload.ref)
     assert abs(s1 - s0) <= 1e-9 * abs(s0)
     delta = 4 * 2.0 ** -53 * w["nt"] * (w["N"] - 1)
     assert got.min() >= -delta and got.max() <= w["N"] - 1 + delta
@@ -357,13 +403,13 @@ def test_unaligned_device_array_takes_gather_path():
     for cfg in (dict(), dict(cells_per_lane=32, waves_per_group=4, exchange=heat.EXCHANGE_LDS)):
         view.copy_(torch.from_numpy(u0).cuda())
         heat.solve_dev(view, 1, 0.5, 90, **cfg)
-        assert np.array_equal(view.cpu().numpy(), want), cfg
+        assert same_bits(view.cpu().numpy(), want), cfg
     v32 = torch.zeros(N + 1, dtype=torch.float32, device="cuda")
     u32 = u0.astype(np.float32)
     v32[1:] = torch.from_numpy(u32).cuda()
     heat.solve_dev(v32[1:], 1, 0.25, 70, precision=heat.FP32C)
     T = heat.plan(N, 70, heat.FP32C)["steps_per_round"]
-    assert np.array_equal(v32[1:].cpu().numpy(), oracle.solve_f32c(u32, 0.25, 70, T))
+    assert same_bits(v32[1:].cpu().numpy(), oracle.solve_f32c(u32, 0.25, 70, T))
 
 
 def test_ring_beyond_2_pow_31_cells():

@@ -15,6 +15,22 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+def same_bits(a, b):
+    """Bit-for-bit equality of two arrays (np.array_equal takes -0.0 == +0.0).
+    A binary32 array compared with a binary64 one is widened first, which is
+    exact and keeps the sign of zero."""
+    a, b = np.asarray(a), np.asarray(b)
+    if a.shape != b.shape:
+        return False
+    if a.dtype != b.dtype and a.dtype.kind == "f" and b.dtype.kind == "f":
+        a, b = a.astype(np.float64), b.astype(np.float64)
+    if a.dtype.kind == "f":
+        it = {4: np.uint32, 8: np.uint64}[a.dtype.itemsize]
+        return bool(np.array_equal(np.ascontiguousarray(a).view(it),
+                                   np.ascontiguousarray(b).view(it)))
+    return bool(np.array_equal(a, b))
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     if not torch.cuda.is_available():
@@ -47,7 +63,7 @@ def test_single_request_matches_oracle():
         t = s.submit(u0, 300, 0.5)
         res = s.wait(t)
         assert res.status == heat.HEAT_OK
-        assert np.array_equal(res.u, oracle.solve(u0, 0.5, 300))
+        assert same_bits(res.u, oracle.solve(u0, 0.5, 300))
         assert abs(res.sum_nt - res.sum0) < 1e-9
         st = s.stats()
         assert st["completed"] == 1 and st["hbm_in_use"] == 0
@@ -63,7 +79,7 @@ def test_mix_equals_alone():
         assert s.stats()["ticks"] >= 1
     for (u0, nt, r, prec), res in zip(reqs, results):
         assert res.status == heat.HEAT_OK
-        assert np.array_equal(res.u, alone(u0, nt, r, prec)), (u0.size, nt, prec)
+        assert same_bits(res.u, alone(u0, nt, r, prec)), (u0.size, nt, prec)
 
 
 def test_alone_on_idle_server_equals_in_mix():
@@ -83,7 +99,7 @@ def test_alone_on_idle_server_equals_in_mix():
             else:
                 s.wait(t)
     for k in range(4):
-        assert np.array_equal(solo[k], mixed[k])
+        assert same_bits(solo[k], mixed[k])
 
 
 def test_mean_shifted_requests():
@@ -106,7 +122,7 @@ def test_mean_shifted_requests():
         else:
             T = heat.plan(u0.size, nt, heat.FP32C)["steps_per_round"]
             want = oracle.solve_f32c_shifted(u0, r, nt, T, sh)
-        assert np.array_equal(res.u, want), (u0.size, nt, prec, sh)
+        assert same_bits(res.u, want), (u0.size, nt, prec, sh)
 
 
 def test_tick_size_does_not_change_results(monkeypatch):
@@ -120,7 +136,7 @@ def test_tick_size_does_not_change_results(monkeypatch):
             outs = [s.wait(t) for t in [s.submit(*q) for q in reqs]]
         for q, res in zip(reqs, outs):
             assert res.status == heat.HEAT_OK
-            assert np.array_equal(res.u, alone(*q)), (steps, q[0].size, q[1], q[3])
+            assert same_bits(res.u, alone(*q)), (steps, q[0].size, q[1], q[3])
 
 
 def test_budget_admission_and_enomem():
@@ -136,7 +152,7 @@ def test_budget_admission_and_enomem():
         st = s.stats()
         assert st["hbm_peak"] <= budget and st["hbm_in_use"] == 0
     for (u0, nt, r, _), res in zip(reqs, outs):
-        assert np.array_equal(res.u, oracle.solve(u0, r, nt))
+        assert same_bits(res.u, oracle.solve(u0, r, nt))
 
 
 def test_queue_limit_busy():
@@ -166,7 +182,7 @@ def test_cancel_and_unknown_ticket():
             s.poll(t1)
         assert ei.value.code == heat.HEAT_ENOENT
         res = s.wait(t2)
-        assert np.array_equal(res.u, oracle.solve(short[0], 0.3, 100))
+        assert same_bits(res.u, oracle.solve(short[0], 0.3, 100))
         assert s.stats()["cancelled"] == 1
     with pytest.raises(heat.HeatError):
         heat.Server(hbm_budget=16)   # below the minimum arena
@@ -188,7 +204,7 @@ def test_submit_from_many_threads_and_destroy_with_work_outstanding():
         t.join()
     got = [s.wait(t) for t in tickets[:16]]
     for q, res in zip(reqs[:16], got):
-        assert np.array_equal(res.u, alone(*q))
+        assert same_bits(res.u, alone(*q))
     # more work outstanding: destroy must cancel it cleanly
     for q in reqs[:8]:
         s.submit(*q)
