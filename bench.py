@@ -42,8 +42,8 @@ OPS_PER_CUP = {"fp64": 4, "fp32": 4, "fp32c": 10}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="ring_1e8",
                     choices=["ring_1e6", "ring_1e8", "ring_1e8_perturbed", "paper_ramp_1e6"])
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32c"])
