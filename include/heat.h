@@ -119,7 +119,9 @@ int heat_solve(double *u, int64_t N, int32_t nparts, double r, int64_t nt);
 
 /*
  * Device form.  d_u: device array of N values (double* for HEAT_FP64, float*
- * for HEAT_FP32/HEAT_FP32C), 16-byte aligned, advanced in place.  Work is
+ * for HEAT_FP32/HEAT_FP32C), aligned to its element size, advanced in place
+ * (16-byte aligned arrays take the vector loads; any other alignment runs
+ * every tile through the cell-by-cell path: same bits, slower).  Work is
  * queued on `hip_stream` (a hipStream_t; NULL = the legacy default stream).
  * Device scratch of the same size as d_u is taken from the stream-ordered
  * pool of the device.  If sum0_out / sum_out are not NULL they receive the
@@ -187,16 +189,19 @@ typedef struct heat_problem {
 
 /*
  * Batching form (host buffers): validates every problem, copies them to the
- * device, advances all of them in one persistent fused launch, copies back.
- * Blocking.  Returns HEAT_OK if every problem succeeded, else the first
+ * device, advances all of them together (as heat_solve_batch_dev without
+ * flags: one launch per round over the tiles of every still-running ring),
+ * copies back.  Blocking.  Returns HEAT_OK if every problem succeeded, else the first
  * error; probs[i].status tells which.
  */
 int heat_solve_batch(heat_problem *probs, int32_t count);
 
 /*
  * One ring of a device-resident batch.  d_u: device state (N values of the
- * precision's storage type, 16-byte aligned), advanced in place; d_work:
- * device scratch of the same size.  The caller owns both.
+ * precision's storage type, aligned to its element size), advanced in
+ * place; d_work: device scratch of the same size.  The caller owns both.
+ * Rings whose two arrays are both 16-byte aligned take the vector loads,
+ * others the cell-by-cell path (same bits).
  */
 typedef struct heat_ring {
     int64_t N;
@@ -292,10 +297,11 @@ int heat_server_destroy(heat_server *s);
 
 /*
  * Autotuner: times every temporal-blocking launch shape (cells per lane,
- * steps per round, wavefronts per workgroup, register form) on a synthetic
- * ring of N cells of the given precision on the current device (HIP events,
- * two rounds per shape) and returns the fastest in *best_out (host) with its
- * rate in GCUP/s.  If `install` is nonzero the shape becomes the planner's
+ * steps per round, wavefronts per workgroup, register form, lone or
+ * LDS-exchanging waves) on a synthetic ring of N cells of the given
+ * precision on the current device (HIP events over an even number of whole
+ * rounds, at least 4 and at least 384 steps) and returns the fastest in
+ * *best_out (host) with its rate in GCUP/s.  If `install` is nonzero the shape becomes the planner's
  * default for rings of N's decade (log10 bucket) in this process.  Shapes
  * never change binary64 or binary32 results; for HEAT_FP32C only shapes with
  * the form's fixed round length are tried.  Allocates and frees 2 * N * 8
@@ -306,7 +312,9 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
 
 /*
  * Save / load the planner's tuning table as text (one line per precision and
- * decade: "precision bucket K T waves form").  The library also loads the
+ * decade: "precision bucket K T waves form exchange"; a line of six columns
+ * loads as lone waves, exchange HEAT_EXCHANGE_NONE).  A malformed line makes
+ * heat_tune_load return HEAT_EINVAL and keeps the lines read before it.  The library also loads the
  * file named by the environment variable HEAT_TUNE_TABLE at first use.
  */
 int heat_tune_save(const char *path);
