@@ -91,8 +91,10 @@ hipError_t launch_window_xchg(const WindowLaunch &a, hipStream_t st);   // kerne
 // Output cells of one tile: 64K - 2H for a lone wave; for wpg cooperating
 // waves, wpg windows of 64K cells overlapping by 2*(K/4), minus 2H.
 int64_t window_tile_cells(int K, int H, int wpg, bool xchg);
-// Sum n per-tile partials (fixed order) into d_out[0].
-hipError_t launch_sum_partials(const double *partial, int64_t n, double *d_out, hipStream_t st);
+// Reduce `arrays` consecutive arrays of n partial sums each (partial[a*n, a*n + n))
+// into d_out[a], one workgroup per array, in one launch.
+hipError_t launch_sum_partials(const double *partial, int64_t n, int arrays, double *d_out,
+                               hipStream_t st);
 
 // One step of the coalesced sweep (binary64 or binary32).
 hipError_t launch_step(int precision, const void *src, void *dst, int64_t N, double r, int wpg,

@@ -91,11 +91,12 @@ __device__ __forceinline__ void neumaier_add(double &s, double &c, double x) {
     s = t;
 }
 
+template <int BS>
 __device__ __forceinline__ double block_tree_sum(double v) {
-    __shared__ double red[256];
+    __shared__ double red[BS];
     red[threadIdx.x] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = BS / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
         __syncthreads();
     }
@@ -126,28 +127,35 @@ __global__ void __launch_bounds__(256) k_sum_partial(const T *__restrict__ u, in
     } else {
         for (int64_t i = lo + threadIdx.x; i < hi; i += 256) neumaier_add(s, c, (double)u[i]);
     }
-    const double tot = block_tree_sum(s + c);
+    const double tot = block_tree_sum<256>(s + c);
     if (threadIdx.x == 0) partial[b] = tot;
 }
 
-__global__ void __launch_bounds__(256) k_sum_final(const double *__restrict__ partial, int64_t G,
-                                                   double *__restrict__ out) {
+// Final pass: workgroup b reduces the n partial sums partial[b*n, b*n + n)
+// into out[b], so the sums before and after a run reduce in one launch.
+// Thread t adds partial[t], partial[t + 1024], ... in that order (a fixed
+// order for a given n); each thread keeps 16 loads in flight, so up to 16,384
+// partials cost one memory latency instead of one per 2,048.
+constexpr int FINAL_THREADS = 1024;
+constexpr int FINAL_LOADS = 16;
+
+__global__ void __launch_bounds__(FINAL_THREADS) k_sum_final(const double *__restrict__ partial,
+                                                             int64_t n, double *__restrict__ out) {
+    const double *p = partial + (int64_t)blockIdx.x * n;
     double s = 0.0, c = 0.0;
-    // thread t adds partial[t], partial[t + 256], ... in that order; the loads
-    // of 8 consecutive terms are issued together so their latencies overlap
-    for (int64_t base = threadIdx.x; base < G; base += 8 * 256) {
-        double x[8];
+    for (int64_t base = threadIdx.x; base < n; base += (int64_t)FINAL_LOADS * FINAL_THREADS) {
+        double x[FINAL_LOADS];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t i = base + u * 256;
-            x[u] = i < G ? partial[i] : 0.0;
+        for (int u = 0; u < FINAL_LOADS; ++u) {
+            const int64_t i = base + (int64_t)u * FINAL_THREADS;
+            x[u] = i < n ? p[i] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (base + u * 256 < G) neumaier_add(s, c, x[u]);
+        for (int u = 0; u < FINAL_LOADS; ++u)
+            if (base + (int64_t)u * FINAL_THREADS < n) neumaier_add(s, c, x[u]);
     }
-    const double tot = block_tree_sum(s + c);
-    if (threadIdx.x == 0) out[0] = tot;
+    const double tot = block_tree_sum<FINAL_THREADS>(s + c);
+    if (threadIdx.x == 0) out[blockIdx.x] = tot;
 }
 
 // ================================================================= CONVERT
@@ -205,8 +213,10 @@ hipError_t launch_window_lone(const WindowLaunch &a, hipStream_t st) {
     return launch_window_any<false>(a, st);
 }
 
-hipError_t launch_sum_partials(const double *partial, int64_t n, double *d_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial, n, d_out);
+hipError_t launch_sum_partials(const double *partial, int64_t n, int arrays, double *d_out,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_final, dim3((unsigned)arrays), dim3(FINAL_THREADS), 0, st, partial, n,
+                       d_out);
     return hipGetLastError();
 }
 
@@ -244,7 +254,8 @@ hipError_t launch_sum(int precision, const void *u, int64_t N, double *partial, 
                            reinterpret_cast<const float *>(u), N, partial, vec_ok);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, partial, (int64_t)SUM_BLOCKS, d_out);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(FINAL_THREADS), 0, st, partial,
+                       (int64_t)SUM_BLOCKS, d_out);
     return hipGetLastError();
 }
 

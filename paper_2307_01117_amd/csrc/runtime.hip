@@ -250,8 +250,8 @@ static int run_rounds(const Plan &pl, int precision, void *a, void *b, int64_t N
             done += w.steps;
         }
         if (fused) {
-            HEAT_HIP(launch_sum_partials(sums->partial, pl.parts, sums->d_out, st));
-            HEAT_HIP(launch_sum_partials(sums->partial + pl.parts, pl.parts, sums->d_out + 1, st));
+            // partial[0, parts): before the first round; [parts, 2 parts): after the last
+            HEAT_HIP(launch_sum_partials(sums->partial, pl.parts, 2, sums->d_out, st));
         }
     }
     if (cur != a)
