@@ -117,13 +117,18 @@ def precision_report(heat, torch, u0, nparts, r, nt, prec, stream):
 
 
 def kernel_source_digest() -> str:
-    """sha256 of the kernel sources; HBM traffic taken from counters is only
-    reported while the kernels are the ones that were counted."""
+    """sha256 of the kernel sources and of the build script (its per-source
+    compiler flags); HBM traffic taken from counters is only reported while
+    the kernels are the ones that were counted."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("heat_device.h", "window.h", "round.h", "kernels.hip", "kernels_xchg.hip"):
-        with open(os.path.join(ROOT, "paper_2307_01117_amd", "csrc", f), "rb") as fh:
+    pkg = os.path.join(ROOT, "paper_2307_01117_amd")
+    for f in ("heat_device.h", "window.h", "round.h", "kernels.hip", "kernels_xchg.hip",
+              "kernels_f32c.hip"):
+        with open(os.path.join(pkg, "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(pkg, "build.py"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()
 
 

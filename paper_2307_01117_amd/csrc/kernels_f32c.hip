@@ -1,0 +1,41 @@
+// kernels_f32c.hip -- every kernel of the compensated binary32 form: the
+// round kernels of the plain path, lone and exchanging waves (round.h), and
+// the batching form's class (batch_kernels.h).  This file alone is built
+// with LLVM's max-ilp instruction scheduler (see build.py): the compensated
+// update is a chain of ten dependent operations per cell, and interleaving
+// the chains of neighbouring cells pairs more VALU instructions than the
+// default occupancy-first schedule (measured on MI355X: 5,430 against 4,790
+// GCUP/s for the best shape of each on a 1e8-cell ring).  The instruction
+// order does not change any result.
+#include "batch_kernels.h"
+#include "round.h"
+
+namespace heat {
+
+hipError_t launch_window_fp32c(const WindowLaunch &a, hipStream_t st) {
+    if (a.precision != HEAT_FP32C) return hipErrorInvalidValue;
+    return a.xchg ? launch_window_f<F32C, true>(a, st) : launch_window_f<F32C, false>(a, st);
+}
+
+// The batch class: 32-cell lanes, one wave per tile, in-place sweeps (under
+// this file's scheduler the fastest form at 32 cells per lane).
+constexpr int BATCH_FP32C_FORM = FORM_INPLACE;
+
+hipError_t launch_batch_round_fp32c(int K, const BatchRing *rings, const int64_t *tile_prefix,
+                                    int k, int active, int64_t items, int wpg, hipStream_t st) {
+    if (K != 32) return hipErrorInvalidValue;
+    return launch_batch_round_t<F32C, 32, BATCH_FP32C_FORM>(rings, tile_prefix, k, active, items,
+                                                            wpg, st);
+}
+
+hipError_t launch_batch_fp32c(int K, const BatchPlanDev &plan, int grid, int wpg,
+                              hipStream_t st) {
+    if (K != 32) return hipErrorInvalidValue;
+    return launch_batch_t<F32C, 32>(plan, grid, wpg, st);
+}
+
+int batch_occupancy_fp32c(int K, int wpg) {
+    return K == 32 ? occupancy_blocks<F32C, 32>(wpg) : 0;
+}
+
+}  // namespace heat
