@@ -1,7 +1,11 @@
-"""GPU parity of the batching form (one persistent fused launch for many
-uneven rings) through the C ABI: every ring must come out bit-identical to
-the CPU oracle and to the same ring solved alone by the plain device form."""
+"""GPU parity of the batching form (many uneven rings advanced together: one
+launch per round over all running rings, or one persistent launch) through
+the C ABI: every ring must come out bit-identical to the CPU oracle and to the
+same ring solved alone by the plain device form."""
 import math
+import os
+import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -189,6 +193,41 @@ def test_device_batch_seeded_256_ring_subset():
         assert torch.equal(u, a), (s.N, s.nt)
         i = int(rng.integers(0, s.N))
         assert u[i].item() == oracle.cone(u0, i, s.r, s.nt), (s.N, s.nt, i)
+
+
+@pytest.mark.skipif(os.environ.get("HEAT_FULL_BATCH_PARITY") != "1",
+                    reason="one-off full check, minutes of host CPU: set HEAT_FULL_BATCH_PARITY=1")
+def test_device_batch_full_4096_rings_vs_oracle():
+    """Every ring of the full batching workload (4,096 rings, about 3e12 cell
+    updates), batched in binary64 as the benchmark runs it, compared bit for
+    bit with the oracle's segmented solver, one host thread per ring and up to
+    16 rings at a time (the C oracle runs without the interpreter lock)."""
+    specs = inputs.batch_specs(count=4096, seed=4)
+    u0s = [inputs.ring_initial(s) for s in specs]
+    us = [torch.from_numpy(u).cuda() for u in u0s]
+    work = [torch.empty_like(u) for u in us]
+    heat.solve_batch_dev([(u, w, s.nt, s.r, heat.FP64) for u, w, s in zip(us, work, specs)])
+    torch.cuda.synchronize()
+    got = [u.cpu().numpy() for u in us]
+    del us, work
+    torch.cuda.empty_cache()
+
+    def check(j):
+        s = specs[j]
+        return same_bits(got[j], oracle.solve_threads(u0s[j], 1, s.r, s.nt))
+
+    t0 = time.perf_counter()
+    bad, done = [], 0
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(workers) as ex:
+        for j, ok in zip(range(len(specs)), ex.map(check, range(len(specs)))):
+            done += 1
+            if not ok:
+                bad.append(j)
+            if done % 256 == 0:
+                print(f"full batch parity: {done}/{len(specs)} rings checked, "
+                      f"{len(bad)} mismatches, {time.perf_counter() - t0:.0f} s", flush=True)
+    assert not bad, [(specs[j].N, specs[j].nt) for j in bad[:10]]
 
 
 def test_device_batch_long_rings_all_classes():
