@@ -1,8 +1,10 @@
 """GPU tests of the serving form (continuous batching) through the C ABI:
 results bit-identical to the oracle and to the same request solved alone,
 admission by HBM footprint, queue limits, cancellation and shutdown."""
+import os
 import threading
 import time
+from concurrent.futures import ThreadPoolExecutor, as_completed
 
 import numpy as np
 import pytest
@@ -209,3 +211,73 @@ def test_submit_from_many_threads_and_destroy_with_work_outstanding():
     for q in reqs[:8]:
         s.submit(*q)
     s.close()
+
+
+@pytest.mark.skipif(os.environ.get("HEAT_FULL_SERVE_PARITY") != "1",
+                    reason="one-off check, minutes of host CPU: set HEAT_FULL_SERVE_PARITY=1")
+def test_serving_trace_vs_oracle():
+    """The serving workload at 200 requests/s (Poisson arrivals, 20 s unless
+    HEAT_SERVE_PARITY_SECONDS says otherwise) through one server: every
+    request with N*nt <= 1e9 compared bit for bit with the oracle over the
+    whole ring (binary64: the segmented C solver; compensated binary32: its C
+    solver with the form's round length), and a seeded 2 % sample of the
+    larger ones at 16 cells each through the oracle's light cone."""
+    duration = float(os.environ.get("HEAT_SERVE_PARITY_SECONDS", "20"))
+    P, nmax = 1 << 24, 10_000_000
+    pool = np.empty(P + nmax)
+    pool[:P] = inputs.serving_pool(P)
+    pool[P:] = pool[:nmax]        # u0 of a request = one contiguous slice
+    trace = inputs.serving_trace(200.0, duration, pool_size=P)
+    rng = np.random.default_rng(53)
+    whole = [q.N * q.nt <= 1e9 for q in trace]
+    sampled = [not w and rng.random() < 0.02 for w in whole]
+    sink = np.empty(nmax)
+    server = heat.Server()
+    subs = []
+    t0 = time.perf_counter()
+    for j, (q, w, sm) in enumerate(zip(trace, whole, sampled)):
+        delay = t0 + q.t_arrival - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        out = np.empty(q.N) if (w or sm) else sink[:q.N]
+        subs.append((j, q, w, sm, server.submit(pool[q.offset:q.offset + q.N], q.nt, q.r,
+                                                q.precision, out=out)))
+    done = [(j, q, w, sm, server.wait(t)) for j, q, w, sm, t in subs]
+    server.close()
+    print(f"served {len(done)} requests in {time.perf_counter() - t0:.0f} s; checking "
+          f"{sum(whole)} whole and {sum(sampled)} sampled", flush=True)
+    T = {j: heat.plan(q.N, q.nt, heat.FP32C)["steps_per_round"]
+         for j, q, w, sm, _ in done if q.precision == heat.FP32C and (w or sm)}
+
+    def verify(item):
+        j, q, w, sm, res = item
+        u0 = pool[q.offset:q.offset + q.N]
+        if w:
+            if q.precision == heat.FP64:
+                want = oracle.solve_threads(u0, 1, q.r, q.nt)
+            else:
+                want = oracle.solve_f32c(u0.astype(np.float32), q.r, q.nt, T[j])
+            return j, q, same_bits(res.u, want)
+        cells = np.random.default_rng([54, j]).integers(0, q.N, 16)
+        for i in cells:
+            if q.precision == heat.FP64:
+                c = np.array([oracle.cone(u0, int(i), q.r, q.nt)])
+            else:   # the cone rounds its window of u0 to binary32 itself
+                c = np.array([oracle.cone_f32c(u0, int(i), q.r, q.nt, T[j])], dtype=np.float32)
+            ok = same_bits(res.u[i:i + 1], c)
+            if not ok:
+                return j, q, False
+        return j, q, True
+
+    items = [d for d in done if d[2] or d[3]]
+    bad, n = [], 0
+    with ThreadPoolExecutor(max(1, min(16, len(os.sched_getaffinity(0))))) as ex:
+        for f in as_completed([ex.submit(verify, it) for it in items]):
+            j, q, ok = f.result()
+            n += 1
+            if not ok:
+                bad.append((j, q.N, q.nt, q.precision))
+            if n % 200 == 0 or n == len(items):
+                print(f"serving parity: {n}/{len(items)} checked, {len(bad)} mismatches, "
+                      f"{time.perf_counter() - t0:.0f} s", flush=True)
+    assert not bad, bad[:10]
