@@ -264,7 +264,9 @@ int validate_ring(const heat_ring &g) {
     return HEAT_OK;
 }
 
-// Enqueue one fused launch per precision present, all on `st`.
+// Enqueue the launches of every kernel class present (one launch per round
+// of each (precision, cells-per-lane, waves-per-tile) class, or one
+// persistent launch per class with HEAT_BATCH_PERSISTENT), all on `st`.
 int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
                       std::vector<BatchLaunch> &launches, void **dev_mem_out, int32_t flags) {
     *dev_mem_out = nullptr;

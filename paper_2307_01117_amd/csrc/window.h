@@ -244,7 +244,7 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
     }
     if constexpr (!XCHG) {
         // The lone wave's loops are written out here rather than through
-        // advance(): with the in-place form the compiler's register
+        // advance(): with the binary64 in-place form the compiler's register
         // assignment depends on this shape (rotating K registers per step
         // instead of copying the array), and so does the occupancy.
         if constexpr (P::COMP) {
