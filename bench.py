@@ -74,6 +74,8 @@ def parse():
                     help="batch: skip solving the rings one by one for comparison")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="time steps of the full ring the CPU oracle runs as its sample")
+    ap.add_argument("--no-host-path", action="store_true",
+                    help="skip timing the host-buffer boundary (heat_solve: PCIe both ways)")
     ap.add_argument("--no-cpu-threads", action="store_true",
                     help="skip the thread axis of the threaded CPU oracle (binary64 ring only)")
     ap.add_argument("--cpu-thread-steps", type=int, default=5,
@@ -167,6 +169,26 @@ def cpu_baseline(u0, r, steps, precision, T):
     return {"value": round(u0.size * steps / dt / 1e9, 4), "unit": "GCUP/s", "cores": 1,
             "kind": "oracle",
             "sample": f"full ring of {u0.size} cells, {steps} steps ({dt:.1f} s, single thread)"}
+
+
+def host_path(heat, u0, nparts, r, nt, reps=2):
+    """The host-buffer boundary: heat_solve on a pageable binary64 array
+    (device allocation, copy in, every step, copy out, free), best of `reps`
+    calls after one untimed call.  A reported rate beside `value`, never it."""
+    import numpy as np
+    a = np.array(u0, dtype=np.float64, copy=True)
+    lib = heat.load()
+    best = None
+    for i in range(reps + 1):
+        a[:] = u0
+        t0 = time.perf_counter()
+        heat._check(lib.heat_solve(a.ctypes.data, a.size, int(nparts), float(r), int(nt)))
+        dt = time.perf_counter() - t0
+        if i > 0:
+            best = dt if best is None else min(best, dt)
+    return {"value": round(u0.size * nt / best / 1e9, 1), "unit": "GCUP/s",
+            "ms": round(best * 1e3, 1),
+            "what": "heat_solve on a pageable host array: H2D, all steps, D2H"}
 
 
 def cpu_model():
@@ -370,6 +392,8 @@ def main():
     if err is None:
         del d_u, d_work
     torch.cuda.empty_cache()
+    if prec_name == "fp64" and kernel == 0 and not args.no_host_path:
+        out["host_path"] = host_path(heat, u0, nparts, r, nt)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u0, r, args.cpu_steps, prec_name,
                                            heat.plan(N, nt, prec)["steps_per_round"])
