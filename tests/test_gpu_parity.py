@@ -192,6 +192,31 @@ def test_signed_zeros_fp32_forms():
                 assert same_bits(got, want_c), ("fp32c", cfg, r, nt)
 
 
+def test_golden_ramp_exact_on_gpu():
+    """The stored exact solutions for the paper's ramp initial condition
+    (tests/golden/ramp_exact.txt, rational arithmetic from the definition)
+    through the C ABI in every kernel family: bit for bit."""
+    import os
+    from fractions import Fraction
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ramp_exact.txt")
+    cases = []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.split()
+            N, r, nt = int(f[0]), float(Fraction(f[1])), int(f[2])
+            cases.append((N, r, nt, np.array([float(Fraction(x)) for x in f[3:3 + N]])))
+    assert len(cases) >= 4
+    for N, r, nt, want in cases:
+        u0 = np.arange(N, dtype=np.float64)
+        for cfg in (dict(), dict(kernel=heat.KERNEL_STEP),
+                    dict(cells_per_lane=8, steps_per_round=4, register_form=1),
+                    dict(cells_per_lane=32, steps_per_round=8, waves_per_group=4,
+                         exchange=heat.EXCHANGE_LDS)):
+            assert same_bits(run_dev(u0, nt, r, **cfg), want), (N, r, nt, cfg)
+
+
 # ------------------------------------------------------------ invariances on the GPU
 
 def test_partition_count_does_not_change_result():

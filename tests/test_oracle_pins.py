@@ -378,3 +378,36 @@ def test_shifted_storage_error():
     # the offsets really are small: about the perturbation, not the mean
     v = oracle.to_offsets(u0, s)
     assert np.abs(v).max() <= 1.1e-3
+
+
+# ------------------------------------------------------------ stored exact values
+
+def load_ramp_golden():
+    """Cases of tests/golden/ramp_exact.txt: (N, r, nt, exact values)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ramp_exact.txt")
+    out = []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.split()
+            N, r, nt = int(f[0]), Fraction(f[1]), int(f[2])
+            out.append((N, r, nt, [Fraction(x) for x in f[3:3 + N]]))
+    return out
+
+
+def test_golden_ramp_exact():
+    """The paper's ramp initial condition (u0[i] = i) on small periodic rings:
+    every oracle implementation reproduces the stored exact rational solution
+    (tests/golden/ramp_exact.txt) bit for bit, whatever the segment count."""
+    cases = load_ramp_golden()
+    assert len(cases) >= 4
+    for N, r, nt, want in cases:
+        assert sum(want) == sum(range(N))          # the fixture itself conserves the sum
+        u0 = np.arange(N, dtype=np.float64)
+        assert as_fractions(oracle.solve(u0, float(r), nt)) == want, (N, r, nt)
+        assert as_fractions(oracle.np_solve(u0, float(r), nt)) == want, (N, r, nt)
+        for P in sorted({1, 2, 3, N}):
+            assert as_fractions(oracle.solve_parts(u0, P, float(r), nt)) == want, (N, P)
+            assert as_fractions(oracle.solve_threads(u0, P, float(r), nt)) == want, (N, P)
