@@ -177,5 +177,18 @@ def test_tuning_table_roundtrip(lib, tmp_path):
         bad.write_text("0 6 12 48 4 1\n")
         with pytest.raises(heat.HeatError):
             heat.tune_load(str(bad))
+        # a malformed line stops the load with HEAT_EINVAL; the lines before it stay
+        part = tmp_path / "part.txt"
+        part.write_text("0 6 32 96 2 3 1\n0 6 32 96 9 3 1\n")
+        with pytest.raises(heat.HeatError) as ei:
+            heat.tune_load(str(part))
+        assert ei.value.code == heat.HEAT_EINVAL
+        p = heat.plan(5_000_000, 1000, heat.FP64)
+        assert (p["cells_per_lane"], p["waves_per_group"], p["register_form"]) == (32, 2, 3)
+        # seven columns: the exchange column is read (LDS for this shape)
+        x = tmp_path / "x.txt"
+        x.write_text("0 6 32 96 4 3 2\n")
+        heat.tune_load(str(x))
+        assert heat.plan(5_000_000, 1000, heat.FP64)["exchange_steps"] == 8
     finally:
         heat.tune_load(str(saved))
