@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--batch-mode", default="rounds", choices=["rounds", "graph", "persistent"])
     ap.add_argument("--no-plain-compare", action="store_true",
                     help="batch: skip solving the rings one by one for comparison")
-    ap.add_argument("--cpu-steps", type=int, default=15,
+    ap.add_argument("--cpu-steps", type=int, default=40,
                     help="time steps of the full ring the CPU oracle runs as its sample")
     ap.add_argument("--no-host-path", action="store_true",
                     help="skip timing the host-buffer boundary (heat_solve: PCIe both ways)")
