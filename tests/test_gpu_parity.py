@@ -437,14 +437,16 @@ def test_unaligned_device_array_takes_gather_path():
     assert same_bits(v32[1:].cpu().numpy(), oracle.solve_f32c(u32, 0.25, 70, T))
 
 
-def test_ring_beyond_2_pow_31_cells():
-    """Largest size class: 2^31 + 12,345 binary32 cells (64-bit tile and cell
-    indices everywhere), a few steps; sampled cells against light cones of
-    the initial state (drawn with torch on the device, copied out before the
-    solve)."""
+@pytest.mark.parametrize("prec", [heat.FP32, heat.FP32C, heat.FP64])
+def test_ring_beyond_2_pow_31_cells(prec):
+    """Largest size class: 2^31 + 12,345 cells (64-bit tile and cell indices
+    everywhere; 52 GB of HBM in binary64), a few steps, lone and cooperating
+    waves; sampled cells against light cones of the initial state (drawn
+    with torch on the device, copied out before the solve)."""
     N = (1 << 31) + 12_345
+    dt = torch.float64 if prec == heat.FP64 else torch.float32
     g = torch.Generator(device="cuda").manual_seed(36)
-    d = torch.rand(N, generator=g, device="cuda", dtype=torch.float32)
+    d = torch.rand(N, generator=g, device="cuda", dtype=dt)
     nt, r = 20, 0.25
     rng = np.random.default_rng(37)
     idx = sorted({0, 1, N - 1, N - 2, (1 << 31) - 1, 1 << 31, (1 << 31) + 1} |
@@ -454,14 +456,22 @@ def test_ring_beyond_2_pow_31_cells():
         w = torch.arange(i - nt, i + nt + 1, device="cuda") % N
         wins[i] = d[w].cpu().numpy()
     d2 = d.clone()
-    heat.solve_dev(d, 1, r, nt, precision=heat.FP32)
+    heat.solve_dev(d, 1, r, nt, precision=prec)
     # and with the waves of a workgroup sharing tiles
-    heat.solve_dev(d2, 1, r, nt, precision=heat.FP32, cells_per_lane=32, waves_per_group=4,
+    heat.solve_dev(d2, 1, r, nt, precision=prec, cells_per_lane=32, waves_per_group=4,
                    exchange=heat.EXCHANGE_LDS)
+    T = heat.plan(N, nt, prec)["steps_per_round"]
     for i in idx:
-        want = oracle.cone_f32(wins[i], nt, r, nt)
-        assert d[i].item() == want, i
-        assert d2[i].item() == want, i
+        if prec == heat.FP32:
+            want = np.float32(oracle.cone_f32(wins[i], nt, r, nt))
+        elif prec == heat.FP32C:
+            want = np.float32(oracle.cone_f32c(wins[i], nt, r, nt, T))
+        else:
+            want = np.float64(oracle.cone(wins[i], nt, r, nt))
+        got = np.array([d[i].item(), d2[i].item()], dtype=want.dtype)
+        assert same_bits(got, np.array([want, want])), (i, prec)
+    del d, d2
+    torch.cuda.empty_cache()
 
 
 def test_copy_probe_and_device_info():
