@@ -73,7 +73,9 @@ int describe_ring(const heat_ring &g, BatchRing *out, int K, int G) {
 int describe_ring_batch(const heat_ring &g, BatchRing *out) {
     const int K = batch_cells_per_lane(g.precision, g.N);
     int rc = describe_ring(g, out, K, 1);
-    if (rc || K != 64 || g.nt == 0) return rc;
+    // the 4-wave classes: binary64 at 64-cell lanes, compensated binary32 at 32
+    const bool has_x = (g.precision == HEAT_FP64 && K == 64) || g.precision == HEAT_FP32C;
+    if (rc || !has_x || g.nt == 0) return rc;
     // Cost in wave-steps: every tile costs its waves x (steps + a per-round
     // overhead for loading and storing the window, about 4 steps' worth);
     // the exchange's own steps cost about 1 % more.

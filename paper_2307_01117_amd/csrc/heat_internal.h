@@ -165,8 +165,9 @@ hipError_t launch_batch_round(int precision, int K, int G, const BatchRing *ring
                               hipStream_t st);
 int batch_grid_size(int precision, int K, int wpg, int *grid);
 // The compensated form's batch classes (kernels_f32c.hip).
-hipError_t launch_batch_round_fp32c(int K, const BatchRing *rings, const int64_t *tile_prefix,
-                                    int k, int active, int64_t items, int wpg, hipStream_t st);
+hipError_t launch_batch_round_fp32c(int K, int G, const BatchRing *rings,
+                                    const int64_t *tile_prefix, int k, int active, int64_t items,
+                                    int wpg, hipStream_t st);
 hipError_t launch_batch_fp32c(int K, const BatchPlanDev &plan, int grid, int wpg,
                               hipStream_t st);
 int batch_occupancy_fp32c(int K, int wpg);

@@ -17,13 +17,20 @@ hipError_t launch_window_fp32c(const WindowLaunch &a, hipStream_t st) {
     return a.xchg ? launch_window_f<F32C, true>(a, st) : launch_window_f<F32C, false>(a, st);
 }
 
-// The batch class: 32-cell lanes, one wave per tile, in-place sweeps (under
-// this file's scheduler the fastest form at 32 cells per lane).
+// The batch classes: 32-cell lanes swept in place (under this file's
+// scheduler the fastest form at 32 cells per lane), one wave per tile, or
+// for long rings tiles of 4 waves that swap edges through LDS (the plain
+// path's tuned compensated shape).
 constexpr int BATCH_FP32C_FORM = FORM_INPLACE;
 
-hipError_t launch_batch_round_fp32c(int K, const BatchRing *rings, const int64_t *tile_prefix,
-                                    int k, int active, int64_t items, int wpg, hipStream_t st) {
+hipError_t launch_batch_round_fp32c(int K, int G, const BatchRing *rings,
+                                    const int64_t *tile_prefix, int k, int active, int64_t items,
+                                    int wpg, hipStream_t st) {
     if (K != 32) return hipErrorInvalidValue;
+    if (G == 4)
+        return launch_batch_round_x<F32C, 32, BATCH_FP32C_FORM>(rings, tile_prefix, k, active,
+                                                                items, G, st);
+    if (G != 1) return hipErrorInvalidValue;
     return launch_batch_round_t<F32C, 32, BATCH_FP32C_FORM>(rings, tile_prefix, k, active, items,
                                                             wpg, st);
 }
