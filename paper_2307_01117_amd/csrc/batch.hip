@@ -18,7 +18,7 @@ namespace heat {
 static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 int batch_cells_per_lane(int precision, int64_t N) {
-    return precision == HEAT_FP64 && N >= 65536 ? 64 : 32;
+    return precision != HEAT_FP32C && N >= 65536 ? 64 : 32;
 }
 
 // Shortest target round length of a batch kernel class.  The tuning table's
@@ -73,8 +73,9 @@ int describe_ring(const heat_ring &g, BatchRing *out, int K, int G) {
 int describe_ring_batch(const heat_ring &g, BatchRing *out) {
     const int K = batch_cells_per_lane(g.precision, g.N);
     int rc = describe_ring(g, out, K, 1);
-    // the 4-wave classes: binary64 at 64-cell lanes, compensated binary32 at 32
-    const bool has_x = (g.precision == HEAT_FP64 && K == 64) || g.precision == HEAT_FP32C;
+    // the 4-wave classes: binary64 and binary32 at 64-cell lanes, compensated
+    // binary32 at 32
+    const bool has_x = (g.precision != HEAT_FP32C && K == 64) || g.precision == HEAT_FP32C;
     if (rc || !has_x || g.nt == 0) return rc;
     // Cost in wave-steps: every tile costs its waves x (steps + a per-round
     // overhead for loading and storing the window, about 4 steps' worth);

@@ -15,6 +15,9 @@ hipError_t launch_batch_round(int precision, int K, int G, const BatchRing *ring
         if (precision == HEAT_FP64 && K == 64)
             return launch_batch_round_x<F64, 64, FORM_ALTERNATING>(rings, tile_prefix, k, active,
                                                                    items, G, st);
+        if (precision == HEAT_FP32 && K == 64)
+            return launch_batch_round_x<F32, 64, FORM_INPLACE>(rings, tile_prefix, k, active, items,
+                                                               G, st);
         if (precision == HEAT_FP32C)
             return launch_batch_round_fp32c(K, G, rings, tile_prefix, k, active, items, wpg, st);
         return hipErrorInvalidValue;
@@ -25,6 +28,9 @@ hipError_t launch_batch_round(int precision, int K, int G, const BatchRing *ring
     if (precision == HEAT_FP64 && K == 32)
         return launch_batch_round_t<F64, 32, FORM_ALTERNATING>(rings, tile_prefix, k, active, items,
                                                                wpg, st);
+    if (precision == HEAT_FP32 && K == 64)
+        return launch_batch_round_t<F32, 64, FORM_INPLACE>(rings, tile_prefix, k, active, items,
+                                                           wpg, st);
     if (precision == HEAT_FP32 && K == 32)
         return launch_batch_round_t<F32, 32, FORM_INPLACE>(rings, tile_prefix, k, active, items,
                                                            wpg, st);

@@ -263,12 +263,14 @@ def test_device_batch_long_rings_all_classes():
             assert u[i].item() == oracle.cone(u0, i, r, nt), (N, nt, i)
 
 
-def test_device_batch_compensated_long_rings():
-    """Compensated binary32 rings long enough for the 4-wave class (tiles of
-    4 waves swapping edges through LDS) batched with short ones that stay on
-    one wave per tile: every ring bit for bit equal to the ring solved alone,
-    and sampled cells (tile and wave edges of both shapes) equal to the
-    oracle's light cones with the form's round length."""
+@pytest.mark.parametrize("prec", [heat.FP32, heat.FP32C])
+def test_device_batch_binary32_long_rings(prec):
+    """Binary32 rings long enough for the wide classes (plain: 64-cell lanes,
+    the longest as tiles of 4 waves swapping edges through LDS; compensated:
+    4-wave tiles at 32-cell lanes) batched with short ones that stay on one
+    wave per tile: every ring bit for bit equal to the ring solved alone, and
+    sampled cells (tile and wave edges of the shapes the batch may use) equal
+    to the oracle's light cones."""
     rng = np.random.default_rng(55)
     Ns = [100_003, 250_000, 1_000_001, 2_000_003, 777, 20_000]
     nts = [301, 77, 130, 64, 999, 65]
@@ -279,22 +281,29 @@ def test_device_batch_compensated_long_rings():
         us.append(torch.from_numpy(u0).cuda())
     work = [torch.empty_like(u) for u in us]
     rs = [float(0.5 - 0.4 * rng.random()) for _ in Ns]
-    heat.solve_batch_dev([(u, w, nt, r, heat.FP32C) for u, w, nt, r in zip(us, work, nts, rs)])
+    heat.solve_batch_dev([(u, w, nt, r, prec) for u, w, nt, r in zip(us, work, nts, rs)])
     torch.cuda.synchronize()
     T = heat.plan(1000, 1000, heat.FP32C)["steps_per_round"]
+    if prec == heat.FP32C:   # (tile cells, offset of the second wave's window)
+        shapes = ((64 * 32 - 2 * 64, 0, 8, 64), (4 * 2048 - 3 * 16 - 2 * 64, 2048 - 16, 8, 64))
+    else:
+        shapes = ((64 * 64 - 2 * 256, 0, 16, 256), (4 * 4096 - 3 * 32 - 2 * 256, 4096 - 32, 16, 256))
     for k, (N, nt, r, u0, u) in enumerate(zip(Ns, nts, rs, u0s, us)):
         a = torch.from_numpy(u0).cuda()
-        heat.solve_dev(a, 1, r, nt, precision=heat.FP32C)
+        heat.solve_dev(a, 1, r, nt, precision=prec)
         assert same_bits(u.cpu().numpy(), a.cpu().numpy()), (N, nt)
         cells = {0, N - 1, int(rng.integers(0, N))}
-        for W, step in ((64 * 32 - 2 * 64, 0), (4 * 2048 - 3 * 16 - 2 * 64, 2048 - 16)):
+        for W, step, S, H in shapes:
             for t in (1, 2):
                 cells.update({(t * W + d) % N for d in (-1, 0, 1)})
                 if step:
-                    cells.update({(t * W + step + 8 - 64 + d) % N for d in (-1, 0, 1)})
+                    cells.update({(t * W + step + S - H + d) % N for d in (-1, 0, 1)})
         got = u.cpu().numpy()
         for i in sorted(cells):
-            want = np.float32(oracle.cone_f32c(u0, i, r, nt, T))
+            if prec == heat.FP32C:
+                want = np.float32(oracle.cone_f32c(u0, i, r, nt, T))
+            else:
+                want = np.float32(oracle.cone_f32(u0, i, r, nt))
             assert same_bits(got[i:i + 1], np.array([want])), (N, nt, i)
 
 
