@@ -223,13 +223,17 @@ enum heat_batch_flags {
 };
 
 /*
- * Device-resident batching form: every ring advances round by round; by
- * default each round of all still-running rings is one launch over the flat
- * list of their tiles (the kernel boundary is the round barrier).  Rings are
- * ordered by their number of rounds, so the running ones are a prefix of the
- * table.  The per-ring T comes from the same rule as heat_plan, so each
- * ring's result is bit-identical to solving it alone.  With
- * HEAT_BATCH_PERSISTENT all rounds of all rings run in a single launch:
+ * Device-resident batching form: every ring advances round by round.  Rings
+ * fall into kernel classes by precision and length (32- or 64-cell lanes, or
+ * for the longest rings tiles of 4 waves that swap edges through LDS); by
+ * default each round of a class's still-running rings is one launch over the
+ * flat list of their tiles (the kernel boundary is the round barrier).  Rings
+ * are ordered by their number of rounds, so the running ones are a prefix of
+ * their class's table.  A class may run longer rounds than heat_plan would,
+ * which changes no binary64 or binary32 result, and the compensated form
+ * keeps its fixed round length, so each ring's result is bit-identical to
+ * solving it alone.  With HEAT_BATCH_PERSISTENT (32-cell lanes, one wave per
+ * tile) all rounds of all rings run in a single launch:
  * tiles are claimed in round order from one counter and each waits for the
  * tiles within H cells of it to finish the previous round (agent-scope
  * release/acquire; a bounded wait turns a stall into HEAT_EDEVICE instead of
