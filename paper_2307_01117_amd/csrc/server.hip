@@ -104,7 +104,13 @@ constexpr int32_t TICK_ROUNDS = 2;
 // requests/s: p50 / p99 13.4 / 63.7 ms with 32-cell lanes against 25.6 /
 // 75.9 ms with the batching form's classes, at the same throughput.
 constexpr int SERVER_CELLS_PER_LANE = 32;
-constexpr int TABLE_GROUPS = 6;        // (precision, 32- or 64-cell lanes) round tables per tick
+constexpr int TABLE_GROUPS = 9;        // (precision, kernel class) round tables per tick
+// Requests admitted while more than this many are resident take the batching
+// form's classes (64-cell lanes, 4-wave tiles for the longest rings): under
+// load throughput decides latency, and those classes carry more cell updates
+// per launch; at light load every request keeps 32-cell lanes.  A request
+// keeps its class for life, and no class changes a result.
+constexpr int32_t SERVER_BUSY_SLOTS = 64;
 
 }  // namespace heat
 
@@ -228,7 +234,8 @@ static int run_tick(heat_server *s, std::vector<Req *> &act, uint64_t tick) {
     // group by precision and kernel class; every ring advances the rounds
     // that cover the tick's steps
     std::vector<BatchRing> groups[TABLE_GROUPS];
-    for (Req *q : act) groups[q->ring.precision * 2 + (q->br.K == 64)].push_back(q->br);
+    for (Req *q : act)
+        groups[q->ring.precision * 3 + (q->br.G > 1 ? 2 : (q->br.K == 64))].push_back(q->br);
     const int slot = (int)(tick & 1);
     HEAT_HIP(hipEventSynchronize(s->table_ev[slot]));   // the tick that used this slot is done
     char *dt = s->d_tables + slot * s->table_slot_bytes;
@@ -237,7 +244,7 @@ static int run_tick(heat_server *s, std::vector<Req *> &act, uint64_t tick) {
     for (int g = 0; g < TABLE_GROUPS; ++g) {
         if (groups[g].empty()) continue;
         BatchLaunch L;
-        int rc = L.build(groups[g], g / 2, s->tick_steps ? 0 : TICK_ROUNDS, s->tick_steps);
+        int rc = L.build(groups[g], g / 3, s->tick_steps ? 0 : TICK_ROUNDS, s->tick_steps);
         if (!rc) rc = L.enqueue_rounds(dt + g * per_group, ht + g * per_group, s->compute);
         if (rc) return rc;
     }
@@ -264,7 +271,10 @@ static void sched_loop(heat_server *s) {
             q->ring.d_work = b + Arena::round((size_t)q->ring.N * es);
             q->d_sums = (double *)(b + Arena::round((size_t)q->ring.N * es) +
                                    Arena::round((size_t)q->ring.N * std::max<size_t>(es, 8)));
-            describe_ring(q->ring, &q->br, SERVER_CELLS_PER_LANE);
+            if (s->slots_used > SERVER_BUSY_SLOTS)
+                describe_ring_batch(q->ring, &q->br);
+            else
+                describe_ring(q->ring, &q->br, SERVER_CELLS_PER_LANE);
             q->state = STAGING;
             ++s->st.admitted;
             s->h2d.push_back(q);

@@ -213,6 +213,28 @@ def test_submit_from_many_threads_and_destroy_with_work_outstanding():
     s.close()
 
 
+def test_busy_server_classes_equal_alone():
+    """More requests resident at once than the server's light-load limit
+    (64), so the later ones are admitted into the batching form's wide
+    classes (64-cell lanes, 4-wave tiles): every result, of all three
+    precisions, bit for bit equal to the request solved alone."""
+    rng = np.random.default_rng(61)
+    reqs = []
+    for k in range(120):
+        # the first 64 are long enough (tens of ms together) to be resident
+        # when the others are admitted
+        N = int(10 ** rng.uniform(6.0, 6.3)) if k < 64 else int(10 ** rng.uniform(4.5, 6.3))
+        nt = int(rng.integers(2000, 3000)) if k < 64 else int(rng.integers(60, 900))
+        r = float(0.5 - 0.4 * rng.random())
+        prec = (heat.FP64, heat.FP32C, heat.FP32)[k % 3]
+        reqs.append((inputs.uniform_ring(N, (62, k)), nt, r, prec))
+    with heat.Server() as srv:
+        tickets = [srv.submit(u0, nt, r, prec) for u0, nt, r, prec in reqs]
+        results = [srv.wait(t) for t in tickets]
+    for (u0, nt, r, prec), res in zip(reqs, results):
+        assert same_bits(res.u, alone(u0, nt, r, prec)), (u0.size, nt, prec)
+
+
 @pytest.mark.skipif(os.environ.get("HEAT_FULL_SERVE_PARITY") != "1",
                     reason="one-off check, minutes of host CPU: set HEAT_FULL_SERVE_PARITY=1")
 def test_serving_trace_vs_oracle():
