@@ -96,11 +96,11 @@ static size_t footprint(int64_t N, int precision) {
 // HEAT_SERVER_TICK_STEPS (optional) instead sizes ticks in steps.
 constexpr int32_t TICK_ROUNDS = 2;
 
-// Cells per lane of every served ring.  A tick's rounds are launches that a
-// mix of requests fills only partly, so a round lasts about as long as its
-// slowest tile, and a 64-cell tile takes twice as long as a 32-cell one; the
-// batching form, which fills the GPU, uses 64-cell lanes for long binary64
-// rings instead.  Measured on MI355X with the serving mix at 1,000
+// Cells per lane of a ring served at light load.  A tick's rounds are
+// launches that a mix of requests fills only partly, so a round lasts about
+// as long as its slowest tile, and a 64-cell tile takes twice as long as a
+// 32-cell one; the batching form, which fills the GPU, uses wider classes
+// (and so does the server under load, see SERVER_BUSY_SLOTS).  Measured on MI355X with the serving mix at 1,000
 // requests/s: p50 / p99 13.4 / 63.7 ms with 32-cell lanes against 25.6 /
 // 75.9 ms with the batching form's classes, at the same throughput.
 constexpr int SERVER_CELLS_PER_LANE = 32;
