@@ -217,6 +217,52 @@ def test_golden_ramp_exact_on_gpu():
             assert same_bits(run_dev(u0, nt, r, **cfg), want), (N, r, nt, cfg)
 
 
+def test_device_form_from_many_threads():
+    """The device form called from several host threads at once, each on its
+    own stream and with checksums (per-thread checksum scratch, the shared
+    stream-ordered pool): every result bit for bit the oracle's and every
+    pair of sums equal to the exact sums."""
+    import math
+    import threading
+    cases = [(50_000 + 7919 * k, 40 + 9 * k, 0.5 - 0.05 * k, heat.FP64 if k % 2 == 0 else heat.FP32C)
+             for k in range(8)]
+    inputs_ = [inputs.uniform_ring(N, (63, k)) for k, (N, _, _, _) in enumerate(cases)]
+    out, errs = {}, []
+
+    def work(k):
+        try:
+            N, nt, r, prec = cases[k]
+            st = torch.cuda.Stream()
+            dt = torch.float64 if prec == heat.FP64 else torch.float32
+            with torch.cuda.stream(st):
+                d = torch.from_numpy(inputs_[k]).to("cuda", dtype=dt)
+                for _ in range(3):      # repeated calls reuse the thread's scratch
+                    d.copy_(torch.from_numpy(inputs_[k]).to("cuda", dtype=dt))
+                    sums = heat.solve_dev(d, 1, r, nt, precision=prec, stream=st, sums=True)
+                out[k] = (d.cpu().numpy(), sums)
+        except Exception as e:   # reported below, on the main thread
+            errs.append((k, e))
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(cases))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errs, errs
+    for k, (N, nt, r, prec) in enumerate(cases):
+        got, (s0, s1) = out[k]
+        if prec == heat.FP64:
+            want = oracle.solve(inputs_[k], r, nt)
+            start = inputs_[k]
+        else:
+            T = heat.plan(N, nt, heat.FP32C)["steps_per_round"]
+            start = inputs_[k].astype(np.float32)
+            want = oracle.solve_f32c(start, r, nt, T)
+        assert same_bits(got, want), (k, N, nt, prec)
+        assert abs(s0 - math.fsum(start.astype(np.float64))) <= 1e-12 * abs(s0), k
+        assert abs(s1 - math.fsum(want.astype(np.float64))) <= 1e-12 * abs(s1), k
+
+
 # ------------------------------------------------------------ invariances on the GPU
 
 def test_partition_count_does_not_change_result():
