@@ -205,9 +205,9 @@ def cpu_model():
 def cpu_threads(u0, r, steps, workload, max_threads=16):
     """The paper's own CPU method, timed along its thread axis: one thread per
     segment, ghost cells through single-producer single-consumer queues (the
-    threaded oracle; every thread count gives the same bits).  Two samples:
-    the paper's workload (ramp, 1e6 cells, 1,000 steps) and a few steps of the
-    full ring timed above."""
+    threaded oracle; every thread count gives the same bits).  Three samples:
+    the paper's workload (ramp, 1e6 cells, 1,000 steps), the 1e6-cell
+    Uniform ring of 100 steps, and a few steps of the full ring timed above."""
     import numpy as np
 
     import oracle
@@ -215,8 +215,11 @@ def cpu_threads(u0, r, steps, workload, max_threads=16):
     avail = len(os.sched_getaffinity(0))
     threads = [t for t in (1, 2, 4, 8, 16) if t <= min(avail, max_threads)]
     ramp = inputs.WORKLOADS["paper_ramp_1e6"]
+    small = inputs.WORKLOADS["ring_1e6"]
     samples = [("paper_ramp_1e6", inputs.make_initial(ramp["init"], ramp["N"], ramp["seed"]),
                 ramp["r"], ramp["nt"]),
+               ("ring_1e6", inputs.make_initial(small["init"], small["N"], small["seed"]),
+                small["r"], small["nt"]),
                (f"{workload}, {steps} steps", u0, r, steps)]
     res = {}
     for name, u, rr, nt in samples:
