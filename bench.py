@@ -126,7 +126,7 @@ def kernel_source_digest() -> str:
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2307_01117_amd")
     for f in ("heat_device.h", "window.h", "round.h", "kernels.hip", "kernels_xchg.hip",
-              "kernels_f32c.hip"):
+              "kernels_f32.hip", "kernels_f32c.hip"):
         with open(os.path.join(pkg, "csrc", f), "rb") as fh:
             h.update(fh.read())
     with open(os.path.join(pkg, "build.py"), "rb") as fh:

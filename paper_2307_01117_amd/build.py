@@ -15,13 +15,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libheat.so")
-SOURCES = ["kernels.hip", "kernels_xchg.hip", "kernels_f32c.hip", "batch_kernels.hip",
-           "runtime.hip", "batch.hip", "server.hip", "tune.hip"]
+SOURCES = ["kernels.hip", "kernels_xchg.hip", "kernels_f32.hip", "kernels_f32c.hip",
+           "batch_kernels.hip", "runtime.hip", "batch.hip", "server.hip", "tune.hip"]
 
-# Per-source additions: the compensated binary32 kernels are scheduled for
-# instruction-level parallelism (their ten-operation chains per cell pair
-# better when neighbouring cells interleave); the order changes no result.
+# Per-source additions: the binary32 kernels are scheduled for instruction-
+# level parallelism (their per-cell operation chains pair better when
+# neighbouring cells interleave); the order changes no result.  Binary64
+# instructions do not pair, so its kernels keep the default schedule.
 SOURCE_FLAGS = {
+    "kernels_f32.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
     "kernels_f32c.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
 }
 

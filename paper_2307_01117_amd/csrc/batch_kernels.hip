@@ -1,6 +1,6 @@
-// batch_kernels.hip -- the batching form's launchers and its binary64 and
-// binary32 kernel classes (batch_kernels.h); the compensated form's classes
-// are in kernels_f32c.hip.
+// batch_kernels.hip -- the batching form's launchers and its binary64
+// kernel classes (batch_kernels.h); the binary32 forms' classes are in
+// kernels_f32.hip and kernels_f32c.hip.
 #include "batch_kernels.h"
 
 namespace heat {
@@ -15,9 +15,8 @@ hipError_t launch_batch_round(int precision, int K, int G, const BatchRing *ring
         if (precision == HEAT_FP64 && K == 64)
             return launch_batch_round_x<F64, 64, FORM_ALTERNATING>(rings, tile_prefix, k, active,
                                                                    items, G, st);
-        if (precision == HEAT_FP32 && K == 64)
-            return launch_batch_round_x<F32, 64, FORM_INPLACE>(rings, tile_prefix, k, active, items,
-                                                               G, st);
+        if (precision == HEAT_FP32)
+            return launch_batch_round_fp32(K, G, rings, tile_prefix, k, active, items, wpg, st);
         if (precision == HEAT_FP32C)
             return launch_batch_round_fp32c(K, G, rings, tile_prefix, k, active, items, wpg, st);
         return hipErrorInvalidValue;
@@ -28,12 +27,8 @@ hipError_t launch_batch_round(int precision, int K, int G, const BatchRing *ring
     if (precision == HEAT_FP64 && K == 32)
         return launch_batch_round_t<F64, 32, FORM_ALTERNATING>(rings, tile_prefix, k, active, items,
                                                                wpg, st);
-    if (precision == HEAT_FP32 && K == 64)
-        return launch_batch_round_t<F32, 64, FORM_INPLACE>(rings, tile_prefix, k, active, items,
-                                                           wpg, st);
-    if (precision == HEAT_FP32 && K == 32)
-        return launch_batch_round_t<F32, 32, FORM_INPLACE>(rings, tile_prefix, k, active, items,
-                                                           wpg, st);
+    if (precision == HEAT_FP32)
+        return launch_batch_round_fp32(K, 1, rings, tile_prefix, k, active, items, wpg, st);
     if (precision == HEAT_FP32C)
         return launch_batch_round_fp32c(K, 1, rings, tile_prefix, k, active, items, wpg, st);
     return hipErrorInvalidValue;
@@ -42,7 +37,7 @@ hipError_t launch_batch_round(int precision, int K, int G, const BatchRing *ring
 hipError_t launch_batch(int precision, int K, const BatchPlanDev &plan, int grid, int wpg,
                         hipStream_t st) {
     if (precision == HEAT_FP64 && K == 32) return launch_batch_t<F64, 32>(plan, grid, wpg, st);
-    if (precision == HEAT_FP32 && K == 32) return launch_batch_t<F32, 32>(plan, grid, wpg, st);
+    if (precision == HEAT_FP32) return launch_batch_fp32(K, plan, grid, wpg, st);
     if (precision == HEAT_FP32C) return launch_batch_fp32c(K, plan, grid, wpg, st);
     return hipErrorInvalidValue;
 }
@@ -53,7 +48,7 @@ int batch_grid_size(int precision, int K, int wpg, int *grid) {
     HEAT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int nb = 0;
     if (precision == HEAT_FP64 && K == 32) nb = occupancy_blocks<F64, 32>(wpg);
-    else if (precision == HEAT_FP32 && K == 32) nb = occupancy_blocks<F32, 32>(wpg);
+    else if (precision == HEAT_FP32) nb = batch_occupancy_fp32(K, wpg);
     else if (precision == HEAT_FP32C) nb = batch_occupancy_fp32c(K, wpg);
     if (nb < 1) nb = 1;
     *grid = nb * cus;

@@ -88,6 +88,8 @@ struct WindowLaunch {
 hipError_t launch_window(const WindowLaunch &a, hipStream_t st);
 hipError_t launch_window_lone(const WindowLaunch &a, hipStream_t st);   // kernels.hip
 hipError_t launch_window_xchg(const WindowLaunch &a, hipStream_t st);   // kernels_xchg.hip
+// binary32, lone or exchanging waves as a.xchg says                  // kernels_f32.hip
+hipError_t launch_window_fp32(const WindowLaunch &a, hipStream_t st);
 // compensated binary32, lone or exchanging waves as a.xchg says       // kernels_f32c.hip
 hipError_t launch_window_fp32c(const WindowLaunch &a, hipStream_t st);
 // Output cells of one tile: 64K - 2H for a lone wave; for wpg cooperating
@@ -164,6 +166,12 @@ hipError_t launch_batch_round(int precision, int K, int G, const BatchRing *ring
                               const int64_t *tile_prefix, int k, int active, int64_t items, int wpg,
                               hipStream_t st);
 int batch_grid_size(int precision, int K, int wpg, int *grid);
+// The plain binary32 form's batch classes (kernels_f32.hip).
+hipError_t launch_batch_round_fp32(int K, int G, const BatchRing *rings,
+                                   const int64_t *tile_prefix, int k, int active, int64_t items,
+                                   int wpg, hipStream_t st);
+hipError_t launch_batch_fp32(int K, const BatchPlanDev &plan, int grid, int wpg, hipStream_t st);
+int batch_occupancy_fp32(int K, int wpg);
 // The compensated form's batch classes (kernels_f32c.hip).
 hipError_t launch_batch_round_fp32c(int K, int G, const BatchRing *rings,
                                     const int64_t *tile_prefix, int k, int active, int64_t items,

@@ -2,10 +2,11 @@
 // launcher, as templates: kernels.hip instantiates the lone-wave variant,
 // kernels_xchg.hip the variant whose waves share a tile through LDS (kept
 // apart so that the two compile in parallel and each kernel holds one loop
-// structure, which keeps its register count at what the window needs), both
-// for binary64 and binary32.  kernels_f32c.hip instantiates both variants of
-// the compensated form, which is built with its own instruction scheduler;
-// no other file may instantiate them (see launch_window_any).
+// structure, which keeps its register count at what the window needs) for
+// binary64.  kernels_f32.hip and kernels_f32c.hip instantiate both variants
+// of the plain and the compensated binary32 forms, which are built with
+// their own instruction scheduler; no other file may instantiate them (see
+// launch_window_any).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -89,14 +90,14 @@ hipError_t launch_window_f(const WindowLaunch &a, hipStream_t st) {
     }
 }
 
-// The compensated form's kernels live in kernels_f32c.hip alone: a second
-// instantiation elsewhere, compiled with another scheduler, would leave it
-// to the linker which of the two copies a launch runs.
+// The binary32 forms' kernels live in kernels_f32.hip and kernels_f32c.hip
+// alone: a second instantiation elsewhere, compiled with another scheduler,
+// would leave it to the linker which of the two copies a launch runs.
 template <bool XCHG>
 hipError_t launch_window_any(const WindowLaunch &a, hipStream_t st) {
     switch (a.precision) {
         case HEAT_FP64: return launch_window_f<F64, XCHG>(a, st);
-        case HEAT_FP32: return launch_window_f<F32, XCHG>(a, st);
+        case HEAT_FP32: return launch_window_fp32(a, st);
         case HEAT_FP32C: return launch_window_fp32c(a, st);
         default: return hipErrorInvalidValue;
     }
