@@ -107,7 +107,8 @@ hipError_t launch_step(int precision, const void *src, void *dst, int64_t N, dou
 // Cells per wave chunk of the step kernel.
 int64_t step_chunk_cells(int precision);
 
-// Deterministic binary64 sum: `partial` needs SUM_BLOCKS doubles, result in
+// Deterministic binary64 sum: `partial` needs SUM_BLOCKS doubles (fewer are
+// used for rings under 16.8 M cells: one slice per 4,096 cells), result in
 // d_out[0].
 constexpr int SUM_BLOCKS = 4096;
 hipError_t launch_sum(int precision, const void *u, int64_t N, double *partial, double *d_out,

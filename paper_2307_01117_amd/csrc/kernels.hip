@@ -13,6 +13,8 @@
 //     counters (fused batch form).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "heat_device.h"
 #include "heat_internal.h"
 #include "round.h"
@@ -243,19 +245,28 @@ hipError_t launch_step(int precision, const void *src, void *dst, int64_t N, dou
     return hipGetLastError();
 }
 
+// Workgroups of the first pass: one per 4,096 cells, at most SUM_BLOCKS.  A
+// fixed shape for a given N, so the sum is deterministic; a short ring (the
+// requests of the serving mix) no longer launches thousands of empty slices.
+static unsigned sum_blocks(int64_t N) {
+    const int64_t b = (N + 4095) / 4096;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(SUM_BLOCKS, b));
+}
+
 hipError_t launch_sum(int precision, const void *u, int64_t N, double *partial, double *d_out,
                       hipStream_t st) {
     const int vec_ok = aligned16(u);
+    const unsigned G = sum_blocks(N);
     if (precision == HEAT_FP64)
-        hipLaunchKernelGGL(k_sum_partial<double>, dim3(SUM_BLOCKS), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_sum_partial<double>, dim3(G), dim3(256), 0, st,
                            reinterpret_cast<const double *>(u), N, partial, vec_ok);
     else
-        hipLaunchKernelGGL(k_sum_partial<float>, dim3(SUM_BLOCKS), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_sum_partial<float>, dim3(G), dim3(256), 0, st,
                            reinterpret_cast<const float *>(u), N, partial, vec_ok);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(FINAL_THREADS), 0, st, partial,
-                       (int64_t)SUM_BLOCKS, d_out);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(FINAL_THREADS), 0, st, partial, (int64_t)G,
+                       d_out);
     return hipGetLastError();
 }
 
