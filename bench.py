@@ -12,7 +12,7 @@ r = 1/2, 1,000 explicit-Euler steps per pass, Uniform[0,1) seed 1, binary64.
 The metric is giga cell-updates per second (N * nt / time), the paper's
 "cells processed per second".
 
-Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -243,7 +243,7 @@ def cpu_threads(u0, r, steps, workload, max_threads=16):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
