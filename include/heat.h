@@ -273,8 +273,10 @@ int heat_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t max_q
  * Submit a request (non-blocking).  *p, p->u0 and p->u_out must stay valid
  * and untouched until heat_poll returns something other than HEAT_PENDING
  * or heat_cancel returns.  Returns HEAT_EINVAL for a bad problem, HEAT_ENOMEM
- * if its footprint (2 * N * storage bytes) exceeds the whole budget,
- * HEAT_EBUSY if the queue is full.  *ticket identifies the request.
+ * if its footprint exceeds the whole budget (16 N bytes for binary64, 12 N
+ * for the binary32 forms -- the state plus a binary64 staging buffer -- each
+ * part rounded up to 256 bytes, plus 256), HEAT_EBUSY if the queue is full.
+ * *ticket identifies the request.
  */
 int heat_submit(heat_server *s, heat_problem *p, uint64_t *ticket);
 
@@ -286,15 +288,22 @@ int heat_submit(heat_server *s, heat_problem *p, uint64_t *ticket);
  */
 int heat_poll(heat_server *s, uint64_t ticket);
 
-/* Block until the request is done (or failed); same returns as heat_poll. */
+/* Block until the request is done (or failed); same returns as heat_poll.
+ * Any thread may poll, wait on or cancel any ticket: the first call that
+ * finds the request finished consumes the ticket, and a call that was
+ * waiting on it meanwhile returns HEAT_ENOENT. */
 int heat_wait(heat_server *s, uint64_t ticket);
 
-/* Cancel a queued or running request; its ticket is consumed. */
+/* Cancel a queued or running request; its ticket is consumed.  A request
+ * already copying its result out completes first, and its status is still
+ * set to HEAT_ECANCELED.  HEAT_ENOENT if another call consumed the ticket
+ * while this one waited for the device to let go of the request. */
 int heat_cancel(heat_server *s, uint64_t ticket);
 
 int heat_server_get_stats(heat_server *s, heat_server_stats *out);
 
-/* Cancel all outstanding work, stop the thread, free the arena. */
+/* Cancel all outstanding work, stop the server's threads, free the arena.
+ * No other call on this server may be running or follow. */
 int heat_server_destroy(heat_server *s);
 
 /* ---------------------------------------------------------------- tuning */

@@ -63,6 +63,7 @@ class Arena {
 };
 
 enum ReqState { QUEUED, STAGING, READY, ACTIVE, DRAINING, DONE, FAILED, CANCELLED };
+static bool finished_state(int st) { return st == DONE || st == FAILED || st == CANCELLED; }
 
 struct Req {
     uint64_t ticket = 0;
@@ -490,19 +491,33 @@ int heat_poll(heat_server *s, uint64_t ticket) {
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return fail(HEAT_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
-    const int st = it->second->state;
-    if (st == DONE || st == FAILED || st == CANCELLED) return consume_locked(s, it);
+    if (finished_state(it->second->state)) return consume_locked(s, it);
     return HEAT_PENDING;
+}
+
+// Wait until `ticket` is finished or gone.  Another thread may consume the
+// ticket (poll, wait, cancel) and free its request meanwhile, so the request
+// is looked up again on every wake and never held across the wait.  Returns
+// the ticket's entry, or end() when another call consumed it.
+static std::unordered_map<uint64_t, Req *>::iterator
+wait_finished_locked(heat_server *s, std::unique_lock<std::mutex> &lk, uint64_t ticket) {
+    auto it = s->reqs.find(ticket);
+    s->cv_done.wait(lk, [&] {
+        it = s->reqs.find(ticket);
+        return it == s->reqs.end() || finished_state(it->second->state);
+    });
+    return it;
 }
 
 int heat_wait(heat_server *s, uint64_t ticket) {
     if (!s) return fail(HEAT_EINVAL, "NULL server");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return fail(HEAT_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
-    Req *q = it->second;
-    s->cv_done.wait(lk, [&] { return q->state == DONE || q->state == FAILED || q->state == CANCELLED; });
-    return consume_locked(s, s->reqs.find(ticket));
+    if (!s->reqs.count(ticket))
+        return fail(HEAT_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    auto it = wait_finished_locked(s, lk, ticket);
+    if (it == s->reqs.end())
+        return fail(HEAT_ENOENT, "ticket %llu was consumed by another call", (unsigned long long)ticket);
+    return consume_locked(s, it);
 }
 
 int heat_cancel(heat_server *s, uint64_t ticket) {
@@ -515,16 +530,21 @@ int heat_cancel(heat_server *s, uint64_t ticket) {
         s->queue.erase(std::find(s->queue.begin(), s->queue.end(), q));
         q->state = CANCELLED;
         ++s->st.cancelled;
-    } else if (q->state != DONE && q->state != FAILED && q->state != CANCELLED) {
+    } else if (!finished_state(q->state)) {
         // resident: the scheduler (or the stage-in thread) lets go of it; a request
         // already draining completes normally
         q->cancel = true;
         s->cv_sched.notify_one();
-        s->cv_done.wait(lk, [&] { return q->state == DONE || q->state == FAILED || q->state == CANCELLED; });
+        it = wait_finished_locked(s, lk, ticket);
+        if (it == s->reqs.end())
+            return fail(HEAT_ENOENT, "ticket %llu was consumed by another call",
+                        (unsigned long long)ticket);
+        q = it->second;
     }
     q->p->status = HEAT_ECANCELED;
-    s->reqs.erase(ticket);
+    s->reqs.erase(it);
     delete q;
+    s->cv_done.notify_all();   // other waiters on this ticket find it gone
     return HEAT_OK;
 }
 

@@ -308,26 +308,32 @@ class Server:
         p, _, out = self._live.pop(t)
         return BatchResult(out, p.sum0, p.sum_nt, p.status, p.latency_s)
 
+    def _settle(self, ticket: int, rc: int):
+        # HEAT_ENOENT: unknown, or consumed by a call on another thread, which
+        # owns the buffers' entry; any other code means this call consumed it
+        if rc != HEAT_ENOENT:
+            self._live.pop(ticket, None)
+        raise HeatError(rc, last_error())
+
     def poll(self, ticket: int):
         rc = load().heat_poll(self._h, ctypes.c_uint64(ticket))
         if rc == HEAT_PENDING:
             return None
         if rc < 0:
-            self._live.pop(ticket, None)
-            raise HeatError(rc, last_error())
+            self._settle(ticket, rc)
         return self._result(ticket)
 
     def wait(self, ticket: int):
         rc = load().heat_wait(self._h, ctypes.c_uint64(ticket))
         if rc < 0:
-            self._live.pop(ticket, None)
-            raise HeatError(rc, last_error())
+            self._settle(ticket, rc)
         return self._result(ticket)
 
     def cancel(self, ticket: int) -> None:
         rc = load().heat_cancel(self._h, ctypes.c_uint64(ticket))
+        if rc < 0:
+            self._settle(ticket, rc)
         self._live.pop(ticket, None)
-        _check(rc)
 
     def stats(self) -> dict:
         s = heat_server_stats()

@@ -190,6 +190,65 @@ def test_cancel_and_unknown_ticket():
         heat.Server(hbm_budget=16)   # below the minimum arena
 
 
+def test_one_ticket_from_many_threads():
+    """Several threads wait on, poll and cancel the same tickets: exactly one
+    call consumes each ticket, the others get HEAT_ENOENT, and the consumed
+    result is the request's own."""
+    u0 = inputs.uniform_ring(1_000_000, 71)
+    want = alone(u0, 4000, 0.4, heat.FP64)
+    with heat.Server(hbm_budget=1 << 30) as s:
+        for trial in range(3):
+            t = s.submit(u0, 4000, 0.4, heat.FP64)
+            outcome = []
+
+            def waiter():
+                try:
+                    outcome.append(("result", s.wait(t)))
+                except heat.HeatError as e:
+                    outcome.append(("error", e.code))
+
+            def poller():
+                while True:
+                    try:
+                        res = s.poll(t)
+                    except heat.HeatError as e:
+                        outcome.append(("error", e.code))
+                        return
+                    if res is not None:
+                        outcome.append(("result", res))
+                        return
+                    time.sleep(0.0005)
+
+            def canceller():
+                time.sleep(0.002)
+                try:
+                    s.cancel(t)
+                    outcome.append(("cancelled", None))
+                except heat.HeatError as e:
+                    outcome.append(("error", e.code))
+
+            work = [waiter, waiter, poller] + ([canceller] if trial == 2 else [])
+            th = [threading.Thread(target=f) for f in work]
+            for x in th:
+                x.start()
+            for x in th:
+                x.join(timeout=60)
+            assert not any(x.is_alive() for x in th)
+            assert len(outcome) == len(work)
+            consumed = [o for o in outcome if o[0] != "error" or o[1] != heat.HEAT_ENOENT]
+            assert len(consumed) == 1, outcome
+            kind, val = consumed[0]
+            if kind == "result":
+                assert same_bits(val.u, want)
+            elif kind == "error":
+                assert val == heat.HEAT_ECANCELED and trial == 2
+            else:
+                assert trial == 2
+            with pytest.raises(heat.HeatError) as ei:
+                s.poll(t)
+            assert ei.value.code == heat.HEAT_ENOENT
+
+
 def test_submit_from_many_threads_and_destroy_with_work_outstanding():
     reqs = requests(70, 64, nmax=100_000, ntmax=800)
     s = heat.Server(hbm_budget=1 << 30)
