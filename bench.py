@@ -205,9 +205,12 @@ def cpu_model():
 def cpu_threads(u0, r, steps, workload, max_threads=16):
     """The paper's own CPU method, timed along its thread axis: one thread per
     segment, ghost cells through single-producer single-consumer queues (the
-    threaded oracle; every thread count gives the same bits).  Three samples:
-    the paper's workload (ramp, 1e6 cells, 1,000 steps), the 1e6-cell
-    Uniform ring of 100 steps, and a few steps of the full ring timed above."""
+    threaded oracle; every thread count gives the same bits), in its scalar
+    build ("value") and with the segment sweep vectorised ("value_simd", the
+    counterpart of the paper's SIMD Rust build; the same bits again).  Three
+    samples: the paper's workload (ramp, 1e6 cells, 1,000 steps), the
+    1e6-cell Uniform ring of 100 steps, and a few steps of the full ring timed
+    above."""
     import numpy as np
 
     import oracle
@@ -223,19 +226,20 @@ def cpu_threads(u0, r, steps, workload, max_threads=16):
                (f"{workload}, {steps} steps", u0, r, steps)]
     res = {}
     for name, u, rr, nt in samples:
-        rates, ref, same = [], None, True
-        for t in threads:
-            t0 = time.perf_counter()
-            out = oracle.solve_threads(u, t, rr, nt)
-            dt = time.perf_counter() - t0
-            rates.append(round(u.size * nt / dt / 1e9, 4))
-            if ref is None:
-                ref = out
-            else:
-                same = same and bool(np.array_equal(out, ref))
-            del out
-        res[name] = {"N": int(u.size), "nt": int(nt), "value": rates,
-                     "bitwise_equal_across_threads": same}
+        rates, ref, same = {False: [], True: []}, None, True
+        for simd in (False, True):
+            for t in threads:
+                t0 = time.perf_counter()
+                out = oracle.solve_threads(u, t, rr, nt, simd=simd)
+                dt = time.perf_counter() - t0
+                rates[simd].append(round(u.size * nt / dt / 1e9, 4))
+                if ref is None:
+                    ref = out
+                else:
+                    same = same and bool(np.array_equal(out.view(np.uint64), ref.view(np.uint64)))
+                del out
+        res[name] = {"N": int(u.size), "nt": int(nt), "value": rates[False],
+                     "value_simd": rates[True], "bitwise_equal_across_threads": same}
     return {"kind": "oracle_threads", "unit": "GCUP/s", "threads": threads,
             "cores_available": avail, "cpu": cpu_model(), "samples": res}
 

@@ -27,24 +27,31 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import tempfile
 
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "heat_oracle.c")
+_SRC_SIMD = os.path.join(_HERE, "heat_cpu_simd.c")
 _LIB = os.path.join(_HERE, "libheat_oracle.so")
 
 _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile heat_oracle.c with gcc (no FMA contraction, no fast-math)."""
+    """Compile heat_oracle.c (-O2, scalar) and heat_cpu_simd.c (-O3, the
+    vectorised segment sweep) with gcc, both with no FMA contraction and no
+    fast-math, and link them into one library."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-            "-fexcess-precision=standard", "-pthread", "-shared", "-fPIC", "-o", tmp, _SRC,
-        ])
+        fp = ["-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard",
+              "-fPIC"]
+        with tempfile.TemporaryDirectory() as d:
+            o1, o2 = os.path.join(d, "oracle.o"), os.path.join(d, "simd.o")
+            subprocess.check_call(["gcc", "-O2", *fp, "-pthread", "-c", "-o", o1, _SRC])
+            subprocess.check_call(["gcc", "-O3", *fp, "-c", "-o", o2, _SRC_SIMD])
+            subprocess.check_call(["gcc", "-shared", "-pthread", "-o", tmp, o1, o2])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -64,6 +71,8 @@ def _load():
     lib.heat_oracle_solve_parts.restype = None
     lib.heat_oracle_solve_threads.argtypes = [p, p, i64, i64, d, i64]
     lib.heat_oracle_solve_threads.restype = ctypes.c_int
+    lib.heat_oracle_solve_threads_simd.argtypes = [p, p, i64, i64, d, i64]
+    lib.heat_oracle_solve_threads_simd.restype = ctypes.c_int
     lib.heat_oracle_cone.argtypes = [p, i64, d]
     lib.heat_oracle_cone.restype = d
     lib.heat_oracle_solve_f32.argtypes = [p, p, i64, f, i64]
@@ -111,16 +120,19 @@ def solve_parts(u0, nparts: int, r: float, nt: int) -> np.ndarray:
     return out
 
 
-def solve_threads(u0, nparts: int, r: float, nt: int) -> np.ndarray:
+def solve_threads(u0, nparts: int, r: float, nt: int, simd: bool = False) -> np.ndarray:
     """The same segmented solver with one thread per segment and the ghost
     cells passed through single-producer single-consumer queues, as the
-    paper's CPU codes run it (Section 2, last paragraph)."""
+    paper's CPU codes run it (Section 2, last paragraph).  ``simd``: the
+    segment sweep vectorised, as the paper's SIMD build of its Rust code
+    (Section 3); bit-identical."""
     a = _f64(u0)
     if not 1 <= nparts <= min(a.size, 4096) or nt < 0:
         raise ValueError("need 1 <= nparts <= min(N, 4096) and nt >= 0")
     out = np.empty_like(a)
-    rc = _load().heat_oracle_solve_threads(_ptr(a), _ptr(out), a.size, int(nparts),
-                                           float(r), int(nt))
+    lib = _load()
+    fn = lib.heat_oracle_solve_threads_simd if simd else lib.heat_oracle_solve_threads
+    rc = fn(_ptr(a), _ptr(out), a.size, int(nparts), float(r), int(nt))
     if rc != 0:
         raise MemoryError(f"threaded oracle failed ({rc}): no memory or threads")
     return out

@@ -42,6 +42,10 @@
  *     Steps are grouped into rounds of T steps; at the end of every round
  *     (and at the end of the run) u := fl32(u + e), e := 0.
  *
+ * heat_oracle_solve_threads runs the segments as the paper's CPU codes do,
+ * one thread each; heat_oracle_solve_threads_simd is the same with the
+ * segment sweep vectorised (heat_cpu_simd.c, bit-identical).
+ *
  * Error behaviour: no argument checks beyond what is needed not to crash
  * (N < 1 or nt < 0 do nothing); r is NOT range-checked, so unstable r can be
  * exercised as a negative control.
@@ -189,11 +193,27 @@ typedef struct {
     int state;      /* 0 wait, 1 run, -1 abort */
 } start_gate;
 
+/* One step of a segment: b[1..len] from a[0..len+1] (a[0], a[len+1] are the
+ * ghost cells).  The scalar sweep is written below; heat_cpu_simd.c holds the
+ * same sweep vectorised (bit-identical, see there). */
+typedef void (*segment_sweep)(const double *a, double *b, int64_t len, double r);
+
+static void sweep_scalar(const double *a, double *b, int64_t len, double r)
+{
+    for (int64_t j = 1; j <= len; ++j) {
+        double l = a[j - 1], c = a[j], q = a[j + 1];
+        b[j] = c + r * ((l - 2.0 * c) + q);
+    }
+}
+
+void heat_cpu_sweep_simd(const double *a, double *b, int64_t len, double r);
+
 typedef struct {
     const double *u0;
     double *out;
     int64_t start, len, nt;
     double r;
+    segment_sweep sweep;
     ghost_queue *from_left, *from_right;  /* my ghosts arrive here */
     ghost_queue *to_right, *to_left;      /* my edge cells leave here */
     start_gate *gate;
@@ -223,10 +243,7 @@ static void *segment_worker(void *arg)
             ghost_push(t->to_left, a[1]);
             a[0] = ghost_pop(t->from_left);
             a[len + 1] = ghost_pop(t->from_right);
-            for (int64_t j = 1; j <= len; ++j) {
-                double l = a[j - 1], c = a[j], q = a[j + 1];
-                b[j] = c + r * ((l - 2.0 * c) + q);
-            }
+            t->sweep(a, b, len, r);
             double *s = a; a = b; b = s;
         }
         memcpy(t->out + t->start, a + 1, (size_t)len * sizeof(double));
@@ -236,8 +253,8 @@ static void *segment_worker(void *arg)
     return NULL;
 }
 
-int heat_oracle_solve_threads(const double *u0, double *out, int64_t N, int64_t nparts,
-                              double r, int64_t nt)
+static int solve_threads_with(const double *u0, double *out, int64_t N, int64_t nparts,
+                              double r, int64_t nt, segment_sweep sweep)
 {
     if (N < 1 || nparts < 1 || nparts > N || nparts > 4096 || nt < 0) return -1;
     int64_t P = nparts;
@@ -269,6 +286,7 @@ int heat_oracle_solve_threads(const double *u0, double *out, int64_t N, int64_t 
         t->len = ((p + 1) * N) / P - t->start;
         t->nt = nt;
         t->r = r;
+        t->sweep = sweep;
         t->from_left = &from_left[p];
         t->from_right = &from_right[p];
         t->to_right = &from_left[(p + 1) % P];
@@ -298,6 +316,19 @@ int heat_oracle_solve_threads(const double *u0, double *out, int64_t N, int64_t 
     pthread_cond_destroy(&gate.cv);
     free(from_left); free(from_right); free(task); free(tid);
     return ok ? 0 : -2;
+}
+
+int heat_oracle_solve_threads(const double *u0, double *out, int64_t N, int64_t nparts,
+                              double r, int64_t nt)
+{
+    return solve_threads_with(u0, out, N, nparts, r, nt, sweep_scalar);
+}
+
+/* The same method with the vectorised segment sweep (heat_cpu_simd.c). */
+int heat_oracle_solve_threads_simd(const double *u0, double *out, int64_t N, int64_t nparts,
+                                   double r, int64_t nt)
+{
+    return solve_threads_with(u0, out, N, nparts, r, nt, heat_cpu_sweep_simd);
 }
 
 /*

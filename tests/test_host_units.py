@@ -40,3 +40,4 @@ def test_bench_thread_axis_is_bitwise_stable():
     for name, s in rep["samples"].items():
         assert s["bitwise_equal_across_threads"], name
         assert len(s["value"]) == len(rep["threads"]) and min(s["value"]) > 0
+        assert len(s["value_simd"]) == len(rep["threads"]) and min(s["value_simd"]) > 0

@@ -25,6 +25,13 @@ import pytest
 import oracle
 from paper_2307_01117_amd import inputs
 
+
+def same_bits(a, b):
+    """Bit-for-bit equality of two binary64 arrays (np.array_equal takes
+    -0.0 == +0.0)."""
+    a, b = np.ascontiguousarray(a, np.float64), np.ascontiguousarray(b, np.float64)
+    return a.shape == b.shape and bool(np.array_equal(a.view(np.uint64), b.view(np.uint64)))
+
 DYADIC_R = [Fraction(0), Fraction(1, 8), Fraction(1, 4), Fraction(3, 8), Fraction(1, 2)]
 
 
@@ -68,6 +75,8 @@ def test_brute_force_exact_fp64(N):
             assert as_fractions(gp) == want, (N, P, r, nt)
             gt = oracle.solve_threads(u0, P, float(r), nt)
             assert as_fractions(gt) == want, ("threads", N, P, r, nt)
+            gv = oracle.solve_threads(u0, P, float(r), nt, simd=True)
+            assert as_fractions(gv) == want, ("threads, vectorised", N, P, r, nt)
         assert as_fractions(oracle.np_solve(u0, float(r), nt)) == want
 
 
@@ -212,18 +221,29 @@ def test_partition_invariance():
         assert np.array_equal(oracle.solve_parts(u0, P, 0.5, 37), want), P
     for P in (1, 2, 3, 16, 64):
         assert np.array_equal(oracle.solve_threads(u0, P, 0.5, 37), want), ("threads", P)
+        assert np.array_equal(oracle.solve_threads(u0, P, 0.5, 37, simd=True), want), ("simd", P)
 
 
 def test_threaded_segments_ragged_and_long():
     """One thread per segment with queued ghost cells: ragged segments (P does
     not divide N), more steps than the ghost queues hold, every thread count
-    bitwise equal to the unpartitioned ring."""
+    bitwise equal to the unpartitioned ring -- in the scalar build and with the
+    vectorised sweep (segment lengths that leave every vector remainder)."""
     N = 20_011
     u0 = inputs.uniform_ring(N, 12)
     want = oracle.solve(u0, 0.375, 301)
     for P in (1, 2, 5, 7, 33):
         assert np.array_equal(oracle.solve_threads(u0, P, 0.375, 301), want), P
+        assert same_bits(oracle.solve_threads(u0, P, 0.375, 301, simd=True), want), P
     assert np.array_equal(oracle.solve_threads(u0, 7, 0.375, 0), u0)
+    assert np.array_equal(oracle.solve_threads(u0, 7, 0.375, 0, simd=True), u0)
+    # segments of 1 to 17 cells and longer: shorter than one vector, and every
+    # remainder of 2-, 4- and 8-wide vectors
+    N1 = 820
+    u1 = inputs.uniform_ring(N1, 14)
+    want1 = oracle.solve(u1, 0.25, 23)
+    for P in sorted({N1 // L for L in range(1, 18)} | {17, 9}):
+        assert same_bits(oracle.solve_threads(u1, P, 0.25, 23, simd=True), want1), P
 
 
 def test_threaded_rejects_bad_arguments():
@@ -235,6 +255,10 @@ def test_threaded_rejects_bad_arguments():
     out = np.empty_like(u0)
     assert lib.heat_oracle_solve_threads(u0.ctypes.data, out.ctypes.data, 8, 9, 0.5, 1) == -1
     assert lib.heat_oracle_solve_threads(u0.ctypes.data, out.ctypes.data, 0, 1, 0.5, 1) == -1
+    for P, nt in ((0, 1), (9, 1), (2, -1)):
+        with pytest.raises(ValueError):
+            oracle.solve_threads(u0, P, 0.5, nt, simd=True)
+    assert lib.heat_oracle_solve_threads_simd(u0.ctypes.data, out.ctypes.data, 8, 9, 0.5, 1) == -1
 
 
 def test_shift_composition_scaling():
@@ -411,3 +435,4 @@ def test_golden_ramp_exact():
         for P in sorted({1, 2, 3, N}):
             assert as_fractions(oracle.solve_parts(u0, P, float(r), nt)) == want, (N, P)
             assert as_fractions(oracle.solve_threads(u0, P, float(r), nt)) == want, (N, P)
+            assert as_fractions(oracle.solve_threads(u0, P, float(r), nt, simd=True)) == want, (N, P)
