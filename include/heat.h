@@ -113,7 +113,11 @@ typedef struct heat_plan_info {
 /*
  * Plain form.  u: host array of N binary64 values, overwritten in place by
  * the state after nt steps.  FP64.  Blocking.  Copies to and from the current
- * device, allocates and frees its own device memory.
+ * device, allocates and frees its own device memory.  u may be pageable:
+ * arrays of 64 MiB or more are copied through 8 lanes of pinned chunks (8
+ * host threads; 128 MiB of pinned host memory, allocated on the first such
+ * call per device and kept until the process ends); concurrent calls take
+ * turns for those lanes.
  */
 int heat_solve(double *u, int64_t N, int32_t nparts, double r, int64_t nt);
 

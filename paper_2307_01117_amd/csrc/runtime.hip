@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "heat_internal.h"
@@ -299,6 +300,138 @@ static int sum_scratch(size_t doubles, SumCache **out) {
     return HEAT_OK;
 }
 
+// ============================================================ host staging
+// heat_solve takes a pageable host array.  A plain copy of pageable memory
+// runs through the runtime's own staging at a fraction of the PCIe rate, so
+// large arrays go through pinned chunks instead: the array is cut into one
+// contiguous slice per lane, and each lane (a host thread with its own
+// stream and two pinned chunks) overlaps the host-side copy of one chunk
+// with the DMA of the other.  The pinned chunks are allocated once per
+// device (hipHostMalloc) and kept until the process ends; calls that stage
+// at the same time take turns.
+namespace {
+
+constexpr size_t STAGE_CHUNK = size_t(8) << 20;        // bytes per pinned chunk
+constexpr int STAGE_LANES = 8;                          // threads, each with 2 chunks
+constexpr size_t STAGE_MIN_BYTES = size_t(64) << 20;    // smaller arrays: one plain copy
+
+struct StageLane {
+    char *buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipStream_t st = nullptr;
+};
+
+struct StagePool {
+    std::mutex mu;
+    bool ready = false;
+    StageLane lane[STAGE_LANES];
+};
+
+StagePool g_stage[64];
+
+// Allocate the device's pool on first use (caller holds pool.mu).  On
+// failure the parts made so far are kept and the next call retries them.
+hipError_t stage_pool_init(StagePool &pool) {
+    if (pool.ready) return hipSuccess;
+    for (StageLane &L : pool.lane) {
+        for (int b = 0; b < 2; ++b) {
+            if (!L.buf[b]) {
+                hipError_t e = hipHostMalloc((void **)&L.buf[b], STAGE_CHUNK, hipHostMallocDefault);
+                if (e != hipSuccess) return e;
+            }
+            if (!L.ev[b]) {
+                hipError_t e = hipEventCreateWithFlags(&L.ev[b], hipEventDisableTiming);
+                if (e != hipSuccess) return e;
+            }
+        }
+        if (!L.st) {
+            hipError_t e = hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+        }
+    }
+    pool.ready = true;
+    return hipSuccess;
+}
+
+// One lane: bytes [0, n) of its slice, host <-> device through its two chunks.
+hipError_t stage_lane(StageLane &L, bool to_device, char *dev, char *host, size_t n, int device) {
+    hipError_t e = hipSetDevice(device);
+    const size_t chunks = (n + STAGE_CHUNK - 1) / STAGE_CHUNK;
+    auto len = [&](size_t k) { return std::min(STAGE_CHUNK, n - k * STAGE_CHUNK); };
+    if (to_device) {
+        // host -> chunk k%2 (once the DMA of chunk k-2 has left it) -> device
+        for (size_t k = 0; e == hipSuccess && k < chunks; ++k) {
+            const int b = (int)(k & 1);
+            if (k >= 2) e = hipEventSynchronize(L.ev[b]);
+            if (e != hipSuccess) break;
+            std::memcpy(L.buf[b], host + k * STAGE_CHUNK, len(k));
+            e = hipMemcpyAsync(dev + k * STAGE_CHUNK, L.buf[b], len(k), hipMemcpyHostToDevice, L.st);
+            if (e == hipSuccess) e = hipEventRecord(L.ev[b], L.st);
+        }
+    } else {
+        // device -> chunk k%2, the DMA of chunk k+1 in flight while chunk k
+        // is copied out to the host
+        auto issue = [&](size_t k) {
+            const int b = (int)(k & 1);
+            hipError_t x = hipMemcpyAsync(L.buf[b], dev + k * STAGE_CHUNK, len(k),
+                                          hipMemcpyDeviceToHost, L.st);
+            return x == hipSuccess ? hipEventRecord(L.ev[b], L.st) : x;
+        };
+        if (e == hipSuccess && chunks > 0) e = issue(0);
+        for (size_t k = 0; e == hipSuccess && k < chunks; ++k) {
+            if (k + 1 < chunks) e = issue(k + 1);
+            if (e == hipSuccess) e = hipEventSynchronize(L.ev[k & 1]);
+            if (e == hipSuccess) std::memcpy(host + k * STAGE_CHUNK, L.buf[k & 1], len(k));
+        }
+    }
+    const hipError_t f = hipStreamSynchronize(L.st);
+    return e != hipSuccess ? e : f;
+}
+
+}  // namespace
+
+// Blocking copy between a pageable host array and device memory; small
+// arrays take one plain copy on `st`.
+static int stage_copy(bool to_device, void *dev, void *host, size_t bytes, hipStream_t st) {
+    int device = 0;
+    HEAT_HIP(hipGetDevice(&device));
+    if (bytes < STAGE_MIN_BYTES || device < 0 || device >= 64) {
+        if (to_device) HEAT_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st));
+        else HEAT_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st));
+        HEAT_HIP(hipStreamSynchronize(st));
+        return HEAT_OK;
+    }
+    StagePool &pool = g_stage[device];
+    std::lock_guard<std::mutex> lk(pool.mu);
+    HEAT_HIP(stage_pool_init(pool));
+    // slices of whole 4 KiB pages, the last one takes the remainder
+    const size_t slice = (bytes / STAGE_LANES + 4095) & ~size_t(4095);
+    hipError_t err[STAGE_LANES];
+    std::vector<std::thread> th;
+    for (int t = 0; t < STAGE_LANES; ++t) {
+        const size_t lo = std::min(bytes, (size_t)t * slice);
+        const size_t hi = t + 1 == STAGE_LANES ? bytes : std::min(bytes, lo + slice);
+        err[t] = hipSuccess;
+        if (hi <= lo) continue;
+        auto run = [&, t, lo, hi]() {
+            err[t] = stage_lane(pool.lane[t], to_device, (char *)dev + lo, (char *)host + lo,
+                                hi - lo, device);
+        };
+        if (t == 0) continue;   // lane 0 runs on the calling thread below
+        try {
+            th.emplace_back(run);
+        } catch (...) {
+            run();              // no thread to be had: this lane runs here
+        }
+    }
+    if (bytes > 0) err[0] = stage_lane(pool.lane[0], to_device, (char *)dev, (char *)host,
+                                       std::min(bytes, slice), device);
+    for (std::thread &x : th) x.join();
+    for (hipError_t e : err)
+        if (e != hipSuccess) return fail_hip(e, to_device ? "staged copy to device" : "staged copy to host");
+    return HEAT_OK;
+}
+
 static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, double r, int64_t nt,
                           int32_t precision, const heat_config *cfg, hipStream_t st,
                           double *sum0_out, double *sum_out) {
@@ -424,17 +557,12 @@ int heat_solve(double *u, int64_t N, int32_t nparts, double r, int64_t nt) {
         (void)hipStreamDestroy(st);
         return fail_hip(e, "hipMalloc(state)");
     }
-    rc = HEAT_OK;
-    e = hipMemcpyAsync(d, u, bytes, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) rc = fail_hip(e, "hipMemcpyAsync(H2D)");
+    rc = stage_copy(true, d, u, bytes, st);
     if (!rc) rc = solve_dev_impl(d, nullptr, N, nparts, r, nt, HEAT_FP64, nullptr, st, nullptr,
                                  nullptr);
-    if (!rc) {
-        e = hipMemcpyAsync(u, d, bytes, hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) rc = fail_hip(e, "hipMemcpyAsync(D2H)");
-    }
     e = hipStreamSynchronize(st);
     if (!rc && e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");
+    if (!rc) rc = stage_copy(false, d, u, bytes, st);
     (void)hipFree(d);
     (void)hipStreamDestroy(st);
     return rc;

@@ -115,6 +115,20 @@ def test_exact_small_integer_cases():
                 assert same_bits(run_dev(u0, 12, r, **cfg), oracle.solve(u0, r, 12))
 
 
+def test_host_form_staged_copies():
+    """heat_solve on host arrays past the size where the copies go through the
+    pinned multi-lane staging (64 MiB): a ragged length that leaves a short
+    last chunk in every lane, bit-identical to the oracle; nt = 0 returns the
+    input bit for bit through both directions of the staging; a small ring
+    takes the plain copy."""
+    N = 10_000_019
+    u0 = inputs.uniform_ring(N, 77)
+    assert same_bits(heat.solve(u0, 3, 0.375, 7), oracle.solve(u0, 0.375, 7))
+    assert same_bits(heat.solve(u0, 1, 0.5, 0), u0)
+    small = inputs.uniform_ring(1000, 78)
+    assert same_bits(heat.solve(small, 2, 0.25, 9), oracle.solve(small, 0.25, 9))
+
+
 # ------------------------------------------------------------ mid-size, ragged
 
 @pytest.mark.parametrize("N", [1000, 4097, 100_003, 262_144 + 77])
