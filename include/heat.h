@@ -196,7 +196,9 @@ typedef struct heat_problem {
  * device, advances all of them together (as heat_solve_batch_dev without
  * flags: one launch per round over the tiles of every still-running ring),
  * copies back.  Blocking.  Returns HEAT_OK if every problem succeeded, else the first
- * error; probs[i].status tells which.
+ * error; probs[i].status tells which.  Host arrays may be pageable; when
+ * the problems' arrays add up to 64 MiB or more, the copies go through the
+ * same pinned lanes as heat_solve's.
  */
 int heat_solve_batch(heat_problem *probs, int32_t count);
 

@@ -372,7 +372,9 @@ int heat_solve_batch(heat_problem *probs, int32_t count) {
         cleanup();
         return rc;
     }
-    // stage in: binary64 host values -> device state (rounded for FP32 forms)
+    // stage in: binary64 host values -> device state (rounded for FP32 forms);
+    // the copies of all problems go through the staging together
+    std::vector<StageSeg> segs;
     for (int32_t i = 0; i < count && !rc; ++i) {
         if (!ok[i]) continue;
         heat_problem &p = probs[i];
@@ -388,19 +390,16 @@ int heat_solve_batch(heat_problem *probs, int32_t count) {
             rc = fail_hip(e, "hipMallocAsync(batch state)");
             break;
         }
-        if (p.precision == HEAT_FP64) {
-            e = hipMemcpyAsync(a, p.u0, (size_t)p.N * 8, hipMemcpyHostToDevice, st);
-        } else {
-            e = hipMemcpyAsync(b, p.u0, (size_t)p.N * 8, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess)
-                e = launch_f64_to_f32((const double *)b, (float *)a, p.N, st, p.shift);
-        }
-        if (e != hipSuccess) {
-            rc = fail_hip(e, "stage-in");
-            break;
-        }
+        segs.push_back(StageSeg{p.precision == HEAT_FP64 ? a : b, (void *)p.u0, (size_t)p.N * 8});
         rings.push_back(heat_ring{p.N, p.nt, p.r, p.precision, p.nparts, a, b});
         idx.push_back(i);
+    }
+    if (!rc) rc = stage_copies(true, segs.data(), segs.size(), st);
+    for (size_t j = 0; j < rings.size() && !rc; ++j) {
+        if (rings[j].precision == HEAT_FP64) continue;
+        hipError_t e = launch_f64_to_f32((const double *)rings[j].d_work, (float *)rings[j].d_u,
+                                         rings[j].N, st, probs[idx[j]].shift);
+        if (e != hipSuccess) rc = fail_hip(e, "stage-in");
     }
     if (!rc) {
         hipError_t e = hipMallocAsync((void **)&sums, (2 * rings.size() + SUM_BLOCKS + 1) * 8, st);
@@ -424,30 +423,28 @@ int heat_solve_batch(heat_problem *probs, int32_t count) {
         if (e != hipSuccess) rc = fail_hip(e, "sum_nt");
     }
     // stage out (FP32 forms are widened exactly into the scratch buffer first)
+    segs.clear();
     for (size_t j = 0; j < rings.size() && !rc; ++j) {
         heat_problem &p = probs[idx[j]];
-        hipError_t e;
-        if (p.precision == HEAT_FP64) {
-            e = hipMemcpyAsync(p.u_out, rings[j].d_u, (size_t)p.N * 8, hipMemcpyDeviceToHost, st);
-        } else {
-            e = launch_f32_to_f64((const float *)rings[j].d_u, (double *)rings[j].d_work, p.N, st,
-                                  p.shift);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(p.u_out, rings[j].d_work, (size_t)p.N * 8,
-                                   hipMemcpyDeviceToHost, st);
+        if (p.precision != HEAT_FP64) {
+            hipError_t e = launch_f32_to_f64((const float *)rings[j].d_u,
+                                             (double *)rings[j].d_work, p.N, st, p.shift);
+            if (e != hipSuccess) rc = fail_hip(e, "stage-out");
         }
-        if (e != hipSuccess) rc = fail_hip(e, "stage-out");
-    }
-    std::vector<double> hs(2 * rings.size());
-    if (!rc && !rings.empty()) {
-        hipError_t e = hipMemcpyAsync(hs.data(), sums, hs.size() * 8, hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) rc = fail_hip(e, "sums D2H");
+        segs.push_back(StageSeg{p.precision == HEAT_FP64 ? rings[j].d_u : rings[j].d_work,
+                                p.u_out, (size_t)p.N * 8});
     }
     if (!rc)
         for (BatchLaunch &L : launches) {
             rc = L.check_status(st);
             if (rc) break;
         }
+    if (!rc) rc = stage_copies(false, segs.data(), segs.size(), st);
+    std::vector<double> hs(2 * rings.size());
+    if (!rc && !rings.empty()) {
+        hipError_t e = hipMemcpyAsync(hs.data(), sums, hs.size() * 8, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) rc = fail_hip(e, "sums D2H");
+    }
     if (!rc) {
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");

@@ -23,6 +23,18 @@ int fail_hip(hipError_t e, const char *what);
         if (_e != hipSuccess) return ::heat::fail_hip(_e, #call);  \
     } while (0)
 
+// One piece of a host <-> device copy (runtime.hip, stage_copies).
+struct StageSeg {
+    void *dev;
+    void *host;
+    size_t bytes;
+};
+// Blocking copy of a list of segments between pageable host memory and the
+// device: waits for `st` first (the device side may be stream-ordered
+// memory or the result of work on it); totals of 64 MiB or more go through
+// the pinned multi-lane staging, smaller ones through plain copies on `st`.
+int stage_copies(bool to_device, const StageSeg *segs, size_t count, hipStream_t st);
+
 inline size_t storage_bytes(int precision) { return precision == HEAT_FP64 ? 8 : 4; }
 
 // A launch's grid counts work-items in 32 bits: one wavefront per tile must

@@ -308,7 +308,9 @@ static int sum_scratch(size_t doubles, SumCache **out) {
 // stream and two pinned chunks) overlaps the host-side copy of one chunk
 // with the DMA of the other.  The pinned chunks are allocated once per
 // device (hipHostMalloc) and kept until the process ends; calls that stage
-// at the same time take turns.
+// at the same time take turns.  A copy may be a list of segments (the
+// problems of a batch): the lanes then cut the segments' concatenation, and
+// a chunk may hold pieces of several segments.
 namespace {
 
 constexpr size_t STAGE_CHUNK = size_t(8) << 20;        // bytes per pinned chunk
@@ -353,19 +355,40 @@ hipError_t stage_pool_init(StagePool &pool) {
     return hipSuccess;
 }
 
-// One lane: bytes [0, n) of its slice, host <-> device through its two chunks.
-hipError_t stage_lane(StageLane &L, bool to_device, char *dev, char *host, size_t n, int device) {
+// The pieces of segments that fall in the logical byte range [c0, c1): calls
+// f(seg, offset in the segment, offset from c0, length) in order.
+template <class F>
+void for_pieces(const StageSeg *segs, const std::vector<size_t> &pre, size_t c0, size_t c1,
+                F &&f) {
+    size_t i = std::upper_bound(pre.begin(), pre.end(), c0) - pre.begin() - 1;
+    for (; i + 1 < pre.size() && pre[i] < c1; ++i) {
+        const size_t a = std::max(c0, pre[i]), b = std::min(c1, pre[i + 1]);
+        if (b > a) f(segs[i], a - pre[i], a - c0, b - a);
+    }
+}
+
+// One lane: the logical bytes [lo, hi) of the segments, host <-> device
+// through its two chunks.
+hipError_t stage_lane(StageLane &L, bool to_device, const StageSeg *segs,
+                      const std::vector<size_t> &pre, size_t lo, size_t hi, int device) {
     hipError_t e = hipSetDevice(device);
-    const size_t chunks = (n + STAGE_CHUNK - 1) / STAGE_CHUNK;
-    auto len = [&](size_t k) { return std::min(STAGE_CHUNK, n - k * STAGE_CHUNK); };
+    const size_t chunks = (hi - lo + STAGE_CHUNK - 1) / STAGE_CHUNK;
+    auto c0 = [&](size_t k) { return lo + k * STAGE_CHUNK; };
+    auto c1 = [&](size_t k) { return std::min(hi, lo + (k + 1) * STAGE_CHUNK); };
     if (to_device) {
         // host -> chunk k%2 (once the DMA of chunk k-2 has left it) -> device
         for (size_t k = 0; e == hipSuccess && k < chunks; ++k) {
             const int b = (int)(k & 1);
             if (k >= 2) e = hipEventSynchronize(L.ev[b]);
             if (e != hipSuccess) break;
-            std::memcpy(L.buf[b], host + k * STAGE_CHUNK, len(k));
-            e = hipMemcpyAsync(dev + k * STAGE_CHUNK, L.buf[b], len(k), hipMemcpyHostToDevice, L.st);
+            for_pieces(segs, pre, c0(k), c1(k), [&](const StageSeg &g, size_t so, size_t bo, size_t n) {
+                std::memcpy(L.buf[b] + bo, (const char *)g.host + so, n);
+            });
+            for_pieces(segs, pre, c0(k), c1(k), [&](const StageSeg &g, size_t so, size_t bo, size_t n) {
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync((char *)g.dev + so, L.buf[b] + bo, n, hipMemcpyHostToDevice,
+                                       L.st);
+            });
             if (e == hipSuccess) e = hipEventRecord(L.ev[b], L.st);
         }
     } else {
@@ -373,15 +396,23 @@ hipError_t stage_lane(StageLane &L, bool to_device, char *dev, char *host, size_
         // is copied out to the host
         auto issue = [&](size_t k) {
             const int b = (int)(k & 1);
-            hipError_t x = hipMemcpyAsync(L.buf[b], dev + k * STAGE_CHUNK, len(k),
-                                          hipMemcpyDeviceToHost, L.st);
+            hipError_t x = hipSuccess;
+            for_pieces(segs, pre, c0(k), c1(k), [&](const StageSeg &g, size_t so, size_t bo, size_t n) {
+                if (x == hipSuccess)
+                    x = hipMemcpyAsync(L.buf[b] + bo, (const char *)g.dev + so, n,
+                                       hipMemcpyDeviceToHost, L.st);
+            });
             return x == hipSuccess ? hipEventRecord(L.ev[b], L.st) : x;
         };
         if (e == hipSuccess && chunks > 0) e = issue(0);
         for (size_t k = 0; e == hipSuccess && k < chunks; ++k) {
             if (k + 1 < chunks) e = issue(k + 1);
             if (e == hipSuccess) e = hipEventSynchronize(L.ev[k & 1]);
-            if (e == hipSuccess) std::memcpy(host + k * STAGE_CHUNK, L.buf[k & 1], len(k));
+            if (e != hipSuccess) break;
+            const int b = (int)(k & 1);
+            for_pieces(segs, pre, c0(k), c1(k), [&](const StageSeg &g, size_t so, size_t bo, size_t n) {
+                std::memcpy((char *)g.host + so, L.buf[b] + bo, n);
+            });
         }
     }
     const hipError_t f = hipStreamSynchronize(L.st);
@@ -390,45 +421,57 @@ hipError_t stage_lane(StageLane &L, bool to_device, char *dev, char *host, size_
 
 }  // namespace
 
-// Blocking copy between a pageable host array and device memory; small
-// arrays take one plain copy on `st`.
-static int stage_copy(bool to_device, void *dev, void *host, size_t bytes, hipStream_t st) {
+int stage_copies(bool to_device, const StageSeg *segs, size_t count, hipStream_t st) {
+    // the device side may be stream-ordered memory or results of work on st
+    HEAT_HIP(hipStreamSynchronize(st));
+    std::vector<size_t> pre(count + 1, 0);
+    for (size_t i = 0; i < count; ++i) pre[i + 1] = pre[i] + segs[i].bytes;
+    const size_t total = pre[count];
     int device = 0;
     HEAT_HIP(hipGetDevice(&device));
-    if (bytes < STAGE_MIN_BYTES || device < 0 || device >= 64) {
-        if (to_device) HEAT_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st));
-        else HEAT_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st));
+    if (total < STAGE_MIN_BYTES || device < 0 || device >= 64) {
+        for (size_t i = 0; i < count; ++i) {
+            if (!segs[i].bytes) continue;
+            if (to_device)
+                HEAT_HIP(hipMemcpyAsync(segs[i].dev, segs[i].host, segs[i].bytes,
+                                        hipMemcpyHostToDevice, st));
+            else
+                HEAT_HIP(hipMemcpyAsync(segs[i].host, segs[i].dev, segs[i].bytes,
+                                        hipMemcpyDeviceToHost, st));
+        }
         HEAT_HIP(hipStreamSynchronize(st));
         return HEAT_OK;
     }
     StagePool &pool = g_stage[device];
     std::lock_guard<std::mutex> lk(pool.mu);
     HEAT_HIP(stage_pool_init(pool));
-    // slices of whole 4 KiB pages, the last one takes the remainder
-    const size_t slice = (bytes / STAGE_LANES + 4095) & ~size_t(4095);
+    // lanes take slices of whole 4 KiB of the logical byte stream; the last
+    // one takes the remainder
+    const size_t slice = (total / STAGE_LANES + 4095) & ~size_t(4095);
     hipError_t err[STAGE_LANES];
     std::vector<std::thread> th;
     for (int t = 0; t < STAGE_LANES; ++t) {
-        const size_t lo = std::min(bytes, (size_t)t * slice);
-        const size_t hi = t + 1 == STAGE_LANES ? bytes : std::min(bytes, lo + slice);
+        const size_t lo = std::min(total, (size_t)t * slice);
+        const size_t hi = t + 1 == STAGE_LANES ? total : std::min(total, lo + slice);
         err[t] = hipSuccess;
         if (hi <= lo) continue;
         auto run = [&, t, lo, hi]() {
-            err[t] = stage_lane(pool.lane[t], to_device, (char *)dev + lo, (char *)host + lo,
-                                hi - lo, device);
+            err[t] = stage_lane(pool.lane[t], to_device, segs, pre, lo, hi, device);
         };
-        if (t == 0) continue;   // lane 0 runs on the calling thread below
+        if (t == 0) {
+            continue;           // lane 0 runs on the calling thread below
+        }
         try {
             th.emplace_back(run);
         } catch (...) {
             run();              // no thread to be had: this lane runs here
         }
     }
-    if (bytes > 0) err[0] = stage_lane(pool.lane[0], to_device, (char *)dev, (char *)host,
-                                       std::min(bytes, slice), device);
+    err[0] = stage_lane(pool.lane[0], to_device, segs, pre, 0, std::min(total, slice), device);
     for (std::thread &x : th) x.join();
     for (hipError_t e : err)
-        if (e != hipSuccess) return fail_hip(e, to_device ? "staged copy to device" : "staged copy to host");
+        if (e != hipSuccess)
+            return fail_hip(e, to_device ? "staged copy to device" : "staged copy to host");
     return HEAT_OK;
 }
 
@@ -557,12 +600,13 @@ int heat_solve(double *u, int64_t N, int32_t nparts, double r, int64_t nt) {
         (void)hipStreamDestroy(st);
         return fail_hip(e, "hipMalloc(state)");
     }
-    rc = stage_copy(true, d, u, bytes, st);
+    const StageSeg seg{d, u, bytes};
+    rc = stage_copies(true, &seg, 1, st);
     if (!rc) rc = solve_dev_impl(d, nullptr, N, nparts, r, nt, HEAT_FP64, nullptr, st, nullptr,
                                  nullptr);
+    if (!rc) rc = stage_copies(false, &seg, 1, st);
     e = hipStreamSynchronize(st);
     if (!rc && e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");
-    if (!rc) rc = stage_copy(false, d, u, bytes, st);
     (void)hipFree(d);
     (void)hipStreamDestroy(st);
     return rc;

@@ -81,6 +81,28 @@ def test_host_batch_matches_oracle(precs):
         assert abs(q.sum_nt - math.fsum(want)) <= 1e-13 * max(abs(s0), 1.0)
 
 
+def test_host_batch_staged_copies():
+    """A host batch of more than 64 MiB, whose copies go through the pinned
+    multi-lane staging as one byte stream: four rings of 1e6-3e6 cells (each
+    spanning chunks and lanes) among 60 small ones (many per chunk), empty
+    steps and every precision; bit-identical to the oracle."""
+    rng = np.random.default_rng(91)
+    sizes = [3_000_017, 2_500_001, 1_999_999, 1_000_003] + \
+        [int(rng.integers(1, 20_000)) for _ in range(60)]
+    precs = [heat.FP64, heat.FP32, heat.FP32C]
+    probs = []
+    for k, N in enumerate(sizes):
+        nt = int(rng.integers(0, 12)) if k >= 4 else 6 + k
+        probs.append(dict(u0=inputs.uniform_ring(N, (92, k)), nparts=1,
+                          r=float(0.5 - 0.4 * rng.random()), nt=nt, precision=precs[k % 3]))
+    assert sum(sizes) * 8 >= 64 << 20
+    res = heat.solve_batch(probs)
+    for p, q in zip(probs, res):
+        assert q.status == heat.HEAT_OK
+        want = oracle_for(p["precision"], p["u0"], p["r"], p["nt"])
+        assert same_bits(q.u, want), (p["u0"].size, p["nt"], p["precision"])
+
+
 @pytest.mark.parametrize("prec", [heat.FP32, heat.FP32C])
 def test_host_batch_mean_shifted_storage(prec):
     """binary32 forms stored as offsets from a shift (the ring's mean, or any
