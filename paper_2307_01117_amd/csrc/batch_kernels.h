@@ -41,11 +41,17 @@ __device__ __forceinline__ int64_t upper_bound_i64(const int64_t *a, int64_t n, 
     return lo;
 }
 
+// Spin until the epoch counter *f reaches `need`.  The polls are relaxed
+// (coherent at agent scope, no cache maintenance): an acquiring poll would
+// invalidate the XCD's L2 on every iteration, under the feet of the waves
+// that are working.  The caller issues one acquire fence after all of an
+// item's waits; with the writer's release fence before its counter store,
+// that orders the tile data after the counters.
 __device__ __forceinline__ bool wait_epoch(const BatchPlanDev &plan, const uint32_t *f,
                                            uint32_t need) {
     int64_t spins = 0;
     while (true) {
-        const uint32_t v = __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (__builtin_amdgcn_readfirstlane(v) >= need) break;
         if (++spins > plan.spin_limit) {
             __hip_atomic_store(plan.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -56,7 +62,6 @@ __device__ __forceinline__ bool wait_epoch(const BatchPlanDev &plan, const uint3
             return false;
         __builtin_amdgcn_s_sleep(2);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
@@ -105,6 +110,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
                 acc += q == tiles - 1 ? last_len : R.W;
             }
             if (!ok) return;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // one for all the waits above
             const int64_t b = t * R.W;
             if (k < R.rounds) {
                 const T *src = reinterpret_cast<const T *>(R.buf[k & 1]);
@@ -120,10 +126,12 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
                 const int64_t wlen = (R.N - b) < R.W ? (R.N - b) : R.W;
                 for (int64_t i = lane; i < wlen; i += 64) dst[b + i] = src[b + i];
             }
+            // the release fence orders this tile's stores before the counter
+            // store, which then needs no release of its own
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __builtin_amdgcn_wave_barrier();
             if (lane == 0)
-                __hip_atomic_store(fl + t, (uint32_t)(k + 1), __ATOMIC_RELEASE,
+                __hip_atomic_store(fl + t, (uint32_t)(k + 1), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             // next item in numbering order
             if (++t == tiles) {
