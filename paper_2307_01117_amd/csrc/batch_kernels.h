@@ -21,7 +21,8 @@ namespace heat {
 // then round 1, ...  Rings are sorted by their number of rounds (descending)
 // so the rings alive in round k are a prefix.  Item (k, p, t) reads tiles
 // t-1, t, t+1 of ring p as written in round k-1, so it waits until their
-// epoch counters reach k; when done it raises its own counter to k + 1.
+// epoch counters reach k; when done it raises its own counter to k + 1
+// (together with the other tiles of its chunk in the same ring and round).
 // Items are claimed in increasing order from one atomic counter, and every
 // item waits only on items with smaller numbers, which were claimed earlier
 // by running wavefronts: the earliest unfinished item can always proceed, so
@@ -83,11 +84,30 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
         int64_t y = x - plan.round_start[k];
         int64_t p = upper_bound_i64(plan.tile_prefix, plan.active[k] + 1, y) - 1;
         int64_t t = y - plan.tile_prefix[p];
+        // Tiles computed but not yet published: [pub_lo, pub_lo + pub_n) of
+        // one ring in one round.  They are published together (one release
+        // fence, then their counters) at the end of the chunk, or before the
+        // walk moves on to another ring or round: an item waits only for
+        // tiles of the previous round, so never for its own unpublished ones.
+        uint32_t *pub_fl = nullptr;
+        uint32_t pub_epoch = 0;
+        int64_t pub_lo = 0, pub_n = 0;
+        auto publish = [&]() {
+            if (pub_n == 0) return;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0)
+                for (int64_t i = 0; i < pub_n; ++i)
+                    __hip_atomic_store(pub_fl + pub_lo + i, pub_epoch, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            pub_n = 0;
+        };
         for (; x < x_end; ++x) {
             const BatchRing &R = plan.rings[p];
             const int64_t tiles = R.tiles;
             uint32_t *fl = plan.flags + R.flag_base;
             const uint32_t need = (uint32_t)k;
+            if (pub_n && (pub_fl != fl || pub_epoch != (uint32_t)(k + 1))) publish();
             // Wait for every tile whose cells lie within H of this tile on
             // the ring: exactly the tiles this window reads (read after
             // write) and the tiles whose windows read this tile's cells in
@@ -126,13 +146,15 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
                 const int64_t wlen = (R.N - b) < R.W ? (R.N - b) : R.W;
                 for (int64_t i = lane; i < wlen; i += 64) dst[b + i] = src[b + i];
             }
-            // the release fence orders this tile's stores before the counter
-            // store, which then needs no release of its own
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0)
-                __hip_atomic_store(fl + t, (uint32_t)(k + 1), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            // published with the chunk's other tiles of this ring and round
+            // (the release fence there orders their stores before the
+            // counters, which then need no release of their own)
+            if (pub_n == 0) {
+                pub_fl = fl;
+                pub_epoch = (uint32_t)(k + 1);
+                pub_lo = t;
+            }
+            ++pub_n;
             // next item in numbering order
             if (++t == tiles) {
                 t = 0;
@@ -142,6 +164,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
                 }
             }
         }
+        publish();
     }
 }
 
