@@ -99,3 +99,84 @@ def test_random_interleaving_is_race_free(seed):
                     raise AssertionError("overwrote data still needed")
             dst[i] = k + 1
         done[t] = k + 1
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_chunked_publication_drains_and_is_race_free(seed):
+    """The persistent launch as the kernel runs it: waves claim chunks of
+    consecutive items (round-major over rings sorted by their rounds, then
+    tiles), and a wave publishes the tiles it computed only at the end of its
+    chunk or before it moves on to another ring or round.  Waits see only
+    published counters.  Under random interleavings of a few waves the
+    schedule never deadlocks, every window reads the right round and no
+    round k-1 value is overwritten while a reader is still to come."""
+    rng = random.Random(5000 + seed)
+    W, H = 40, 12
+    chunk = rng.choice([1, 2, 3, 4, 8])
+    nwaves = rng.randint(1, 6)
+    rings = [(rng.choice([17, W * 3 + 1, W * 5 + 3, W * 6 + 11, W * 2]), rng.randint(1, 6))
+             for _ in range(rng.randint(1, 4))]
+    rings.sort(key=lambda g: -g[1])                     # by rounds, descending
+    tiles = [-(-N // W) for N, _ in rings]
+    items = [(k, p, t) for k in range(max(r for _, r in rings))
+             for p in range(len(rings)) if rings[p][1] > k for t in range(tiles[p])]
+    buf = [[[0] * N, [None] * N] for N, _ in rings]
+    computed = set()
+    published = [[0] * tiles[p] for p in range(len(rings))]
+    counter = 0
+    waves = [dict(todo=[], pend=[], key=None) for _ in range(nwaves)]
+
+    def deps_ready(k, p, t):
+        N = rings[p][0]
+        return all(published[p][q] >= k for q in walk_deps(t, tiles[p], N, W, H))
+
+    def publish(w):
+        for (p, t, e) in w["pend"]:
+            published[p][t] = e
+        w["pend"], w["key"] = [], None
+
+    def compute(k, p, t):
+        N = rings[p][0]
+        src, dst = buf[p][k & 1], buf[p][(k + 1) & 1]
+        for i in range(t * W - H, min(N, t * W + W) + H):
+            assert src[i % N] == k, (k, p, t, i)
+        for i in cells_of(t, tiles[p], N, W):
+            for (k2, p2, t2) in items:
+                if p2 == p and k2 == k - 1 and (k2, p2, t2) not in computed and \
+                        t in needed_tiles(t2, tiles[p], N, W, H):
+                    raise AssertionError("overwrote data still needed")
+            dst[i] = k + 1
+        computed.add((k, p, t))
+
+    while len(computed) < len(items) or any(w["pend"] for w in waves):
+        moves = []
+        for w in waves:
+            if not w["todo"]:
+                if w["pend"] or counter < len(items):
+                    moves.append(w)
+            else:
+                k, p, t = items[w["todo"][0]]
+                if w["pend"] and w["key"] != (p, k):
+                    moves.append(w)                 # publish before switching
+                elif deps_ready(k, p, t):
+                    moves.append(w)
+        assert moves, "schedule deadlocked"
+        w = rng.choice(moves)
+        if not w["todo"]:
+            if w["pend"]:
+                publish(w)                          # end of its chunk
+            else:
+                w["todo"] = list(range(counter, min(len(items), counter + chunk)))
+                counter += chunk
+            continue
+        k, p, t = items[w["todo"][0]]
+        if w["pend"] and w["key"] != (p, k):
+            publish(w)
+            continue
+        compute(k, p, t)
+        w["todo"].pop(0)
+        w["pend"].append((p, t, k + 1))
+        w["key"] = (p, k)
+    for p, (N, r) in enumerate(rings):
+        assert all(e == r for e in published[p])
+        assert all(v == r for v in buf[p][r & 1])
