@@ -349,7 +349,7 @@ const char *heat_last_error(void);
  * 16-byte aligned) between two device buffers on hip_stream, with the same
  * launch shape as the one-step kernel.  It measures the HBM bandwidth a
  * read-once/write-once kernel reaches on this device, the ceiling the
- * one-step sweep is judged against.  Asynchronous.
+ * one-step sweep is measured against.  Asynchronous.
  */
 int heat_copy_dev(const void *d_src, void *d_dst, size_t bytes, void *hip_stream);
 
