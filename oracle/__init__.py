@@ -1,14 +1,16 @@
 """CPU oracle for the periodic 1D heat stencil -- TEST INFRASTRUCTURE ONLY.
 
-Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
-``bench.py`` may import this package.  The GPU library never imports, links or
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline legs of
+``bench.py`` (``cpu_baseline``, ``cpu_threads``) may import this package.  The GPU library never imports, links or
 calls it and shares no code with it.
 
 Two independent implementations of the same definition live here:
 
 * ``heat_oracle.c`` (plain C, built with ``-O2 -ffp-contract=off``), loaded
   through ctypes: ``solve``, ``solve_parts``, ``solve_threads`` (one POSIX
-  thread per segment, ghost cells through queues), ``cone``, ``solve_f32``,
+  thread per segment, ghost cells through queues; with ``simd=True`` its
+  segment sweep is the vectorised one of ``heat_cpu_simd.c``, built with
+  ``-O3``, bit-identical), ``cone``, ``solve_f32``,
   ``cone_f32``, ``solve_f32c``, ``cone_f32c`` (and, composed around the
   binary32 ones in NumPy, the mean-shifted storage ``solve_f32_shifted``,
   ``solve_f32c_shifted``);
