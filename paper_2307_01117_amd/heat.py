@@ -192,9 +192,17 @@ def plan(N: int, nt: int, precision: int = FP64, **cfg) -> dict:
     return {f: getattr(out, f) for f, _ in heat_plan_info._fields_}
 
 
-def solve(u: np.ndarray, nparts: int, r: float, nt: int) -> np.ndarray:
-    """Plain form on a host binary64 array (copied; the result is returned)."""
-    a = np.ascontiguousarray(u, dtype=np.float64).copy()
+def solve(u: np.ndarray, nparts: int, r: float, nt: int, inplace: bool = False) -> np.ndarray:
+    """Plain form on a host binary64 array.  By default the input is copied
+    and the result returned; with ``inplace`` a writeable C-contiguous
+    float64 array is advanced in place (no host copy) and returned."""
+    if inplace:
+        if not (isinstance(u, np.ndarray) and u.dtype == np.float64 and u.flags.c_contiguous
+                and u.flags.writeable):
+            raise ValueError("inplace needs a writeable C-contiguous float64 numpy array")
+        a = u
+    else:
+        a = np.ascontiguousarray(u, dtype=np.float64).copy()
     _check(load().heat_solve(a.ctypes.data, a.size, int(nparts), float(r), int(nt)))
     return a
 

@@ -123,7 +123,10 @@ def test_host_form_staged_copies():
     takes the plain copy."""
     N = 10_000_019
     u0 = inputs.uniform_ring(N, 77)
-    assert same_bits(heat.solve(u0, 3, 0.375, 7), oracle.solve(u0, 0.375, 7))
+    want = oracle.solve(u0, 0.375, 7)
+    assert same_bits(heat.solve(u0, 3, 0.375, 7), want)
+    a = u0.copy()
+    assert heat.solve(a, 3, 0.375, 7, inplace=True) is a and same_bits(a, want)
     assert same_bits(heat.solve(u0, 1, 0.5, 0), u0)
     small = inputs.uniform_ring(1000, 78)
     assert same_bits(heat.solve(small, 2, 0.25, 9), oracle.solve(small, 0.25, 9))

@@ -41,3 +41,16 @@ def test_bench_thread_axis_is_bitwise_stable():
         assert s["bitwise_equal_across_threads"], name
         assert len(s["value"]) == len(rep["threads"]) and min(s["value"]) > 0
         assert len(s["value_simd"]) == len(rep["threads"]) and min(s["value_simd"]) > 0
+
+
+def test_inplace_solve_rejects_arrays_it_cannot_write():
+    """The binding's in-place plain form refuses, before any library call,
+    arrays whose memory the library could not advance in place."""
+    import numpy as np
+    import pytest
+    from paper_2307_01117_amd import heat
+    ro = np.zeros(8)
+    ro.flags.writeable = False
+    for bad in (np.zeros(8, np.float32), np.zeros((4, 4))[:, 0], ro, [0.0] * 8):
+        with pytest.raises(ValueError):
+            heat.solve(bad, 1, 0.5, 1, inplace=True)
