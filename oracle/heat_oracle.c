@@ -3,7 +3,7 @@
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
  * reference that the GPU library is checked against.  Only the test suite,
- * the smoke check and the CPU-baseline leg of the benchmark load it; the GPU
+ * the smoke check and the CPU-baseline legs of the benchmark load it; the GPU
  * library never includes, links or calls it, and it shares no code with it.
  *
  * What it computes (paper, Section 2 "Model problem"):
