@@ -223,7 +223,9 @@ typedef struct heat_ring {
 enum heat_batch_flags {
     HEAT_BATCH_WAIT = 1,       /* wait for completion and report kernel-side errors */
     HEAT_BATCH_PERSISTENT = 2, /* one persistent launch whose tiles synchronise through
-                                  per-tile epoch counters instead of one launch per round */
+                                  per-tile epoch counters instead of one launch per round
+                                  (needs HEAT_BATCH_WAIT: a stalled wait is reported as
+                                  HEAT_EDEVICE once the launch has drained) */
     HEAT_BATCH_GRAPH = 4       /* capture the per-round launches in a hipGraph and replay it
                                   (needs HEAT_BATCH_WAIT) */
 };
@@ -353,7 +355,10 @@ const char *heat_last_error(void);
  */
 int heat_copy_dev(const void *d_src, void *d_dst, size_t bytes, void *hip_stream);
 
-/* Library version string. */
+/* Library version string: "heat-mi355x <version> (gfx950) src <sha256>", the
+ * last field the sha256 of the sources the library was built from (every
+ * file of csrc/, this header and the build script), or "unknown" for a
+ * build that did not supply it. */
 const char *heat_version(void);
 
 /*

@@ -4,6 +4,7 @@ Usage: python -m paper_2307_01117_amd.build
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -27,6 +28,26 @@ SOURCE_FLAGS = {
     "kernels_f32c.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
 }
 
+def source_digest() -> str:
+    """sha256 over the library's sources: every file under csrc/, the public
+    header and this build script (its flags), each preceded by its name, in
+    name order.  It is compiled into the library (heat_version) and compared
+    by the binding at load time, so a library built from other sources is
+    refused instead of silently run."""
+    h = hashlib.sha256()
+    files = [os.path.join("csrc", f) for f in sorted(os.listdir(CSRC))
+             if f.endswith((".hip", ".h"))]
+    paths = [(f, os.path.join(HERE, f)) for f in files]
+    paths.append(("include/heat.h", os.path.join(ROOT, "include", "heat.h")))
+    paths.append(("build.py", os.path.abspath(__file__)))
+    for name, path in paths:
+        h.update(name.encode() + b"\0")
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
@@ -47,7 +68,8 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmpdir = tempfile.mkdtemp(prefix="heat_build_")
     try:
-        inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+        inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC,
+               f"-DHEAT_SOURCE_SHA256=\"{source_digest()}\""]
         objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
         cmds = [[hipcc, *HIPCC_FLAGS, *SOURCE_FLAGS.get(s, []), *inc, "-c", os.path.join(CSRC, s),
                  "-o", o] for s, o in zip(SOURCES, objs)]

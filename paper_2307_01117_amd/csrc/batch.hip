@@ -321,6 +321,10 @@ int heat_solve_batch_dev(const heat_ring *rings, int32_t count, void *hip_stream
         return fail(HEAT_EINVAL, "unknown batch flags 0x%x", flags);
     if ((flags & HEAT_BATCH_GRAPH) && !(flags & HEAT_BATCH_WAIT))
         return fail(HEAT_EINVAL, "HEAT_BATCH_GRAPH needs HEAT_BATCH_WAIT");
+    // the persistent launch reports a timed-out dependency wait through a
+    // status word that only a waiting call reads back
+    if ((flags & HEAT_BATCH_PERSISTENT) && !(flags & HEAT_BATCH_WAIT))
+        return fail(HEAT_EINVAL, "HEAT_BATCH_PERSISTENT needs HEAT_BATCH_WAIT");
     for (int32_t i = 0; i < count; ++i) {
         int rc = validate_ring(rings[i]);
         if (rc) return fail(rc, "ring %d: %s", i, heat_last_error());

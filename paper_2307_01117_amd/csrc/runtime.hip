@@ -533,7 +533,12 @@ extern "C" {
 
 const char *heat_last_error(void) { return heat::g_err; }
 
-const char *heat_version(void) { return "heat-mi355x 0.1 (gfx950)"; }
+// The build compiles in the sha256 of the sources it compiled (build.py,
+// source_digest), so a caller can tell a library built from other sources.
+#ifndef HEAT_SOURCE_SHA256
+#define HEAT_SOURCE_SHA256 "unknown"
+#endif
+const char *heat_version(void) { return "heat-mi355x 0.2 (gfx950) src " HEAT_SOURCE_SHA256; }
 
 int heat_device_info(int32_t *cus, int32_t *lds_bytes, int32_t *wave_size, int32_t *clock_khz,
                      size_t *mem_total, size_t *mem_free) {

@@ -158,6 +158,27 @@ static void finish_locked(heat_server *s, Req *q, int state, int rc) {
     s->cv_sched.notify_one();
 }
 
+// After a device error: fail every request the scheduler still holds --
+// resident, staged, waiting for its stage-in, or queued -- and release their
+// blocks.  The caller has waited for the compute stream, so no kernel still
+// writes the arena; a stage-in in progress fails its request itself when it
+// ends (stage_in_loop checks `fatal`).
+static void fail_all_locked(heat_server *s, int rc) {
+    auto fail_list = [&](auto &list) {
+        for (Req *q : list) {
+            q->p->status = rc;
+            finish_locked(s, q, FAILED, rc);
+        }
+        list.clear();
+    };
+    fail_list(s->active);
+    fail_list(s->ready);
+    fail_list(s->h2d);
+    fail_list(s->queue);
+    s->st.active = 0;
+    s->st.queued = 0;
+}
+
 // ------------------------------------------------------------ copy threads
 // Stage-in and stage-out run on threads and streams of their own: the two
 // directions overlap on the DMA engines, and a stage-out that waits for its
@@ -220,6 +241,9 @@ static void stage_in_loop(heat_server *s) {
         if (e != hipSuccess) {
             q->p->status = HEAT_EDEVICE;
             finish_locked(s, q, FAILED, fail_hip(e, "server stage-in"));
+        } else if (s->fatal) {
+            q->p->status = s->fatal;
+            finish_locked(s, q, FAILED, fail(s->fatal, "server failed earlier: device error"));
         } else if (q->cancel) {
             finish_locked(s, q, CANCELLED, HEAT_ECANCELED);
         } else {
@@ -258,7 +282,7 @@ static void sched_loop(heat_server *s) {
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
         // admission in arrival order while memory and slots allow
-        while (!s->stop && !s->queue.empty() && s->slots_used < s->max_slots) {
+        while (!s->stop && !s->fatal && !s->queue.empty() && s->slots_used < s->max_slots) {
             Req *q = s->queue.front();
             size_t off = 0;
             if (!s->arena.alloc(q->bytes, &off)) break;
@@ -354,13 +378,17 @@ static void sched_loop(heat_server *s) {
         lk.lock();
         ++s->st.ticks;
         if (rc) {
-            // a device error poisons the server: fail everything resident
+            // A device error poisons the server: no more admissions; once the
+            // compute stream has drained (the tick's kernels may still be
+            // writing the arena) every request it holds fails and its block
+            // is released.
             s->fatal = rc;
-            for (Req *q : s->active) {
-                q->p->status = rc;
-                finish_locked(s, q, FAILED, rc);
-            }
-            s->active.clear();
+            const std::string msg = heat_last_error();
+            lk.unlock();
+            (void)hipStreamSynchronize(s->compute);
+            lk.lock();
+            (void)fail(rc, "%s", msg.c_str());
+            fail_all_locked(s, rc);
             continue;
         }
         for (Req *q : finished) {

@@ -91,6 +91,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: run `python -m paper_2307_01117_amd.build`")
     lib = ctypes.CDLL(path)
+    lib.heat_version.restype = ctypes.c_char_p
+    built = lib.heat_version().decode().rsplit(" ", 1)[-1]
+    from paper_2307_01117_amd.build import source_digest
+    if built != source_digest():
+        raise RuntimeError(f"{path} was built from other sources (src {built[:16]}, tree "
+                           f"{source_digest()[:16]}): rebuild with "
+                           "`python -m paper_2307_01117_amd.build`")
     i32, i64, d, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     pd = ctypes.POINTER(ctypes.c_double)
     P = ctypes.POINTER

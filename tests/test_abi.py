@@ -192,3 +192,23 @@ def test_tuning_table_roundtrip(lib, tmp_path):
         assert heat.plan(5_000_000, 1000, heat.FP64)["exchange_steps"] == 8
     finally:
         heat.tune_load(str(saved))
+
+
+def test_library_built_from_this_tree(lib):
+    """The library carries the sha256 of the sources it was built from, and
+    it is the digest of the sources in this tree (the binding refuses a
+    library built from others)."""
+    from paper_2307_01117_amd.build import source_digest
+    v = heat.version()
+    assert v.startswith("heat-mi355x ") and v.rsplit(" ", 1)[-1] == source_digest()
+
+
+def test_batch_flags_refused_without_wait(lib):
+    """The graph and persistent batch modes report kernel-side failures only
+    to a call that waits, so without HEAT_BATCH_WAIT they are refused before
+    any device work."""
+    for flags in (heat.BATCH_PERSISTENT, heat.BATCH_GRAPH,
+                  heat.BATCH_PERSISTENT | heat.BATCH_GRAPH):
+        assert lib.heat_solve_batch_dev(None, 0, None, flags) == heat.HEAT_EINVAL
+        assert "HEAT_BATCH_WAIT" in heat.last_error()
+    assert lib.heat_solve_batch_dev(None, 0, None, 8) == heat.HEAT_EINVAL
