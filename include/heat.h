@@ -137,6 +137,31 @@ int heat_solve_dev(void *d_u, int64_t N, int32_t nparts, double r, int64_t nt,
                    int32_t precision, void *hip_stream, double *sum0_out, double *sum_out);
 
 /*
+ * Device form that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  As heat_solve_dev with the planner's
+ * default shape, except:
+ *   - its scratch (the ping-pong state buffer and the checksum partials) is
+ *     one static device array of HEAT_NOALLOC_SCRATCH_BYTES per device, held
+ *     from the library's first use on that device until the process ends;
+ *     a ring whose scratch (N * element size rounded up to 256 bytes, plus
+ *     8 * max(4096, 2 * tiles) bytes when sums are asked for) does not fit
+ *     is refused with HEAT_EINVAL -- for binary64 about 8.3 million cells,
+ *     for the binary32 forms about 16.7 million;
+ *   - d_sums_out: NULL, or a device array of 2 doubles that receives the
+ *     binary64 sums of the state before and after the run, on the stream;
+ *     the call never waits for the stream.
+ * Every call on one device shares that device's array, and the array keeps
+ * the last call's contents (every byte a call reads it has written first):
+ * calls that overlap on one device -- on different streams or threads --
+ * race and must be serialised by the caller.  No hipMalloc, hipFree or
+ * other allocating call is made.
+ */
+#define HEAT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int heat_solve_dev_noalloc(void *d_u, int64_t N, int32_t nparts, double r, int64_t nt,
+                           int32_t precision, void *hip_stream, double *d_sums_out);
+
+/*
  * Device form with explicit configuration and scratch.  d_work: NULL, or a
  * caller-owned device array with room for N values of the storage type (not
  * overlapping d_u).  cfg: NULL or overrides.  Otherwise as heat_solve_dev.

@@ -523,6 +523,67 @@ static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, do
     return HEAT_OK;
 }
 
+// ============================================================ no-alloc form
+// Device scratch of heat_solve_dev_noalloc: the ping-pong state buffer and
+// the checksum partials of one call, in one fixed array that the code object
+// holds on every device the library runs on (until the process ends).  Host
+// code never uses the array's name as an address: on each device the
+// address is looked up once (hipGetSymbolAddress, with that device
+// current) and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[HEAT_NOALLOC_SCRATCH_BYTES];
+
+static std::once_flag g_scratch_once[64];
+static void *g_scratch_ptr[64];
+static hipError_t g_scratch_err[64];
+
+static int noalloc_scratch(void **out) {
+    int dev = 0;
+    HEAT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(HEAT_EDEVICE, "device %d out of range", dev);
+    std::call_once(g_scratch_once[dev], [&]() {
+        g_scratch_err[dev] = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+    });
+    if (g_scratch_err[dev] != hipSuccess)
+        return fail_hip(g_scratch_err[dev], "hipGetSymbolAddress(scratch)");
+    *out = g_scratch_ptr[dev];
+    return HEAT_OK;
+}
+
+// Bytes of scratch a call needs: the state buffer (whole 256-byte units),
+// then the checksum partials (max(SUM_BLOCKS, 2 * parts) doubles).
+static size_t noalloc_bytes(const Plan &pl, int64_t N, int precision, int64_t nt, bool sums,
+                            size_t *partial_off) {
+    const size_t work = nt > 0 ? ((size_t)N * storage_bytes(precision) + 255) & ~size_t(255) : 0;
+    *partial_off = work;
+    const size_t np = sums ? (size_t)std::max<int64_t>(SUM_BLOCKS, 2 * pl.parts) : 0;
+    return work + np * sizeof(double);
+}
+
+static int solve_dev_noalloc_impl(void *d_u, int64_t N, int32_t nparts, double r, int64_t nt,
+                                  int32_t precision, hipStream_t st, double *d_sums_out) {
+    int rc = check_problem(N, nparts, r, nt, precision);
+    if (rc) return rc;
+    if (!d_u) return fail(HEAT_EINVAL, "d_u is NULL");
+    Plan pl;
+    rc = make_plan(N, nt, precision, nullptr, &pl);
+    if (rc) return rc;
+    size_t partial_off = 0;
+    const size_t need = noalloc_bytes(pl, N, precision, nt, d_sums_out != nullptr, &partial_off);
+    if (need > (size_t)HEAT_NOALLOC_SCRATCH_BYTES)
+        return fail(HEAT_EINVAL, "ring of %lld cells needs %zu bytes of scratch; the static "
+                    "scratch holds %zu", (long long)N, need, (size_t)HEAT_NOALLOC_SCRATCH_BYTES);
+    void *base = nullptr;
+    rc = noalloc_scratch(&base);
+    if (rc) return rc;
+    SumArea area;
+    if (d_sums_out) {
+        area.partial = (double *)((char *)base + partial_off);
+        area.d_out = d_sums_out;
+    }
+    return run_rounds(pl, precision, d_u, nt > 0 ? base : nullptr, N, r, nt, st,
+                      d_sums_out ? &area : nullptr);
+}
+
 }  // namespace heat
 
 using namespace heat;
@@ -590,6 +651,12 @@ int heat_solve_dev(void *d_u, int64_t N, int32_t nparts, double r, int64_t nt, i
                    void *hip_stream, double *sum0_out, double *sum_out) {
     return solve_dev_impl(d_u, nullptr, N, nparts, r, nt, precision, nullptr,
                           (hipStream_t)hip_stream, sum0_out, sum_out);
+}
+
+int heat_solve_dev_noalloc(void *d_u, int64_t N, int32_t nparts, double r, int64_t nt,
+                           int32_t precision, void *hip_stream, double *d_sums_out) {
+    return solve_dev_noalloc_impl(d_u, N, nparts, r, nt, precision, (hipStream_t)hip_stream,
+                                  d_sums_out);
 }
 
 int heat_solve(double *u, int64_t N, int32_t nparts, double r, int64_t nt) {

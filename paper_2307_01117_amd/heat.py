@@ -33,8 +33,10 @@ EXPORTS = [
     "heat_solve_batch", "heat_solve_batch_dev", "heat_server_create", "heat_submit",
     "heat_poll", "heat_wait", "heat_cancel", "heat_server_get_stats", "heat_server_destroy",
     "heat_last_error", "heat_version", "heat_device_info", "heat_copy_dev",
-    "heat_autotune", "heat_tune_save", "heat_tune_load",
+    "heat_autotune", "heat_tune_save", "heat_tune_load", "heat_solve_dev_noalloc",
 ]
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # HEAT_NOALLOC_SCRATCH_BYTES
 
 
 class HeatError(RuntimeError):
@@ -104,6 +106,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "heat_solve": ([vp, i64, i32, d, i64], i32),
         "heat_solve_dev": ([vp, i64, i32, d, i64, i32, vp, pd, pd], i32),
+        "heat_solve_dev_noalloc": ([vp, i64, i32, d, i64, i32, vp, vp], i32),
         "heat_solve_dev_cfg": ([vp, vp, i64, i32, d, i64, i32, P(heat_config), vp, pd, pd], i32),
         "heat_plan": ([i64, i64, i32, P(heat_config), P(heat_plan_info)], i32),
         "heat_checksum_dev": ([vp, i64, i32, vp, pd], i32),
@@ -233,6 +236,25 @@ def solve_dev(d_u, nparts: int, r: float, nt: int, precision: int | None = None,
                                      d_u.numel(), int(nparts), float(r), int(nt), int(precision),
                                      _cfg(**cfg), _stream_handle(stream), ps0, ps1))
     return (s0.value, s1.value) if sums else None
+
+
+def solve_dev_noalloc(d_u, nparts: int, r: float, nt: int, precision: int | None = None,
+                      stream=None, sums_out=None) -> None:
+    """Device form that allocates nothing (static library scratch): d_u as in
+    solve_dev; ``sums_out`` None or a float64 device tensor of at least 2
+    elements that receives (sum0, sum_nt) on the stream.  Never waits."""
+    import torch
+    if precision is None:
+        precision = FP64 if d_u.dtype == torch.float64 else FP32
+    want = torch.float64 if precision == FP64 else torch.float32
+    if d_u.dtype != want or not d_u.is_contiguous() or not d_u.is_cuda:
+        raise ValueError("d_u must be a contiguous device tensor of the precision's dtype")
+    if sums_out is not None and (sums_out.dtype != torch.float64 or not sums_out.is_cuda
+                                 or not sums_out.is_contiguous() or sums_out.numel() < 2):
+        raise ValueError("sums_out must be a contiguous float64 device tensor of 2 elements")
+    _check(load().heat_solve_dev_noalloc(d_u.data_ptr(), d_u.numel(), int(nparts), float(r),
+                                         int(nt), int(precision), _stream_handle(stream),
+                                         sums_out.data_ptr() if sums_out is not None else None))
 
 
 def copy_dev(src, dst, stream=None) -> None:

@@ -212,3 +212,13 @@ def test_batch_flags_refused_without_wait(lib):
         assert lib.heat_solve_batch_dev(None, 0, None, flags) == heat.HEAT_EINVAL
         assert "HEAT_BATCH_WAIT" in heat.last_error()
     assert lib.heat_solve_batch_dev(None, 0, None, 8) == heat.HEAT_EINVAL
+
+
+def test_noalloc_size_limit_checked_on_host(lib):
+    """The no-allocation device form refuses rings whose scratch exceeds its
+    static array before any device work (the pointer is never touched)."""
+    fake = 256
+    for N, prec in ((8_500_000, heat.FP64), (17_000_000, heat.FP32C)):
+        assert lib.heat_solve_dev_noalloc(fake, N, 1, 0.5, 10, prec, None, None) == heat.HEAT_EINVAL
+        assert "static scratch" in heat.last_error()
+    assert lib.heat_solve_dev_noalloc(None, 10, 1, 0.5, 10, heat.FP64, None, None) == heat.HEAT_EINVAL
