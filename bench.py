@@ -12,6 +12,16 @@ r = 1/2, 1,000 explicit-Euler steps per pass, Uniform[0,1) seed 1, binary64.
 The metric is giga cell-updates per second (N * nt / time), the paper's
 "cells processed per second".
 
+The default run adds, in the same line, the rest of the metric measured on
+the same GPU: ``precision`` (compensated and plain binary32 on the 1e8-cell
+perturbed ring, r = 1/4, with the whole-ring error against binary64),
+``batch`` (4,096 uneven rings batched in binary64 against the same rings
+solved one by one, and in compensated binary32 with every ring's error
+against binary64) and ``serve`` (Poisson arrivals at 200 requests/s for 15 s:
+p50/p99 latency, GCUP/s against the offered load, alone-vs-mix bit equality
+and the compensated requests' error against binary64).  ``value`` is the
+plain binary64 ring's rate.
+
 Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
@@ -26,16 +36,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-# Vector ALU ceilings in lane operations per second, from the published
-# vector peaks (which count an FMA as 2 flops): FP64 78.6 TFLOP/s -> 39.3e12
-# FP64 ops/s (256 CUs x 64 lanes x 2.4 GHz); FP32 157.3 TFLOP/s -> 78.65e12
-# FP32 ops/s (FP32 issues at twice the FP64 rate).
+# Published MI355X vector peaks (an FMA counts as 2 flops): FP64 78.6 TFLOP/s,
+# FP32 157.3 TFLOP/s (256 CUs x 2.4 GHz x 128 resp. 256 flops per CU-cycle).
+VECTOR_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp32c": 157.3}
+# Algorithmic flops per cell update (CUP) of each form, the update formula as
+# written: binary64 c + r*((l - 2c) + q) = 5 (2c, -, +, *, +); plain binary32
+# the same five; compensated binary32 12: the Laplacian of u (3) and of e (3),
+# their sum (1), times r (1), the Fast2Sum update (4).
+FLOPS_PER_CUP = {"fp64": 5, "fp32": 5, "fp32c": 12}
+# Issue-rate view of the same kernels: VALU lane operations per second against
+# the instruction ceiling (FP64 39.3e12 = 256 CUs x 64 lanes x 2.4 GHz; FP32
+# twice that when two instructions issue together), and the minimal
+# instructions per update of each form: binary64 fma(-2,c,l), +q, *r, +c = 4;
+# binary32 in flux form (q-c) - (c-l), whose one-sided difference serves two
+# cells: one difference, the difference of differences, *r, +c = 4;
+# compensated 10 (the same two steps for u and for e 4, sum 1, *r 1,
+# Fast2Sum 4).  Since the published flops count an FMA as two, a kernel that
+# issues OPS_PER_CUP instructions for FLOPS_PER_CUP flops can reach at most
+# FLOPS_PER_CUP / (2 * OPS_PER_CUP) of the flops peak: 0.625 for binary64
+# and plain binary32 (one FMA, the exact 2c, is all the bitwise contract
+# allows), 0.6 for the compensated form.
 VALU_PEAK_TOPS = {"fp64": 39.3, "fp32": 78.65, "fp32c": 78.65}
-# Minimal VALU operations per cell update of each form (the update formula,
-# nothing else): binary64 fma(-2,c,l), +q, *r, +c = 4; binary32 in flux form
-# (q-c) - (c-l), whose one-sided difference serves two cells: one difference,
-# the difference of differences, *r, +c = 4; compensated 10 (the same two
-# steps for u and for e 4, sum 1, *r 1, Fast2Sum 4).
 OPS_PER_CUP = {"fp64": 4, "fp32": 4, "fp32c": 10}
 
 
@@ -78,6 +99,8 @@ def parse():
                     help="skip timing the host-buffer boundary (heat_solve: PCIe both ways)")
     ap.add_argument("--no-cpu-threads", action="store_true",
                     help="skip the thread axis of the threaded CPU oracle (binary64 ring only)")
+    ap.add_argument("--no-sub-records", action="store_true",
+                    help="default run: skip the precision, batch and serve records")
     ap.add_argument("--cpu-thread-steps", type=int, default=5,
                     help="time steps of the full ring per thread count on the thread axis")
     return ap.parse_args()
@@ -119,18 +142,19 @@ def precision_report(heat, torch, u0, nparts, r, nt, prec, stream):
 
 
 def kernel_source_digest() -> str:
-    """sha256 of the kernel sources and of the build script (its per-source
-    compiler flags); HBM traffic taken from counters is only reported while
-    the kernels are the ones that were counted."""
+    """sha256 of the kernel sources and of the compiler flags they are built
+    with (build.py's flag lists); HBM traffic taken from counters is only
+    reported while the kernels are the ones that were counted."""
     import hashlib
+
+    from paper_2307_01117_amd import build
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2307_01117_amd")
     for f in ("heat_device.h", "window.h", "round.h", "kernels.hip", "kernels_xchg.hip",
               "kernels_f32.hip", "kernels_f32c.hip"):
         with open(os.path.join(pkg, "csrc", f), "rb") as fh:
             h.update(fh.read())
-    with open(os.path.join(pkg, "build.py"), "rb") as fh:
-        h.update(fh.read())
+    h.update(repr((build.HIPCC_FLAGS, sorted(build.SOURCE_FLAGS.items()))).encode())
     return h.hexdigest()
 
 
@@ -244,13 +268,160 @@ def cpu_threads(u0, r, steps, workload, max_threads=16):
             "cores_available": avail, "cpu": cpu_model(), "samples": res}
 
 
+def run_plain(args, workload, prec_name, steps, warmup, cfg, host=True):
+    """One ring: `warmup` untimed passes, then `steps` timed passes of the hot
+    path (each one heat_solve_dev call with both checksums), HIP events on the
+    passes' stream around every timed pass; returns the bench dict (without
+    the CPU legs) and the initial state."""
+    import torch
+
+    from paper_2307_01117_amd import heat, inputs
+    w = inputs.WORKLOADS[workload]
+    prec = heat.PRECISIONS[prec_name]
+    N, nparts, r, nt = w["N"], w["nparts"], w["r"], w["nt"]
+    pl = heat.plan(N, nt, prec, **cfg)
+
+    u0 = inputs.make_initial(w["init"], N, w["seed"])
+    dt = torch.float64 if prec == heat.FP64 else torch.float32
+    dev = torch.device("cuda", 0)
+    d_u = torch.from_numpy(u0).to(dev, dtype=dt)
+    d_work = torch.empty_like(d_u)
+    stream = torch.cuda.current_stream(dev)
+
+    def one_step():
+        # the whole hot path in one call: checksum of the state in (fused into
+        # the first round), the rounds, checksum of the state out (fused into
+        # the last round)
+        return heat.solve_dev(d_u, nparts, r, nt, precision=prec, stream=stream, work=d_work,
+                              sums=True, **cfg)
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        one_step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timed_ms = sum(a.elapsed_time(b) for a, b in evs)
+
+    # the round launches alone: one pass without checksums between two HIP
+    # events (no other kernel: rounds are even, so no copy-back)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    kern_ms = []
+    for _ in range(max(2, min(steps, 5))):
+        ev[0].record(stream)
+        heat.solve_dev(d_u, nparts, r, nt, precision=prec, stream=stream, work=d_work, **cfg)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        kern_ms.append(ev[0].elapsed_time(ev[1]))
+
+    ms_per_step = elapsed * 1e3 / steps
+    value = N * nt * steps / elapsed / 1e9
+
+    launches = pl["rounds"]
+    # average launch duration over the timed region: the events around each
+    # timed pass hold its round launches plus the final checksum reduction
+    # and the copy of the two sums (about 10 us per pass), so this is an
+    # upper bound on the round kernel's duration
+    k_avg_ms = timed_ms / steps / launches
+    k_alone_ms = sum(kern_ms) / len(kern_ms) / launches
+    es = 8 if prec == heat.FP64 else 4
+    alg_bytes = 2 * es * N                    # read the state once, write it once per launch
+    steps_per_launch = nt / launches
+    if pl["kernel"] == heat.KERNEL_STEP:
+        achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+        # the achievable bandwidth: the library's streaming copy of the same
+        # bytes, timed here on the same stream
+        heat.copy_dev(d_u, d_work, stream)
+        ev[0].record(stream)
+        for _ in range(20):
+            heat.copy_dev(d_u, d_work, stream)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = alg_bytes / (ev[0].elapsed_time(ev[1]) / 20 * 1e-3) / 1e9
+        roof["copy_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    else:
+        # Temporal blocking moves 2*es bytes per cell per T steps and is
+        # limited by the vector ALU: achieved = algorithmic flops of the cell
+        # updates per launch / launch time, against the published vector peak.
+        # Beside it, the issue-rate view (VALU lane operations per second
+        # against the instruction ceiling), which the bitwise contract caps the
+        # flops fraction by (see OPS_PER_CUP).
+        cups = N * steps_per_launch
+        tflops = FLOPS_PER_CUP[prec_name] * cups / (k_avg_ms * 1e-3) / 1e12
+        peak = VECTOR_PEAK_TFLOPS[prec_name]
+        ops = OPS_PER_CUP[prec_name] * cups / (k_avg_ms * 1e-3) / 1e12
+        hbm = alg_bytes / (k_avg_ms * 1e-3) / 1e9
+        roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(tflops / peak, 4), "traffic": None,
+                "flops_per_cup": FLOPS_PER_CUP[prec_name],
+                "valu_issue": {
+                    "achieved": round(ops, 2), "peak": VALU_PEAK_TOPS[prec_name],
+                    "unit": "T VALU lane-ops/s", "frac": round(ops / VALU_PEAK_TOPS[prec_name], 4),
+                    "ops_per_cup": OPS_PER_CUP[prec_name],
+                    "flops_frac_cap": round(FLOPS_PER_CUP[prec_name] /
+                                            (2 * OPS_PER_CUP[prec_name]), 4)},
+                "hbm_algorithmic_GBs": round(hbm, 1),
+                "hbm_frac": round(hbm / HBM_PEAK_GBS, 4),
+                # cell updates per second against the roofline of one step per
+                # launch (every step reads and writes the state: 2*es bytes per
+                # cell update at 8 TB/s); temporal blocking exceeds it T-fold
+                "vs_one_step_hbm_roofline": round(cups / (k_avg_ms * 1e-3)
+                                                  / (HBM_PEAK_GBS * 1e9 / (2 * es)), 2)}
+    roof["kernel"] = ("k_step" if pl["kernel"] == heat.KERNEL_STEP else "k_window")
+    roof["traffic"] = measured_traffic(roof["kernel"], workload, prec_name, pl)
+    roof["avg_launch_ms"] = round(k_avg_ms, 4)
+    roof["avg_launch_ms_kernel_only"] = round(k_alone_ms, 4)
+    roof["launches_per_step"] = launches
+
+    err = None
+    del d_u, d_work
+    torch.cuda.empty_cache()
+    if prec != heat.FP64:
+        err = precision_report(heat, torch, u0, nparts, r, nt, prec, stream)
+    out = {
+        "metric": "GCUP/s (giga cell-updates per second)",
+        "value": round(value, 3),
+        "unit": "GCUP/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32c": "f32 (compensated)"}[prec_name],
+        "data": "synthetic",
+        "config": {"workload": workload, "N": N, "nparts": nparts, "r": r, "nt": nt,
+                   "init": w["init"], "seed": w["seed"], "precision": prec_name,
+                   "kernel": roof["kernel"], "cells_per_lane": pl["cells_per_lane"],
+                   "steps_per_round": pl["steps_per_round"],
+                   "waves_per_group": pl["waves_per_group"],
+                   "register_form": pl["register_form"],
+                   "exchange_steps": pl["exchange_steps"]},
+        "roofline": roof,
+    }
+    if err is not None:
+        out["error_vs_fp64"] = err
+    if host and prec_name == "fp64" and not cfg.get("kernel"):
+        out["host_path"] = host_path(heat, u0, nparts, r, nt)
+    return out, u0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2307_01117_amd import heat, inputs
@@ -268,18 +439,14 @@ def main():
     cfg = dict(kernel=kernel, cells_per_lane=args.cells_per_lane,
                steps_per_round=args.steps_per_round, waves_per_group=args.waves_per_group,
                register_form=args.register_form, exchange=exchange)
-    N, nparts, r, nt = w["N"], w["nparts"], w["r"], w["nt"]
-    pl = heat.plan(N, nt, prec, **cfg)
-
-    u0 = inputs.make_initial(w["init"], N, w["seed"])
-    dt = torch.float64 if prec == heat.FP64 else torch.float32
-    dev = torch.device("cuda", 0)
-    d_u = torch.from_numpy(u0).to(dev, dtype=dt)
-    d_work = torch.empty_like(d_u)
-    stream = torch.cuda.current_stream(dev)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
     if args.copy_probe:
+        N = w["N"]
+        dt = torch.float64 if prec == heat.FP64 else torch.float32
+        d_u = torch.from_numpy(inputs.make_initial(w["init"], N, w["seed"])).to("cuda", dtype=dt)
+        d_work = torch.empty_like(d_u)
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         torch.cuda.synchronize()
         heat.copy_dev(d_u, d_work, stream)
         torch.cuda.synchronize()
@@ -294,119 +461,116 @@ def main():
                           "GBs": round(2 * nbytes / ms / 1e6, 1)}), flush=True)
         return
 
-    def one_step():
-        # the whole hot path in one call: checksum of the state in (fused into
-        # the first round), the rounds, checksum of the state out (fused into
-        # the last round)
-        return heat.solve_dev(d_u, nparts, r, nt, precision=prec, stream=stream, work=d_work,
-                              sums=True, **cfg)
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    # dominant kernel alone: the round launches of one pass, between two HIP
-    # events on the stream they run on (no checksums, rounds are even so no
-    # copy-back)
-    kern_ms = []
-    for _ in range(max(2, min(args.steps, 5))):
-        ev[0].record(stream)
-        heat.solve_dev(d_u, nparts, r, nt, precision=prec, stream=stream, work=d_work, **cfg)
-        ev[1].record(stream)
-        torch.cuda.synchronize()
-        kern_ms.append(ev[0].elapsed_time(ev[1]))
-
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = N * nt * args.steps / elapsed / 1e9
-
-    launches = pl["rounds"]
-    k_avg_ms = sum(kern_ms) / len(kern_ms) / launches
-    es = 8 if prec == heat.FP64 else 4
-    alg_bytes = 2 * es * N                    # read the state once, write it once per launch
-    steps_per_launch = nt / launches
-    if pl["kernel"] == heat.KERNEL_STEP:
-        bound = "hbm"
-        achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
-        # the achievable bandwidth: the library's streaming copy of the same
-        # bytes, timed here on the same stream
-        heat.copy_dev(d_u, d_work, stream)
-        ev[0].record(stream)
-        for _ in range(20):
-            heat.copy_dev(d_u, d_work, stream)
-        ev[1].record(stream)
-        torch.cuda.synchronize()
-        copy_gbs = alg_bytes / (ev[0].elapsed_time(ev[1]) / 20 * 1e-3) / 1e9
-        roof["copy_GBs"] = round(copy_gbs, 1)
-        roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
-    else:
-        # temporal blocking moves 2*es bytes per cell per T steps; it is
-        # limited by the vector ALU: achieved = minimal lane operations of the
-        # update formula per second, against the chip's VALU op rate
-        ops = OPS_PER_CUP[prec_name] * N * steps_per_launch
-        peak = VALU_PEAK_TOPS[prec_name]
-        achieved = ops / (k_avg_ms * 1e-3) / 1e12
-        hbm = alg_bytes / (k_avg_ms * 1e-3) / 1e9
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "Tops/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "hbm_algorithmic_GBs": round(hbm, 1),
-                "hbm_frac": round(hbm / HBM_PEAK_GBS, 4),
-                # cell updates per second against the roofline of one step per
-                # launch (every step reads and writes the state: 2*es bytes per
-                # cell update at 8 TB/s); temporal blocking exceeds it T-fold
-                "vs_one_step_hbm_roofline": round(N * steps_per_launch / (k_avg_ms * 1e-3)
-                                                  / (HBM_PEAK_GBS * 1e9 / (2 * es)), 2)}
-    roof["kernel"] = ("k_step" if pl["kernel"] == heat.KERNEL_STEP else "k_window")
-    roof["traffic"] = measured_traffic(roof["kernel"], args.workload, prec_name, pl)
-    roof["avg_launch_ms"] = round(k_avg_ms, 4)
-    roof["launches_per_step"] = launches
-
-    err = None
-    if prec != heat.FP64:
-        del d_u, d_work
-        torch.cuda.empty_cache()
-        err = precision_report(heat, torch, u0, nparts, r, nt, prec, stream)
-    out = {
-        "metric": "GCUP/s (giga cell-updates per second)",
-        "value": round(value, 3),
-        "unit": "GCUP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp32c": "f32 (compensated)"}[prec_name],
-        "data": "synthetic",
-        "config": {"workload": args.workload, "N": N, "nparts": nparts, "r": r, "nt": nt,
-                   "init": w["init"], "seed": w["seed"], "precision": prec_name,
-                   "kernel": roof["kernel"], "cells_per_lane": pl["cells_per_lane"],
-                   "steps_per_round": pl["steps_per_round"],
-                   "waves_per_group": pl["waves_per_group"],
-                   "register_form": pl["register_form"],
-                   "exchange_steps": pl["exchange_steps"]},
-        "roofline": roof,
-    }
-    if err is not None:
-        out["error_vs_fp64"] = err
-    if err is None:
-        del d_u, d_work
+    out, u0 = run_plain(args, args.workload, prec_name, args.steps, args.warmup, cfg,
+                        host=not args.no_host_path)
     torch.cuda.empty_cache()
-    if prec_name == "fp64" and kernel == 0 and not args.no_host_path:
-        out["host_path"] = host_path(heat, u0, nparts, r, nt)
+    N, nt, r = w["N"], w["nt"], w["r"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u0, r, args.cpu_steps, prec_name,
                                            heat.plan(N, nt, prec)["steps_per_round"])
     if not args.no_cpu_threads and prec_name == "fp64" and args.cpu_thread_steps > 0:
         out["cpu_threads"] = cpu_threads(u0, r, args.cpu_thread_steps, args.workload)
+    del u0
+    # The rest of the metric on the same GPU, in the same line: the precision
+    # form on its workload, the batching form and a serving run, each against
+    # the plain form (default run only).
+    if args.workload == "ring_1e8" and prec_name == "fp64" and not kernel and \
+            not args.no_sub_records:
+        out["precision"] = sub_precision(args)
+        torch.cuda.empty_cache()
+        out["batch"] = sub_batch(args)
+        torch.cuda.empty_cache()
+        out["serve"] = sub_serve(args)
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
+
+
+def sub_precision(args):
+    """The precision form on its workload (1e8-cell perturbed ring, r 1/4,
+    1,000 steps): compensated binary32 (and plain binary32 for comparison)
+    timed like the plain line, with the whole-ring error against binary64."""
+    res = {}
+    for name in ("fp32c", "fp32"):
+        o, _ = run_plain(args, "ring_1e8_perturbed", name, 5, 2, {}, host=False)
+        res[name] = {"value": o["value"], "unit": "GCUP/s", "ms_per_step": o["ms_per_step"],
+                     "config": {k: o["config"][k] for k in
+                                ("cells_per_lane", "steps_per_round", "waves_per_group",
+                                 "exchange_steps")},
+                     "roofline": {k: o["roofline"][k] for k in
+                                  ("bound", "achieved", "peak", "unit", "frac", "avg_launch_ms",
+                                   "traffic")},
+                     "error_vs_fp64": o["error_vs_fp64"]}
+    res["workload"] = "ring_1e8_perturbed (N 1e8, r 0.25, 1,000 steps, 1 + 1e-3*U[-1,1) seed 2)"
+    res["error_metric"] = "max |x - y| / max |y| over the whole ring, y the binary64 result"
+    return res
+
+
+def sub_batch(args, count=4096, steps=3):
+    """The batching form on its workload (4,096 rings): binary64 batched
+    against the same rings solved one by one with the plain device form, and
+    the compensated binary32 batch with the error of every ring against the
+    binary64 batch (bit-identical to the oracle ring by ring)."""
+    import numpy as np
+    import torch
+
+    from paper_2307_01117_amd import heat, inputs
+    specs = inputs.batch_specs(count=count, seed=4)
+    cups = sum(s.N * s.nt for s in specs)
+    stream = torch.cuda.current_stream()
+    u0 = [torch.from_numpy(inputs.ring_initial(s)).cuda() for s in specs]
+    out = {"workload": f"batch_{count}_rings (N log-uniform [1e3, 1e6], nt uniform "
+                       "[100, 10000], r in (0.1, 0.5], U[0,1) per ring)",
+           "rings": count, "cell_updates": cups}
+    res = {}
+    for name, dt in (("fp64", torch.float64), ("fp32c", torch.float32)):
+        prec = heat.PRECISIONS[name]
+        us = [u.to(dt, copy=True) for u in u0]     # never an alias of the initial states
+        ws = [torch.empty_like(u) for u in us]
+        rings = [(u, w, s.nt, s.r, prec) for u, w, s in zip(us, ws, specs)]
+        heat.solve_batch_dev(rings, stream=stream)        # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            heat.solve_batch_dev(rings, stream=stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rec = {"value": round(cups * steps / el / 1e9, 1), "unit": "GCUP/s",
+               "ms_per_step": round(el * 1e3 / steps, 1)}
+        if name == "fp64":
+            # the same rings one by one with the plain device form
+            for u, w, s in zip(us, ws, specs):
+                heat.solve_dev(u, s.nparts, s.r, s.nt, precision=prec, stream=stream, work=w)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for u, w, s in zip(us, ws, specs):
+                heat.solve_dev(u, s.nparts, s.r, s.nt, precision=prec, stream=stream, work=w)
+            torch.cuda.synchronize()
+            plain_s = time.perf_counter() - t1
+            rec["plain_one_by_one"] = round(cups / plain_s / 1e9, 1)
+            rec["batched_vs_plain"] = round(rec["value"] / rec["plain_one_by_one"], 3)
+        # one pass from the initial states, kept for the error
+        for u, a in zip(us, u0):
+            u.copy_(a)
+        heat.solve_batch_dev(rings, stream=stream)
+        torch.cuda.synchronize()
+        res[name] = (rec, us)
+        del ws, rings
+    ref = res["fp64"][1]
+    errs = np.array([float((c.double() - f).abs().max() / f.abs().max())
+                     for c, f in zip(res["fp32c"][1], ref)])
+    out["fp64"] = res["fp64"][0]
+    out["fp32c"] = res["fp32c"][0]
+    out["fp32c"]["error_vs_fp64"] = {"rings": int(errs.size), "max": float(errs.max()),
+                                     "p99": float(np.percentile(errs, 99)),
+                                     "median": float(np.median(errs)),
+                                     "metric": "per ring max |x - y| / max |y|"}
+    out["fp32c"]["vs_fp64_batched"] = round(out["fp32c"]["value"] / out["fp64"]["value"], 3)
+    return out
+
+
+def sub_serve(args, rate=200.0, duration=15.0, warm_s=2.0):
+    """A short serving run in the default line (200 requests/s for 15 s)."""
+    return serve_rate(rate, duration, warm_s, check_every=23)
 
 
 def bench_batch(args):
@@ -464,79 +628,123 @@ def bench_batch(args):
     }), flush=True)
 
 
-def bench_serve(args):
-    """Serving form: Poisson arrivals of heat-solve requests (N log-uniform in
-    [1e3, 1e7], nt uniform in [100, 5000], r in (0.1, 0.5], FP64 or
-    compensated FP32 with probability 1/2) into one continuous-batching
-    server.  Latency = completion - scheduled arrival.  One JSON line per rate."""
+_SERVE_POOL = None
+
+
+def serving_pool():
+    """Pinned host pool the requests take their initial states from:
+    u0[i] = pool[(off + i) mod P] as one contiguous slice (the pool's first
+    10 million values are repeated at its end), plus a pinned sink for the
+    results that are not checked."""
+    global _SERVE_POOL
+    if _SERVE_POOL is None:
+        import torch
+
+        from paper_2307_01117_amd import inputs
+        P, nmax = 1 << 24, 10_000_000
+        pool = torch.empty(P + nmax, dtype=torch.float64, pin_memory=True).numpy()
+        pool[:P] = inputs.serving_pool(P)
+        pool[P:] = pool[:nmax]
+        sink = torch.empty(nmax, dtype=torch.float64, pin_memory=True).numpy()
+        _SERVE_POOL = (pool, sink, P)
+    return _SERVE_POOL
+
+
+def serve_rate(rate, duration, warm_s, check_every=97):
+    """Poisson arrivals of heat-solve requests (N log-uniform in [1e3, 1e7],
+    nt uniform in [100, 5000], r in (0.1, 0.5], FP64 or compensated FP32 with
+    probability 1/2) into one continuous-batching server for `duration`
+    seconds.  Latency = completion - scheduled arrival.  Every
+    `check_every`-th request keeps its own result, which is compared with the
+    same request solved alone (same precision: bitwise) and, for compensated
+    FP32 requests, with the request solved alone in binary64 (error)."""
     import numpy as np
     import torch
 
     from paper_2307_01117_amd import heat, inputs
-    P = 1 << 24
-    nmax = 10_000_000
-    pool = torch.empty(P + nmax, dtype=torch.float64, pin_memory=True).numpy()
-    pool[:P] = inputs.serving_pool(P)
-    pool[P:] = pool[:nmax]           # u0[i] = pool[(off + i) mod P] as one contiguous slice
-    sink = torch.empty(nmax, dtype=torch.float64, pin_memory=True).numpy()
+    pool, sink, P = serving_pool()
+    trace = inputs.serving_trace(rate, duration, pool_size=P)
+    server = heat.Server()
+    submitted = []          # (req, ticket, t_submit_rel, checked)
+    rejected = 0
+    t0 = time.perf_counter()
+    for k, q in enumerate(trace):
+        delay = t0 + q.t_arrival - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        u0 = pool[q.offset:q.offset + q.N]
+        check = k % check_every == 0
+        out = np.empty(q.N) if check else sink[:q.N]
+        try:
+            t = server.submit(u0, q.nt, q.r, q.precision, out=out)
+        except heat.HeatError as e:
+            if e.code != heat.HEAT_EBUSY:
+                raise
+            rejected += 1
+            continue
+        submitted.append((q, t, time.perf_counter() - t0, check))
+    results = [(q, server.wait(t), ts, check) for (q, t, ts, check) in submitted]
+    t_end = time.perf_counter() - t0
+    stats = server.stats()
+    server.close()
+    lat = []
+    cups = 0
+    for q, res, ts, _ in results:
+        cups += q.N * q.nt
+        if q.t_arrival >= warm_s:
+            lat.append((ts - q.t_arrival) + res.latency_s)
+    lat = np.sort(np.array(lat)) if lat else np.array([float("nan")])
+    # alone vs in the mix, and the compensated requests' error against binary64
+    same = total = 0
+    errs = []
+    for q, res, _, check in results:
+        if not check:
+            continue
+        dt = torch.float64 if q.precision == heat.FP64 else torch.float32
+        src = torch.from_numpy(pool[q.offset:q.offset + q.N]).to("cuda")
+        d = src.to(dt)
+        heat.solve_dev(d, 1, q.r, q.nt, precision=q.precision)
+        total += 1
+        same += int(np.array_equal(d.double().cpu().numpy().view(np.uint64),
+                                   res.u.view(np.uint64)))
+        if q.precision == heat.FP32C:
+            heat.solve_dev(src, 1, q.r, q.nt, precision=heat.FP64)
+            got = torch.from_numpy(res.u).to("cuda")
+            errs.append(float((got - src).abs().max() / src.abs().max()))
+            del got
+        del src, d
+    offered = sum(q.N * q.nt for q in trace) / duration / 1e9
+    return {
+        "rate_req_s": rate, "value": round(cups / t_end / 1e9, 3), "unit": "GCUP/s",
+        "duration_s": duration, "requests": len(trace), "completed": len(results),
+        "rejected_busy": rejected,
+        "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+        "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+        "latency_max_s": round(float(lat[-1]), 4),
+        "latency_from_s": warm_s,
+        "offered_GCUPs": round(offered, 1), "wall_s": round(t_end, 2),
+        "ticks": stats["ticks"], "hbm_peak_GB": round(stats["hbm_peak"] / 1e9, 2),
+        "alone_vs_mix_bitwise": f"{same}/{total}",
+        "fp32c_error_vs_fp64": {
+            "requests": len(errs),
+            "max": max(errs) if errs else None,
+            "p99": float(np.percentile(errs, 99)) if errs else None,
+            "metric": "per checked request max |x - y| / max |y|, y the request solved "
+                      "alone in binary64"},
+        "config": {"workload": "poisson_serving", "N": "log-uniform [1e3, 1e7]",
+                   "nt": "uniform [100, 5000]", "precision": "fp64 or fp32c (p = 1/2)",
+                   "checked": f"every {check_every}th request"},
+    }
+
+
+def bench_serve(args):
+    """Serving form: one JSON line per arrival rate (see serve_rate)."""
     for rate in [float(x) for x in args.rates.split(",")]:
-        trace = inputs.serving_trace(rate, args.duration, pool_size=P)
-        server = heat.Server()
-        submitted = []          # (req, ticket, t_submit_rel, private_out)
-        rejected = 0
-        t0 = time.perf_counter()
-        for k, q in enumerate(trace):
-            delay = t0 + q.t_arrival - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            u0 = pool[q.offset:q.offset + q.N]
-            check = k % 97 == 0
-            out = np.empty(q.N) if check else sink[:q.N]
-            try:
-                t = server.submit(u0, q.nt, q.r, q.precision, out=out)
-            except heat.HeatError as e:
-                if e.code != heat.HEAT_EBUSY:
-                    raise
-                rejected += 1
-                continue
-            submitted.append((q, t, time.perf_counter() - t0, check))
-        results = [(q, server.wait(t), ts, check) for (q, t, ts, check) in submitted]
-        t_end = time.perf_counter() - t0
-        stats = server.stats()
-        server.close()
-        lat = []
-        cups = 0
-        for q, res, ts, _ in results:
-            cups += q.N * q.nt
-            if q.t_arrival >= args.warm_s:
-                lat.append((ts - q.t_arrival) + res.latency_s)
-        lat = np.sort(np.array(lat)) if lat else np.array([float("nan")])
-        # alone vs in the mix, on every 97th request
-        same = total = 0
-        for q, res, _, check in results:
-            if not check:
-                continue
-            dt = torch.float64 if q.precision == heat.FP64 else torch.float32
-            d = torch.from_numpy(pool[q.offset:q.offset + q.N]).to("cuda", dtype=dt)
-            heat.solve_dev(d, 1, q.r, q.nt, precision=q.precision)
-            total += 1
-            same += int(np.array_equal(d.double().cpu().numpy(), res.u))
-        offered = sum(q.N * q.nt for q in trace) / args.duration / 1e9
-        print(json.dumps({
-            "metric": "serving: p50/p99 latency and GCUP/s", "rate_req_s": rate,
-            "value": round(cups / t_end / 1e9, 3), "unit": "GCUP/s", "n_gpus": 1,
-            "duration_s": args.duration, "requests": len(trace), "completed": len(results),
-            "rejected_busy": rejected,
-            "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
-            "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
-            "latency_max_s": round(float(lat[-1]), 4),
-            "offered_GCUPs": round(offered, 1), "wall_s": round(t_end, 2),
-            "ticks": stats["ticks"], "hbm_peak_GB": round(stats["hbm_peak"] / 1e9, 2),
-            "alone_vs_mix_bitwise": f"{same}/{total}",
-            "higher_is_better": True, "data": "synthetic",
-            "config": {"workload": "poisson_serving", "N": "log-uniform [1e3, 1e7]",
-                       "nt": "uniform [100, 5000]", "precision": "fp64 or fp32c (p = 1/2)"},
-        }), flush=True)
+        o = serve_rate(rate, args.duration, args.warm_s)
+        line = {"metric": "serving: p50/p99 latency and GCUP/s", "n_gpus": 1,
+                "higher_is_better": True, "data": "synthetic"}
+        line.update(o)
+        print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -83,7 +83,8 @@ def build(verbose: bool = False) -> str:
         with ThreadPoolExecutor(jobs) as ex:
             list(ex.map(run, cmds))
         tmp = LIB + ".tmp"
-        run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp])
+        run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs,
+             "-L/opt/rocm/lib", "-lhsa-runtime64", "-o", tmp])
         os.replace(tmp, LIB)
     finally:
         shutil.rmtree(tmpdir, ignore_errors=True)

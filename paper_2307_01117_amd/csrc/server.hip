@@ -6,14 +6,21 @@
 // free, and advances every resident request together: each tick is a short
 // sequence of round launches (the batching form's k_batch_round) over all
 // active requests, so requests that arrive while others run join at the next
-// tick and their work shares the device.  Two copy threads, each with its
-// own stream, move request data host->device at admission and device->host
-// at completion, off the scheduler's path and past each other (measured on
-// MI355X with the serving mix: one thread for both directions saturated at
-// 3,700 GCUP/s, two at 5,050).  A request's rounds are exactly those it would run alone
-// (same T rule, same buffers, same order), so its result is bit-identical
-// alone and in any mix.
+// tick and their work shares the device.  Copy threads move request data
+// host->device at admission (one thread, its own stream) and device->host at
+// completion (STAGE_OUT_LANES threads), off the scheduler's path and past
+// each other (measured on MI355X with the serving mix: one thread for both
+// directions saturated at 3,700 GCUP/s, two at 5,050).  The device->host
+// copies are issued to the DMA engines through ROCr (a HIP copy to host
+// memory runs as a blit kernel on the compute units, beside the rounds):
+// each stage-out lane owns two pinned chunks and copies a result chunk by
+// chunk, the DMA of one chunk overlapping the host-side copy of the other.
+// A request's rounds are exactly those it would run alone (same T rule,
+// same buffers, same order), so its result is bit-identical alone and in
+// any mix.
 #include <hip/hip_runtime.h>
+#include <hsa/hsa.h>
+#include <hsa/hsa_ext_amd.h>
 
 #include <algorithm>
 #include <cmath>
@@ -113,6 +120,129 @@ constexpr int TABLE_GROUPS = 9;        // (precision, kernel class) round tables
 // keeps its class for life, and no class changes a result.
 constexpr int32_t SERVER_BUSY_SLOTS = 64;
 
+// ------------------------------------------------------- DMA stage-out
+// Device -> host copies on the DMA engines: hsa_amd_memory_async_copy with
+// the host's CPU agent as destination runs on an SDMA engine (ROCr keeps
+// blit kernels for copies within one agent).  Its destination must be memory
+// the GPU can reach, so results go through pinned chunks; the source must be
+// released to system scope first, which the completion event of a request's
+// last kernels does (hipEventReleaseToSystem).
+constexpr int STAGE_OUT_LANES = 2;
+constexpr size_t STAGE_OUT_CHUNK = size_t(8) << 20;
+constexpr int64_t DMA_WAIT_NS = int64_t(60) * 1000 * 1000 * 1000;   // a copy stuck this long fails
+
+struct DmaAgents {
+    hsa_agent_t gpu{}, cpu{};
+    bool gpu_found = false, cpu_found = false;
+    uint32_t bdf = 0, domain = 0;
+};
+
+static hsa_status_t find_agents(hsa_agent_t a, void *data) {
+    DmaAgents *d = (DmaAgents *)data;
+    hsa_device_type_t t;
+    if (hsa_agent_get_info(a, HSA_AGENT_INFO_DEVICE, &t) != HSA_STATUS_SUCCESS)
+        return HSA_STATUS_SUCCESS;
+    if (t == HSA_DEVICE_TYPE_CPU && !d->cpu_found) {
+        d->cpu = a;
+        d->cpu_found = true;
+    } else if (t == HSA_DEVICE_TYPE_GPU && !d->gpu_found) {
+        uint32_t bdf = 0, dom = 0;
+        if (hsa_agent_get_info(a, (hsa_agent_info_t)HSA_AMD_AGENT_INFO_BDFID, &bdf) ==
+                HSA_STATUS_SUCCESS &&
+            hsa_agent_get_info(a, (hsa_agent_info_t)HSA_AMD_AGENT_INFO_DOMAIN, &dom) ==
+                HSA_STATUS_SUCCESS &&
+            bdf == d->bdf && dom == d->domain) {
+            d->gpu = a;
+            d->gpu_found = true;
+        }
+    }
+    return HSA_STATUS_SUCCESS;
+}
+
+// One stage-out lane: two pinned chunks, a pinned landing spot for a
+// request's two sums, and a completion signal for each.
+struct OutLane {
+    char *buf[2] = {nullptr, nullptr};
+    double *sums = nullptr;
+    hsa_signal_t sig[2] = {{0}, {0}};
+    hsa_signal_t sig_sums = {0};
+    std::thread th;
+};
+
+static int hsa_fail(hsa_status_t st, const char *what) {
+    const char *msg = nullptr;
+    if (hsa_status_string(st, &msg) != HSA_STATUS_SUCCESS || !msg) msg = "unknown";
+    return fail(HEAT_EDEVICE, "%s: %s", what, msg);
+}
+
+// Start a DMA copy of n bytes from device memory to pinned host memory.
+static int dma_start(const DmaAgents &ag, void *dst, const void *src, size_t n,
+                     hsa_signal_t sig) {
+    hsa_signal_store_relaxed(sig, 1);
+    const hsa_status_t st = hsa_amd_memory_async_copy(dst, ag.cpu, src, ag.gpu, n, 0, nullptr, sig);
+    return st == HSA_STATUS_SUCCESS ? HEAT_OK : hsa_fail(st, "hsa_amd_memory_async_copy");
+}
+
+// Wait for a copy started by dma_start (bounded: a copy that does not end
+// within DMA_WAIT_NS fails instead of hanging the lane).
+static int dma_wait(hsa_signal_t sig) {
+    const auto t0 = std::chrono::steady_clock::now();
+    while (true) {
+        const hsa_signal_value_t v = hsa_signal_wait_scacquire(
+            sig, HSA_SIGNAL_CONDITION_LT, 1, 100 * 1000 * 1000, HSA_WAIT_STATE_BLOCKED);
+        if (v < 0) return fail(HEAT_EDEVICE, "DMA copy to host failed");
+        if (v == 0) return HEAT_OK;
+        if (std::chrono::duration_cast<std::chrono::nanoseconds>(
+                std::chrono::steady_clock::now() - t0).count() > DMA_WAIT_NS)
+            return fail(HEAT_EDEVICE, "DMA copy to host did not finish");
+    }
+}
+
+// Host memory the GPU can reach (pinned by hipHostMalloc or registered):
+// the DMA may write it directly.
+static bool gpu_reachable_host(const void *p) {
+    hipPointerAttribute_t a;
+    const hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();   // pageable memory: not an error here
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
+// Copy n bytes of device memory into a host array: straight into it when
+// the GPU can reach it, otherwise through the lane's two pinned chunks, the
+// DMA of chunk k+1 running while chunk k is copied out.
+static int dma_to_host(const DmaAgents &ag, OutLane &L, void *host, const void *dev, size_t n) {
+    if (n > 0 && gpu_reachable_host(host)) {
+        int rc = dma_start(ag, host, dev, n, L.sig[0]);
+        if (rc == HEAT_OK) rc = dma_wait(L.sig[0]);
+        return rc;
+    }
+    const size_t chunks = (n + STAGE_OUT_CHUNK - 1) / STAGE_OUT_CHUNK;
+    auto len = [&](size_t k) { return std::min(STAGE_OUT_CHUNK, n - k * STAGE_OUT_CHUNK); };
+    int rc = chunks > 0 ? dma_start(ag, L.buf[0], dev, len(0), L.sig[0]) : HEAT_OK;
+    bool next_in_flight = false;
+    for (size_t k = 0; rc == HEAT_OK && k < chunks; ++k) {
+        const int b = (int)(k & 1);
+        next_in_flight = false;
+        if (k + 1 < chunks) {
+            rc = dma_start(ag, L.buf[b ^ 1], (const char *)dev + (k + 1) * STAGE_OUT_CHUNK,
+                           len(k + 1), L.sig[b ^ 1]);
+            next_in_flight = rc == HEAT_OK;
+        }
+        const int rw = dma_wait(L.sig[b]);
+        if (rc == HEAT_OK) rc = rw;
+        if (rc == HEAT_OK) std::memcpy((char *)host + k * STAGE_OUT_CHUNK, L.buf[b], len(k));
+    }
+    // a failed wait may leave the next chunk's copy in flight: let it end
+    // before the lane's chunks are reused
+    if (rc != HEAT_OK && next_in_flight) {
+        for (int b = 0; b < 2; ++b) (void)dma_wait(L.sig[b]);
+    }
+    return rc;
+}
+
 }  // namespace heat
 
 using namespace heat;
@@ -127,7 +257,7 @@ struct heat_server {
     int device = 0;
     int32_t max_slots = 4096, max_queue = 65536, slots_used = 0;
     int32_t tick_steps = 0;   // 0: TICK_ROUNDS rounds per tick
-    hipStream_t compute = nullptr, copy_in = nullptr, copy_out = nullptr;
+    hipStream_t compute = nullptr, copy_in = nullptr;
     double *d_partial = nullptr;
     // round tables, double-buffered across ticks (TABLE_GROUPS groups each)
     size_t table_slot_bytes = 0;
@@ -136,7 +266,10 @@ struct heat_server {
     uint64_t tick = 0, next_ticket = 1;
     bool stop = false;
     int fatal = HEAT_OK;
-    std::thread sched, stager_in, stager_out;
+    std::thread sched, stager_in;
+    DmaAgents dma;
+    bool hsa_up = false;
+    OutLane out[STAGE_OUT_LANES];
     heat_server_stats st{};
 };
 
@@ -184,8 +317,9 @@ static void fail_all_locked(heat_server *s, int rc) {
 // directions overlap on the DMA engines, and a stage-out that waits for its
 // request's last round never holds up the next request's stage-in.  Each
 // loop drains its queue before it honours `stop`.
-static void stage_out_loop(heat_server *s) {
+static void stage_out_loop(heat_server *s, int lane) {
     (void)hipSetDevice(s->device);
+    OutLane &L = s->out[lane];
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
         s->cv_out.wait(lk, [&] { return s->stop || !s->d2h.empty(); });
@@ -194,21 +328,28 @@ static void stage_out_loop(heat_server *s) {
         s->d2h.pop_front();
         lk.unlock();
         const int64_t N = q->ring.N;
+        int rc = HEAT_OK;
         hipError_t e = hipEventSynchronize(q->fin);
-        double sums[2] = {0.0, 0.0};
+        if (e != hipSuccess) rc = fail_hip(e, "server stage-out (wait for the last round)");
         // FP32 forms were widened exactly into the scratch buffer
         const void *src = q->ring.precision == HEAT_FP64 ? q->ring.d_u : q->ring.d_work;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(q->p->u_out, src, (size_t)N * 8, hipMemcpyDeviceToHost, s->copy_out);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(sums, q->d_sums, sizeof sums, hipMemcpyDeviceToHost, s->copy_out);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->copy_out);
+        bool sums_in_flight = false;
+        if (rc == HEAT_OK) {
+            rc = dma_start(s->dma, L.sums, q->d_sums, 2 * sizeof(double), L.sig_sums);
+            sums_in_flight = rc == HEAT_OK;
+        }
+        if (rc == HEAT_OK) rc = dma_to_host(s->dma, L, q->p->u_out, src, (size_t)N * 8);
+        if (sums_in_flight) {
+            const int rw = dma_wait(L.sig_sums);
+            if (rc == HEAT_OK) rc = rw;
+        }
+        const std::string msg = rc ? heat_last_error() : "";
         lk.lock();
-        if (e == hipSuccess) {
+        if (rc == HEAT_OK) {
             // sums of the stored offsets, plus N*shift for the shifted forms
             const double base = q->ring.precision == HEAT_FP64 ? 0.0 : (double)N * q->shift;
-            q->p->sum0 = base + sums[0];
-            q->p->sum_nt = base + sums[1];
+            q->p->sum0 = base + L.sums[0];
+            q->p->sum_nt = base + L.sums[1];
             q->p->status = HEAT_OK;
             q->p->latency_s =
                 std::chrono::duration<double>(Clock::now() - q->t_submit).count();
@@ -217,7 +358,8 @@ static void stage_out_loop(heat_server *s) {
             finish_locked(s, q, DONE, HEAT_OK);
         } else {
             q->p->status = HEAT_EDEVICE;
-            finish_locked(s, q, FAILED, fail_hip(e, "server stage-out"));
+            (void)fail(HEAT_EDEVICE, "server stage-out: %s", msg.c_str());
+            finish_locked(s, q, FAILED, HEAT_EDEVICE);
         }
     }
 }
@@ -371,7 +513,9 @@ static void sched_loop(heat_server *s) {
             if (e == hipSuccess && q->ring.precision != HEAT_FP64)
                 e = launch_f32_to_f64((const float *)q->ring.d_u, (double *)q->ring.d_work,
                                       q->ring.N, s->compute, q->shift);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&q->fin, hipEventDisableTiming);
+            // system-scope release: the DMA engines read the result from memory
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&q->fin, hipEventDisableTiming | hipEventReleaseToSystem);
             if (e == hipSuccess) e = hipEventRecord(q->fin, s->compute);
             if (e != hipSuccess && !rc) rc = fail_hip(e, "server complete");
         }
@@ -400,6 +544,52 @@ static void sched_loop(heat_server *s) {
     }
 }
 
+// DMA agents of the server's device and the stage-out lanes' pinned chunks
+// and signals (ROCr is initialised here and shut down in release_out_lanes;
+// ROCr counts its initialisations, HIP holds its own).
+static int setup_out_lanes(heat_server *s) {
+    hipDeviceProp_t prop;
+    HEAT_HIP(hipGetDeviceProperties(&prop, s->device));
+    s->dma.bdf = ((uint32_t)prop.pciBusID << 8) | ((uint32_t)prop.pciDeviceID << 3);
+    s->dma.domain = (uint32_t)prop.pciDomainID;
+    hsa_status_t st = hsa_init();
+    if (st != HSA_STATUS_SUCCESS) return hsa_fail(st, "hsa_init");
+    s->hsa_up = true;
+    st = hsa_iterate_agents(find_agents, &s->dma);
+    if (st != HSA_STATUS_SUCCESS) return hsa_fail(st, "hsa_iterate_agents");
+    if (!s->dma.gpu_found || !s->dma.cpu_found)
+        return fail(HEAT_EDEVICE, "no ROCr agent for device %d (PCI %x:%x) or the host",
+                    s->device, s->dma.domain, s->dma.bdf);
+    for (OutLane &L : s->out) {
+        for (int b = 0; b < 2; ++b) {
+            HEAT_HIP(hipHostMalloc((void **)&L.buf[b], STAGE_OUT_CHUNK, hipHostMallocDefault));
+            if ((st = hsa_signal_create(0, 0, nullptr, &L.sig[b])) != HSA_STATUS_SUCCESS)
+                return hsa_fail(st, "hsa_signal_create");
+        }
+        HEAT_HIP(hipHostMalloc((void **)&L.sums, 2 * sizeof(double), hipHostMallocDefault));
+        if ((st = hsa_signal_create(0, 0, nullptr, &L.sig_sums)) != HSA_STATUS_SUCCESS)
+            return hsa_fail(st, "hsa_signal_create");
+    }
+    return HEAT_OK;
+}
+
+static void release_out_lanes(heat_server *s) {
+    for (OutLane &L : s->out) {
+        for (int b = 0; b < 2; ++b) {
+            if (L.buf[b]) (void)hipHostFree(L.buf[b]);
+            if (L.sig[b].handle) (void)hsa_signal_destroy(L.sig[b]);
+            L.buf[b] = nullptr;
+            L.sig[b].handle = 0;
+        }
+        if (L.sums) (void)hipHostFree(L.sums);
+        if (L.sig_sums.handle) (void)hsa_signal_destroy(L.sig_sums);
+        L.sums = nullptr;
+        L.sig_sums.handle = 0;
+    }
+    if (s->hsa_up) (void)hsa_shut_down();
+    s->hsa_up = false;
+}
+
 // ================================================================== C ABI
 
 extern "C" {
@@ -425,7 +615,7 @@ int heat_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t max_q
             if (e) (void)hipEventDestroy(e);
         if (s->compute) (void)hipStreamDestroy(s->compute);
         if (s->copy_in) (void)hipStreamDestroy(s->copy_in);
-        if (s->copy_out) (void)hipStreamDestroy(s->copy_out);
+        release_out_lanes(s);
         s->arena.destroy();
         delete s;
         return code;
@@ -443,8 +633,7 @@ int heat_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t max_q
         return bail(fail_hip(e, "hipStreamCreate"));
     if ((e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking)) != hipSuccess)
         return bail(fail_hip(e, "hipStreamCreate"));
-    if ((e = hipStreamCreateWithFlags(&s->copy_out, hipStreamNonBlocking)) != hipSuccess)
-        return bail(fail_hip(e, "hipStreamCreate"));
+    if ((rc = setup_out_lanes(s))) return bail(rc);
     if ((e = hipMalloc((void **)&s->d_partial, SUM_BLOCKS * sizeof(double))) != hipSuccess)
         return bail(fail_hip(e, "hipMalloc(partials)"));
     const size_t group = Arena::round((size_t)s->max_slots * sizeof(BatchRing)) +
@@ -463,7 +652,7 @@ int heat_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t max_q
     s->st.hbm_budget = budget;
     s->sched = std::thread(sched_loop, s);
     s->stager_in = std::thread(stage_in_loop, s);
-    s->stager_out = std::thread(stage_out_loop, s);
+    for (int i = 0; i < STAGE_OUT_LANES; ++i) s->out[i].th = std::thread(stage_out_loop, s, i);
     *out = s;
     return HEAT_OK;
 }
@@ -597,10 +786,10 @@ int heat_server_destroy(heat_server *s) {
     }
     if (s->sched.joinable()) s->sched.join();
     if (s->stager_in.joinable()) s->stager_in.join();
-    if (s->stager_out.joinable()) s->stager_out.join();
+    for (OutLane &L : s->out)
+        if (L.th.joinable()) L.th.join();
     (void)hipStreamSynchronize(s->compute);
     (void)hipStreamSynchronize(s->copy_in);
-    (void)hipStreamSynchronize(s->copy_out);
     for (auto &kv : s->reqs) {
         Req *q = kv.second;
         if (q->fin) (void)hipEventDestroy(q->fin);
@@ -614,7 +803,7 @@ int heat_server_destroy(heat_server *s) {
     for (hipEvent_t &e : s->table_ev) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(s->compute);
     (void)hipStreamDestroy(s->copy_in);
-    (void)hipStreamDestroy(s->copy_out);
+    release_out_lanes(s);
     s->arena.destroy();
     delete s;
     return HEAT_OK;

@@ -151,15 +151,40 @@ def test_host_batch_reports_bad_problem():
     assert ei.value.code == heat.HEAT_EINVAL
 
 
+def oracle_many(prec, u0s, rs, nts):
+    """The oracle on many rings at once, one host thread per ring (the C
+    oracle runs without the interpreter lock)."""
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(lambda a: oracle_for(prec, *a), zip(u0s, rs, nts)))
+
+
+_EQ_SPECS = inputs.batch_specs(count=96, seed=44, logn_hi=5.0, nt_hi=2000)
+_EQ_ORACLE = {}
+
+
+def eq_oracle(prec):
+    """Oracle results of the scaled-down batching workload, per precision
+    (computed once for the three batch modes)."""
+    if prec not in _EQ_ORACLE:
+        specs = _EQ_SPECS
+        _EQ_ORACLE[prec] = oracle_many(prec, [inputs.ring_initial(s) for s in specs],
+                                       [s.r for s in specs], [s.nt for s in specs])
+    return _EQ_ORACLE[prec]
+
+
 @pytest.mark.parametrize("mode", ["rounds", "graph", "persistent"])
 def test_device_batch_equals_alone(mode):
-    """Rings of the uneven batching workload (N log-uniform, nt uniform, r in
-    (0.1, 1/2]), scaled down: each ring in the batch equals the same ring
-    solved alone, bit for bit, in all three precisions."""
-    specs = inputs.batch_specs(count=96, seed=44, logn_hi=5.0, nt_hi=2000)
+    """Rings of the uneven batching workload (N log-uniform in [1e3, 1e5], nt
+    uniform in [100, 2000], r in (0.1, 1/2]) in all three precisions, in each
+    batch mode (one launch per round, the captured graph of those launches,
+    the persistent flag-synchronised launch): every ring bit for bit equal to
+    the oracle's result for it, and to the same ring solved alone."""
+    specs = _EQ_SPECS
     kw = dict(graph=mode == "graph", persistent=mode == "persistent")
     for prec, dt in ((heat.FP64, torch.float64), (heat.FP32, torch.float32),
                      (heat.FP32C, torch.float32)):
+        print(f"batch mode {mode}, precision {prec}: {len(specs)} rings", flush=True)
         us = [torch.from_numpy(inputs.ring_initial(s)).to("cuda", dtype=dt) for s in specs]
         alone = []
         for s, u in zip(specs, us):
@@ -169,8 +194,53 @@ def test_device_batch_equals_alone(mode):
         work = [torch.empty_like(u) for u in us]
         heat.solve_batch_dev([(u, w, s.nt, s.r, prec) for u, w, s in zip(us, work, specs)], **kw)
         torch.cuda.synchronize()
-        for s, u, a in zip(specs, us, alone):
-            assert same_bits(u.cpu().numpy(), a.cpu().numpy()), (prec, s.N, s.nt)
+        want = eq_oracle(prec)
+        for s, u, a, w in zip(specs, us, alone, want):
+            got = u.cpu().numpy()
+            assert same_bits(got, w), (mode, prec, s.N, s.nt)
+            assert same_bits(got, a.cpu().numpy()), (mode, prec, s.N, s.nt)
+
+
+@pytest.mark.parametrize("prec", [heat.FP64, heat.FP32C])
+def test_device_batch_persistent_long_rings(prec):
+    """The persistent flag-synchronised launch on rings of 1e6 to 3e6 cells
+    (hundreds to thousands of tiles, each waiting on its neighbours' epoch
+    counters every round) batched with short rings.  binary64: every ring
+    whole against the oracle's threaded segmented solver.  Compensated
+    binary32: every ring bit for bit equal to the ring solved alone (whose
+    kernels the oracle pins elsewhere) and, against the oracle's light cones,
+    the cells next to the first tile edges of the persistent kernel's
+    geometry (32-cell lanes, one wave per tile, the form's 64-step rounds:
+    halo 64, tiles of 64*32 - 2*64 = 1920 cells) and random cells."""
+    rng = np.random.default_rng(60 + prec)
+    Ns = [1_000_003, 3_000_017, 1_999_999, 777, 20_000]
+    nts = [640, 301, 1000, 999, 65] if prec == heat.FP64 else [130, 64, 199, 999, 65]
+    rs = [float(0.5 - 0.4 * rng.random()) for _ in Ns]
+    dt = torch.float64 if prec == heat.FP64 else torch.float32
+    u0s = [inputs.uniform_ring(N, (61, prec, k)) for k, N in enumerate(Ns)]
+    us = [torch.from_numpy(u).to("cuda", dtype=dt) for u in u0s]
+    work = [torch.empty_like(u) for u in us]
+    print(f"persistent long rings, precision {prec}", flush=True)
+    heat.solve_batch_dev([(u, w, nt, r, prec) for u, w, nt, r in zip(us, work, nts, rs)],
+                         persistent=True)
+    torch.cuda.synchronize()
+    for k, (N, nt, r, u0, u) in enumerate(zip(Ns, nts, rs, u0s, us)):
+        got = u.cpu().numpy()
+        if prec == heat.FP64:
+            want = oracle.solve_threads(u0, min(16, N), r, nt)
+            assert same_bits(got, want), (N, nt)
+            continue
+        a = torch.from_numpy(u0).to("cuda", dtype=dt)
+        heat.solve_dev(a, 1, r, nt, precision=prec)
+        assert same_bits(got, a.cpu().numpy()), (N, nt)
+        u32 = u0.astype(np.float32)
+        W = 64 * 32 - 2 * 64
+        cells = {0, N - 1} | {int(i) for i in rng.integers(0, N, 3)}
+        for t in (1, 2, 3):
+            cells.update({(t * W + d) % N for d in (-1, 0, 1)})
+        for i in sorted(cells):
+            want = np.float32(oracle.cone_f32c(u32, i, r, nt, 64))
+            assert same_bits(got[i:i + 1], np.array([want])), (N, nt, i)
 
 
 def test_device_batch_large_rings_sampled():

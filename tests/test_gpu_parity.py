@@ -8,6 +8,7 @@ the binary64 oracle.  Full-size rings are compared at sampled cells through
 the oracle's light-cone evaluation, which is bit-identical to the full ring.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -396,6 +397,30 @@ def test_ring_1e8_sampled(cfg):
     assert same_bits(got, want), idx[got != want][:10]
     assert abs(s0 - math.fsum(u0)) <= 1e-13 * abs(s0)
     assert abs(s1 - s0) <= 8 * 2.0 ** -53 * N * w["nt"]
+
+
+def test_ring_1e8_whole_vs_threaded_oracle():
+    """The headline workload (100 partitions x 1,000,000 cells, r = 1/2, 1,000
+    steps, Uniform[0,1) seed 1) in the launch configuration the benchmark
+    times, with its fused checksums: all 1e8 cells bit for bit against the
+    oracle's threaded segmented solver (one segment per host thread, ghost
+    cells through queues; bit-identical to the sequential oracle), about 20 s
+    of host time on 16 cores."""
+    w = inputs.WORKLOADS["ring_1e8"]
+    N = w["N"]
+    u0 = inputs.make_initial(w["init"], N, w["seed"])
+    d = dev(u0)
+    print("whole 1e8 ring: GPU pass", flush=True)
+    s0, s1 = heat.solve_dev(d, w["nparts"], w["r"], w["nt"], sums=True)
+    got = d.cpu().numpy()
+    del d
+    torch.cuda.empty_cache()
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    print(f"whole 1e8 ring: threaded oracle on {workers} threads", flush=True)
+    want = oracle.solve_threads(u0, workers, w["r"], w["nt"])
+    bad = np.flatnonzero(got.view(np.uint64) != want.view(np.uint64))
+    assert bad.size == 0, (bad.size, bad[:10])
+    assert abs(s1 - math.fsum(want)) <= 1e-13 * abs(s1)
 
 
 @pytest.mark.parametrize("ci", range(N_CFGS))
