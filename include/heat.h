@@ -23,11 +23,15 @@
  *                 one-sided differences; each is exact for neighbours within
  *                 a factor of 2).
  *   HEAT_FP32C -- binary32 storage; inside the kernels the state is the pair
- *                 (u, e) of binary32 numbers whose sum is the value, advanced
- *                 with a Fast2Sum (Kahan-style) compensated update in which e
- *                 diffuses too.  Steps are grouped into rounds of T steps
- *                 (T reported by heat_plan); at each round end the state is
- *                 folded to u := fl32(u + e).  Only u touches HBM.
+ *                 (u, e) of binary32 numbers whose sum is the value, and r is
+ *                 the pair fl32(r) + fl32(r - fl32(r)).  Each step adds the
+ *                 increment fl32(r)*L (L the Laplacian of u + e) to u and
+ *                 gathers its small parts in e (Kahan-style): the Fast2Sum
+ *                 error of that addition, the product's rounding error (an
+ *                 exact fma) and the coefficient's low part times L.  Steps
+ *                 are grouped into rounds of T steps (T reported by
+ *                 heat_plan); at each round end the state is folded to
+ *                 u := fl32(u + e).  Only u touches HBM.
  *
  * All functions are extern "C", thread-safe, never throw, and return one of
  * the heat_status codes.  After a negative return heat_last_error() gives a
@@ -357,9 +361,26 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
                   double *best_gcups);
 
 /*
+ * Batch autotuner: times every kernel class of the batching form (cells per
+ * lane 32 or 64, one wave per tile or 4 waves sharing a tile through LDS,
+ * as built for the precision) at every round length its window allows
+ * (the compensated form: its fixed length only) on a synthetic batch of
+ * rings of N cells (enough rings for about 3e7 cells, at most 4,096; 640
+ * steps each; one untimed and one timed pass, HIP events) and returns the
+ * fastest class in *K_out, *G_out, *T_out with its rate in GCUP/s (host
+ * pointers, any may be NULL).  If `install` is nonzero, heat_solve_batch,
+ * heat_solve_batch_dev and the server under load use that class for rings of
+ * N's decade and precision in this process.  Classes never change a result.
+ * Allocates and frees about 2 * 3e7 * 8 bytes of device memory.  Blocking.
+ */
+int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *K_out,
+                        int32_t *G_out, int32_t *T_out, double *best_gcups);
+
+/*
  * Save / load the planner's tuning table as text (one line per precision and
  * decade: "precision bucket K T waves form exchange"; a line of six columns
- * loads as lone waves, exchange HEAT_EXCHANGE_NONE).  A malformed line makes
+ * loads as lone waves, exchange HEAT_EXCHANGE_NONE; batch classes picked by
+ * heat_autotune_batch as lines "b precision bucket K G T").  A malformed line makes
  * heat_tune_load return HEAT_EINVAL and keeps the lines read before it.  The library also loads the
  * file named by the environment variable HEAT_TUNE_TABLE at first use.
  */

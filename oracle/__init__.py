@@ -53,7 +53,7 @@ def build(force: bool = True) -> str:
             o1, o2 = os.path.join(d, "oracle.o"), os.path.join(d, "simd.o")
             subprocess.check_call(["gcc", "-O2", *fp, "-pthread", "-c", "-o", o1, _SRC])
             subprocess.check_call(["gcc", "-O3", *fp, "-c", "-o", o2, _SRC_SIMD])
-            subprocess.check_call(["gcc", "-shared", "-pthread", "-o", tmp, o1, o2])
+            subprocess.check_call(["gcc", "-shared", "-pthread", "-o", tmp, o1, o2, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -81,9 +81,9 @@ def _load():
     lib.heat_oracle_solve_f32.restype = None
     lib.heat_oracle_cone_f32.argtypes = [p, i64, f]
     lib.heat_oracle_cone_f32.restype = f
-    lib.heat_oracle_solve_f32c.argtypes = [p, p, p, i64, f, i64, i64]
+    lib.heat_oracle_solve_f32c.argtypes = [p, p, p, i64, d, i64, i64]
     lib.heat_oracle_solve_f32c.restype = None
-    lib.heat_oracle_cone_f32c.argtypes = [p, i64, f, i64]
+    lib.heat_oracle_cone_f32c.argtypes = [p, i64, d, i64]
     lib.heat_oracle_cone_f32c.restype = f
     _lib = lib
     return lib
@@ -178,13 +178,13 @@ def solve_f32c(u0, r: float, nt: int, T: int, return_pair: bool = False):
     e = np.empty_like(a) if return_pair else None
     if a.size:
         _load().heat_oracle_solve_f32c(_ptr(a), _ptr(out), _ptr(e) if e is not None else None,
-                                       a.size, np.float32(r), int(nt), int(T))
+                                       a.size, float(r), int(nt), int(T))
     return (out, e) if return_pair else out
 
 
 def cone_f32c(u0, i: int, r: float, nt: int, T: int) -> np.float32:
     w = _f32(cone_window(np.asarray(u0), int(i), int(nt)))
-    return np.float32(_load().heat_oracle_cone_f32c(_ptr(w), int(nt), np.float32(r), int(T)))
+    return np.float32(_load().heat_oracle_cone_f32c(_ptr(w), int(nt), float(r), int(T)))
 
 
 # -------------------------------------------------------- mean-shifted storage
@@ -241,9 +241,34 @@ def np_solve_f32(u0, r: float, nt: int) -> np.ndarray:
     return a
 
 
+def fma32(a, b, c) -> np.ndarray:
+    """fl32(a*b + c) with one rounding (binary32 fused multiply-add), for
+    binary32 arrays: a*b is exact in binary64 (two 24-bit significands); the
+    binary64 sum s and its exact error err (TwoSum) give a*b + c = s + err
+    exactly, and rounding s to binary32 rounds the exact sum the same way
+    unless s lies exactly halfway between two binary32 neighbours and err is
+    not zero -- then the exact sum lies on err's side of that midpoint."""
+    a = np.asarray(a, dtype=np.float32)
+    b = np.asarray(b, dtype=np.float32)
+    c = np.asarray(c, dtype=np.float32)
+    p = a.astype(np.float64) * b.astype(np.float64)
+    c64 = c.astype(np.float64)
+    s = p + c64
+    bp = s - p
+    err = (p - (s - bp)) + (c64 - bp)
+    r = s.astype(np.float32)
+    r64 = r.astype(np.float64)
+    lo = np.nextafter(r, np.float32(-np.inf))
+    hi = np.nextafter(r, np.float32(np.inf))
+    tie_lo = (s == (r64 + lo.astype(np.float64)) * 0.5) & (err < 0)
+    tie_hi = (s == (r64 + hi.astype(np.float64)) * 0.5) & (err > 0)
+    return np.where(tie_lo, lo, np.where(tie_hi, hi, r))
+
+
 def np_solve_f32c(u0, r: float, nt: int, T: int) -> np.ndarray:
     u = _f32(u0).copy()
-    r = np.float32(r)
+    rh = np.float32(r)
+    rl = np.float32(float(r) - float(rh))
     done = 0
     while done < nt:
         s = min(T, nt - done)
@@ -251,10 +276,11 @@ def np_solve_f32c(u0, r: float, nt: int, T: int) -> np.ndarray:
         for _ in range(s):
             l, q = np.roll(u, 1), np.roll(u, -1)
             el, eq = np.roll(e, 1), np.roll(e, -1)
-            d = r * (((q - u) - (u - l)) + ((eq - e) - (e - el)))
-            y = d + e
-            t = u + y
-            e = y - (t - u)
+            L = ((q - u) - (u - l)) + ((eq - e) - (e - el))
+            d = rh * L
+            g = fma32(rh, L, -d)
+            t = u + d
+            e = (fma32(rl, L, g) + e) + (d - (t - u))
             u = t
         u = u + e
         done += s

@@ -33,14 +33,24 @@
  * differences (the flux form of the numerator of Eq. (heat:discrete)):
  *   - plain FP32:  new = c + r * ((q - c) - (c - l))   (all in binary32)
  *   - compensated FP32: the state is the unevaluated sum u + e of two binary32
- *     numbers.  One step is
- *         d  = r * (((q - c) - (c - l)) + ((eq - ec) - (ec - el)))
- *         y  = d + ec
- *         t  = c + y
- *         e' = y - (t - c)          (Fast2Sum error term of c + y)
+ *     numbers, and the coefficient is the unevaluated sum rh + rl of two
+ *     binary32 numbers, rh = fl32(r), rl = fl32(r - rh) (the difference taken
+ *     in binary64, where it is exact), so r is carried to about 2^-48
+ *     relative instead of 2^-25.  One step is
+ *         L  = ((q - c) - (c - l)) + ((eq - ec) - (ec - el))
+ *         d  = rh * L
+ *         g  = fma(rh, L, -d)       (the rounding error of rh * L, exact)
+ *         t  = c + d
+ *         e' = (fma(rl, L, g) + ec) + (d - (t - c))
  *         u' = t
- *     Steps are grouped into rounds of T steps; at the end of every round
- *     (and at the end of the run) u := fl32(u + e), e := 0.
+ *     where d - (t - c) is the Fast2Sum error term of c + d (exact when
+ *     |c| >= |d|) and fma is the binary32 fused multiply-add (one rounding).
+ *     So u' + e' = (u + e) + (rh + rl) * L up to the roundings of L and of
+ *     the small terms: the increment's small parts -- the coefficient's low
+ *     part, the rounding of the product and that of c + d -- gather in e
+ *     instead of being rounded away.  Steps are grouped into rounds of T
+ *     steps; at the end of every round (and at the end of the run)
+ *     u := fl32(u + e), e := 0.
  *
  * heat_oracle_solve_threads runs the segments as the paper's CPU codes do,
  * one thread each; heat_oracle_solve_threads_simd is the same with the
@@ -50,6 +60,7 @@
  * (N < 1 or nt < 0 do nothing); r is NOT range-checked, so unstable r can be
  * exercised as a negative control.
  */
+#include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -400,19 +411,33 @@ float heat_oracle_cone_f32(const float *w, int64_t nt, float r)
 
 /* ------------------------------------------------------ compensated FP32 */
 
+/* The coefficient as two binary32 numbers: rh = fl32(r), rl = fl32(r - rh). */
+static void split_r(double r, float *rh, float *rl)
+{
+    *rh = (float)r;
+    *rl = (float)(r - (double)*rh);
+}
+
+/* One compensated step of a cell: updates (*un, *en) from its values and
+ * its neighbours' (u and e at the old time level). */
+static void comp_cell(float l, float c, float q, float el, float ec, float eq, float rh,
+                      float rl, float *un, float *en)
+{
+    float L = ((q - c) - (c - l)) + ((eq - ec) - (ec - el));
+    float d = rh * L;
+    float g = fmaf(rh, L, -d);
+    float t = c + d;
+    *en = (fmaf(rl, L, g) + ec) + (d - (t - c));
+    *un = t;
+}
+
 /* One compensated step of the pair (u, e) on the ring. */
 static void step_ring_f32c(const float *u, const float *e, float *un, float *en,
-                           int64_t N, float r)
+                           int64_t N, float rh, float rl)
 {
     for (int64_t i = 0; i < N; ++i) {
         int64_t il = (i - 1 + N) % N, iq = (i + 1) % N;
-        float l = u[il], c = u[i], q = u[iq];
-        float el = e[il], ec = e[i], eq = e[iq];
-        float d = r * (((q - c) - (c - l)) + ((eq - ec) - (ec - el)));
-        float y = d + ec;
-        float t = c + y;
-        en[i] = y - (t - c);
-        un[i] = t;
+        comp_cell(u[il], u[i], u[iq], e[il], e[i], e[iq], rh, rl, &un[i], &en[i]);
     }
 }
 
@@ -423,11 +448,13 @@ static void step_ring_f32c(const float *u, const float *e, float *un, float *en,
  * e_out receives e of the last round, so that the unrounded pair can be
  * inspected.
  */
-void heat_oracle_solve_f32c(const float *u0, float *out, float *e_out, int64_t N, float r,
+void heat_oracle_solve_f32c(const float *u0, float *out, float *e_out, int64_t N, double r,
                             int64_t nt, int64_t T)
 {
     if (N < 1) return;
     if (T < 1) T = 1;
+    float rh, rl;
+    split_r(r, &rh, &rl);
     float *u = (float *)malloc((size_t)N * sizeof(float));
     float *e = (float *)calloc((size_t)N, sizeof(float));
     float *un = (float *)malloc((size_t)N * sizeof(float));
@@ -438,7 +465,7 @@ void heat_oracle_solve_f32c(const float *u0, float *out, float *e_out, int64_t N
         int64_t s = nt - done < T ? nt - done : T;
         for (int64_t i = 0; i < N; ++i) e[i] = 0.0f;
         for (int64_t k = 0; k < s; ++k) {
-            step_ring_f32c(u, e, un, en, N, r);
+            step_ring_f32c(u, e, un, en, N, rh, rl);
             float *t1 = u; u = un; un = t1;
             float *t2 = e; e = en; en = t2;
         }
@@ -459,9 +486,11 @@ void heat_oracle_solve_f32c(const float *u0, float *out, float *e_out, int64_t N
  * binary32 values centred on the cell.  Rounds of T steps as above; the fold
  * u := fl32(u + e) is applied to every still-exact cell of the window.
  */
-float heat_oracle_cone_f32c(const float *w, int64_t nt, float r, int64_t T)
+float heat_oracle_cone_f32c(const float *w, int64_t nt, double r, int64_t T)
 {
     if (T < 1) T = 1;
+    float rh, rl;
+    split_r(r, &rh, &rl);
     int64_t len = 2 * nt + 1;
     float *u = (float *)malloc((size_t)len * sizeof(float));
     float *e = (float *)calloc((size_t)len, sizeof(float));
@@ -474,15 +503,9 @@ float heat_oracle_cone_f32c(const float *w, int64_t nt, float r, int64_t T)
         for (int64_t j = 0; j < len; ++j) e[j] = 0.0f;
         for (int64_t k = 0; k < rs; ++k) {
             ++s;
-            for (int64_t j = s; j <= len - 1 - s; ++j) {
-                float l = u[j - 1], c = u[j], q = u[j + 1];
-                float el = e[j - 1], ec = e[j], eq = e[j + 1];
-                float d = r * (((q - c) - (c - l)) + ((eq - ec) - (ec - el)));
-                float y = d + ec;
-                float t = c + y;
-                en[j] = y - (t - c);
-                un[j] = t;
-            }
+            for (int64_t j = s; j <= len - 1 - s; ++j)
+                comp_cell(u[j - 1], u[j], u[j + 1], e[j - 1], e[j], e[j + 1], rh, rl, &un[j],
+                          &en[j]);
             float *t1 = u; u = un; un = t1;
             float *t2 = e; e = en; en = t2;
         }

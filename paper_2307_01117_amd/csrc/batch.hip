@@ -35,7 +35,13 @@ static int64_t batch_min_steps_per_round(int K, int G) {
     return K >= 64 ? 160 : 96;
 }
 
-int describe_ring(const heat_ring &g, BatchRing *out, int K, int G) {
+bool batch_class_exists(int precision, int K, int G) {
+    if (precision == HEAT_FP32C) return K == 32 && (G == 1 || G == 4);
+    if (precision != HEAT_FP64 && precision != HEAT_FP32) return false;
+    return (K == 32 && G == 1) || (K == 64 && (G == 1 || G == 4));
+}
+
+int describe_ring(const heat_ring &g, BatchRing *out, int K, int G, int T) {
     if (K == 0) K = batch_cells_per_lane(g.precision, g.N);
     if (G < 1 || G > 8 || (G > 1 && K < 16)) return fail(HEAT_EINVAL, "bad batch tile shape");
     // the deepest rounds this class's window allows
@@ -44,7 +50,8 @@ int describe_ring(const heat_ring &g, BatchRing *out, int K, int G) {
     // binary64/binary32 results do not depend on the round length; the
     // compensated form's fixed length is kept (and always fits)
     if (g.precision != HEAT_FP32C)
-        Ttarget = std::min(std::max(Ttarget, batch_min_steps_per_round(K, G)), Tmax);
+        Ttarget = std::min(T > 0 ? (int64_t)T : std::max(Ttarget, batch_min_steps_per_round(K, G)),
+                           Tmax);
     const int64_t Teff = balanced_steps_per_round(g.nt, Ttarget, g.precision);
     BatchRing R{};
     R.buf[0] = g.d_u;
@@ -71,6 +78,10 @@ int describe_ring(const heat_ring &g, BatchRing *out, int K, int G) {
 }
 
 int describe_ring_batch(const heat_ring &g, BatchRing *out) {
+    int tK = 0, tG = 0, tT = 0;
+    if (tuned_batch_class(g.N, g.precision, &tK, &tG, &tT) &&
+        batch_class_exists(g.precision, tK, tG) && describe_ring(g, out, tK, tG, tT) == HEAT_OK)
+        return HEAT_OK;
     const int K = batch_cells_per_lane(g.precision, g.N);
     int rc = describe_ring(g, out, K, 1);
     // the 4-wave classes: binary64 and binary32 at 64-cell lanes, compensated
@@ -307,6 +318,31 @@ int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
         p += L.device_bytes();
     }
     return HEAT_OK;
+}
+
+int batch_run_class(const heat_ring *rings, int32_t count, hipStream_t st, int K, int G, int T) {
+    if (count < 1) return HEAT_OK;
+    std::vector<BatchRing> rs((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        if (!batch_class_exists(rings[i].precision, K, G) ||
+            rings[i].precision != rings[0].precision)
+            return fail(HEAT_EINVAL, "no batch kernel class K %d G %d for precision %d", K, G,
+                        rings[i].precision);
+        int rc = describe_ring(rings[i], &rs[(size_t)i], K, G, T);
+        if (rc) return rc;
+    }
+    BatchLaunch L;
+    int rc = L.build(rs, rings[0].precision);
+    if (rc) return rc;
+    rc = device_pool_setup();
+    if (rc) return rc;
+    void *mem = nullptr;
+    HEAT_HIP(hipMallocAsync(&mem, L.device_bytes(), st));
+    rc = L.enqueue(mem, st, false, false);
+    const hipError_t e = hipStreamSynchronize(st);
+    (void)hipFreeAsync(mem, st);
+    if (!rc && e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");
+    return rc;
 }
 
 }  // namespace heat

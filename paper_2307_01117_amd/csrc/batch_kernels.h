@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchPlanDev plan) {
                 T *dst = reinterpret_cast<T *>(R.buf[(k + 1) & 1]);
                 const int64_t done = k * (int64_t)R.T;
                 const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
-                window_tile<P, K, FORM_ALTERNATING>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W,
+                window_tile<P, K, FORM_ALTERNATING>(src, dst, R.N, R.H, steps, R.r, b, R.W,
                                                     R.vec_ok != 0, lane);
             } else {
                 // copy-back round: the final state sits in buf[1]
@@ -194,7 +194,7 @@ k_batch_round(const BatchRing *__restrict__ rings, const int64_t *__restrict__ t
         T *dst = reinterpret_cast<T *>(R.buf[(kk + 1) & 1]);
         const int64_t done = (int64_t)kk * R.T;
         const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
-        window_tile<P, K, FORM>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0, lane);
+        window_tile<P, K, FORM>(src, dst, R.N, R.H, steps, R.r, b, R.W, R.vec_ok != 0, lane);
     } else {
         // copy-back round: after an odd number of rounds the state sits in buf[1]
         const T *src = reinterpret_cast<const T *>(R.buf[1]);
@@ -227,7 +227,7 @@ k_batch_round_x(const BatchRing *__restrict__ rings, const int64_t *__restrict__
         T *dst = reinterpret_cast<T *>(R.buf[(kk + 1) & 1]);
         const int64_t done = (int64_t)kk * R.T;
         const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
-        window_tile<P, K, FORM, true>(src, dst, R.N, R.H, steps, (T)R.r, b, R.W, R.vec_ok != 0,
+        window_tile<P, K, FORM, true>(src, dst, R.N, R.H, steps, R.r, b, R.W, R.vec_ok != 0,
                                       lane, nullptr, nullptr, 0, G, wave,
                                       reinterpret_cast<T *>(heat_batch_xlds));
     } else {

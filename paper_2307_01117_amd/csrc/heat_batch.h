@@ -20,10 +20,21 @@ int validate_ring(const heat_ring &g);
 // raised to the kernel class's minimum (binary64/binary32) and balanced into
 // equal rounds like the plain planner; K = 0 picks batch_cells_per_lane.
 // G > 1: G waves share each tile and swap edges through LDS (K >= 16).
-int describe_ring(const heat_ring &g, BatchRing *out, int K = 0, int G = 1);
-// Batching form's shape for a ring: 32- or 64-cell lanes, and for long
-// binary64 rings 4 waves per tile when that costs fewer wave-steps.
+// T > 0 (binary64/binary32): target round length instead of that rule
+// (capped by the window); the compensated form keeps its fixed length.
+int describe_ring(const heat_ring &g, BatchRing *out, int K = 0, int G = 1, int T = 0);
+// Batching form's shape for a ring: the class the batch autotuner picked for
+// the ring's precision and length decade (tune.hip), else 32- or 64-cell
+// lanes, and for long rings 4 waves per tile when that costs fewer
+// wave-steps.
 int describe_ring_batch(const heat_ring &g, BatchRing *out);
+// Whether a batch kernel class (precision, K, G) is built.
+bool batch_class_exists(int precision, int K, int G);
+// Advance the rings on st in one forced class (K, G, target round length
+// T), one launch per round; blocking.  For the batch autotuner.
+int batch_run_class(const heat_ring *rings, int32_t count, hipStream_t st, int K, int G, int T);
+// The batch autotuner's pick for (precision, length decade of N), if any.
+bool tuned_batch_class(int64_t N, int precision, int *K, int *G, int *T);
 
 // Rounds a ring advances in one scheduling step: its remaining rounds
 // (copy-back included), at most `cap` (0 = no cap) or, with tick_steps > 0,

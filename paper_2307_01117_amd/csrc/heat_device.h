@@ -240,22 +240,29 @@ __device__ __forceinline__ void window_step_bwd(T (&v)[K], T r) {
     }
 }
 
-// Compensated binary32 step of the pair (u, e): the Laplacian of u + e is
-// formed from the flux-form differences of both parts (each one-sided
-// difference formed once per sweep), then added to u with Fast2Sum so that
-// the rounding error of the addition is kept in e.
+// Compensated binary32 step of the pair (u, e).  The coefficient is the pair
+// r + rl (r = fl32 of the binary64 coefficient, rl = fl32 of the rest).  The
+// Laplacian L of u + e is formed from the flux-form differences of both
+// parts (each one-sided difference formed once per sweep); the increment
+// r*L goes to u with Fast2Sum, and the increment's small parts -- the
+// rounding error of r*L (exact through an fma), the coefficient's low part
+// times L, and the Fast2Sum error of c + r*L -- gather in e:
+//     d = r*L;  g = fma(r, L, -d);  t = c + d;
+//     e' = (fma(rl, L, g) + e) + (d - (t - c));  u' = t.
 __device__ __forceinline__ void comp_update(float &u, float &e, float dlu, float dru, float dle,
-                                            float dre, float r) {
+                                            float dre, float r, float rl) {
     const float c = u;
-    const float d = r * ((dru - dlu) + (dre - dle));
-    const float y = d + e;
-    const float t = c + y;
-    e = y - (t - c);
+    const float L = (dru - dlu) + (dre - dle);
+    const float d = r * L;
+    const float g = __builtin_fmaf(r, L, -d);
+    const float t = c + d;
+    e = (__builtin_fmaf(rl, L, g) + e) + (d - (t - c));
     u = t;
 }
 
 template <int K>
-__device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], float r) {
+__device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], float r,
+                                                 float rl) {
     float dlu = u[0] - from_prev(u[K - 1]);
     float dle = e[0] - from_prev(e[K - 1]);
     const float ru = from_next(u[0]);
@@ -264,14 +271,15 @@ __device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], f
     for (int j = 0; j < K; ++j) {
         const float dru = ((j + 1 < K) ? u[j + 1] : ru) - u[j];
         const float dre = ((j + 1 < K) ? e[j + 1] : re) - e[j];
-        comp_update(u[j], e[j], dlu, dru, dle, dre, r);
+        comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
         dlu = dru;
         dle = dre;
     }
 }
 
 template <int K>
-__device__ __forceinline__ void window_step_comp_bwd(float (&u)[K], float (&e)[K], float r) {
+__device__ __forceinline__ void window_step_comp_bwd(float (&u)[K], float (&e)[K], float r,
+                                                     float rl) {
     const float lu = from_prev(u[K - 1]);
     const float le = from_prev(e[K - 1]);
     float dru = from_next(u[0]) - u[K - 1];
@@ -280,7 +288,7 @@ __device__ __forceinline__ void window_step_comp_bwd(float (&u)[K], float (&e)[K
     for (int j = K - 1; j >= 0; --j) {
         const float dlu = u[j] - (j > 0 ? u[j - 1] : lu);
         const float dle = e[j] - (j > 0 ? e[j - 1] : le);
-        comp_update(u[j], e[j], dlu, dru, dle, dre, r);
+        comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
         dru = dlu;
         dre = dle;
     }
@@ -288,7 +296,8 @@ __device__ __forceinline__ void window_step_comp_bwd(float (&u)[K], float (&e)[K
 
 template <int K>
 __device__ __forceinline__ void window_step_comp_pp(const float (&u)[K], const float (&e)[K],
-                                                    float (&un)[K], float (&en)[K], float r) {
+                                                    float (&un)[K], float (&en)[K], float r,
+                                                    float rl) {
     const float ru = from_next(u[0]);
     const float re = from_next(e[0]);
     float dlu = u[0] - from_prev(u[K - 1]);
@@ -298,7 +307,7 @@ __device__ __forceinline__ void window_step_comp_pp(const float (&u)[K], const f
         const float dru = ((j + 1 < K) ? u[j + 1] : ru) - u[j];
         const float dre = ((j + 1 < K) ? e[j + 1] : re) - e[j];
         float a = u[j], b = e[j];
-        comp_update(a, b, dlu, dru, dle, dre, r);
+        comp_update(a, b, dlu, dru, dle, dre, r, rl);
         un[j] = a;
         en[j] = b;
         dlu = dru;

@@ -37,7 +37,7 @@ k_window(const typename P::T *__restrict__ src, typename P::T *__restrict__ dst,
     const int64_t part = blk * wpg + wave;
     const int64_t tile = XCHG ? blk : part;
     if (tile >= tiles) return;
-    window_tile<P, K, FORM, XCHG>(src, dst, N, H, steps, (typename P::T)r, tile * W, W,
+    window_tile<P, K, FORM, XCHG>(src, dst, N, H, steps, r, tile * W, W,
                                   vec_ok != 0, lane, part_in, part_out, part, wpg, wave,
                                   reinterpret_cast<typename P::T *>(heat_xlds));
 }

@@ -8,6 +8,11 @@
 // compensated form's round length is fixed outside the table, so tuning is
 // always result-neutral.  The autotuner times every candidate shape with HIP
 // events on a synthetic ring of the requested length and keeps the fastest.
+//
+// A second table holds the batching form's kernel class per (precision,
+// bucket): cells per lane K, waves per tile G and the target round length,
+// picked by the batch autotuner, which times every built class on a
+// synthetic batch of rings of one length.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +23,7 @@
 #include <mutex>
 #include <vector>
 
+#include "heat_batch.h"
 #include "heat_internal.h"
 
 namespace heat {
@@ -31,9 +37,14 @@ struct TuneEntry {
     int xchg;              // heat_exchange: 1 lone waves, 2 LDS exchange
 };
 
+struct BatchEntry {
+    int K = 0, G = 0, T = 0;   // K = 0: not tuned (the batching form's own rule)
+};
+
 struct TuneTable {
     std::mutex mu;
     TuneEntry e[3][NBUCKETS];
+    BatchEntry b[3][NBUCKETS];
     bool env_loaded = false;
     TuneTable() {
         for (int p = 0; p < 3; ++p)
@@ -62,6 +73,20 @@ int load_file(const char *path) {
     int n = 0, rc = HEAT_OK;
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
+        if (line[0] == 'b') {
+            // batch class: "b precision bucket K G T"
+            int p, b, K, G, T;
+            const int got = std::sscanf(line + 1, "%d %d %d %d %d", &p, &b, &K, &G, &T);
+            if (got != 5 || p < 0 || p > 2 || b < 0 || b >= NBUCKETS ||
+                !batch_class_exists(p, K, G) || T < 1 || (T % 4) || 3 * T > 64 * K) {
+                rc = fail(HEAT_EINVAL, "bad tuning table line: %s", line);
+                break;
+            }
+            std::lock_guard<std::mutex> lk(t.mu);
+            t.b[p][b] = BatchEntry{K, G, T};
+            ++n;
+            continue;
+        }
         int p, b, K, T, wpg, form, xchg = HEAT_EXCHANGE_NONE;
         const int got = std::sscanf(line, "%d %d %d %d %d %d %d", &p, &b, &K, &T, &wpg, &form, &xchg);
         if ((got != 6 && got != 7) || p < 0 || p > 2 || b < 0 || b >= NBUCKETS ||
@@ -93,6 +118,19 @@ void load_env_once() {
 }
 
 }  // namespace
+
+bool tuned_batch_class(int64_t N, int precision, int *K, int *G, int *T) {
+    if (precision < 0 || precision > 2) return false;
+    load_env_once();
+    TuneTable &t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    const BatchEntry &e = t.b[precision][bucket_of(N)];
+    if (e.K == 0) return false;
+    *K = e.K;
+    *G = e.G;
+    *T = e.T;
+    return true;
+}
 
 void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form, int *exchange) {
     load_env_once();
@@ -139,7 +177,110 @@ int heat_tune_save(const char *path) {
         for (int b = 0; b < NBUCKETS; ++b)
             std::fprintf(f, "%d %d %d %d %d %d %d\n", p, b, t.e[p][b].K, t.e[p][b].T, t.e[p][b].wpg,
                          t.e[p][b].form, t.e[p][b].xchg);
+    bool any = false;
+    for (int p = 0; p < 3; ++p)
+        for (int b = 0; b < NBUCKETS; ++b) {
+            const BatchEntry &e = t.b[p][b];
+            if (!e.K) continue;
+            if (!any)
+                std::fprintf(f, "# batch class: b precision bucket(log10 N) cells_per_lane "
+                                "waves_per_tile steps_per_round\n");
+            any = true;
+            std::fprintf(f, "b %d %d %d %d %d\n", p, b, e.K, e.G, e.T);
+        }
     std::fclose(f);
+    return HEAT_OK;
+}
+
+int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *K_out,
+                        int32_t *G_out, int32_t *T_out, double *best_gcups) {
+    if (precision != HEAT_FP64 && precision != HEAT_FP32 && precision != HEAT_FP32C)
+        return fail(HEAT_EINVAL, "unknown precision %d", precision);
+    if (N < 1 || N > (int64_t(1) << 30)) return fail(HEAT_EINVAL, "N out of range");
+    int rc = device_pool_setup();
+    if (rc) return rc;
+    // enough rings of N cells to hold about 3e7 cells (at most 4,096 rings)
+    const int64_t count = std::max<int64_t>(1, std::min<int64_t>(4096, (30000000 + N - 1) / N));
+    const int64_t nt = 640;   // whole rounds at T = 64, 128, 160, 320
+    hipStream_t st = nullptr;
+    HEAT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    const size_t es = storage_bytes(precision);
+    void *a = nullptr, *w = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (a) (void)hipFreeAsync(a, st);
+        if (w) (void)hipFreeAsync(w, st);
+        (void)hipStreamSynchronize(st);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamDestroy(st);
+    };
+    // the rings' states and scratch, each ring 256-byte aligned
+    const size_t ring_bytes = ((size_t)N * std::max<size_t>(es, 8) + 255) & ~size_t(255);
+    hipError_t e = hipMallocAsync(&a, ring_bytes * count, st);
+    if (e == hipSuccess) e = hipMallocAsync(&w, ring_bytes * count, st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail_hip(e, "batch autotune setup");
+    }
+    hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(256), 0, st, (double *)w,
+                       (int64_t)(ring_bytes * count / 8));
+    std::vector<heat_ring> rings((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        char *u = (char *)a + i * ring_bytes, *s2 = (char *)w + i * ring_bytes;
+        if (precision == HEAT_FP64)
+            e = hipMemcpyAsync(u, s2, (size_t)N * 8, hipMemcpyDeviceToDevice, st);
+        else
+            e = launch_f64_to_f32((const double *)s2, (float *)u, N, st);
+        if (e != hipSuccess) break;
+        rings[(size_t)i] = heat_ring{N, nt, 0.25, precision, 1, u, s2};
+    }
+    if (e != hipSuccess) {
+        cleanup();
+        return fail_hip(e, "batch autotune fill");
+    }
+    const int Ts_all[] = {64, 96, 128, 160, 192, 256, 320, 480, 640};
+    double best = -1.0;
+    int bK = 0, bG = 0, bT = 0;
+    for (int K : {32, 64})
+        for (int G : {1, 4})
+            for (int T : Ts_all) {
+                if (!batch_class_exists(precision, K, G)) continue;
+                if (precision == HEAT_FP32C && T != default_steps_per_round(N, precision)) continue;
+                if (3 * T > 64 * K) continue;
+                // one untimed pass, then one timed pass
+                rc = batch_run_class(rings.data(), (int32_t)count, st, K, G, T);
+                if (!rc) e = hipEventRecord(e0, st);
+                if (!rc && e == hipSuccess)
+                    rc = batch_run_class(rings.data(), (int32_t)count, st, K, G, T);
+                if (!rc && e == hipSuccess) e = hipEventRecord(e1, st);
+                if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (rc || e != hipSuccess) {
+                    cleanup();
+                    return rc ? rc : fail_hip(e, "batch autotune timing");
+                }
+                const double g = (double)count * (double)N * (double)nt / (ms * 1e-3) / 1e9;
+                if (g > best) {
+                    best = g;
+                    bK = K;
+                    bG = G;
+                    bT = T;
+                }
+            }
+    cleanup();
+    if (install && bK) {
+        TuneTable &t = table();
+        std::lock_guard<std::mutex> lk(t.mu);
+        t.b[precision][bucket_of(N)] = BatchEntry{bK, bG, bT};
+    }
+    if (K_out) *K_out = bK;
+    if (G_out) *G_out = bG;
+    if (T_out) *T_out = bT;
+    if (best_gcups) *best_gcups = best;
     return HEAT_OK;
 }
 

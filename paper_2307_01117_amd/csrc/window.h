@@ -107,26 +107,26 @@ enum RegForm { FORM_INPLACE = 1, FORM_PINGPONG = 2, FORM_ALTERNATING = 3 };
 // and e afterwards).
 template <class P, int K, int FORM>
 __device__ __forceinline__ void advance(typename P::T (&v)[K], typename P::T (&e)[K], int n,
-                                        typename P::T r) {
+                                        typename P::T r, typename P::T rl) {
     using T = typename P::T;
     if constexpr (P::COMP) {
         if constexpr (FORM == FORM_PINGPONG) {
             T v2[K], e2[K];
             int s = 0;
             for (; s + 2 <= n; s += 2) {
-                window_step_comp_pp<K>(v, e, v2, e2, r);
-                window_step_comp_pp<K>(v2, e2, v, e, r);
+                window_step_comp_pp<K>(v, e, v2, e2, r, rl);
+                window_step_comp_pp<K>(v2, e2, v, e, r, rl);
             }
-            if (s < n) window_step_comp<K>(v, e, r);
+            if (s < n) window_step_comp<K>(v, e, r, rl);
         } else if constexpr (FORM == FORM_ALTERNATING) {
             int s = 0;
             for (; s + 2 <= n; s += 2) {
-                window_step_comp<K>(v, e, r);
-                window_step_comp_bwd<K>(v, e, r);
+                window_step_comp<K>(v, e, r, rl);
+                window_step_comp_bwd<K>(v, e, r, rl);
             }
-            if (s < n) window_step_comp<K>(v, e, r);
+            if (s < n) window_step_comp<K>(v, e, r, rl);
         } else {
-            for (int s = 0; s < n; ++s) window_step_comp<K>(v, e, r);
+            for (int s = 0; s < n; ++s) window_step_comp<K>(v, e, r, rl);
         }
     } else {
         if constexpr (FORM == FORM_PINGPONG) {
@@ -218,7 +218,7 @@ __device__ __forceinline__ void exchange_take(T (&v)[K], const T *x, int buf, in
 template <class P, int K, int FORM, bool XCHG = false>
 __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ src,
                                             typename P::T *__restrict__ dst, int64_t N, int H,
-                                            int steps, typename P::T r, int64_t b, int64_t W,
+                                            int steps, double r64, int64_t b, int64_t W,
                                             bool vec_ok, int lane, double *part_in = nullptr,
                                             double *part_out = nullptr, int64_t part = 0,
                                             int G = 1, int w = 0,
@@ -226,6 +226,10 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
     using T = typename P::T;
     constexpr int WIN = 64 * K;
     constexpr int S = exchange_depth<K>();
+    // the coefficient in the storage type; the compensated form also carries
+    // the rest of the binary64 coefficient, rl = fl32(r64 - r)
+    const T r = (T)r64;
+    const T rl = P::COMP ? (T)(r64 - (double)r) : T(0);
     // this wave's window in tile coordinates: [off, off + WIN)
     const int64_t off = XCHG ? (int64_t)w * (WIN - 2 * S) : 0;
     const int64_t g0 = b - H + off;
@@ -255,19 +259,19 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
                 T v2[K], e2[K];
                 int s = 0;
                 for (; s + 2 <= steps; s += 2) {
-                    window_step_comp_pp<K>(v, e, v2, e2, r);
-                    window_step_comp_pp<K>(v2, e2, v, e, r);
+                    window_step_comp_pp<K>(v, e, v2, e2, r, rl);
+                    window_step_comp_pp<K>(v2, e2, v, e, r, rl);
                 }
-                if (s < steps) window_step_comp<K>(v, e, r);
+                if (s < steps) window_step_comp<K>(v, e, r, rl);
             } else if constexpr (FORM == FORM_ALTERNATING) {
                 int s = 0;
                 for (; s + 2 <= steps; s += 2) {
-                    window_step_comp<K>(v, e, r);
-                    window_step_comp_bwd<K>(v, e, r);
+                    window_step_comp<K>(v, e, r, rl);
+                    window_step_comp_bwd<K>(v, e, r, rl);
                 }
-                if (s < steps) window_step_comp<K>(v, e, r);
+                if (s < steps) window_step_comp<K>(v, e, r, rl);
             } else {
-                for (int s = 0; s < steps; ++s) window_step_comp<K>(v, e, r);
+                for (int s = 0; s < steps; ++s) window_step_comp<K>(v, e, r, rl);
             }
 #pragma unroll
             for (int j = 0; j < K; ++j) v[j] = v[j] + e[j];   // fold: u := fl32(u + e)
@@ -305,7 +309,7 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
         T *xe = xlds + 2 * G * 2 * S;
         int s = 0, buf = 0;
         for (; steps - s > S; s += S) {
-            advance<P, K, FORM>(v, e, S, r);
+            advance<P, K, FORM>(v, e, S, r, rl);
             exchange_part<K>(v, xu, buf, G, w, lane);
             if constexpr (P::COMP) exchange_part<K>(e, xe, buf, G, w, lane);
             __syncthreads();
@@ -313,7 +317,7 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
             if constexpr (P::COMP) exchange_take<K>(e, xe, buf, G, w, lane);
             buf ^= 1;
         }
-        advance<P, K, FORM>(v, e, steps - s, r);
+        advance<P, K, FORM>(v, e, steps - s, r, rl);
         if constexpr (P::COMP) {
 #pragma unroll
             for (int j = 0; j < K; ++j) v[j] = v[j] + e[j];   // fold: u := fl32(u + e)

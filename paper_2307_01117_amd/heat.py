@@ -34,6 +34,7 @@ EXPORTS = [
     "heat_poll", "heat_wait", "heat_cancel", "heat_server_get_stats", "heat_server_destroy",
     "heat_last_error", "heat_version", "heat_device_info", "heat_copy_dev",
     "heat_autotune", "heat_tune_save", "heat_tune_load", "heat_solve_dev_noalloc",
+    "heat_autotune_batch",
 ]
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # HEAT_NOALLOC_SCRATCH_BYTES
@@ -125,6 +126,7 @@ def load(path: str = LIB_PATH):
                               P(ctypes.c_size_t)], i32),
         "heat_copy_dev": ([vp, vp, ctypes.c_size_t, vp], i32),
         "heat_autotune": ([i32, i64, i32, P(heat_config), pd], i32),
+        "heat_autotune_batch": ([i32, i64, i32, P(i32), P(i32), P(i32), pd], i32),
         "heat_tune_save": ([ctypes.c_char_p], i32),
         "heat_tune_load": ([ctypes.c_char_p], i32),
     }
@@ -175,6 +177,18 @@ def autotune(precision: int, N: int, install: bool = True):
     _check(load().heat_autotune(int(precision), int(N), int(bool(install)), ctypes.byref(cfg),
                                 ctypes.byref(g)))
     return {f: getattr(cfg, f) for f, _ in heat_config._fields_}, g.value
+
+
+def autotune_batch(precision: int, N: int, install: bool = True):
+    """Time every batch kernel class on a batch of N-cell rings; returns
+    ({"cells_per_lane", "waves_per_tile", "steps_per_round"}, GCUP/s)."""
+    K, G, T = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    g = ctypes.c_double()
+    _check(load().heat_autotune_batch(int(precision), int(N), int(bool(install)),
+                                      ctypes.byref(K), ctypes.byref(G), ctypes.byref(T),
+                                      ctypes.byref(g)))
+    return {"cells_per_lane": K.value, "waves_per_tile": G.value,
+            "steps_per_round": T.value}, g.value
 
 
 def tune_save(path: str) -> None:

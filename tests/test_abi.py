@@ -222,3 +222,22 @@ def test_noalloc_size_limit_checked_on_host(lib):
         assert lib.heat_solve_dev_noalloc(fake, N, 1, 0.5, 10, prec, None, None) == heat.HEAT_EINVAL
         assert "static scratch" in heat.last_error()
     assert lib.heat_solve_dev_noalloc(None, 10, 1, 0.5, 10, heat.FP64, None, None) == heat.HEAT_EINVAL
+
+
+def test_tune_table_batch_lines(lib, tmp_path):
+    """Batch class lines ("b precision bucket K G T") load, are written back
+    by heat_tune_save, and a line naming a class that is not built is
+    refused.  (Bucket 9, rings of 1e9 cells and more, which no test runs.)"""
+    good = tmp_path / "good.txt"
+    good.write_text("b 0 9 64 4 256\nb 2 9 32 1 64\n")
+    heat.tune_load(str(good))
+    out = tmp_path / "out.txt"
+    heat.tune_save(str(out))
+    text = out.read_text()
+    assert "b 0 9 64 4 256" in text and "b 2 9 32 1 64" in text
+    for bad in ("b 2 9 64 1 64\n", "b 0 9 32 4 64\n", "b 0 9 64 1 66\n", "b 1 9 64 1 4000\n"):
+        f = tmp_path / "bad.txt"
+        f.write_text(bad)
+        with pytest.raises(heat.HeatError) as ei:
+            heat.tune_load(str(f))
+        assert ei.value.code == heat.HEAT_EINVAL

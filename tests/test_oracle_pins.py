@@ -344,6 +344,92 @@ def test_compensated_rounds_beat_plain_fp32():
         assert err <= 1e-6 and err < plain / 50, (T, err, plain)
 
 
+def test_compensated_carries_the_binary64_coefficient():
+    """Near the stability limit r = 1/2 on a rough field (Uniform[0,1)) the
+    high-frequency modes barely decay, so errors made in every step add up:
+    rounding the coefficient to binary32 once (r = 0.49999 is not a binary32
+    number) moves the binary64 solution by more than 1e-6, and so does plain
+    binary32 arithmetic.  The compensated form carries r as the pair
+    fl32(r) + fl32(r - fl32(r)) and gathers the rounding error of every
+    increment r*L in e, so it stays within 3e-7 of binary64 run with the
+    binary64 coefficient; a form that drops either correction (the
+    coefficient's low part, or the product's rounding error) fails."""
+    N, r, nt = 65536, 0.49999, 300
+    u0 = inputs.uniform_ring(N, 77).astype(np.float32)
+    want = oracle.solve(u0.astype(np.float64), r, nt)
+    scale = np.abs(want).max()
+
+    def rel(x):
+        return float(np.abs(np.asarray(x, dtype=np.float64) - want).max() / scale)
+
+    comp = rel(oracle.solve_f32c(u0, r, nt, 64))
+    assert comp <= 3e-7, comp
+    assert rel(oracle.np_solve_f32c(u0, r, nt, 64)) == comp
+    assert rel(oracle.solve(u0.astype(np.float64), float(np.float32(r)), nt)) > 1e-6
+    assert rel(oracle.solve_f32(u0, r, nt)) > 1e-6
+
+    # the two corrections, each dropped in turn (NumPy steppers of the same
+    # form otherwise): both lose the bound
+    def variant(keep_low, keep_product):
+        u, e = u0.copy(), np.zeros_like(u0)
+        rh = np.float32(r)
+        rl = np.float32(r - float(rh)) if keep_low else np.float32(0)
+        done = 0
+        while done < nt:
+            s = min(64, nt - done)
+            e[:] = 0
+            for _ in range(s):
+                l, q = np.roll(u, 1), np.roll(u, -1)
+                el, eq = np.roll(e, 1), np.roll(e, -1)
+                L = ((q - u) - (u - l)) + ((eq - e) - (e - el))
+                d = rh * L
+                g = oracle.fma32(rh, L, -d) if keep_product else np.zeros_like(d)
+                t = u + d
+                e = (oracle.fma32(rl, L, g) + e) + (d - (t - u))
+                u = t
+            u = u + e
+            done += s
+        return u
+
+    assert rel(variant(True, True)) == comp
+    assert rel(variant(False, True)) > 1e-6
+    assert rel(variant(True, False)) > 5e-7
+
+
+def test_fma32_is_correctly_rounded():
+    """The NumPy oracle's binary32 fused multiply-add against the C library's
+    fmaf (correctly rounded, one rounding) on random operands over a wide
+    range of magnitudes, and on sums that land exactly halfway between two
+    binary32 numbers in binary64 while the exact sum does not (where a plain
+    binary64 evaluation rounded to binary32 goes wrong)."""
+    import ctypes
+    import ctypes.util
+    libm = ctypes.CDLL(ctypes.util.find_library("m"))
+    libm.fmaf.argtypes = [ctypes.c_float] * 3
+    libm.fmaf.restype = ctypes.c_float
+    rng = np.random.default_rng(5)
+    n = 4000
+    a = (rng.standard_normal(n) * 2.0 ** rng.integers(-30, 30, n)).astype(np.float32)
+    b = (rng.standard_normal(n) * 2.0 ** rng.integers(-30, 30, n)).astype(np.float32)
+    c = (rng.standard_normal(n) * 2.0 ** rng.integers(-60, 60, n)).astype(np.float32)
+    # crafted: c in [1, 2), a*b = +-(2^-24 - 2^-70) * 2^k scaled to half an
+    # ulp of c: the binary64 sum is the midpoint, the exact sum lies below
+    # (above) it
+    m = 200
+    cc = (1.0 + rng.integers(0, 2 ** 23, m) * 2.0 ** -23).astype(np.float32)
+    aa = np.where(rng.random(m) < 0.5, 1.0, -1.0) * (1.0 + 2.0 ** -23)
+    bb = np.full(m, 2.0 ** -24 * (1.0 - 2.0 ** -23))
+    a = np.concatenate([a, aa.astype(np.float32)])
+    b = np.concatenate([b, bb.astype(np.float32)])
+    c = np.concatenate([c, cc])
+    got = oracle.fma32(a, b, c)
+    want = np.array([libm.fmaf(float(x), float(y), float(z)) for x, y, z in zip(a, b, c)],
+                    dtype=np.float32)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    naive = (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
+    assert not np.array_equal(naive[n:].view(np.uint32), want[n:].view(np.uint32))
+
+
 # ------------------------------------------------------------ mean-shifted binary32 storage
 
 def test_shifted_zero_is_plain():
