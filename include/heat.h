@@ -365,12 +365,16 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
  * lane 32 or 64, one wave per tile or 4 waves sharing a tile through LDS,
  * as built for the precision) at every round length its window allows
  * (the compensated form: its fixed length only) on a synthetic batch of
- * rings of N cells (enough rings for about 3e7 cells, at most 4,096; 640
- * steps each; one untimed and one timed pass, HIP events) and returns the
- * fastest class in *K_out, *G_out, *T_out with its rate in GCUP/s (host
- * pointers, any may be NULL).  If `install` is nonzero, heat_solve_batch,
- * heat_solve_batch_dev and the server under load use that class for rings of
- * N's decade and precision in this process.  Classes never change a result.
+ * rings whose lengths spread log-uniformly over N's decade (as many as hold
+ * about 3e7 cells, at most 4,096; step counts spread over [100, 7,680];
+ * one untimed and one timed pass, HIP events; 1 <= N < 1e8), beside the
+ * batching form's own rule (each ring in the class its length suggests), and
+ * returns the fastest class in *K_out, *G_out, *T_out with its rate in
+ * GCUP/s (host pointers, any may be NULL) -- or K = G = T = 0 when no class
+ * beats the rule by 3 % or more.  If `install` is nonzero, heat_solve_batch,
+ * heat_solve_batch_dev and the server under load use that class (or the
+ * rule) for rings of N's decade and precision in this process.  Classes
+ * never change a result.
  * Allocates and frees about 2 * 3e7 * 8 bytes of device memory.  Blocking.
  */
 int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *K_out,
@@ -380,7 +384,8 @@ int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *
  * Save / load the planner's tuning table as text (one line per precision and
  * decade: "precision bucket K T waves form exchange"; a line of six columns
  * loads as lone waves, exchange HEAT_EXCHANGE_NONE; batch classes picked by
- * heat_autotune_batch as lines "b precision bucket K G T").  A malformed line makes
+ * heat_autotune_batch as lines "b precision bucket K G T", where K = G = T = 0
+ * stands for the batching form's own rule).  A malformed line makes
  * heat_tune_load return HEAT_EINVAL and keeps the lines read before it.  The library also loads the
  * file named by the environment variable HEAT_TUNE_TABLE at first use.
  */

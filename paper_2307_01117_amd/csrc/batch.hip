@@ -82,6 +82,10 @@ int describe_ring_batch(const heat_ring &g, BatchRing *out) {
     if (tuned_batch_class(g.N, g.precision, &tK, &tG, &tT) &&
         batch_class_exists(g.precision, tK, tG) && describe_ring(g, out, tK, tG, tT) == HEAT_OK)
         return HEAT_OK;
+    return describe_ring_rule(g, out);
+}
+
+int describe_ring_rule(const heat_ring &g, BatchRing *out) {
     const int K = batch_cells_per_lane(g.precision, g.N);
     int rc = describe_ring(g, out, K, 1);
     // the 4-wave classes: binary64 and binary32 at 64-cell lanes, compensated
@@ -322,23 +326,43 @@ int batch_dev_enqueue(const heat_ring *rings, int32_t count, hipStream_t st,
 
 int batch_run_class(const heat_ring *rings, int32_t count, hipStream_t st, int K, int G, int T) {
     if (count < 1) return HEAT_OK;
-    std::vector<BatchRing> rs((size_t)count);
+    // K = 0: every ring in the class the rule picks for it (classes grouped
+    // as heat_solve_batch_dev groups them)
+    std::vector<BatchRing> groups[3];
     for (int32_t i = 0; i < count; ++i) {
-        if (!batch_class_exists(rings[i].precision, K, G) ||
-            rings[i].precision != rings[0].precision)
-            return fail(HEAT_EINVAL, "no batch kernel class K %d G %d for precision %d", K, G,
-                        rings[i].precision);
-        int rc = describe_ring(rings[i], &rs[(size_t)i], K, G, T);
+        if (rings[i].precision != rings[0].precision)
+            return fail(HEAT_EINVAL, "rings of one precision only");
+        BatchRing R;
+        int rc;
+        if (K == 0) {
+            rc = describe_ring_rule(rings[i], &R);
+        } else {
+            if (!batch_class_exists(rings[i].precision, K, G))
+                return fail(HEAT_EINVAL, "no batch kernel class K %d G %d for precision %d", K, G,
+                            rings[i].precision);
+            rc = describe_ring(rings[i], &R, K, G, T);
+        }
         if (rc) return rc;
+        groups[R.G > 1 ? 2 : (R.K == 64)].push_back(R);
     }
-    BatchLaunch L;
-    int rc = L.build(rs, rings[0].precision);
-    if (rc) return rc;
-    rc = device_pool_setup();
+    std::vector<BatchLaunch> launches;
+    size_t bytes = 0;
+    for (auto &g : groups) {
+        if (g.empty()) continue;
+        launches.emplace_back();
+        int rc = launches.back().build(g, rings[0].precision);
+        if (rc) return rc;
+        bytes += launches.back().device_bytes();
+    }
+    int rc = device_pool_setup();
     if (rc) return rc;
     void *mem = nullptr;
-    HEAT_HIP(hipMallocAsync(&mem, L.device_bytes(), st));
-    rc = L.enqueue(mem, st, false, false);
+    HEAT_HIP(hipMallocAsync(&mem, bytes, st));
+    char *p = (char *)mem;
+    for (BatchLaunch &L : launches) {
+        if (!rc) rc = L.enqueue(p, st, false, false);
+        p += L.device_bytes();
+    }
     const hipError_t e = hipStreamSynchronize(st);
     (void)hipFreeAsync(mem, st);
     if (!rc && e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");

@@ -28,10 +28,13 @@ int describe_ring(const heat_ring &g, BatchRing *out, int K = 0, int G = 1, int 
 // lanes, and for long rings 4 waves per tile when that costs fewer
 // wave-steps.
 int describe_ring_batch(const heat_ring &g, BatchRing *out);
+// The rule describe_ring_batch falls back to (no tuned class).
+int describe_ring_rule(const heat_ring &g, BatchRing *out);
 // Whether a batch kernel class (precision, K, G) is built.
 bool batch_class_exists(int precision, int K, int G);
-// Advance the rings on st in one forced class (K, G, target round length
-// T), one launch per round; blocking.  For the batch autotuner.
+// Advance the rings (all of one precision) on st in one forced class (K, G,
+// target round length T), or with K = 0 each in the class the rule picks;
+// one launch per round and class; blocking.  For the batch autotuner.
 int batch_run_class(const heat_ring *rings, int32_t count, hipStream_t st, int K, int G, int T);
 // The batch autotuner's pick for (precision, length decade of N), if any.
 bool tuned_batch_class(int64_t N, int precision, int *K, int *G, int *T);

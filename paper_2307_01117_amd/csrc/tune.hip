@@ -74,11 +74,12 @@ int load_file(const char *path) {
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
         if (line[0] == 'b') {
-            // batch class: "b precision bucket K G T"
+            // batch class: "b precision bucket K G T" ("... 0 0 0": the rule)
             int p, b, K, G, T;
             const int got = std::sscanf(line + 1, "%d %d %d %d %d", &p, &b, &K, &G, &T);
+            const bool rule = got == 5 && K == 0 && G == 0 && T == 0;
             if (got != 5 || p < 0 || p > 2 || b < 0 || b >= NBUCKETS ||
-                !batch_class_exists(p, K, G) || T < 1 || (T % 4) || 3 * T > 64 * K) {
+                (!rule && (!batch_class_exists(p, K, G) || T < 1 || (T % 4) || 3 * T > 64 * K))) {
                 rc = fail(HEAT_EINVAL, "bad tuning table line: %s", line);
                 break;
             }
@@ -192,16 +193,46 @@ int heat_tune_save(const char *path) {
     return HEAT_OK;
 }
 
+// Gain a tuned batch class must show over the rule on the synthetic batch.
+constexpr double BATCH_TUNE_MARGIN = 1.03;
+
 int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *K_out,
                         int32_t *G_out, int32_t *T_out, double *best_gcups) {
     if (precision != HEAT_FP64 && precision != HEAT_FP32 && precision != HEAT_FP32C)
         return fail(HEAT_EINVAL, "unknown precision %d", precision);
-    if (N < 1 || N > (int64_t(1) << 30)) return fail(HEAT_EINVAL, "N out of range");
+    if (N < 1 || N >= 100000000) return fail(HEAT_EINVAL, "N out of range (1 to 99,999,999)");
     int rc = device_pool_setup();
     if (rc) return rc;
-    // enough rings of N cells to hold about 3e7 cells (at most 4,096 rings)
-    const int64_t count = std::max<int64_t>(1, std::min<int64_t>(4096, (30000000 + N - 1) / N));
-    const int64_t nt = 640;   // whole rounds at T = 64, 128, 160, 320
+    // Rings whose lengths spread log-uniformly over N's decade [10^b,
+    // 10^(b+1)) (ring i of n: 10^(b + (i + 1/2)/n) cells), as many as hold
+    // about 3e7 cells (at most 4,096).  One length at the decade's low edge
+    // would favour tiles that happen to fit it (measured: tuned on rings of
+    // exactly 1e5 cells, the classes lost 8 % on the uneven 4,096-ring batch).
+    int b = 0;
+    for (int64_t x = 10; b < NBUCKETS - 1 && N >= x; x *= 10) ++b;
+    const double lo = (double)b;
+    std::vector<int64_t> lens;
+    {
+        const double mean = (std::pow(10.0, lo + 1) - std::pow(10.0, lo)) / std::log(10.0);
+        const int64_t n = std::max<int64_t>(1, std::min<int64_t>(4096, (int64_t)(3e7 / mean)));
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t len = std::max<int64_t>(1, (int64_t)std::pow(10.0, lo + (i + 0.5) / n));
+            lens.push_back(len);
+        }
+    }
+    const int64_t count = (int64_t)lens.size();
+    // Step counts spread over [100, 7,680] (ring i: the golden-ratio sequence
+    // frac(i * 0.618...) scaled): a batch's rings run different numbers of
+    // rounds, and one common count, or a short one, hides the halo work of
+    // deep rounds (measured: tuned over 640 steps the classes picked 640-step
+    // rounds that lost 8 % on the uneven 4,096-ring batch).
+    std::vector<int64_t> nts((size_t)count);
+    int64_t cups_nt = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const double f = std::fmod((double)i * 0.6180339887498949, 1.0);
+        nts[(size_t)i] = 100 + (int64_t)(f * (7680 - 100));
+        cups_nt += lens[(size_t)i] * nts[(size_t)i];
+    }
     hipStream_t st = nullptr;
     HEAT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     const size_t es = storage_bytes(precision);
@@ -216,9 +247,12 @@ int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *
         (void)hipStreamDestroy(st);
     };
     // the rings' states and scratch, each ring 256-byte aligned
-    const size_t ring_bytes = ((size_t)N * std::max<size_t>(es, 8) + 255) & ~size_t(255);
-    hipError_t e = hipMallocAsync(&a, ring_bytes * count, st);
-    if (e == hipSuccess) e = hipMallocAsync(&w, ring_bytes * count, st);
+    std::vector<size_t> off((size_t)count + 1, 0);
+    for (int64_t i = 0; i < count; ++i)
+        off[(size_t)i + 1] = off[(size_t)i] +
+                             (((size_t)lens[(size_t)i] * std::max<size_t>(es, 8) + 255) & ~size_t(255));
+    hipError_t e = hipMallocAsync(&a, off[(size_t)count], st);
+    if (e == hipSuccess) e = hipMallocAsync(&w, off[(size_t)count], st);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) {
@@ -226,30 +260,41 @@ int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *
         return fail_hip(e, "batch autotune setup");
     }
     hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(256), 0, st, (double *)w,
-                       (int64_t)(ring_bytes * count / 8));
+                       (int64_t)(off[(size_t)count] / 8));
     std::vector<heat_ring> rings((size_t)count);
     for (int64_t i = 0; i < count; ++i) {
-        char *u = (char *)a + i * ring_bytes, *s2 = (char *)w + i * ring_bytes;
+        char *u = (char *)a + off[(size_t)i], *s2 = (char *)w + off[(size_t)i];
+        const int64_t len = lens[(size_t)i];
         if (precision == HEAT_FP64)
-            e = hipMemcpyAsync(u, s2, (size_t)N * 8, hipMemcpyDeviceToDevice, st);
+            e = hipMemcpyAsync(u, s2, (size_t)len * 8, hipMemcpyDeviceToDevice, st);
         else
-            e = launch_f64_to_f32((const double *)s2, (float *)u, N, st);
+            e = launch_f64_to_f32((const double *)s2, (float *)u, len, st);
         if (e != hipSuccess) break;
-        rings[(size_t)i] = heat_ring{N, nt, 0.25, precision, 1, u, s2};
+        rings[(size_t)i] = heat_ring{len, nts[(size_t)i], 0.25, precision, 1, u, s2};
     }
     if (e != hipSuccess) {
         cleanup();
         return fail_hip(e, "batch autotune fill");
     }
+    // candidates: the rule (K = 0) first, then every built class at every
+    // round length its window allows
+    struct Cand {
+        int K, G, T;
+    };
+    std::vector<Cand> cands{{0, 0, 0}};
     const int Ts_all[] = {64, 96, 128, 160, 192, 256, 320, 480, 640};
-    double best = -1.0;
-    int bK = 0, bG = 0, bT = 0;
     for (int K : {32, 64})
         for (int G : {1, 4})
             for (int T : Ts_all) {
                 if (!batch_class_exists(precision, K, G)) continue;
                 if (precision == HEAT_FP32C && T != default_steps_per_round(N, precision)) continue;
                 if (3 * T > 64 * K) continue;
+                cands.push_back({K, G, T});
+            }
+    double best = -1.0, rule = -1.0;
+    int bK = 0, bG = 0, bT = 0;
+    for (const Cand &cd : cands) {
+                const int K = cd.K, G = cd.G, T = cd.T;
                 // one untimed pass, then one timed pass
                 rc = batch_run_class(rings.data(), (int32_t)count, st, K, G, T);
                 if (!rc) e = hipEventRecord(e0, st);
@@ -263,16 +308,23 @@ int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *
                     cleanup();
                     return rc ? rc : fail_hip(e, "batch autotune timing");
                 }
-                const double g = (double)count * (double)N * (double)nt / (ms * 1e-3) / 1e9;
+                const double g = (double)cups_nt / (ms * 1e-3) / 1e9;
+                if (K == 0) rule = g;
                 if (g > best) {
                     best = g;
                     bK = K;
                     bG = G;
                     bT = T;
                 }
-            }
+    }
     cleanup();
-    if (install && bK) {
+    // a class replaces the rule only if it is clearly faster on this batch
+    // (the synthetic batch stands in for real ones only roughly)
+    if (bK && best < BATCH_TUNE_MARGIN * rule) {
+        bK = bG = bT = 0;
+        best = rule;
+    }
+    if (install) {
         TuneTable &t = table();
         std::lock_guard<std::mutex> lk(t.mu);
         t.b[precision][bucket_of(N)] = BatchEntry{bK, bG, bT};

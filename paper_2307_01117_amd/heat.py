@@ -93,6 +93,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: run `python -m paper_2307_01117_amd.build`")
+    # torch (which supplies device memory and streams) ships its own HIP and
+    # ROCr runtimes under the same sonames as the ones the library links:
+    # loading torch first makes the library bind to those, so the process
+    # holds one runtime (loaded the other way round, torch's runtime finds
+    # no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     lib.heat_version.restype = ctypes.c_char_p
     built = lib.heat_version().decode().rsplit(" ", 1)[-1]

@@ -235,7 +235,14 @@ def test_tune_table_batch_lines(lib, tmp_path):
     heat.tune_save(str(out))
     text = out.read_text()
     assert "b 0 9 64 4 256" in text and "b 2 9 32 1 64" in text
-    for bad in ("b 2 9 64 1 64\n", "b 0 9 32 4 64\n", "b 0 9 64 1 66\n", "b 1 9 64 1 4000\n"):
+    # K = G = T = 0 restores the batching form's own rule (no line is saved)
+    rule = tmp_path / "rule.txt"
+    rule.write_text("b 0 9 0 0 0\nb 2 9 0 0 0\n")
+    heat.tune_load(str(rule))
+    heat.tune_save(str(out))
+    assert "b 0 9" not in out.read_text() and "b 2 9" not in out.read_text()
+    for bad in ("b 2 9 64 1 64\n", "b 0 9 32 4 64\n", "b 0 9 64 1 66\n", "b 1 9 64 1 4000\n",
+                "b 0 9 0 1 0\n"):
         f = tmp_path / "bad.txt"
         f.write_text(bad)
         with pytest.raises(heat.HeatError) as ei:
