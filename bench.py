@@ -73,9 +73,9 @@ def parse():
     ap.add_argument("--steps-per-round", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
     ap.add_argument("--register-form", type=int, default=0, choices=[0, 1, 2, 3])
-    ap.add_argument("--exchange", default="auto", choices=["auto", "none", "lds"],
+    ap.add_argument("--exchange", default="auto", choices=["auto", "none", "lds", "deep"],
                     help="waves of a workgroup: own tiles (none) or one shared tile with "
-                         "LDS edge exchanges (lds)")
+                         "LDS edge exchanges every K/4 steps (lds) or K/2 steps (deep)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time the library's plain streaming copy of the state instead "
@@ -435,7 +435,8 @@ def main():
     prec_name = args.precision or ("fp64" if args.workload != "ring_1e8_perturbed" else "fp32c")
     prec = heat.PRECISIONS[prec_name]
     kernel = {"auto": 0, "tb": heat.KERNEL_TB, "step": heat.KERNEL_STEP}[args.kernel]
-    exchange = {"auto": 0, "none": heat.EXCHANGE_NONE, "lds": heat.EXCHANGE_LDS}[args.exchange]
+    exchange = {"auto": 0, "none": heat.EXCHANGE_NONE, "lds": heat.EXCHANGE_LDS,
+                "deep": heat.EXCHANGE_LDS_DEEP}[args.exchange]
     cfg = dict(kernel=kernel, cells_per_lane=args.cells_per_lane,
                steps_per_round=args.steps_per_round, waves_per_group=args.waves_per_group,
                register_form=args.register_form, exchange=exchange)

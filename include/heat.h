@@ -75,12 +75,15 @@ enum heat_exchange {
     HEAT_EXCHANGE_AUTO = 0, /* planner decides (tuned table)                      */
     HEAT_EXCHANGE_NONE = 1, /* one tile per wavefront; windows overlap by the
                                halo only                                          */
-    HEAT_EXCHANGE_LDS = 2   /* one tile per workgroup: its waves hold adjacent
-                               windows that overlap by S = cells_per_lane / 4
-                               cells and swap S edge cells through LDS every S
-                               steps (a deep ghost-zone exchange between
-                               segments, Section 2); needs waves_per_group >= 2
-                               and cells_per_lane >= 16                         */
+    HEAT_EXCHANGE_LDS = 2,  /* one tile per workgroup: its waves hold adjacent
+                               windows that overlap by 2S cells, S =
+                               cells_per_lane / 4, and swap S edge cells through
+                               LDS every S steps (a deep ghost-zone exchange
+                               between segments, Section 2); needs
+                               waves_per_group >= 2 and cells_per_lane >= 16    */
+    HEAT_EXCHANGE_LDS_DEEP = 3 /* the same with S = cells_per_lane / 2: half as
+                               many exchanges for twice the overlap; needs
+                               waves_per_group >= 2 and cells_per_lane >= 8    */
 };
 
 /* Optional overrides for the planner; zero fields mean "choose". */
@@ -106,7 +109,8 @@ typedef struct heat_plan_info {
     int32_t waves_per_group;
     int32_t register_form;   /* 1 in-place, 2 ping-pong, 3 alternating (TB)      */
     int32_t exchange_steps;  /* S: steps between LDS edge exchanges of the
-                                waves of a tile; 0 = one tile per wave (TB)    */
+                                waves of a tile (K/4 or K/2); 0 = one tile per
+                                wave (TB)                                      */
     int64_t tile_cells;      /* W: output cells per tile (TB): 64*K - 2H for a
                                 lone wave, G*64*K - (G-1)*2S - 2H for G waves,
                                 H >= T the halo                                 */

@@ -59,7 +59,7 @@ int describe_ring(const heat_ring &g, BatchRing *out, int K, int G, int T) {
     R.N = g.N;
     R.H = (int32_t)halo_cells(Teff, g.precision, K);
     R.T = (int32_t)Teff;
-    R.W = window_tile_cells(K, R.H, G, G > 1);
+    R.W = window_tile_cells(K, R.H, G, G > 1 ? 4 : 0);
     R.tiles = (g.N + R.W - 1) / R.W;
     R.r = g.r;
     R.nt = g.nt;

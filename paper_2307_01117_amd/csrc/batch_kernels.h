@@ -227,7 +227,7 @@ k_batch_round_x(const BatchRing *__restrict__ rings, const int64_t *__restrict__
         T *dst = reinterpret_cast<T *>(R.buf[(kk + 1) & 1]);
         const int64_t done = (int64_t)kk * R.T;
         const int steps = (int)((R.nt - done) < R.T ? (R.nt - done) : R.T);
-        window_tile<P, K, FORM, true>(src, dst, R.N, R.H, steps, R.r, b, R.W, R.vec_ok != 0,
+        window_tile<P, K, FORM, 4>(src, dst, R.N, R.H, steps, R.r, b, R.W, R.vec_ok != 0,
                                       lane, nullptr, nullptr, 0, G, wave,
                                       reinterpret_cast<T *>(heat_batch_xlds));
     } else {
@@ -256,7 +256,7 @@ inline hipError_t launch_batch_round_t(const BatchRing *rings, const int64_t *ti
 template <class P, int K, int FORM>
 inline hipError_t launch_batch_round_x(const BatchRing *rings, const int64_t *tile_prefix, int k,
                                        int active, int64_t items, int G, hipStream_t st) {
-    const unsigned lds = (unsigned)exchange_lds_bytes<P>(K, G);
+    const unsigned lds = (unsigned)exchange_lds_bytes<P>(K, G, 4);
     hipLaunchKernelGGL((k_batch_round_x<P, K, FORM>), dim3((unsigned)items), dim3(64 * G), lds, st,
                        rings, tile_prefix, k, active, items);
     return hipGetLastError();

@@ -50,7 +50,8 @@ struct Plan {
     int H = 32;          // halo cells per side of a window (multiple of 4, >= T)
     int wpg = 4;         // wavefronts per workgroup
     int form = 3;        // TB register form: 1 in-place, 2 ping-pong, 3 alternating
-    bool xchg = false;   // TB: the workgroup's waves share a tile (LDS edge exchange)
+    int xd = 0;          // TB: 0 = a tile per wave; 4 or 2 = the workgroup's waves share a
+                         // tile and swap K/xd edge cells through LDS every K/xd steps
     int64_t W = 0;       // output cells per tile (TB) / cells per chunk (STEP)
     int64_t tiles = 0;   // tiles (TB) or chunks (STEP) per launch
     int64_t parts = 0;   // per-wave partial sums of a fused checksum (TB)
@@ -93,20 +94,22 @@ struct WindowLaunch {
     int steps = 0;
     double r = 0.0;
     int wpg = 2;
-    bool xchg = false;            // the wpg waves of a workgroup share one tile
+    int xd = 0;                   // 0: a tile per wave; 4 or 2: the wpg waves of a workgroup
+                                  // share one tile, exchange depth K/xd
     double *part_in = nullptr;    // per-wave sums of the input (first round), or NULL
     double *part_out = nullptr;   // per-wave sums of the output (last round), or NULL
 };
 hipError_t launch_window(const WindowLaunch &a, hipStream_t st);
 hipError_t launch_window_lone(const WindowLaunch &a, hipStream_t st);   // kernels.hip
 hipError_t launch_window_xchg(const WindowLaunch &a, hipStream_t st);   // kernels_xchg.hip
-// binary32, lone or exchanging waves as a.xchg says                  // kernels_f32.hip
+hipError_t launch_window_xchg2(const WindowLaunch &a, hipStream_t st);  // kernels_xchg2.hip
+// binary32, lone or exchanging waves as a.xd says                    // kernels_f32.hip
 hipError_t launch_window_fp32(const WindowLaunch &a, hipStream_t st);
-// compensated binary32, lone or exchanging waves as a.xchg says       // kernels_f32c.hip
+// compensated binary32, lone or exchanging waves as a.xd says         // kernels_f32c.hip
 hipError_t launch_window_fp32c(const WindowLaunch &a, hipStream_t st);
-// Output cells of one tile: 64K - 2H for a lone wave; for wpg cooperating
-// waves, wpg windows of 64K cells overlapping by 2*(K/4), minus 2H.
-int64_t window_tile_cells(int K, int H, int wpg, bool xchg);
+// Output cells of one tile: 64K - 2H for a lone wave (xd = 0); for wpg
+// cooperating waves, wpg windows of 64K cells overlapping by 2*(K/xd), minus 2H.
+int64_t window_tile_cells(int K, int H, int wpg, int xd);
 // Reduce `arrays` consecutive arrays of n partial sums each (partial[a*n, a*n + n))
 // into d_out[a], one workgroup per array, in one launch.
 hipError_t launch_sum_partials(const double *partial, int64_t n, int arrays, double *d_out,

@@ -201,18 +201,23 @@ __global__ void __launch_bounds__(256) k_copy(const v4u32 *__restrict__ src, v4u
 // ================================================================ LAUNCHERS
 
 
-int64_t window_tile_cells(int K, int H, int wpg, bool xchg) {
+int64_t window_tile_cells(int K, int H, int wpg, int xd) {
     const int64_t win = 64 * (int64_t)K;
-    if (!xchg) return win - 2 * (int64_t)H;
-    return wpg * win - (wpg - 1) * 2 * (int64_t)(K / 4) - 2 * (int64_t)H;
+    if (!xd) return win - 2 * (int64_t)H;
+    return wpg * win - (wpg - 1) * 2 * (int64_t)(K / xd) - 2 * (int64_t)H;
 }
 
 hipError_t launch_window(const WindowLaunch &a, hipStream_t st) {
-    return a.xchg ? launch_window_xchg(a, st) : launch_window_lone(a, st);
+    switch (a.xd) {
+        case 0: return launch_window_lone(a, st);
+        case 4: return launch_window_xchg(a, st);
+        case 2: return launch_window_xchg2(a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_window_lone(const WindowLaunch &a, hipStream_t st) {
-    return launch_window_any<false>(a, st);
+    return launch_window_any<0>(a, st);
 }
 
 hipError_t launch_sum_partials(const double *partial, int64_t n, int arrays, double *d_out,

@@ -13,7 +13,12 @@ namespace heat {
 
 hipError_t launch_window_fp32(const WindowLaunch &a, hipStream_t st) {
     if (a.precision != HEAT_FP32) return hipErrorInvalidValue;
-    return a.xchg ? launch_window_f<F32, true>(a, st) : launch_window_f<F32, false>(a, st);
+    switch (a.xd) {
+        case 0: return launch_window_f<F32, 0>(a, st);
+        case 4: return launch_window_f<F32, 4>(a, st);
+        case 2: return launch_window_f<F32, 2>(a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // The batch classes: in-place sweeps, 32-cell lanes, or 64-cell lanes for

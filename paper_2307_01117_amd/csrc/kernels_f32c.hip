@@ -14,7 +14,12 @@ namespace heat {
 
 hipError_t launch_window_fp32c(const WindowLaunch &a, hipStream_t st) {
     if (a.precision != HEAT_FP32C) return hipErrorInvalidValue;
-    return a.xchg ? launch_window_f<F32C, true>(a, st) : launch_window_f<F32C, false>(a, st);
+    switch (a.xd) {
+        case 0: return launch_window_f<F32C, 0>(a, st);
+        case 4: return launch_window_f<F32C, 4>(a, st);
+        case 2: return launch_window_f<F32C, 2>(a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // The batch classes: 32-cell lanes swept in place (under this file's

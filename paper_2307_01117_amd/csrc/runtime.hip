@@ -155,18 +155,20 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
         return fail(HEAT_EINVAL, "cells_per_lane must be 8, 16, 32 or 64 (got %d)", q.K);
     if (q.K == 64 && q.form == 2 && precision != HEAT_FP32)
         return fail(HEAT_EINVAL, "the ping-pong form holds at most 32 cells per lane here");
-    if (c.exchange < 0 || c.exchange > HEAT_EXCHANGE_LDS)
-        return fail(HEAT_EINVAL, "exchange must be 0, 1 or 2 (got %d)", c.exchange);
+    if (c.exchange < 0 || c.exchange > HEAT_EXCHANGE_LDS_DEEP)
+        return fail(HEAT_EINVAL, "exchange must be 0, 1, 2 or 3 (got %d)", c.exchange);
     int xchg = c.exchange ? c.exchange : default_exchange(N, precision);
-    // a tuned exchange that the overridden shape cannot use falls back to
-    // lone waves; an explicit request is checked
-    if (xchg == HEAT_EXCHANGE_LDS && (q.wpg < 2 || q.K < 16)) {
-        if (c.exchange == HEAT_EXCHANGE_LDS)
-            return fail(HEAT_EINVAL, "the LDS exchange needs waves_per_group >= 2 and "
-                        "cells_per_lane >= 16");
+    // exchange depth K/4 (LDS) or K/2 (LDS_DEEP), at least 4 cells, between
+    // at least 2 waves; a tuned exchange that the overridden shape cannot use
+    // falls back to lone waves, an explicit request is checked
+    const int xd = xchg == HEAT_EXCHANGE_LDS ? 4 : xchg == HEAT_EXCHANGE_LDS_DEEP ? 2 : 0;
+    if (xd && (q.wpg < 2 || q.K / xd < 4)) {
+        if (c.exchange == xchg)
+            return fail(HEAT_EINVAL, "the LDS exchange needs waves_per_group >= 2 and an "
+                        "exchange depth of at least 4 cells (cells_per_lane >= %d)", 4 * xd);
         xchg = HEAT_EXCHANGE_NONE;
     }
-    q.xchg = xchg == HEAT_EXCHANGE_LDS;
+    q.xd = xchg == HEAT_EXCHANGE_NONE ? 0 : xd;
     int T = c.steps_per_round ? c.steps_per_round : default_steps_per_round(N, precision);
     if (T < 1) return fail(HEAT_EINVAL, "steps_per_round must be >= 1 (got %d)", T);
     if (c.steps_per_round && (T % 4) != 0)
@@ -178,11 +180,11 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
         c.steps_per_round ? (nt > 0 ? std::min<int64_t>(T, nt) : 1) : planned_steps_per_round(N, nt, precision);
     q.T = (int)Teff;
     q.H = halo_cells(Teff, precision, q.K);
-    q.W = window_tile_cells(q.K, q.H, q.wpg, q.xchg);
+    q.W = window_tile_cells(q.K, q.H, q.wpg, q.xd);
     q.tiles = (N + q.W - 1) / q.W;
-    q.parts = q.xchg ? q.tiles * q.wpg : q.tiles;
+    q.parts = q.xd ? q.tiles * q.wpg : q.tiles;
     q.rounds = nt > 0 ? (nt + Teff - 1) / Teff : 0;
-    const int64_t threads = q.xchg ? q.tiles * q.wpg * 64 : q.tiles * 64;
+    const int64_t threads = q.xd ? q.tiles * q.wpg * 64 : q.tiles * 64;
     if (threads > MAX_GRID_THREADS)
         return fail(HEAT_EINVAL, "ring of %lld cells needs more than one launch's tiles at %d cells "
                     "per lane", (long long)N, q.K);
@@ -238,7 +240,7 @@ static int run_rounds(const Plan &pl, int precision, void *a, void *b, int64_t N
         w.H = pl.H;
         w.r = r;
         w.wpg = pl.wpg;
-        w.xchg = pl.xchg;
+        w.xd = pl.xd;
         int64_t done = 0;
         while (done < nt) {
             w.steps = (int)std::min<int64_t>(pl.T, nt - done);
@@ -633,7 +635,7 @@ int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
     out->steps_per_round = pl.T;
     out->waves_per_group = pl.wpg;
     out->register_form = pl.form;
-    out->exchange_steps = pl.kernel == HEAT_KERNEL_TB && pl.xchg ? pl.K / 4 : 0;
+    out->exchange_steps = pl.kernel == HEAT_KERNEL_TB && pl.xd ? pl.K / pl.xd : 0;
     out->tile_cells = pl.W;
     out->tiles = pl.tiles;
     out->rounds = pl.rounds;

@@ -94,8 +94,9 @@ int load_file(const char *path) {
             (K != 8 && K != 16 && K != 32 && K != 64) || T < 1 || (T % 4) || 3 * T > 64 * K ||
             wpg < 1 || wpg > 8 ||
             (K == 64 && form == 2 && p != HEAT_FP32) || form < 1 || form > 3 ||
-            (xchg != HEAT_EXCHANGE_NONE && xchg != HEAT_EXCHANGE_LDS) ||
-            (xchg == HEAT_EXCHANGE_LDS && (wpg < 2 || K < 16))) {
+            xchg < HEAT_EXCHANGE_NONE || xchg > HEAT_EXCHANGE_LDS_DEEP ||
+            (xchg == HEAT_EXCHANGE_LDS && (wpg < 2 || K < 16)) ||
+            (xchg == HEAT_EXCHANGE_LDS_DEEP && (wpg < 2 || K < 8))) {
             rc = fail(HEAT_EINVAL, "bad tuning table line: %s", line);
             break;
         }
@@ -378,14 +379,15 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
     heat_config bc{};
     for (int K : {8, 16, 32, 64})
         for (int form : {1, 2, 3})
-            for (int wpg : {1, 2, 4})
-                for (int xchg : {HEAT_EXCHANGE_NONE, HEAT_EXCHANGE_LDS})
+            for (int wpg : {1, 2, 4, 8})
+                for (int xchg : {HEAT_EXCHANGE_NONE, HEAT_EXCHANGE_LDS, HEAT_EXCHANGE_LDS_DEEP})
                     for (int T : Ts_all) {
                         if (precision == HEAT_FP32C && T != default_steps_per_round(N, precision))
                             continue;
                         if (3 * T > 64 * K) continue;
                         if (K == 64 && form == 2 && precision != HEAT_FP32) continue;
                         if (xchg == HEAT_EXCHANGE_LDS && (wpg < 2 || K < 16)) continue;
+                        if (xchg == HEAT_EXCHANGE_LDS_DEEP && (wpg < 2 || K < 8)) continue;
                         heat_config c{HEAT_KERNEL_TB, K, T, wpg, form, xchg};
                         // whole rounds, at least 4 and at least 384 steps, so the
                         // per-launch overheads weigh as they do in real runs

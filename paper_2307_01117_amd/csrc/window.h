@@ -154,31 +154,35 @@ __device__ __forceinline__ void advance(typename P::T (&v)[K], typename P::T (&e
 //
 // The G waves of a workgroup can share one tile: wave w's window starts
 // w*(64K - 2S) cells right of wave 0's, so neighbouring windows overlap by 2S
-// cells, with S = K/4.  Inside the group, each wave's edge cells go stale at
-// one cell per step from each side; every S steps the waves swap S edge
-// cells through LDS, which makes every window exact again except at the
-// group's two outer edges (the halo H, as for a lone wave).  This is the
-// ghost-zone exchange between segments, one level down: each wave is a
-// segment, and the exchange is deep (S cells every S steps) instead of one
-// cell every step.  Only the tile's outer halo is recomputed redundantly.
+// cells, with the exchange depth S = K/XD (XD = 4 or 2).  Inside the group,
+// each wave's edge cells go stale at one cell per step from each side; every
+// S steps the waves swap S edge cells through LDS, which makes every window
+// exact again except at the group's two outer edges (the halo H, as for a
+// lone wave).  This is the ghost-zone exchange between segments, one level
+// down: each wave is a segment, and the exchange is deep (S cells every S
+// steps) instead of one cell every step.  Only the tile's outer halo is
+// recomputed redundantly, plus 2S cells per pair of neighbouring waves: the
+// deeper exchange (XD = 2) halves the number of exchanges for twice that
+// overlap.
 //
 // LDS layout (per workgroup): two buffers (alternated, so one barrier per
 // exchange suffices) x G waves x 2 edges x S cells, for u and, in the
 // compensated form, e.  Edge 0 of wave w holds its cells [S, 2S) (what wave
 // w-1 needs at its right end), edge 1 its cells [64K - 2S, 64K - S) (what
 // wave w+1 needs at its left end); both live in one lane (S <= K/2).
-template <int K>
-constexpr int exchange_depth() { return K / 4; }
-static_assert(exchange_depth<16>() % 2 == 0, "exchange chunks must be whole step pairs");
+template <int K, int XD>
+constexpr int exchange_depth() { return XD ? K / XD : 0; }
+static_assert(exchange_depth<16, 4>() % 2 == 0 && exchange_depth<8, 2>() % 2 == 0,
+              "exchange chunks must be whole step pairs");
 
 template <class P>
-constexpr int exchange_lds_bytes(int K, int G) {
-    return 2 * G * 2 * (K / 4) * (int)sizeof(typename P::T) * (P::COMP ? 2 : 1);
+constexpr int exchange_lds_bytes(int K, int G, int XD) {
+    return 2 * G * 2 * (K / XD) * (int)sizeof(typename P::T) * (P::COMP ? 2 : 1);
 }
 
-template <int K, class T>
+template <int K, int XD, class T>
 __device__ __forceinline__ void exchange_part(T (&v)[K], T *x, int buf, int G, int w, int lane) {
-    constexpr int S = exchange_depth<K>();
+    constexpr int S = exchange_depth<K, XD>();
     T *mine = x + (size_t)(buf * G + w) * 2 * S;
     if (lane == 0 && w > 0) {
 #pragma unroll
@@ -192,10 +196,10 @@ __device__ __forceinline__ void exchange_part(T (&v)[K], T *x, int buf, int G, i
 
 // Lane 0 and lane 63 read their neighbours' edges straight into the state
 // registers (the loads run with only that lane enabled).
-template <int K, class T>
+template <int K, int XD, class T>
 __device__ __forceinline__ void exchange_take(T (&v)[K], const T *x, int buf, int G, int w,
                                               int lane) {
-    constexpr int S = exchange_depth<K>();
+    constexpr int S = exchange_depth<K, XD>();
     if (lane == 0 && w > 0) {
         const T *src = x + (size_t)(buf * G + w - 1) * 2 * S + S;   // left wave's edge 1
 #pragma unroll
@@ -209,13 +213,13 @@ __device__ __forceinline__ void exchange_take(T (&v)[K], const T *x, int buf, in
 }
 
 // Process one tile: output cells [b, b + min(W, N - b)).  Lone wave
-// (XCHG = false): G = 1, w = 0, W = 64K - 2H.  Cooperating waves: wave w of
-// G, xlds = the workgroup's exchange area (see above),
-// W = G*64K - (G-1)*2S - 2H.  part_in / part_out (may be NULL): per-wave
+// (XD = 0): G = 1, w = 0, W = 64K - 2H.  Cooperating waves (XD = 4 or 2):
+// wave w of G, xlds = the workgroup's exchange area (see above),
+// W = G*64K - (G-1)*2S - 2H, S = K/XD.  part_in / part_out (may be NULL): per-wave
 // binary64 sums of the state before and after the round, written at index
 // `part` -- the conservation checksum fused into the first and last rounds
 // (no extra pass over HBM).
-template <class P, int K, int FORM, bool XCHG = false>
+template <class P, int K, int FORM, int XD = 0>
 __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ src,
                                             typename P::T *__restrict__ dst, int64_t N, int H,
                                             int steps, double r64, int64_t b, int64_t W,
@@ -225,7 +229,8 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
                                             typename P::T *xlds = nullptr) {
     using T = typename P::T;
     constexpr int WIN = 64 * K;
-    constexpr int S = exchange_depth<K>();
+    constexpr bool XCHG = XD != 0;
+    constexpr int S = exchange_depth<K, XD>();
     // the coefficient in the storage type; the compensated form also carries
     // the rest of the binary64 coefficient, rl = fl32(r64 - r)
     const T r = (T)r64;
@@ -310,11 +315,11 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
         int s = 0, buf = 0;
         for (; steps - s > S; s += S) {
             advance<P, K, FORM>(v, e, S, r, rl);
-            exchange_part<K>(v, xu, buf, G, w, lane);
-            if constexpr (P::COMP) exchange_part<K>(e, xe, buf, G, w, lane);
+            exchange_part<K, XD>(v, xu, buf, G, w, lane);
+            if constexpr (P::COMP) exchange_part<K, XD>(e, xe, buf, G, w, lane);
             __syncthreads();
-            exchange_take<K>(v, xu, buf, G, w, lane);
-            if constexpr (P::COMP) exchange_take<K>(e, xe, buf, G, w, lane);
+            exchange_take<K, XD>(v, xu, buf, G, w, lane);
+            if constexpr (P::COMP) exchange_take<K, XD>(e, xe, buf, G, w, lane);
             buf ^= 1;
         }
         advance<P, K, FORM>(v, e, steps - s, r, rl);

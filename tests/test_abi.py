@@ -103,9 +103,10 @@ def test_compensated_round_length_is_fixed(lib):
     dict(kernel=7), dict(cells_per_lane=12), dict(steps_per_round=6), dict(register_form=4),
     dict(cells_per_lane=64, register_form=2),
     dict(cells_per_lane=8, steps_per_round=256), dict(waves_per_group=9), dict(waves_per_group=-1),
-    dict(exchange=3), dict(exchange=-1),
+    dict(exchange=4), dict(exchange=-1),
     dict(exchange=2, waves_per_group=1, cells_per_lane=32),
     dict(exchange=2, waves_per_group=4, cells_per_lane=8),
+    dict(exchange=3, waves_per_group=1, cells_per_lane=16),
 ])
 def test_planner_rejects_bad_config(lib, cfg):
     with pytest.raises(heat.HeatError) as ei:
@@ -248,3 +249,23 @@ def test_tune_table_batch_lines(lib, tmp_path):
         with pytest.raises(heat.HeatError) as ei:
             heat.tune_load(str(f))
         assert ei.value.code == heat.HEAT_EINVAL
+
+
+@pytest.mark.parametrize("K,G,T", [(8, 8, 64), (16, 4, 60), (32, 2, 96), (64, 4, 248)])
+def test_planner_deep_exchange_geometry(lib, K, G, T):
+    """Waves sharing a tile with the deep exchange (every K/2 steps): windows
+    of 64K cells overlapping by 2S = K, the tile's outer halo H >= T."""
+    N = 1_000_000
+    p = heat.plan(N, 1000, heat.FP64, kernel=heat.KERNEL_TB, cells_per_lane=K,
+                  steps_per_round=T, waves_per_group=G, exchange=heat.EXCHANGE_LDS_DEEP)
+    S = K // 2
+    assert p["exchange_steps"] == S and p["waves_per_group"] == G
+    H = (G * 64 * K - (G - 1) * 2 * S - p["tile_cells"]) // 2
+    assert H >= p["steps_per_round"] and 3 * H <= 64 * K
+    assert p["tiles"] == -(-N // p["tile_cells"])
+    # the K/4 exchange on the same shape overlaps by half as much
+    if K >= 16:
+        q = heat.plan(N, 1000, heat.FP64, kernel=heat.KERNEL_TB, cells_per_lane=K,
+                      steps_per_round=T, waves_per_group=G, exchange=heat.EXCHANGE_LDS)
+        assert q["exchange_steps"] == K // 4
+        assert q["tile_cells"] - p["tile_cells"] == (G - 1) * (K - K // 2)

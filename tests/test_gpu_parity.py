@@ -85,6 +85,17 @@ def cfgs_fp64():
         dict(kernel=heat.KERNEL_TB, cells_per_lane=16, steps_per_round=12, waves_per_group=3,
              register_form=2, exchange=heat.EXCHANGE_LDS),
         dict(kernel=heat.KERNEL_TB, cells_per_lane=8, steps_per_round=8, waves_per_group=5),
+        # the deep exchange (every K/2 steps, overlap K)
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=8, steps_per_round=60, waves_per_group=8,
+             exchange=heat.EXCHANGE_LDS_DEEP),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=8, steps_per_round=12, waves_per_group=3,
+             register_form=1, exchange=heat.EXCHANGE_LDS_DEEP),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=16, steps_per_round=60, waves_per_group=4,
+             exchange=heat.EXCHANGE_LDS_DEEP),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=32, steps_per_round=36, waves_per_group=2,
+             register_form=2, exchange=heat.EXCHANGE_LDS_DEEP),
+        dict(kernel=heat.KERNEL_TB, cells_per_lane=64, steps_per_round=124, waves_per_group=4,
+             register_form=3, exchange=heat.EXCHANGE_LDS_DEEP),
     ]
 
 
@@ -159,7 +170,11 @@ def test_midsize_fp32_bitwise(N):
                 dict(cells_per_lane=32, steps_per_round=36, waves_per_group=4, register_form=1,
                      exchange=heat.EXCHANGE_LDS),
                 dict(cells_per_lane=16, steps_per_round=16, waves_per_group=2, register_form=3,
-                     exchange=heat.EXCHANGE_LDS)):
+                     exchange=heat.EXCHANGE_LDS),
+                dict(cells_per_lane=8, steps_per_round=32, waves_per_group=8, register_form=3,
+                     exchange=heat.EXCHANGE_LDS_DEEP),
+                dict(cells_per_lane=64, steps_per_round=96, waves_per_group=4, register_form=1,
+                     exchange=heat.EXCHANGE_LDS_DEEP)):
         got = run_dev(u0, nt, r, precision=heat.FP32, **cfg)
         assert same_bits(got, want), (cfg, N)
 
@@ -174,7 +189,9 @@ def test_midsize_fp32c_bitwise(N):
         for K, form, wpg, x in ((8, 1, 0, 0), (16, 2, 0, 0), (32, 3, 0, 0), (64, 3, 0, 0),
                                 (64, 1, 0, 0), (16, 3, 2, heat.EXCHANGE_LDS),
                                 (32, 2, 4, heat.EXCHANGE_LDS), (32, 3, 8, heat.EXCHANGE_LDS),
-                                (64, 3, 4, heat.EXCHANGE_LDS)):
+                                (64, 3, 4, heat.EXCHANGE_LDS), (8, 1, 8, heat.EXCHANGE_LDS_DEEP),
+                                (16, 3, 4, heat.EXCHANGE_LDS_DEEP),
+                                (32, 1, 4, heat.EXCHANGE_LDS_DEEP)):
             got = run_dev(u0, nt, r, precision=heat.FP32C, cells_per_lane=K, register_form=form,
                           waves_per_group=wpg, exchange=x)
             assert same_bits(got, want), (K, form, wpg, x, N, nt)
@@ -194,7 +211,8 @@ def test_signed_zeros_fp32_forms():
     shapes = [dict(kernel=heat.KERNEL_STEP)] + [
         dict(cells_per_lane=K, register_form=f, waves_per_group=g, exchange=x)
         for K in (8, 32, 64) for f in (1, 2, 3)
-        for (g, x) in ((1, heat.EXCHANGE_NONE), (4, heat.EXCHANGE_LDS))
+        for (g, x) in ((1, heat.EXCHANGE_NONE), (4, heat.EXCHANGE_LDS),
+                       (4, heat.EXCHANGE_LDS_DEEP))
         if not (x == heat.EXCHANGE_LDS and K < 16) and not (K == 64 and f == 2)]
     for r in (0.25, 0.375):
         for nt in (1, 9, 130):
