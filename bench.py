@@ -40,24 +40,28 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # FP32 157.3 TFLOP/s (256 CUs x 2.4 GHz x 128 resp. 256 flops per CU-cycle).
 VECTOR_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp32c": 157.3}
 # Algorithmic flops per cell update (CUP) of each form, the update formula as
-# written: binary64 c + r*((l - 2c) + q) = 5 (2c, -, +, *, +); plain binary32
-# the same five; compensated binary32 12: the Laplacian of u (3) and of e (3),
-# their sum (1), times r (1), the Fast2Sum update (4).
-FLOPS_PER_CUP = {"fp64": 5, "fp32": 5, "fp32c": 12}
+# written (an fma counts as 2): binary64 c + r*((l - 2c) + q) = 5 (2c, -, +,
+# *, +); plain binary32 the same five; compensated binary32 17: the Laplacian
+# of u (3) and of e (3) and their sum (1), the product r*L (1) and its exact
+# rounding error (an fma, 2), the Fast2Sum of c + r*L (3), the coefficient's
+# low part times L added to that error (an fma, 2), and the two additions that
+# gather the small parts in e (2).
+FLOPS_PER_CUP = {"fp64": 5, "fp32": 5, "fp32c": 17}
 # Issue-rate view of the same kernels: VALU lane operations per second against
 # the instruction ceiling (FP64 39.3e12 = 256 CUs x 64 lanes x 2.4 GHz; FP32
 # twice that when two instructions issue together), and the minimal
 # instructions per update of each form: binary64 fma(-2,c,l), +q, *r, +c = 4;
 # binary32 in flux form (q-c) - (c-l), whose one-sided difference serves two
 # cells: one difference, the difference of differences, *r, +c = 4;
-# compensated 10 (the same two steps for u and for e 4, sum 1, *r 1,
-# Fast2Sum 4).  Since the published flops count an FMA as two, a kernel that
-# issues OPS_PER_CUP instructions for FLOPS_PER_CUP flops can reach at most
-# FLOPS_PER_CUP / (2 * OPS_PER_CUP) of the flops peak: 0.625 for binary64
-# and plain binary32 (one FMA, the exact 2c, is all the bitwise contract
-# allows), 0.6 for the compensated form.
+# compensated 13 (the same two steps for u and for e 4, sum 1, product 1,
+# its error 1, Fast2Sum 3, low-part fma 1, two additions into e 2).  Since
+# the published flops count an FMA as two, a kernel that issues OPS_PER_CUP
+# instructions for FLOPS_PER_CUP flops can reach at most FLOPS_PER_CUP /
+# (2 * OPS_PER_CUP) of the flops peak: 0.625 for binary64 and plain binary32
+# (one FMA, the exact 2c, is all the bitwise contract allows), 0.654 for the
+# compensated form.
 VALU_PEAK_TOPS = {"fp64": 39.3, "fp32": 78.65, "fp32c": 78.65}
-OPS_PER_CUP = {"fp64": 4, "fp32": 4, "fp32c": 10}
+OPS_PER_CUP = {"fp64": 4, "fp32": 4, "fp32c": 13}
 
 
 def parse():

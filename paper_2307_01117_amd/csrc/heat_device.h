@@ -260,6 +260,13 @@ __device__ __forceinline__ void comp_update(float &u, float &e, float dlu, float
     u = t;
 }
 
+// The compensated sweeps below run, from 16 cells per lane on, as two
+// interleaved chains over [0, M) and [M, K), M = K/2 + 1, like the binary32
+// sweeps: each chain carries its own one-sided differences, the differences
+// across the chain boundary are formed before either chain writes, and the
+// two chains' independent operations sit next to each other in the
+// instruction stream (the update of every cell is the same as in one
+// sweep, so are the bits).
 template <int K>
 __device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], float r,
                                                  float rl) {
@@ -267,13 +274,37 @@ __device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], f
     float dle = e[0] - from_prev(e[K - 1]);
     const float ru = from_next(u[0]);
     const float re = from_next(e[0]);
+    if constexpr (K >= 16) {
+        constexpr int M = K / 2 + 1;
+        constexpr int NB = K - M;
+        float dlub = u[M] - u[M - 1];
+        float dleb = e[M] - e[M - 1];
+        const float dru_last = dlub, dre_last = dleb;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const float dru = ((j + 1 < K) ? u[j + 1] : ru) - u[j];
-        const float dre = ((j + 1 < K) ? e[j + 1] : re) - e[j];
-        comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
-        dlu = dru;
-        dle = dre;
+        for (int j = 0; j < M; ++j) {
+            const float dru = (j + 1 < M) ? u[j + 1] - u[j] : dru_last;
+            const float dre = (j + 1 < M) ? e[j + 1] - e[j] : dre_last;
+            comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
+            dlu = dru;
+            dle = dre;
+            if (j < NB) {
+                const int b = M + j;
+                const float drub = ((b + 1 < K) ? u[b + 1] : ru) - u[b];
+                const float dreb = ((b + 1 < K) ? e[b + 1] : re) - e[b];
+                comp_update(u[b], e[b], dlub, drub, dleb, dreb, r, rl);
+                dlub = drub;
+                dleb = dreb;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const float dru = ((j + 1 < K) ? u[j + 1] : ru) - u[j];
+            const float dre = ((j + 1 < K) ? e[j + 1] : re) - e[j];
+            comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
+            dlu = dru;
+            dle = dre;
+        }
     }
 }
 
@@ -284,13 +315,41 @@ __device__ __forceinline__ void window_step_comp_bwd(float (&u)[K], float (&e)[K
     const float le = from_prev(e[K - 1]);
     float dru = from_next(u[0]) - u[K - 1];
     float dre = from_next(e[0]) - e[K - 1];
+    if constexpr (K >= 16) {
+        // chain a: cells K-1 .. M (NB cells); chain b: cells M-1 .. 0 (M
+        // cells); each carries its last left difference as the next cell's
+        // right difference
+        constexpr int M = K / 2 + 1;
+        constexpr int NB = K - M;
+        float drub = u[M] - u[M - 1];
+        float dreb = e[M] - e[M - 1];
+        const float dlu_last = drub, dle_last = dreb;
 #pragma unroll
-    for (int j = K - 1; j >= 0; --j) {
-        const float dlu = u[j] - (j > 0 ? u[j - 1] : lu);
-        const float dle = e[j] - (j > 0 ? e[j - 1] : le);
-        comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
-        dru = dlu;
-        dre = dle;
+        for (int j = 0; j < M; ++j) {
+            if (j < NB) {
+                const int a = K - 1 - j;
+                const float dlu = a > M ? u[a] - u[a - 1] : dlu_last;
+                const float dle = a > M ? e[a] - e[a - 1] : dle_last;
+                comp_update(u[a], e[a], dlu, dru, dle, dre, r, rl);
+                dru = dlu;
+                dre = dle;
+            }
+            const int b = M - 1 - j;
+            const float dlub = u[b] - (b > 0 ? u[b - 1] : lu);
+            const float dleb = e[b] - (b > 0 ? e[b - 1] : le);
+            comp_update(u[b], e[b], dlub, drub, dleb, dreb, r, rl);
+            drub = dlub;
+            dreb = dleb;
+        }
+    } else {
+#pragma unroll
+        for (int j = K - 1; j >= 0; --j) {
+            const float dlu = u[j] - (j > 0 ? u[j - 1] : lu);
+            const float dle = e[j] - (j > 0 ? e[j - 1] : le);
+            comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
+            dru = dlu;
+            dre = dle;
+        }
     }
 }
 
@@ -302,8 +361,16 @@ __device__ __forceinline__ void window_step_comp_pp(const float (&u)[K], const f
     const float re = from_next(e[0]);
     float dlu = u[0] - from_prev(u[K - 1]);
     float dle = e[0] - from_prev(e[K - 1]);
+    // from 16 cells per lane, a second chain over [K/2, K) interleaved with
+    // the first (the inputs are never overwritten, so no boundary care)
+    constexpr int NA = K >= 16 ? K / 2 : K;
+    float dlub = 0.f, dleb = 0.f;
+    if constexpr (K >= 16) {
+        dlub = u[NA] - u[NA - 1];
+        dleb = e[NA] - e[NA - 1];
+    }
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < NA; ++j) {
         const float dru = ((j + 1 < K) ? u[j + 1] : ru) - u[j];
         const float dre = ((j + 1 < K) ? e[j + 1] : re) - e[j];
         float a = u[j], b = e[j];
@@ -312,6 +379,17 @@ __device__ __forceinline__ void window_step_comp_pp(const float (&u)[K], const f
         en[j] = b;
         dlu = dru;
         dle = dre;
+        if constexpr (K >= 16) {
+            const int i = NA + j;
+            const float drub = ((i + 1 < K) ? u[i + 1] : ru) - u[i];
+            const float dreb = ((i + 1 < K) ? e[i + 1] : re) - e[i];
+            float c = u[i], d = e[i];
+            comp_update(c, d, dlub, drub, dleb, dreb, r, rl);
+            un[i] = c;
+            en[i] = d;
+            dlub = drub;
+            dleb = dreb;
+        }
     }
 }
 
