@@ -80,6 +80,10 @@ def parse():
     ap.add_argument("--exchange", default="auto", choices=["auto", "none", "lds", "deep"],
                     help="waves of a workgroup: own tiles (none) or one shared tile with "
                          "LDS edge exchanges every K/4 steps (lds) or K/2 steps (deep)")
+    ap.add_argument("--launch", default="rounds", choices=["rounds", "batch", "persistent"],
+                    help="plain workload: heat_solve_dev (rounds, with both checksums), or the "
+                         "ring alone through the batching form (one launch per round) or its "
+                         "persistent flag-synchronised launch (no checksums in those two)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time the library's plain streaming copy of the state instead "
@@ -292,7 +296,13 @@ def run_plain(args, workload, prec_name, steps, warmup, cfg, host=True):
     d_work = torch.empty_like(d_u)
     stream = torch.cuda.current_stream(dev)
 
+    launch = getattr(args, "launch", "rounds")
+
     def one_step():
+        if launch != "rounds":
+            # the ring alone through the batching form (no checksums)
+            return heat.solve_batch_dev([(d_u, d_work, nt, r, prec)], stream=stream,
+                                        persistent=launch == "persistent")
         # the whole hot path in one call: checksum of the state in (fused into
         # the first round), the rounds, checksum of the state out (fused into
         # the last round)
@@ -312,6 +322,19 @@ def run_plain(args, workload, prec_name, steps, warmup, cfg, host=True):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timed_ms = sum(a.elapsed_time(b) for a, b in evs)
+
+    if launch != "rounds":
+        # the batching form's geometry and launches are its own: the rate only
+        del d_u, d_work
+        return {"metric": "GCUP/s (giga cell-updates per second)",
+                "value": round(N * nt * steps / elapsed / 1e9, 3), "unit": "GCUP/s",
+                "n_gpus": 1, "steps": steps, "warmup": warmup,
+                "ms_per_step": round(elapsed * 1e3 / steps, 3), "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+                "dtype": {"fp64": "f64", "fp32": "f32", "fp32c": "f32 (compensated)"}[prec_name],
+                "config": {"workload": workload, "N": N, "nt": nt, "r": r,
+                           "precision": prec_name, "launch": launch},
+                "roofline": None}, u0
 
     # the round launches alone: one pass without checksums between two HIP
     # events (no other kernel: rounds are even, so no copy-back)
@@ -405,7 +428,7 @@ def run_plain(args, workload, prec_name, steps, warmup, cfg, host=True):
         "dtype": {"fp64": "f64", "fp32": "f32", "fp32c": "f32 (compensated)"}[prec_name],
         "data": "synthetic",
         "config": {"workload": workload, "N": N, "nparts": nparts, "r": r, "nt": nt,
-                   "init": w["init"], "seed": w["seed"], "precision": prec_name,
+                   "init": w["init"], "seed": w["seed"], "precision": prec_name, "launch": launch,
                    "kernel": roof["kernel"], "cells_per_lane": pl["cells_per_lane"],
                    "steps_per_round": pl["steps_per_round"],
                    "waves_per_group": pl["waves_per_group"],
