@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="ring_1e8",
-                    choices=["ring_1e6", "ring_1e8", "ring_1e8_perturbed", "paper_ramp_1e6"])
+                    choices=["ring_1e6", "ring_1e7", "ring_1e8", "ring_1e8_perturbed",
+                             "paper_ramp_1e6"])
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32c"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "tb", "step"])
     ap.add_argument("--cells-per-lane", type=int, default=0)

@@ -35,6 +35,8 @@ WORKLOADS = {
     # same ring, r = 0.25, perturbed state, for the FP32 / compensated FP32 forms
     "ring_1e8_perturbed": dict(N=100_000_000, nparts=100, r=0.25, nt=1000,
                                init="perturbed", seed=2),
+    # a mid-size ring: 10 partitions x 1,000,000 cells, 1,000 steps
+    "ring_1e7": dict(N=10_000_000, nparts=10, r=0.5, nt=1000, init="uniform", seed=0),
     # the paper's own run: 1,000,000 nodes, 1,000 steps, initial condition
     # u(0, x_i) = x_i (h = 1); r = 0.5 (the paper does not state alpha, dt, h)
     "paper_ramp_1e6": dict(N=1_000_000, nparts=40, r=0.5, nt=1000, init="ramp", seed=0),
