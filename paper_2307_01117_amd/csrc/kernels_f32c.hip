@@ -2,11 +2,12 @@
 // round kernels of the plain path, lone and exchanging waves (round.h), and
 // the batching form's class (batch_kernels.h).  This file alone is built
 // with LLVM's max-ilp instruction scheduler (see build.py): the compensated
-// update is a chain of ten dependent operations per cell, and interleaving
-// the chains of neighbouring cells pairs more VALU instructions than the
-// default occupancy-first schedule (measured on MI355X: 5,430 against 4,790
-// GCUP/s for the best shape of each on a 1e8-cell ring).  The instruction
-// order does not change any result.
+// update is a chain of dependent operations per cell (thirteen), and
+// interleaving the chains of neighbouring cells pairs more VALU instructions
+// than the default occupancy-first schedule (measured on MI355X with the
+// earlier ten-operation update: 5,430 against 4,790 GCUP/s for the best
+// shape of each on a 1e8-cell ring).  The instruction order does not change
+// any result.
 #include "batch_kernels.h"
 #include "round.h"
 
