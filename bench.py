@@ -41,27 +41,38 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 VECTOR_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp32c": 157.3}
 # Algorithmic flops per cell update (CUP) of each form, the update formula as
 # written (an fma counts as 2): binary64 c + r*((l - 2c) + q) = 5 (2c, -, +,
-# *, +); plain binary32 the same five; compensated binary32 17: the Laplacian
-# of u (3) and of e (3) and their sum (1), the product r*L (1) and its exact
-# rounding error (an fma, 2), the Fast2Sum of c + r*L (3), the coefficient's
-# low part times L added to that error (an fma, 2), and the two additions that
-# gather the small parts in e (2).
-FLOPS_PER_CUP = {"fp64": 5, "fp32": 5, "fp32c": 17}
+# *, +); plain binary32 the same five; compensated binary32 15: the Laplacian
+# of the pair ((q-c) + (eq-ec)) - ((c-l) + (ec-el)) (7), t = fma(r, L, c)
+# (2), c - t (1), its rounding error fma(r, L, c - t) (2), the coefficient's
+# low part fma(rl, L, res) (2) and the addition into e (1); 13 when the
+# coefficient is a binary32 number (no low part).
+FLOPS_PER_CUP = {"fp64": 5, "fp32": 5, "fp32c": 15}
 # Issue-rate view of the same kernels: VALU lane operations per second against
 # the instruction ceiling (FP64 39.3e12 = 256 CUs x 64 lanes x 2.4 GHz; FP32
 # twice that when two instructions issue together), and the minimal
 # instructions per update of each form: binary64 fma(-2,c,l), +q, *r, +c = 4;
 # binary32 in flux form (q-c) - (c-l), whose one-sided difference serves two
 # cells: one difference, the difference of differences, *r, +c = 4;
-# compensated 13 (the same two steps for u and for e 4, sum 1, product 1,
-# its error 1, Fast2Sum 3, low-part fma 1, two additions into e 2).  Since
-# the published flops count an FMA as two, a kernel that issues OPS_PER_CUP
-# instructions for FLOPS_PER_CUP flops can reach at most FLOPS_PER_CUP /
-# (2 * OPS_PER_CUP) of the flops peak: 0.625 for binary64 and plain binary32
-# (one FMA, the exact 2c, is all the bitwise contract allows), 0.654 for the
-# compensated form.
+# compensated 9 (the pair's flux, shared by two cells, 3; L 1; t 1; c - t 1;
+# the error fma 1; the low-part fma 1; the addition into e 1), 8 without the
+# low part.  Since the published flops count an FMA as two, a kernel that
+# issues OPS_PER_CUP instructions for FLOPS_PER_CUP flops can reach at most
+# FLOPS_PER_CUP / (2 * OPS_PER_CUP) of the flops peak: 0.625 for binary64 and
+# plain binary32 (one FMA, the exact 2c, is all the bitwise contract allows),
+# 0.83 / 0.81 for the compensated form.
 VALU_PEAK_TOPS = {"fp64": 39.3, "fp32": 78.65, "fp32c": 78.65}
-OPS_PER_CUP = {"fp64": 4, "fp32": 4, "fp32c": 13}
+OPS_PER_CUP = {"fp64": 4, "fp32": 4, "fp32c": 9}
+
+
+def cup_costs(prec_name: str, r: float):
+    """(flops, VALU instructions) per cell update of a form at coefficient r:
+    the compensated form drops its low-part term when r is a binary32 number
+    (the kernels' rl = fl32(r - fl32(r)) is zero)."""
+    import numpy as np
+    flops, ops = FLOPS_PER_CUP[prec_name], OPS_PER_CUP[prec_name]
+    if prec_name == "fp32c" and np.float32(float(r) - float(np.float32(r))) == 0:
+        flops, ops = flops - 2, ops - 1
+    return flops, ops
 
 
 def parse():
@@ -160,7 +171,7 @@ def kernel_source_digest() -> str:
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2307_01117_amd")
     for f in ("heat_device.h", "window.h", "round.h", "kernels.hip", "kernels_xchg.hip",
-              "kernels_f32.hip", "kernels_f32c.hip"):
+              "kernels_xchg2.hip", "kernels_f32.hip", "kernels_f32c.hip"):
         with open(os.path.join(pkg, "csrc", f), "rb") as fh:
             h.update(fh.read())
     h.update(repr((build.HIPCC_FLAGS, sorted(build.SOURCE_FLAGS.items()))).encode())
@@ -384,19 +395,19 @@ def run_plain(args, workload, prec_name, steps, warmup, cfg, host=True):
         # against the instruction ceiling), which the bitwise contract caps the
         # flops fraction by (see OPS_PER_CUP).
         cups = N * steps_per_launch
-        tflops = FLOPS_PER_CUP[prec_name] * cups / (k_avg_ms * 1e-3) / 1e12
+        fpc, opc = cup_costs(prec_name, r)
+        tflops = fpc * cups / (k_avg_ms * 1e-3) / 1e12
         peak = VECTOR_PEAK_TFLOPS[prec_name]
-        ops = OPS_PER_CUP[prec_name] * cups / (k_avg_ms * 1e-3) / 1e12
+        ops = opc * cups / (k_avg_ms * 1e-3) / 1e12
         hbm = alg_bytes / (k_avg_ms * 1e-3) / 1e9
         roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(tflops / peak, 4), "traffic": None,
-                "flops_per_cup": FLOPS_PER_CUP[prec_name],
+                "flops_per_cup": fpc,
                 "valu_issue": {
                     "achieved": round(ops, 2), "peak": VALU_PEAK_TOPS[prec_name],
                     "unit": "T VALU lane-ops/s", "frac": round(ops / VALU_PEAK_TOPS[prec_name], 4),
-                    "ops_per_cup": OPS_PER_CUP[prec_name],
-                    "flops_frac_cap": round(FLOPS_PER_CUP[prec_name] /
-                                            (2 * OPS_PER_CUP[prec_name]), 4)},
+                    "ops_per_cup": opc,
+                    "flops_frac_cap": round(fpc / (2 * opc), 4)},
                 "hbm_algorithmic_GBs": round(hbm, 1),
                 "hbm_frac": round(hbm / HBM_PEAK_GBS, 4),
                 # cell updates per second against the roofline of one step per

@@ -24,14 +24,16 @@
  *                 a factor of 2).
  *   HEAT_FP32C -- binary32 storage; inside the kernels the state is the pair
  *                 (u, e) of binary32 numbers whose sum is the value, and r is
- *                 the pair fl32(r) + fl32(r - fl32(r)).  Each step adds the
- *                 increment fl32(r)*L (L the Laplacian of u + e) to u and
- *                 gathers its small parts in e (Kahan-style): the Fast2Sum
- *                 error of that addition, the product's rounding error (an
- *                 exact fma) and the coefficient's low part times L.  Steps
- *                 are grouped into rounds of T steps (T reported by
- *                 heat_plan); at each round end the state is folded to
- *                 u := fl32(u + e).  Only u touches HBM.
+ *                 the pair rh + rl, rh = fl32(r), rl = fl32(r - rh).  With L
+ *                 the Laplacian of u + e, formed as the difference of the
+ *                 pair's one-sided fluxes ((q - c) + (eq - ec)) - ((c - l) +
+ *                 (ec - el)), each step is t = fma(rh, L, c), res =
+ *                 fma(rh, L, c - t) (the rounding error of t, taken with the
+ *                 product unrounded), e' = fma(rl, L, res) + e, u' = t: the
+ *                 increment's small parts gather in e (Kahan-style) instead
+ *                 of being rounded away.  Steps are grouped into rounds of T
+ *                 steps (T reported by heat_plan); at each round end the
+ *                 state is folded to u := fl32(u + e).  Only u touches HBM.
  *
  * All functions are extern "C", thread-safe, never throw, and return one of
  * the heat_status codes.  After a negative return heat_last_error() gives a
@@ -358,8 +360,9 @@ int heat_server_destroy(heat_server *s);
  * *best_out (host) with its rate in GCUP/s.  If `install` is nonzero the shape becomes the planner's
  * default for rings of N's decade (log10 bucket) in this process.  Shapes
  * never change binary64 or binary32 results; for HEAT_FP32C only shapes with
- * the form's fixed round length are tried.  Allocates and frees 2 * N * 8
- * bytes of device memory.  Blocking.
+ * the form's fixed round length are tried, at a coefficient that is not a
+ * binary32 number (r = 0.3; the others are timed at r = 1/4).  Allocates and
+ * frees 2 * N * 8 bytes of device memory.  Blocking.
  */
 int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *best_out,
                   double *best_gcups);

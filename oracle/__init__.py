@@ -276,11 +276,10 @@ def np_solve_f32c(u0, r: float, nt: int, T: int) -> np.ndarray:
         for _ in range(s):
             l, q = np.roll(u, 1), np.roll(u, -1)
             el, eq = np.roll(e, 1), np.roll(e, -1)
-            L = ((q - u) - (u - l)) + ((eq - e) - (e - el))
-            d = rh * L
-            g = fma32(rh, L, -d)
-            t = u + d
-            e = (fma32(rl, L, g) + e) + (d - (t - u))
+            L = ((q - u) + (eq - e)) - ((u - l) + (e - el))
+            t = fma32(rh, L, u)
+            res = fma32(rh, L, u - t)
+            e = fma32(rl, L, res) + e
             u = t
         u = u + e
         done += s

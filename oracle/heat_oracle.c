@@ -36,21 +36,21 @@
  *     numbers, and the coefficient is the unevaluated sum rh + rl of two
  *     binary32 numbers, rh = fl32(r), rl = fl32(r - rh) (the difference taken
  *     in binary64, where it is exact), so r is carried to about 2^-48
- *     relative instead of 2^-25.  One step is
- *         L  = ((q - c) - (c - l)) + ((eq - ec) - (ec - el))
- *         d  = rh * L
- *         g  = fma(rh, L, -d)       (the rounding error of rh * L, exact)
- *         t  = c + d
- *         e' = (fma(rl, L, g) + ec) + (d - (t - c))
- *         u' = t
- *     where d - (t - c) is the Fast2Sum error term of c + d (exact when
- *     |c| >= |d|) and fma is the binary32 fused multiply-add (one rounding).
- *     So u' + e' = (u + e) + (rh + rl) * L up to the roundings of L and of
- *     the small terms: the increment's small parts -- the coefficient's low
- *     part, the rounding of the product and that of c + d -- gather in e
- *     instead of being rounded away.  Steps are grouped into rounds of T
- *     steps; at the end of every round (and at the end of the run)
- *     u := fl32(u + e), e := 0.
+ *     relative instead of 2^-25.  The Laplacian of u + e is the difference
+ *     of the pair's one-sided fluxes (flux form again).  One step is
+ *         L   = ((q - c) + (eq - ec)) - ((c - l) + (ec - el))
+ *         t   = fma(rh, L, c)
+ *         res = fma(rh, L, c - t)   (the rounding error of t, c + rh*L - t,
+ *                                    rounded once; c - t is exact when t
+ *                                    and c are within a factor 2)
+ *         e'  = fma(rl, L, res) + ec
+ *         u'  = t
+ *     where fma is the binary32 fused multiply-add (one rounding).  So
+ *     u' + e' = (u + e) + (rh + rl) * L up to the roundings of L and of the
+ *     small terms: the increment's small parts -- the coefficient's low part
+ *     and the rounding of c + rh*L -- gather in e instead of being rounded
+ *     away.  Steps are grouped into rounds of T steps; at the end of every
+ *     round (and at the end of the run) u := fl32(u + e), e := 0.
  *
  * heat_oracle_solve_threads runs the segments as the paper's CPU codes do,
  * one thread each; heat_oracle_solve_threads_simd is the same with the
@@ -423,11 +423,10 @@ static void split_r(double r, float *rh, float *rl)
 static void comp_cell(float l, float c, float q, float el, float ec, float eq, float rh,
                       float rl, float *un, float *en)
 {
-    float L = ((q - c) - (c - l)) + ((eq - ec) - (ec - el));
-    float d = rh * L;
-    float g = fmaf(rh, L, -d);
-    float t = c + d;
-    *en = (fmaf(rl, L, g) + ec) + (d - (t - c));
+    float L = ((q - c) + (eq - ec)) - ((c - l) + (ec - el));
+    float t = fmaf(rh, L, c);
+    float res = fmaf(rh, L, c - t);
+    *en = fmaf(rl, L, res) + ec;
     *un = t;
 }
 

@@ -17,16 +17,27 @@ struct F64 {
     using T = double;
     static constexpr int VEC = 2;        // cells per 16-byte access
     static constexpr bool COMP = false;
+    static constexpr bool LOW = false;
 };
 struct F32 {
     using T = float;
     static constexpr int VEC = 4;
     static constexpr bool COMP = false;
+    static constexpr bool LOW = false;
 };
 struct F32C {
     using T = float;
     static constexpr int VEC = 4;
     static constexpr bool COMP = true;   // carries the compensation term e
+    static constexpr bool LOW = true;    // and the coefficient's low part rl
+};
+// The compensated form for a coefficient that is a binary32 number (rl = 0):
+// the same update without the low-part term, bit for bit (see comp_update).
+struct F32C0 {
+    using T = float;
+    static constexpr int VEC = 4;
+    static constexpr bool COMP = true;
+    static constexpr bool LOW = false;
 };
 
 // 16-byte groups as the compiler's own vector types (what the nontemporal
@@ -242,153 +253,142 @@ __device__ __forceinline__ void window_step_bwd(T (&v)[K], T r) {
 
 // Compensated binary32 step of the pair (u, e).  The coefficient is the pair
 // r + rl (r = fl32 of the binary64 coefficient, rl = fl32 of the rest).  The
-// Laplacian L of u + e is formed from the flux-form differences of both
-// parts (each one-sided difference formed once per sweep); the increment
-// r*L goes to u with Fast2Sum, and the increment's small parts -- the
-// rounding error of r*L (exact through an fma), the coefficient's low part
-// times L, and the Fast2Sum error of c + r*L -- gather in e:
-//     d = r*L;  g = fma(r, L, -d);  t = c + d;
-//     e' = (fma(rl, L, g) + e) + (d - (t - c));  u' = t.
-__device__ __forceinline__ void comp_update(float &u, float &e, float dlu, float dru, float dle,
-                                            float dre, float r, float rl) {
+// Laplacian of u + e is the difference of the pair's two one-sided fluxes,
+// sr - sl, each flux (u[i+1] - u[i]) + (e[i+1] - e[i]) formed once per sweep
+// (the right flux of cell j is the left flux of cell j + 1).  u takes the
+// increment in one fused rounding, t = fma(r, L, c); the rounding error of t
+// is c + r*L - t, which one more fma gives to within a rounding of its own
+// (c - t is exact whenever t and c lie within a factor 2 of each other), and
+// it gathers in e with the coefficient's low part times L:
+//     t = fma(r, L, c);  res = fma(r, L, c - t);
+//     e' = fma(rl, L, res) + e;  u' = t.
+// LOW = false drops the fma with rl for a binary32 coefficient (rl = +0).
+// The bits are the same: fma(+0, L, res) is res except that res = -0 may
+// become +0, and then both give e' = e, because e is never -0 (it starts a
+// round at +0, and a binary32 sum is -0 only when both terms are).
+__device__ __forceinline__ float pair_flux(float uq, float uc, float eq, float ec) {
+    return (uq - uc) + (eq - ec);
+}
+template <bool LOW>
+__device__ __forceinline__ void comp_update(float &u, float &e, float sl, float sr, float r,
+                                            float rl) {
     const float c = u;
-    const float L = (dru - dlu) + (dre - dle);
-    const float d = r * L;
-    const float g = __builtin_fmaf(r, L, -d);
-    const float t = c + d;
-    e = (__builtin_fmaf(rl, L, g) + e) + (d - (t - c));
+    const float L = sr - sl;
+    const float t = __builtin_fmaf(r, L, c);
+    const float res = __builtin_fmaf(r, L, c - t);
+    const float lo = LOW ? __builtin_fmaf(rl, L, res) : res;
+    e = lo + e;
     u = t;
 }
 
 // The compensated sweeps below run, from 16 cells per lane on, as two
 // interleaved chains over [0, M) and [M, K), M = K/2 + 1, like the binary32
-// sweeps: each chain carries its own one-sided differences, the differences
-// across the chain boundary are formed before either chain writes, and the
-// two chains' independent operations sit next to each other in the
-// instruction stream (the update of every cell is the same as in one
-// sweep, so are the bits).
-template <int K>
+// sweeps: each chain carries its own flux, the flux across the chain
+// boundary is formed before either chain writes, and the two chains'
+// independent operations sit next to each other in the instruction stream
+// (the update of every cell is the same as in one sweep, so are the bits).
+template <int K, bool LOW>
 __device__ __forceinline__ void window_step_comp(float (&u)[K], float (&e)[K], float r,
                                                  float rl) {
-    float dlu = u[0] - from_prev(u[K - 1]);
-    float dle = e[0] - from_prev(e[K - 1]);
+    float sl = pair_flux(u[0], from_prev(u[K - 1]), e[0], from_prev(e[K - 1]));
     const float ru = from_next(u[0]);
     const float re = from_next(e[0]);
     if constexpr (K >= 16) {
         constexpr int M = K / 2 + 1;
         constexpr int NB = K - M;
-        float dlub = u[M] - u[M - 1];
-        float dleb = e[M] - e[M - 1];
-        const float dru_last = dlub, dre_last = dleb;
+        float slb = pair_flux(u[M], u[M - 1], e[M], e[M - 1]);
+        const float sr_last = slb;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const float dru = (j + 1 < M) ? u[j + 1] - u[j] : dru_last;
-            const float dre = (j + 1 < M) ? e[j + 1] - e[j] : dre_last;
-            comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
-            dlu = dru;
-            dle = dre;
+            const float sr = (j + 1 < M) ? pair_flux(u[j + 1], u[j], e[j + 1], e[j]) : sr_last;
+            comp_update<LOW>(u[j], e[j], sl, sr, r, rl);
+            sl = sr;
             if (j < NB) {
                 const int b = M + j;
-                const float drub = ((b + 1 < K) ? u[b + 1] : ru) - u[b];
-                const float dreb = ((b + 1 < K) ? e[b + 1] : re) - e[b];
-                comp_update(u[b], e[b], dlub, drub, dleb, dreb, r, rl);
-                dlub = drub;
-                dleb = dreb;
+                const float srb = pair_flux((b + 1 < K) ? u[b + 1] : ru, u[b],
+                                            (b + 1 < K) ? e[b + 1] : re, e[b]);
+                comp_update<LOW>(u[b], e[b], slb, srb, r, rl);
+                slb = srb;
             }
         }
     } else {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const float dru = ((j + 1 < K) ? u[j + 1] : ru) - u[j];
-            const float dre = ((j + 1 < K) ? e[j + 1] : re) - e[j];
-            comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
-            dlu = dru;
-            dle = dre;
+            const float sr = pair_flux((j + 1 < K) ? u[j + 1] : ru, u[j],
+                                       (j + 1 < K) ? e[j + 1] : re, e[j]);
+            comp_update<LOW>(u[j], e[j], sl, sr, r, rl);
+            sl = sr;
         }
     }
 }
 
-template <int K>
+template <int K, bool LOW>
 __device__ __forceinline__ void window_step_comp_bwd(float (&u)[K], float (&e)[K], float r,
                                                      float rl) {
     const float lu = from_prev(u[K - 1]);
     const float le = from_prev(e[K - 1]);
-    float dru = from_next(u[0]) - u[K - 1];
-    float dre = from_next(e[0]) - e[K - 1];
+    float sr = pair_flux(from_next(u[0]), u[K - 1], from_next(e[0]), e[K - 1]);
     if constexpr (K >= 16) {
         // chain a: cells K-1 .. M (NB cells); chain b: cells M-1 .. 0 (M
-        // cells); each carries its last left difference as the next cell's
-        // right difference
+        // cells); each carries its last left flux as the next cell's right
+        // flux
         constexpr int M = K / 2 + 1;
         constexpr int NB = K - M;
-        float drub = u[M] - u[M - 1];
-        float dreb = e[M] - e[M - 1];
-        const float dlu_last = drub, dle_last = dreb;
+        float srb = pair_flux(u[M], u[M - 1], e[M], e[M - 1]);
+        const float sl_last = srb;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             if (j < NB) {
                 const int a = K - 1 - j;
-                const float dlu = a > M ? u[a] - u[a - 1] : dlu_last;
-                const float dle = a > M ? e[a] - e[a - 1] : dle_last;
-                comp_update(u[a], e[a], dlu, dru, dle, dre, r, rl);
-                dru = dlu;
-                dre = dle;
+                const float sl = a > M ? pair_flux(u[a], u[a - 1], e[a], e[a - 1]) : sl_last;
+                comp_update<LOW>(u[a], e[a], sl, sr, r, rl);
+                sr = sl;
             }
             const int b = M - 1 - j;
-            const float dlub = u[b] - (b > 0 ? u[b - 1] : lu);
-            const float dleb = e[b] - (b > 0 ? e[b - 1] : le);
-            comp_update(u[b], e[b], dlub, drub, dleb, dreb, r, rl);
-            drub = dlub;
-            dreb = dleb;
+            const float slb = pair_flux(u[b], b > 0 ? u[b - 1] : lu, e[b], b > 0 ? e[b - 1] : le);
+            comp_update<LOW>(u[b], e[b], slb, srb, r, rl);
+            srb = slb;
         }
     } else {
 #pragma unroll
         for (int j = K - 1; j >= 0; --j) {
-            const float dlu = u[j] - (j > 0 ? u[j - 1] : lu);
-            const float dle = e[j] - (j > 0 ? e[j - 1] : le);
-            comp_update(u[j], e[j], dlu, dru, dle, dre, r, rl);
-            dru = dlu;
-            dre = dle;
+            const float sl = pair_flux(u[j], j > 0 ? u[j - 1] : lu, e[j], j > 0 ? e[j - 1] : le);
+            comp_update<LOW>(u[j], e[j], sl, sr, r, rl);
+            sr = sl;
         }
     }
 }
 
-template <int K>
+template <int K, bool LOW>
 __device__ __forceinline__ void window_step_comp_pp(const float (&u)[K], const float (&e)[K],
                                                     float (&un)[K], float (&en)[K], float r,
                                                     float rl) {
     const float ru = from_next(u[0]);
     const float re = from_next(e[0]);
-    float dlu = u[0] - from_prev(u[K - 1]);
-    float dle = e[0] - from_prev(e[K - 1]);
+    float sl = pair_flux(u[0], from_prev(u[K - 1]), e[0], from_prev(e[K - 1]));
     // from 16 cells per lane, a second chain over [K/2, K) interleaved with
     // the first (the inputs are never overwritten, so no boundary care)
     constexpr int NA = K >= 16 ? K / 2 : K;
-    float dlub = 0.f, dleb = 0.f;
-    if constexpr (K >= 16) {
-        dlub = u[NA] - u[NA - 1];
-        dleb = e[NA] - e[NA - 1];
-    }
+    float slb = 0.f;
+    if constexpr (K >= 16) slb = pair_flux(u[NA], u[NA - 1], e[NA], e[NA - 1]);
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-        const float dru = ((j + 1 < K) ? u[j + 1] : ru) - u[j];
-        const float dre = ((j + 1 < K) ? e[j + 1] : re) - e[j];
+        const float sr = pair_flux((j + 1 < K) ? u[j + 1] : ru, u[j], (j + 1 < K) ? e[j + 1] : re,
+                                   e[j]);
         float a = u[j], b = e[j];
-        comp_update(a, b, dlu, dru, dle, dre, r, rl);
+        comp_update<LOW>(a, b, sl, sr, r, rl);
         un[j] = a;
         en[j] = b;
-        dlu = dru;
-        dle = dre;
+        sl = sr;
         if constexpr (K >= 16) {
             const int i = NA + j;
-            const float drub = ((i + 1 < K) ? u[i + 1] : ru) - u[i];
-            const float dreb = ((i + 1 < K) ? e[i + 1] : re) - e[i];
+            const float srb = pair_flux((i + 1 < K) ? u[i + 1] : ru, u[i],
+                                        (i + 1 < K) ? e[i + 1] : re, e[i]);
             float c = u[i], d = e[i];
-            comp_update(c, d, dlub, drub, dleb, dreb, r, rl);
+            comp_update<LOW>(c, d, slb, srb, r, rl);
             un[i] = c;
             en[i] = d;
-            dlub = drub;
-            dleb = dreb;
+            slb = srb;
         }
     }
 }

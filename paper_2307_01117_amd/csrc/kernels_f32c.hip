@@ -2,25 +2,39 @@
 // round kernels of the plain path, lone and exchanging waves (round.h), and
 // the batching form's class (batch_kernels.h).  This file alone is built
 // with LLVM's max-ilp instruction scheduler (see build.py): the compensated
-// update is a chain of dependent operations per cell (thirteen), and
-// interleaving the chains of neighbouring cells pairs more VALU instructions
-// than the default occupancy-first schedule (measured on MI355X with the
-// earlier ten-operation update: 5,430 against 4,790 GCUP/s for the best
-// shape of each on a 1e8-cell ring).  The instruction order does not change
-// any result.
+// update is a chain of dependent operations per cell, and interleaving the
+// chains of neighbouring cells pairs more VALU instructions than the default
+// occupancy-first schedule (measured on MI355X with an earlier ten-operation
+// update: 5,430 against 4,790 GCUP/s for the best shape of each on a
+// 1e8-cell ring).  The instruction order does not change any result.
 #include "batch_kernels.h"
 #include "round.h"
 
 namespace heat {
 
-hipError_t launch_window_fp32c(const WindowLaunch &a, hipStream_t st) {
-    if (a.precision != HEAT_FP32C) return hipErrorInvalidValue;
+// The coefficient's low part as the kernels derive it, rl = fl32(r - fl32(r)),
+// is zero: r is a binary32 number (or within 2^-150 of one).
+static bool low_part_zero(double r) {
+    const float rh = (float)r;
+    return (float)(r - (double)rh) == 0.0f;
+}
+
+// Window kernels for both coefficient classes: the general form, and the
+// form without the low-part term for a binary32 coefficient (one operation
+// fewer per cell update, the same bits).
+template <class P>
+static hipError_t launch_window_comp(const WindowLaunch &a, hipStream_t st) {
     switch (a.xd) {
-        case 0: return launch_window_f<F32C, 0>(a, st);
-        case 4: return launch_window_f<F32C, 4>(a, st);
-        case 2: return launch_window_f<F32C, 2>(a, st);
+        case 0: return launch_window_f<P, 0>(a, st);
+        case 4: return launch_window_f<P, 4>(a, st);
+        case 2: return launch_window_f<P, 2>(a, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_window_fp32c(const WindowLaunch &a, hipStream_t st) {
+    if (a.precision != HEAT_FP32C) return hipErrorInvalidValue;
+    return low_part_zero(a.r) ? launch_window_comp<F32C0>(a, st) : launch_window_comp<F32C>(a, st);
 }
 
 // The batch classes: 32-cell lanes swept in place (under this file's

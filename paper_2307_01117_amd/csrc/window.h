@@ -114,19 +114,19 @@ __device__ __forceinline__ void advance(typename P::T (&v)[K], typename P::T (&e
             T v2[K], e2[K];
             int s = 0;
             for (; s + 2 <= n; s += 2) {
-                window_step_comp_pp<K>(v, e, v2, e2, r, rl);
-                window_step_comp_pp<K>(v2, e2, v, e, r, rl);
+                window_step_comp_pp<K, P::LOW>(v, e, v2, e2, r, rl);
+                window_step_comp_pp<K, P::LOW>(v2, e2, v, e, r, rl);
             }
-            if (s < n) window_step_comp<K>(v, e, r, rl);
+            if (s < n) window_step_comp<K, P::LOW>(v, e, r, rl);
         } else if constexpr (FORM == FORM_ALTERNATING) {
             int s = 0;
             for (; s + 2 <= n; s += 2) {
-                window_step_comp<K>(v, e, r, rl);
-                window_step_comp_bwd<K>(v, e, r, rl);
+                window_step_comp<K, P::LOW>(v, e, r, rl);
+                window_step_comp_bwd<K, P::LOW>(v, e, r, rl);
             }
-            if (s < n) window_step_comp<K>(v, e, r, rl);
+            if (s < n) window_step_comp<K, P::LOW>(v, e, r, rl);
         } else {
-            for (int s = 0; s < n; ++s) window_step_comp<K>(v, e, r, rl);
+            for (int s = 0; s < n; ++s) window_step_comp<K, P::LOW>(v, e, r, rl);
         }
     } else {
         if constexpr (FORM == FORM_PINGPONG) {
@@ -232,9 +232,10 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
     constexpr bool XCHG = XD != 0;
     constexpr int S = exchange_depth<K, XD>();
     // the coefficient in the storage type; the compensated form also carries
-    // the rest of the binary64 coefficient, rl = fl32(r64 - r)
+    // the rest of the binary64 coefficient, rl = fl32(r64 - r) (unused when
+    // P::LOW is false: the launcher takes that form only when rl is +0)
     const T r = (T)r64;
-    const T rl = P::COMP ? (T)(r64 - (double)r) : T(0);
+    const T rl = P::LOW ? (T)(r64 - (double)r) : T(0);
     // this wave's window in tile coordinates: [off, off + WIN)
     const int64_t off = XCHG ? (int64_t)w * (WIN - 2 * S) : 0;
     const int64_t g0 = b - H + off;
@@ -264,19 +265,19 @@ __device__ __forceinline__ void window_tile(const typename P::T *__restrict__ sr
                 T v2[K], e2[K];
                 int s = 0;
                 for (; s + 2 <= steps; s += 2) {
-                    window_step_comp_pp<K>(v, e, v2, e2, r, rl);
-                    window_step_comp_pp<K>(v2, e2, v, e, r, rl);
+                    window_step_comp_pp<K, P::LOW>(v, e, v2, e2, r, rl);
+                    window_step_comp_pp<K, P::LOW>(v2, e2, v, e, r, rl);
                 }
-                if (s < steps) window_step_comp<K>(v, e, r, rl);
+                if (s < steps) window_step_comp<K, P::LOW>(v, e, r, rl);
             } else if constexpr (FORM == FORM_ALTERNATING) {
                 int s = 0;
                 for (; s + 2 <= steps; s += 2) {
-                    window_step_comp<K>(v, e, r, rl);
-                    window_step_comp_bwd<K>(v, e, r, rl);
+                    window_step_comp<K, P::LOW>(v, e, r, rl);
+                    window_step_comp_bwd<K, P::LOW>(v, e, r, rl);
                 }
-                if (s < steps) window_step_comp<K>(v, e, r, rl);
+                if (s < steps) window_step_comp<K, P::LOW>(v, e, r, rl);
             } else {
-                for (int s = 0; s < steps; ++s) window_step_comp<K>(v, e, r, rl);
+                for (int s = 0; s < steps; ++s) window_step_comp<K, P::LOW>(v, e, r, rl);
             }
 #pragma unroll
             for (int j = 0; j < K; ++j) v[j] = v[j] + e[j];   // fold: u := fl32(u + e)
