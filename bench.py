@@ -84,7 +84,7 @@ def parse():
                     choices=["ring_1e6", "ring_1e7", "ring_1e8", "ring_1e8_perturbed",
                              "paper_ramp_1e6"])
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32c"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "tb", "step"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "tb", "step", "resident"])
     ap.add_argument("--cells-per-lane", type=int, default=0)
     ap.add_argument("--steps-per-round", type=int, default=0)
     ap.add_argument("--waves-per-group", type=int, default=0)
@@ -415,7 +415,8 @@ def run_plain(args, workload, prec_name, steps, warmup, cfg, host=True):
                 # cell update at 8 TB/s); temporal blocking exceeds it T-fold
                 "vs_one_step_hbm_roofline": round(cups / (k_avg_ms * 1e-3)
                                                   / (HBM_PEAK_GBS * 1e9 / (2 * es)), 2)}
-    roof["kernel"] = ("k_step" if pl["kernel"] == heat.KERNEL_STEP else "k_window")
+    roof["kernel"] = {heat.KERNEL_STEP: "k_step",
+                      heat.KERNEL_RESIDENT: "k_resident"}.get(pl["kernel"], "k_window")
     roof["traffic"] = measured_traffic(roof["kernel"], workload, prec_name, pl)
     roof["avg_launch_ms"] = round(k_avg_ms, 4)
     roof["avg_launch_ms_kernel_only"] = round(k_alone_ms, 4)
@@ -473,7 +474,8 @@ def main():
     w = inputs.WORKLOADS[args.workload]
     prec_name = args.precision or ("fp64" if args.workload != "ring_1e8_perturbed" else "fp32c")
     prec = heat.PRECISIONS[prec_name]
-    kernel = {"auto": 0, "tb": heat.KERNEL_TB, "step": heat.KERNEL_STEP}[args.kernel]
+    kernel = {"auto": 0, "tb": heat.KERNEL_TB, "step": heat.KERNEL_STEP,
+              "resident": heat.KERNEL_RESIDENT}[args.kernel]
     exchange = {"auto": 0, "none": heat.EXCHANGE_NONE, "lds": heat.EXCHANGE_LDS,
                 "deep": heat.EXCHANGE_LDS_DEEP}[args.exchange]
     cfg = dict(kernel=kernel, cells_per_lane=args.cells_per_lane,

@@ -69,7 +69,23 @@ enum heat_precision { HEAT_FP64 = 0, HEAT_FP32 = 1, HEAT_FP32C = 2 };
 enum heat_kernel_choice {
     HEAT_KERNEL_AUTO = 0, /* planner decides (tuned table)                      */
     HEAT_KERNEL_STEP = 1, /* one step per launch: coalesced sweep, HBM bound    */
-    HEAT_KERNEL_TB = 2    /* temporal blocking: T steps per round in registers  */
+    HEAT_KERNEL_TB = 2,   /* temporal blocking: T steps per round in registers  */
+    HEAT_KERNEL_RESIDENT = 3 /* temporal blocking in ONE launch: every tile (one
+                               per workgroup) keeps its window in registers
+                               for all nt steps and swaps its H edge cells
+                               with its neighbour tiles through memory every T
+                               steps, ordered by per-tile epoch counters (the
+                               segments' ghost-zone exchange of Section 2, H
+                               cells deep).  Every tile must be resident at
+                               once: the call fails with HEAT_EINVAL if the
+                               ring needs more workgroups than the device
+                               holds, and with HEAT_EDEVICE if a wait times
+                               out (another launch holding the CUs).  Lone
+                               waves need waves_per_group 1; the binary32
+                               forms run in place (register_form 1).  The
+                               call waits for its stream (to check the
+                               waits).  Same results as HEAT_KERNEL_TB with
+                               the same T.                                    */
 };
 
 /* How the waves of a workgroup share the work of a round (TB). */
@@ -105,9 +121,10 @@ typedef struct heat_config {
 
 /* What the planner picked for a given problem (filled by heat_plan). */
 typedef struct heat_plan_info {
-    int32_t kernel;          /* HEAT_KERNEL_STEP or HEAT_KERNEL_TB              */
+    int32_t kernel;          /* HEAT_KERNEL_STEP, _TB or _RESIDENT              */
     int32_t cells_per_lane;  /* K (TB)                                          */
-    int32_t steps_per_round; /* T: steps per round (1 for STEP)                 */
+    int32_t steps_per_round; /* T: steps per round (1 for STEP; RESIDENT: steps
+                                between edge exchanges)                        */
     int32_t waves_per_group;
     int32_t register_form;   /* 1 in-place, 2 ping-pong, 3 alternating (TB)      */
     int32_t exchange_steps;  /* S: steps between LDS edge exchanges of the
@@ -117,7 +134,8 @@ typedef struct heat_plan_info {
                                 lone wave, G*64*K - (G-1)*2S - 2H for G waves,
                                 H >= T the halo                                 */
     int64_t tiles;           /* tiles per round                                 */
-    int64_t rounds;          /* launches (STEP: nt, TB: ceil(nt / T))           */
+    int64_t rounds;          /* launches (STEP: nt, TB: ceil(nt / T),
+                                RESIDENT: 1)                                    */
 } heat_plan_info;
 
 /*

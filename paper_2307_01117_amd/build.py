@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libheat.so")
-SOURCES = ["kernels.hip", "kernels_xchg.hip", "kernels_xchg2.hip", "kernels_f32.hip",
+SOURCES = ["kernels.hip", "kernels_xchg.hip", "kernels_xchg2.hip", "kernels_resident.hip",
+           "kernels_f32.hip",
            "kernels_f32c.hip",
            "batch_kernels.hip", "runtime.hip", "batch.hip", "server.hip", "tune.hip"]
 

@@ -139,6 +139,39 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 // Streaming 16-byte copy (bandwidth probe), same launch shape as k_step.
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 
+// ----------------------------------------------------------- resident
+
+// One launch of the resident kernel (resident.h): every tile's window stays
+// in registers for all nt steps; tiles swap edges through buf[] every T steps.
+struct ResidentArgs {
+    void *buf[2];            // buf[0]: state in and out; buf[1]: scratch of N cells
+    int64_t N;
+    int64_t W;               // output cells per tile
+    int64_t tiles;
+    int64_t nt;
+    int32_t H;               // halo cells per side (>= T)
+    int32_t T;               // steps between edge exchanges
+    double r;
+    uint32_t *flags;         // [tiles] epoch counters, all <= epoch_base at launch
+    uint32_t epoch_base;     // this launch's epochs are epoch_base + 1, 2, ...
+    uint32_t *status;        // [1] zero at launch; nonzero once a wait timed out
+    int64_t spin_limit;
+    double *part_in;         // per-wave sums of the input, or NULL
+    double *part_out;        // per-wave sums of the output, or NULL
+    int32_t vec_ok;          // buf[0] and buf[1] 16-byte aligned
+};
+// Launch (or, with blocks_per_cu set, report how many workgroups of that
+// shape one CU holds) for a precision, cells per lane, register form,
+// waves per group and exchange depth (0, 4 or 2).  kernels_resident.hip
+// dispatches; the binary32 forms' instantiations live in kernels_f32.hip /
+// kernels_f32c.hip (in-place form only).
+hipError_t launch_resident(int precision, const ResidentArgs &a, int K, int form, int G, int xd,
+                           hipStream_t st, int *blocks_per_cu);
+hipError_t launch_resident_fp32(const ResidentArgs &a, int K, int form, int G, int xd,
+                                hipStream_t st, int *blocks_per_cu);
+hipError_t launch_resident_fp32c(const ResidentArgs &a, int K, int form, int G, int xd,
+                                 hipStream_t st, int *blocks_per_cu);
+
 // ----------------------------------------------------------- batching
 
 struct BatchRing {          // one ring of a fused launch (device table entry)

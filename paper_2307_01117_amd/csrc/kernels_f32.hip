@@ -7,6 +7,7 @@
 // size: +1 % to +4 % from 1e5 to 1e8 cells).  The instruction order does
 // not change any result.
 #include "batch_kernels.h"
+#include "resident.h"
 #include "round.h"
 
 namespace heat {
@@ -43,6 +44,12 @@ hipError_t launch_batch_round_fp32(int K, int G, const BatchRing *rings,
 hipError_t launch_batch_fp32(int K, const BatchPlanDev &plan, int grid, int wpg, hipStream_t st) {
     if (K != 32) return hipErrorInvalidValue;
     return launch_batch_t<F32, 32>(plan, grid, wpg, st);
+}
+
+// The resident kernel in the in-place form (the binary32 forms' best).
+hipError_t launch_resident_fp32(const ResidentArgs &a, int K, int form, int G, int xd,
+                                hipStream_t st, int *blocks_per_cu) {
+    return resident_any_xd<F32, 1 << FORM_INPLACE>(a, K, form, G, xd, st, blocks_per_cu);
 }
 
 int batch_occupancy_fp32(int K, int wpg) {

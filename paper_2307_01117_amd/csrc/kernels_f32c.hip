@@ -8,6 +8,7 @@
 // update: 5,430 against 4,790 GCUP/s for the best shape of each on a
 // 1e8-cell ring).  The instruction order does not change any result.
 #include "batch_kernels.h"
+#include "resident.h"
 #include "round.h"
 
 namespace heat {
@@ -35,6 +36,14 @@ static hipError_t launch_window_comp(const WindowLaunch &a, hipStream_t st) {
 hipError_t launch_window_fp32c(const WindowLaunch &a, hipStream_t st) {
     if (a.precision != HEAT_FP32C) return hipErrorInvalidValue;
     return low_part_zero(a.r) ? launch_window_comp<F32C0>(a, st) : launch_window_comp<F32C>(a, st);
+}
+
+// The resident kernel in the in-place form, for both coefficient classes.
+hipError_t launch_resident_fp32c(const ResidentArgs &a, int K, int form, int G, int xd,
+                                 hipStream_t st, int *blocks_per_cu) {
+    return low_part_zero(a.r)
+               ? resident_any_xd<F32C0, 1 << FORM_INPLACE>(a, K, form, G, xd, st, blocks_per_cu)
+               : resident_any_xd<F32C, 1 << FORM_INPLACE>(a, K, form, G, xd, st, blocks_per_cu);
 }
 
 // The batch classes: 32-cell lanes swept in place (under this file's

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <thread>
 #include <vector>
 
@@ -122,6 +123,8 @@ static int check_problem(int64_t N, int32_t nparts, double r, int64_t nt, int pr
 }
 
 
+constexpr int FORM_INPLACE_ID = 1;   // register_form of the in-place sweeps
+
 int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan *p) {
     heat_config c{};
     if (cfg) c = *cfg;
@@ -130,7 +133,7 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     if (q.wpg < 1 || q.wpg > 8)
         return fail(HEAT_EINVAL, "waves_per_group must be in [1, 8] (got %d)", q.wpg);
     int kernel = c.kernel ? c.kernel : HEAT_KERNEL_TB;
-    if (kernel != HEAT_KERNEL_STEP && kernel != HEAT_KERNEL_TB)
+    if (kernel != HEAT_KERNEL_STEP && kernel != HEAT_KERNEL_TB && kernel != HEAT_KERNEL_RESIDENT)
         return fail(HEAT_EINVAL, "unknown kernel choice %d", c.kernel);
     if (kernel == HEAT_KERNEL_STEP && precision == HEAT_FP32C)
         return fail(HEAT_EINVAL, "compensated FP32 needs the temporal-blocked kernel");
@@ -169,6 +172,20 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
         xchg = HEAT_EXCHANGE_NONE;
     }
     q.xd = xchg == HEAT_EXCHANGE_NONE ? 0 : xd;
+    if (kernel == HEAT_KERNEL_RESIDENT && precision != HEAT_FP64 && q.form != FORM_INPLACE_ID) {
+        // the binary32 forms' resident kernels are built in place only
+        if (c.register_form)
+            return fail(HEAT_EINVAL, "the resident kernel runs the binary32 forms in place "
+                        "(register_form 1; got %d)", q.form);
+        q.form = FORM_INPLACE_ID;
+    }
+    if (kernel == HEAT_KERNEL_RESIDENT && !q.xd && q.wpg != 1) {
+        // one tile per workgroup: lone waves run one wave per group
+        if (c.waves_per_group)
+            return fail(HEAT_EINVAL, "the resident kernel with lone waves needs "
+                        "waves_per_group 1 (got %d)", q.wpg);
+        q.wpg = 1;
+    }
     int T = c.steps_per_round ? c.steps_per_round : default_steps_per_round(N, precision);
     if (T < 1) return fail(HEAT_EINVAL, "steps_per_round must be >= 1 (got %d)", T);
     if (c.steps_per_round && (T % 4) != 0)
@@ -176,14 +193,25 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     // the window must keep W >= H so a tile only reads its two neighbours
     if (3 * ceil4(T) > 64 * (int64_t)q.K)
         return fail(HEAT_EINVAL, "steps_per_round %d too deep for %d cells per lane", T, q.K);
+    // RESIDENT: the steps between edge exchanges need no balancing (there is
+    // no copy-back), but the compensated form's fold interval is its T
     const int64_t Teff =
-        c.steps_per_round ? (nt > 0 ? std::min<int64_t>(T, nt) : 1) : planned_steps_per_round(N, nt, precision);
+        c.steps_per_round || kernel == HEAT_KERNEL_RESIDENT
+            ? (nt > 0 ? std::min<int64_t>(T, nt) : 1)
+            : planned_steps_per_round(N, nt, precision);
     q.T = (int)Teff;
     q.H = halo_cells(Teff, precision, q.K);
     q.W = window_tile_cells(q.K, q.H, q.wpg, q.xd);
     q.tiles = (N + q.W - 1) / q.W;
     q.parts = q.xd ? q.tiles * q.wpg : q.tiles;
     q.rounds = nt > 0 ? (nt + Teff - 1) / Teff : 0;
+    if (kernel == HEAT_KERNEL_RESIDENT) {
+        // the halo reads wrap the ring at most once
+        if (N < q.H)
+            return fail(HEAT_EINVAL, "the resident kernel needs a ring of at least H = %d cells",
+                        q.H);
+        q.rounds = nt > 0 ? 1 : 0;
+    }
     const int64_t threads = q.xd ? q.tiles * q.wpg * 64 : q.tiles * 64;
     if (threads > MAX_GRID_THREADS)
         return fail(HEAT_EINVAL, "ring of %lld cells needs more than one launch's tiles at %d cells "
@@ -221,8 +249,110 @@ struct SumArea {
     double *d_out = nullptr;     // 2 doubles
 };
 
+// Epoch counters and status word of the resident kernel, per thread and
+// device, with a pinned host word for the status: grown on demand and kept
+// (a resident call waits for its stream before it returns, so the next call
+// from the same thread finds them idle).  The counters are never cleared
+// between calls: each call counts on from `base`, the highest value the
+// previous one left; they are cleared when the buffer is new, after a call
+// that failed, and before `base` could wrap.
+struct ResidentCache {
+    uint32_t *d = nullptr;   // device: [0] status, [1, 1 + tiles) epochs
+    size_t cap = 0;          // words held by d
+    uint32_t *h = nullptr;   // pinned host: status
+    uint32_t base = 0;       // every counter is <= base
+    int cus = 0;             // compute units of the device
+    std::unordered_map<uint64_t, int> per_cu;   // workgroups per CU by shape
+};
+static thread_local ResidentCache g_resident_cache[64];
+
+// Waits of a resident launch give up after this many polls (each a load
+// and a short sleep, about a microsecond): seconds, far beyond any wait of a
+// co-resident grid.
+constexpr int64_t RESIDENT_SPIN_LIMIT = int64_t(1) << 22;
+
+static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t N, double r,
+                        int64_t nt, hipStream_t st, const SumArea *sums) {
+    int dev = 0;
+    HEAT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(HEAT_EDEVICE, "device %d out of range", dev);
+    ResidentCache &c = g_resident_cache[dev];
+    ResidentArgs ra{};
+    ra.W = pl.W;
+    ra.H = pl.H;
+    // every tile must be resident at once (the LDS a group takes depends on
+    // its tile span W + 2H, so the occupancy is asked for each shape)
+    const uint64_t key = (uint64_t)precision | (uint64_t)pl.K << 4 | (uint64_t)pl.form << 12 |
+                         (uint64_t)pl.wpg << 16 | (uint64_t)pl.xd << 20 |
+                         (uint64_t)(pl.W + 2 * pl.H) << 24;
+    auto it = c.per_cu.find(key);
+    if (it == c.per_cu.end()) {
+        int n = 0;
+        HEAT_HIP(launch_resident(precision, ra, pl.K, pl.form, pl.wpg, pl.xd, st, &n));
+        it = c.per_cu.emplace(key, n).first;
+    }
+    if (c.cus == 0) {
+        hipDeviceProp_t prop;
+        HEAT_HIP(hipGetDeviceProperties(&prop, dev));
+        c.cus = prop.multiProcessorCount;
+    }
+    const int64_t capacity = it->second > 0 ? (int64_t)it->second * c.cus : 0;
+    if (pl.tiles > capacity)
+        return fail(HEAT_EINVAL, "the resident kernel needs all %lld tiles resident at once; this "
+                    "shape fits %lld on the device (fewer cells per tile: a longer window, or "
+                    "use HEAT_KERNEL_TB)", (long long)pl.tiles, (long long)capacity);
+    const size_t words = (size_t)pl.tiles + 1;
+    const int64_t epochs = (nt + pl.T - 1) / pl.T;   // exchanges + 1
+    if (!c.h) HEAT_HIP(hipHostMalloc((void **)&c.h, sizeof(uint32_t), hipHostMallocDefault));
+    bool clear = false;
+    if (c.cap < words) {
+        if (c.d) HEAT_HIP(hipFree(c.d));   // idle: the last call waited for its stream
+        c.d = nullptr;
+        c.cap = 0;
+        HEAT_HIP(hipMalloc((void **)&c.d, words * sizeof(uint32_t)));
+        c.cap = words;
+        clear = true;
+    }
+    if (clear || (int64_t)c.base + epochs >= (int64_t(1) << 31)) {
+        HEAT_HIP(launch_fill_u32(c.d, (int64_t)c.cap, 0u, st));
+        c.base = 0;
+    }
+    ra.buf[0] = a;
+    ra.buf[1] = b;
+    ra.N = N;
+    ra.tiles = pl.tiles;
+    ra.nt = nt;
+    ra.T = pl.T;
+    ra.r = r;
+    ra.status = c.d;
+    ra.flags = c.d + 1;
+    ra.epoch_base = c.base;
+    ra.spin_limit = RESIDENT_SPIN_LIMIT;
+    ra.part_in = sums ? sums->partial : nullptr;
+    ra.part_out = sums ? sums->partial + pl.parts : nullptr;
+    // the vector paths read and write both buffers
+    ra.vec_ok = ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
+    HEAT_HIP(launch_resident(precision, ra, pl.K, pl.form, pl.wpg, pl.xd, st, nullptr));
+    if (sums) HEAT_HIP(launch_sum_partials(sums->partial, pl.parts, 2, sums->d_out, st));
+    HEAT_HIP(hipMemcpyAsync(c.h, c.d, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HEAT_HIP(hipStreamSynchronize(st));
+    c.base += (uint32_t)epochs;
+    if (*c.h != 0) {
+        // counters in any state: clear them (and the status) next time
+        c.cap = 0;
+        (void)hipFree(c.d);
+        c.d = nullptr;
+        return fail(HEAT_EDEVICE, "resident kernel: a tile waited too long for its neighbours "
+                    "(were all %lld tiles resident? another launch may hold the CUs); the "
+                    "state is undefined", (long long)pl.tiles);
+    }
+    return HEAT_OK;
+}
+
 static int run_rounds(const Plan &pl, int precision, void *a, void *b, int64_t N, double r,
                       int64_t nt, hipStream_t st, const SumArea *sums) {
+    if (pl.kernel == HEAT_KERNEL_RESIDENT && nt > 0)
+        return run_resident(pl, precision, a, b, N, r, nt, st, sums);
     void *cur = a, *oth = b;
     const bool fused = sums && pl.kernel == HEAT_KERNEL_TB && nt > 0;
     if (sums && !fused) HEAT_HIP(launch_sum(precision, a, N, sums->partial, sums->d_out, st));
@@ -569,6 +699,13 @@ static int solve_dev_noalloc_impl(void *d_u, int64_t N, int32_t nparts, double r
     Plan pl;
     rc = make_plan(N, nt, precision, nullptr, &pl);
     if (rc) return rc;
+    if (pl.kernel == HEAT_KERNEL_RESIDENT) {
+        // it waits for the stream and keeps its own counters: take the round
+        // kernel with the same shape (the same results)
+        heat_config c{HEAT_KERNEL_TB, pl.K, 0, 0, pl.form, 0};
+        rc = make_plan(N, nt, precision, &c, &pl);
+        if (rc) return rc;
+    }
     size_t partial_off = 0;
     const size_t need = noalloc_bytes(pl, N, precision, nt, d_sums_out != nullptr, &partial_off);
     if (need > (size_t)HEAT_NOALLOC_SCRATCH_BYTES)
@@ -635,7 +772,7 @@ int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
     out->steps_per_round = pl.T;
     out->waves_per_group = pl.wpg;
     out->register_form = pl.form;
-    out->exchange_steps = pl.kernel == HEAT_KERNEL_TB && pl.xd ? pl.K / pl.xd : 0;
+    out->exchange_steps = pl.kernel != HEAT_KERNEL_STEP && pl.xd ? pl.K / pl.xd : 0;
     out->tile_cells = pl.W;
     out->tiles = pl.tiles;
     out->rounds = pl.rounds;

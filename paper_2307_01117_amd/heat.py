@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libheat.so")
 HEAT_OK, HEAT_PENDING = 0, 1
 HEAT_EINVAL, HEAT_ENOMEM, HEAT_EBUSY, HEAT_ENOENT, HEAT_EDEVICE, HEAT_ECANCELED = -1, -2, -3, -4, -5, -6
 FP64, FP32, FP32C = 0, 1, 2
-KERNEL_AUTO, KERNEL_STEP, KERNEL_TB = 0, 1, 2
+KERNEL_AUTO, KERNEL_STEP, KERNEL_TB, KERNEL_RESIDENT = 0, 1, 2, 3
 EXCHANGE_AUTO, EXCHANGE_NONE, EXCHANGE_LDS, EXCHANGE_LDS_DEEP = 0, 1, 2, 3
 BATCH_WAIT, BATCH_PERSISTENT, BATCH_GRAPH = 1, 2, 4
 
