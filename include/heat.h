@@ -198,7 +198,15 @@ int heat_solve_dev_cfg(void *d_u, void *d_work, int64_t N, int32_t nparts, doubl
                        int32_t precision, const heat_config *cfg, void *hip_stream,
                        double *sum0_out, double *sum_out);
 
-/* Planner: what heat_solve_dev_cfg would run for this problem.  No device work. */
+/*
+ * Planner: what heat_solve_dev_cfg would run for this problem, in a call that
+ * asks for the sums.  With every heat_config field zero (or cfg NULL), calls
+ * that wait for their result -- those asking for the sums, and heat_solve --
+ * take the resident kernel where the tuning table has a resident shape for
+ * N's bucket, the run has at least its number of steps and the grid can be
+ * resident on the current device; other calls take the round kernel, with
+ * the same results.  No device work (it may query the device's occupancy).
+ */
 int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
               heat_plan_info *out);
 
@@ -379,8 +387,14 @@ int heat_server_destroy(heat_server *s);
  * default for rings of N's decade (log10 bucket) in this process.  Shapes
  * never change binary64 or binary32 results; for HEAT_FP32C only shapes with
  * the form's fixed round length are tried, at a coefficient that is not a
- * binary32 number (r = 0.3; the others are timed at r = 1/4).  Allocates and
- * frees 2 * N * 8 bytes of device memory.  Blocking.
+ * binary32 number (r = 0.3; the others are timed at r = 1/4).  It then times
+ * every HEAT_KERNEL_RESIDENT shape that can be resident for N cells over
+ * 1,024 steps, and the best of them and the round-kernel winner over 128 and
+ * 1,024 steps; if the resident one wins the long run by 3 %, `install` also
+ * records its shape for the bucket with the run length from which it is
+ * faster (both kernels' times taken as a fixed cost plus a cost per step),
+ * and heat_plan shows it.  *best_out is always the round-kernel winner.
+ * Allocates and frees 2 * N * 8 bytes of device memory.  Blocking.
  */
 int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *best_out,
                   double *best_gcups);

@@ -3,9 +3,10 @@
 Usage: python -m paper_2307_01117_amd.autotune [--out FILE] [--sizes 1e4,1e5,...]
 
 For every precision and ring length it calls heat_autotune (which times each
-temporal-blocking shape with HIP events) and installs the winner for that
-decade, then heat_autotune_batch for the batching form's kernel classes; the
-table is then written with heat_tune_save.  The binding loads
+temporal-blocking shape with HIP events, then the resident kernel's shapes
+against the winner) and installs the winner for that decade, then
+heat_autotune_batch for the batching form's kernel classes; the table is
+then written with heat_tune_save.  The binding loads
 tune_mi355x.txt next to the library at start-up unless HEAT_TUNE_TABLE names
 another file.
 """
@@ -39,8 +40,11 @@ def main():
         for n in ([] if args.no_plain else args.sizes.split(",")):
             N = int(float(n))
             cfg, g = heat.autotune(prec, N, install=True)
-            print(json.dumps({"precision": name, "N": N, "best": cfg, "GCUPs": round(g, 1)}),
-                  flush=True)
+            # a long run that asks for the sums: the resident kernel's shape if
+            # the tuner recorded one for this bucket
+            long_run = heat.plan(N, 1024, prec)
+            print(json.dumps({"precision": name, "N": N, "best": cfg, "GCUPs": round(g, 1),
+                              "plan_1024_steps": long_run}), flush=True)
         sizes = [int(float(x)) for x in args.batch_sizes.split(",") if x]
         lines = []
         for N in sizes:

@@ -271,24 +271,24 @@ static thread_local ResidentCache g_resident_cache[64];
 // co-resident grid.
 constexpr int64_t RESIDENT_SPIN_LIMIT = int64_t(1) << 22;
 
-static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t N, double r,
-                        int64_t nt, hipStream_t st, const SumArea *sums) {
+// Tiles of a resident plan's shape the current device holds at once (the
+// LDS a group takes depends on its tile span W + 2H, so the occupancy is
+// asked for each shape, once per thread).
+static int resident_capacity(const Plan &pl, int precision, int64_t *capacity) {
     int dev = 0;
     HEAT_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(HEAT_EDEVICE, "device %d out of range", dev);
     ResidentCache &c = g_resident_cache[dev];
-    ResidentArgs ra{};
-    ra.W = pl.W;
-    ra.H = pl.H;
-    // every tile must be resident at once (the LDS a group takes depends on
-    // its tile span W + 2H, so the occupancy is asked for each shape)
     const uint64_t key = (uint64_t)precision | (uint64_t)pl.K << 4 | (uint64_t)pl.form << 12 |
                          (uint64_t)pl.wpg << 16 | (uint64_t)pl.xd << 20 |
                          (uint64_t)(pl.W + 2 * pl.H) << 24;
     auto it = c.per_cu.find(key);
     if (it == c.per_cu.end()) {
+        ResidentArgs probe{};
+        probe.W = pl.W;
+        probe.H = pl.H;
         int n = 0;
-        HEAT_HIP(launch_resident(precision, ra, pl.K, pl.form, pl.wpg, pl.xd, st, &n));
+        HEAT_HIP(launch_resident(precision, probe, pl.K, pl.form, pl.wpg, pl.xd, nullptr, &n));
         it = c.per_cu.emplace(key, n).first;
     }
     if (c.cus == 0) {
@@ -296,7 +296,22 @@ static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t
         HEAT_HIP(hipGetDeviceProperties(&prop, dev));
         c.cus = prop.multiProcessorCount;
     }
-    const int64_t capacity = it->second > 0 ? (int64_t)it->second * c.cus : 0;
+    *capacity = it->second > 0 ? (int64_t)it->second * c.cus : 0;
+    return HEAT_OK;
+}
+
+static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t N, double r,
+                        int64_t nt, hipStream_t st, const SumArea *sums) {
+    int dev = 0;
+    HEAT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(HEAT_EDEVICE, "device %d out of range", dev);
+    ResidentCache &c = g_resident_cache[dev];
+    int64_t capacity = 0;
+    int rc = resident_capacity(pl, precision, &capacity);
+    if (rc) return rc;
+    ResidentArgs ra{};
+    ra.W = pl.W;
+    ra.H = pl.H;
     if (pl.tiles > capacity)
         return fail(HEAT_EINVAL, "the resident kernel needs all %lld tiles resident at once; this "
                     "shape fits %lld on the device (fewer cells per tile: a longer window, or "
@@ -607,9 +622,35 @@ int stage_copies(bool to_device, const StageSeg *segs, size_t count, hipStream_t
     return HEAT_OK;
 }
 
+static bool config_is_auto(const heat_config *cfg) {
+    return !cfg || !(cfg->kernel || cfg->cells_per_lane || cfg->steps_per_round ||
+                     cfg->waves_per_group || cfg->register_form || cfg->exchange);
+}
+
+// The plan a call runs: make_plan's, except that a call that waits for its
+// result (`waits`) with an all-automatic configuration takes the resident
+// kernel where the tuning table has a resident shape for N's bucket, the run
+// is at least as long as the shortest one that shape won, and the grid fits
+// the device at once.
+static int choose_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, bool waits,
+                       Plan *pl) {
+    int rc = make_plan(N, nt, precision, cfg, pl);
+    if (rc || !waits || nt < 1 || !config_is_auto(cfg)) return rc;
+    heat_config rcfg;
+    int64_t min_nt = 0;
+    if (!tuned_resident(N, precision, &rcfg, &min_nt) || nt < min_nt) return HEAT_OK;
+    Plan q;
+    if (make_plan(N, nt, precision, &rcfg, &q) != HEAT_OK) return HEAT_OK;
+    int64_t capacity = 0;
+    if (resident_capacity(q, precision, &capacity) != HEAT_OK || q.tiles > capacity)
+        return HEAT_OK;
+    *pl = q;
+    return HEAT_OK;
+}
+
 static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, double r, int64_t nt,
                           int32_t precision, const heat_config *cfg, hipStream_t st,
-                          double *sum0_out, double *sum_out) {
+                          double *sum0_out, double *sum_out, bool waits = false) {
     int rc = check_problem(N, nparts, r, nt, precision);
     if (rc) return rc;
     if (!d_u) return fail(HEAT_EINVAL, "d_u is NULL");
@@ -618,12 +659,12 @@ static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, do
         const char *a = (const char *)d_u, *w = (const char *)d_work;
         if (w < a + bytes && a < w + bytes) return fail(HEAT_EINVAL, "d_work overlaps d_u");
     }
+    const bool want_sums = sum0_out || sum_out;
     Plan pl;
-    rc = make_plan(N, nt, precision, cfg, &pl);
+    rc = choose_plan(N, nt, precision, cfg, waits || want_sums, &pl);
     if (rc) return rc;
     rc = device_pool_setup();
     if (rc) return rc;
-    const bool want_sums = sum0_out || sum_out;
     DevBuf work;
     work.st = st;
     SumArea area;
@@ -765,7 +806,7 @@ int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
     if (rc) return rc;
     if (!out) return fail(HEAT_EINVAL, "out is NULL");
     Plan pl;
-    rc = make_plan(N, nt, precision, cfg, &pl);
+    rc = choose_plan(N, nt, precision, cfg, true, &pl);
     if (rc) return rc;
     out->kernel = pl.kernel;
     out->cells_per_lane = pl.K;
@@ -814,7 +855,7 @@ int heat_solve(double *u, int64_t N, int32_t nparts, double r, int64_t nt) {
     const StageSeg seg{d, u, bytes};
     rc = stage_copies(true, &seg, 1, st);
     if (!rc) rc = solve_dev_impl(d, nullptr, N, nparts, r, nt, HEAT_FP64, nullptr, st, nullptr,
-                                 nullptr);
+                                 nullptr, true);
     if (!rc) rc = stage_copies(false, &seg, 1, st);
     e = hipStreamSynchronize(st);
     if (!rc && e != hipSuccess) rc = fail_hip(e, "hipStreamSynchronize");

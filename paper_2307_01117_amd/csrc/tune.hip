@@ -12,7 +12,8 @@
 // A second table holds the batching form's kernel class per (precision,
 // bucket): cells per lane K, waves per tile G and the target round length,
 // picked by the batch autotuner, which times every built class on a
-// synthetic batch of rings of one length.
+// synthetic batch of rings of one length.  A third holds, where it won, the
+// resident kernel's shape and the shortest run it is faster on.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,10 +42,18 @@ struct BatchEntry {
     int K = 0, G = 0, T = 0;   // K = 0: not tuned (the batching form's own rule)
 };
 
+// The resident kernel's shape for a bucket, and the shortest run it is
+// measured faster on (K = 0: the round kernel always).
+struct ResidentEntry {
+    int K = 0, T = 0, G = 0, form = 0, xchg = 0;
+    int64_t min_nt = 0;
+};
+
 struct TuneTable {
     std::mutex mu;
     TuneEntry e[3][NBUCKETS];
     BatchEntry b[3][NBUCKETS];
+    ResidentEntry rs[3][NBUCKETS];
     bool env_loaded = false;
     TuneTable() {
         for (int p = 0; p < 3; ++p)
@@ -73,6 +82,35 @@ int load_file(const char *path) {
     int n = 0, rc = HEAT_OK;
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
+        if (line[0] == 'r') {
+            // resident shape: "r precision bucket K T G form exchange min_nt"
+            int p, b, K, T, G, form, xchg;
+            long long mn;
+            const int got = std::sscanf(line + 1, "%d %d %d %d %d %d %d %lld", &p, &b, &K, &T, &G,
+                                        &form, &xchg, &mn);
+            // "r precision bucket 0 0 0 0 0 0": no resident shape for the bucket
+            if (got == 8 && p >= 0 && p <= 2 && b >= 0 && b < NBUCKETS && K == 0 && T == 0 &&
+                G == 0 && form == 0 && xchg == 0 && mn == 0) {
+                std::lock_guard<std::mutex> lk(t.mu);
+                t.rs[p][b] = ResidentEntry{};
+                ++n;
+                continue;
+            }
+            if (got != 8 || p < 0 || p > 2 || b < 0 || b >= NBUCKETS ||
+                (K != 8 && K != 16 && K != 32 && K != 64) || T < 1 || (T % 4) || 3 * T > 64 * K ||
+                G < 1 || G > 8 || form < 1 || form > 3 || (p != HEAT_FP64 && form != 1) ||
+                xchg < HEAT_EXCHANGE_NONE || xchg > HEAT_EXCHANGE_LDS_DEEP ||
+                (xchg == HEAT_EXCHANGE_NONE && G != 1) ||
+                (xchg == HEAT_EXCHANGE_LDS && (G < 2 || K < 16)) ||
+                (xchg == HEAT_EXCHANGE_LDS_DEEP && (G < 2 || K < 8)) || mn < 1) {
+                rc = fail(HEAT_EINVAL, "bad tuning table line: %s", line);
+                break;
+            }
+            std::lock_guard<std::mutex> lk(t.mu);
+            t.rs[p][b] = ResidentEntry{K, T, G, form, xchg, (int64_t)mn};
+            ++n;
+            continue;
+        }
         if (line[0] == 'b') {
             // batch class: "b precision bucket K G T" ("... 0 0 0": the rule)
             int p, b, K, G, T;
@@ -134,6 +172,18 @@ bool tuned_batch_class(int64_t N, int precision, int *K, int *G, int *T) {
     return true;
 }
 
+bool tuned_resident(int64_t N, int precision, heat_config *c, int64_t *min_nt) {
+    if (precision < 0 || precision > 2) return false;
+    load_env_once();
+    TuneTable &t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    const ResidentEntry &e = t.rs[precision][bucket_of(N)];
+    if (e.K == 0) return false;
+    *c = heat_config{HEAT_KERNEL_RESIDENT, e.K, e.T, e.G, e.form, e.xchg};
+    *min_nt = e.min_nt;
+    return true;
+}
+
 void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form, int *exchange) {
     load_env_once();
     TuneTable &t = table();
@@ -190,12 +240,27 @@ int heat_tune_save(const char *path) {
             any = true;
             std::fprintf(f, "b %d %d %d %d %d\n", p, b, e.K, e.G, e.T);
         }
+    any = false;
+    for (int p = 0; p < 3; ++p)
+        for (int b = 0; b < NBUCKETS; ++b) {
+            const ResidentEntry &e = t.rs[p][b];
+            if (!e.K) continue;
+            if (!any)
+                std::fprintf(f, "# resident kernel: r precision bucket(log10 N) cells_per_lane "
+                                "steps_per_round waves_per_group register_form exchange "
+                                "min_steps\n");
+            any = true;
+            std::fprintf(f, "r %d %d %d %d %d %d %d %lld\n", p, b, e.K, e.T, e.G, e.form, e.xchg,
+                         (long long)e.min_nt);
+        }
     std::fclose(f);
     return HEAT_OK;
 }
 
 // Gain a tuned batch class must show over the rule on the synthetic batch.
 constexpr double BATCH_TUNE_MARGIN = 1.03;
+// Gain the resident kernel must show over the round kernel on a long run.
+constexpr double RESIDENT_TUNE_MARGIN = 1.03;
 
 int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *K_out,
                         int32_t *G_out, int32_t *T_out, double *best_gcups) {
@@ -421,10 +486,87 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
                             bc = c;
                         }
                     }
+    // The resident kernel (one launch per run, tiles swapping edges through
+    // memory): every shape that can be resident for this ring, at the same
+    // coefficient, timed over a long run; its best against the round
+    // kernel's winner at a short and a long run.  Each kernel's time is a
+    // fixed cost plus a cost per step, so the two lengths give the run length
+    // from which the resident one is faster; it is kept if it wins the long
+    // run by RESIDENT_TUNE_MARGIN.
+    const int64_t nt_short = 128, nt_long = 1024;
+    auto time_run = [&](const heat_config &c, int64_t nt, double *ms_out) -> int {
+        int rc2 = heat_solve_dev_cfg(a, w, N, 1, r_tune, nt, precision, &c, st, nullptr, nullptr);
+        if (rc2) return rc2;   // also: a resident shape that cannot be resident
+        hipError_t e2 = hipEventRecord(e0, st);
+        if (e2 == hipSuccess)
+            rc2 = heat_solve_dev_cfg(a, w, N, 1, r_tune, nt, precision, &c, st, nullptr, nullptr);
+        if (!rc2 && e2 == hipSuccess) e2 = hipEventRecord(e1, st);
+        if (!rc2 && e2 == hipSuccess) e2 = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (!rc2 && e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, e0, e1);
+        if (!rc2 && e2 != hipSuccess) rc2 = fail_hip(e2, "autotune timing");
+        *ms_out = ms;
+        return rc2;
+    };
+    ResidentEntry rbest;
+    {
+        const bool comp = precision == HEAT_FP32C;
+        const int T_comp = default_steps_per_round(N, precision);
+        double best_long = -1.0;
+        heat_config rc_best{};
+        struct GX { int G, x; };
+        for (int K : {8, 16, 32})
+            for (GX gx : {GX{1, HEAT_EXCHANGE_NONE}, GX{2, HEAT_EXCHANGE_LDS_DEEP},
+                          GX{4, HEAT_EXCHANGE_LDS}, GX{4, HEAT_EXCHANGE_LDS_DEEP},
+                          GX{8, HEAT_EXCHANGE_LDS_DEEP}})
+                for (int form : {1, 3})
+                    for (int T : {32, 48, 64, 96, 128}) {
+                        if (comp && T != T_comp) continue;
+                        if (precision != HEAT_FP64 && form != 1) continue;
+                        if (3 * T > 64 * K) continue;
+                        if (gx.x == HEAT_EXCHANGE_LDS && K < 16) continue;
+                        heat_config c{HEAT_KERNEL_RESIDENT, K, T, gx.G, form, gx.x};
+                        double ms = 0.0;
+                        rc = time_run(c, nt_long, &ms);
+                        if (rc == HEAT_EINVAL) continue;   // not resident at this size
+                        if (rc) {
+                            cleanup();
+                            return rc;
+                        }
+                        if (ms > 0.0 && (best_long < 0.0 || ms < best_long)) {
+                            best_long = ms;
+                            rc_best = c;
+                        }
+                    }
+        double tb_s = 0.0, tb_l = 0.0, rs_s = 0.0;
+        if (best_long > 0.0) {
+            heat_config tbc = bc;
+            rc = time_run(tbc, nt_short, &tb_s);
+            if (!rc) rc = time_run(tbc, nt_long, &tb_l);
+            if (!rc) rc = time_run(rc_best, nt_short, &rs_s);
+            if (rc) {
+                cleanup();
+                return rc;
+            }
+            if (best_long * RESIDENT_TUNE_MARGIN < tb_l) {
+                // t = a + b * nt for each kernel; the resident one is faster
+                // from nt* = (a_res - a_tb) / (b_tb - b_res) on
+                const double span = (double)(nt_long - nt_short);
+                const double b_tb = (tb_l - tb_s) / span, b_rs = (best_long - rs_s) / span;
+                const double a_tb = tb_s - b_tb * nt_short, a_rs = rs_s - b_rs * nt_short;
+                double cross = b_rs < b_tb ? (a_rs - a_tb) / (b_tb - b_rs) : (double)nt_short;
+                cross = std::min(std::max(cross, 1.0), (double)nt_long);
+                rbest = ResidentEntry{rc_best.cells_per_lane, rc_best.steps_per_round,
+                                      rc_best.waves_per_group, rc_best.register_form,
+                                      rc_best.exchange, (int64_t)std::ceil(cross)};
+            }
+        }
+    }
     cleanup();
     if (install) {
         TuneTable &t = table();
         std::lock_guard<std::mutex> lk(t.mu);
+        t.rs[precision][bucket_of(N)] = rbest;
         TuneEntry &en = t.e[precision][bucket_of(N)];
         en = TuneEntry{bc.cells_per_lane, bc.steps_per_round, bc.waves_per_group, bc.register_form,
                        bc.exchange};
