@@ -83,6 +83,9 @@ def parse():
     ap.add_argument("--workload", default="ring_1e8",
                     choices=["ring_1e6", "ring_1e7", "ring_1e8", "ring_1e8_perturbed",
                              "paper_ramp_1e6"])
+    ap.add_argument("--ring", default=None, metavar="N,STEPS[,R]",
+                    help="instead of a named workload: a Uniform[0,1) ring (seed 3) of N cells, "
+                         "STEPS steps, coefficient R (default 1/2)")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32c"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "tb", "step", "resident"])
     ap.add_argument("--cells-per-lane", type=int, default=0)
@@ -471,6 +474,12 @@ def main():
         return bench_batch(args)
     if args.form == "serve":
         return bench_serve(args)
+    if args.ring:
+        f = args.ring.split(",")
+        N_, nt_ = int(float(f[0])), int(float(f[1]))
+        args.workload = f"ring_{f[0]}_{f[1]}_steps"
+        inputs.WORKLOADS[args.workload] = dict(N=N_, nparts=1, r=float(f[2]) if len(f) > 2 else 0.5,
+                                               nt=nt_, init="uniform", seed=3)
     w = inputs.WORKLOADS[args.workload]
     prec_name = args.precision or ("fp64" if args.workload != "ring_1e8_perturbed" else "fp32c")
     prec = heat.PRECISIONS[prec_name]

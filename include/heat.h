@@ -203,8 +203,8 @@ int heat_solve_dev_cfg(void *d_u, void *d_work, int64_t N, int32_t nparts, doubl
  * asks for the sums.  With every heat_config field zero (or cfg NULL), calls
  * that wait for their result -- those asking for the sums, and heat_solve --
  * take the resident kernel where the tuning table has a resident shape for
- * N's bucket, the run has at least its number of steps and the grid can be
- * resident on the current device; other calls take the round kernel, with
+ * N's quarter decade, the run has at least its number of steps and the grid
+ * can be resident on the current device; other calls take the round kernel, with
  * the same results.  No device work (it may query the device's occupancy).
  */
 int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
@@ -387,17 +387,31 @@ int heat_server_destroy(heat_server *s);
  * default for rings of N's decade (log10 bucket) in this process.  Shapes
  * never change binary64 or binary32 results; for HEAT_FP32C only shapes with
  * the form's fixed round length are tried, at a coefficient that is not a
- * binary32 number (r = 0.3; the others are timed at r = 1/4).  It then times
- * every HEAT_KERNEL_RESIDENT shape that can be resident for N cells over
- * 1,024 steps, and the best of them and the round-kernel winner over 128 and
- * 1,024 steps; if the resident one wins the long run by 3 %, `install` also
- * records its shape for the bucket with the run length from which it is
- * faster (both kernels' times taken as a fixed cost plus a cost per step),
- * and heat_plan shows it.  *best_out is always the round-kernel winner.
- * Allocates and frees 2 * N * 8 bytes of device memory.  Blocking.
+ * binary32 number (r = 0.3; the others are timed at r = 1/4).  Allocates and
+ * frees 2 * N * 8 bytes of device memory.  Blocking.
  */
 int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *best_out,
                   double *best_gcups);
+
+/*
+ * Resident-kernel autotuner for N's quarter decade [10^(q/4), 10^((q+1)/4)):
+ * times every HEAT_KERNEL_RESIDENT shape that can be resident there over
+ * 1,024 steps at both ends of the quarter decade (coefficients as
+ * heat_autotune), against the round kernel the planner runs (the tuning
+ * table's shape); the shape whose smaller gain is the largest wins.  If that
+ * gain is at least 3 %, `install` records the shape for the quarter decade
+ * with the run length from which it is faster at both ends (from the two
+ * kernels' times over 128 and 1,024 steps, each taken as a fixed cost plus a
+ * cost per step); otherwise `install` clears the entry.  Calls that wait for
+ * their result then take it (see heat_plan).  *best_out: the winning shape
+ * (all zero if none can be resident); *min_steps_out: the run length
+ * recorded (0: none); *gain_out: the smaller of the round kernel's time over
+ * the resident time at the two ends, over 1,024 steps (0 if no shape fits).
+ * Any output may be NULL.  Allocates and frees 2 * 10^((q+1)/4) * 8 bytes of
+ * device memory.  Blocking.
+ */
+int heat_autotune_resident(int32_t precision, int64_t N, int32_t install, heat_config *best_out,
+                           int64_t *min_steps_out, double *gain_out);
 
 /*
  * Batch autotuner: times every kernel class of the batching form (cells per

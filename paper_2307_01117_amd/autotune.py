@@ -3,10 +3,11 @@
 Usage: python -m paper_2307_01117_amd.autotune [--out FILE] [--sizes 1e4,1e5,...]
 
 For every precision and ring length it calls heat_autotune (which times each
-temporal-blocking shape with HIP events, then the resident kernel's shapes
-against the winner) and installs the winner for that decade, then
-heat_autotune_batch for the batching form's kernel classes; the table is
-then written with heat_tune_save.  The binding loads
+temporal-blocking shape with HIP events) and installs the winner for that
+decade, then heat_autotune_resident per quarter decade (the resident kernel
+against the round kernel just installed), then heat_autotune_batch for the
+batching form's kernel classes; the table is then written with
+heat_tune_save.  The binding loads
 tune_mi355x.txt next to the library at start-up unless HEAT_TUNE_TABLE names
 another file.
 """
@@ -29,8 +30,12 @@ def main():
                     help="precisions to tune; the others keep the loaded table's entries")
     ap.add_argument("--batch-sizes", default="1e3,1e4,1e5,1e6,1e7",
                     help="ring lengths for the batching form's classes ('' skips them)")
+    ap.add_argument("--resident-sizes",
+                    default="1e5,1.78e5,3.17e5,5.63e5,1e6,1.78e6,3.17e6,5.63e6,1e7",
+                    help="ring lengths (one per quarter decade) at which the resident kernel is "
+                         "timed against the round kernel ('' skips it)")
     ap.add_argument("--no-plain", action="store_true",
-                    help="tune the batching form's classes only")
+                    help="tune the batching form's classes (and resident shapes) only")
     ap.add_argument("--no-verify", action="store_true",
                     help="install the batch classes without the check on a representative batch")
     args = ap.parse_args()
@@ -40,11 +45,15 @@ def main():
         for n in ([] if args.no_plain else args.sizes.split(",")):
             N = int(float(n))
             cfg, g = heat.autotune(prec, N, install=True)
-            # a long run that asks for the sums: the resident kernel's shape if
-            # the tuner recorded one for this bucket
-            long_run = heat.plan(N, 1024, prec)
-            print(json.dumps({"precision": name, "N": N, "best": cfg, "GCUPs": round(g, 1),
-                              "plan_1024_steps": long_run}), flush=True)
+            print(json.dumps({"precision": name, "N": N, "best": cfg, "GCUPs": round(g, 1)}),
+                  flush=True)
+        # the resident kernel against the round kernel just installed, per quarter decade
+        for n in [x for x in args.resident_sizes.split(",") if x]:
+            N = int(float(n))
+            cfg, min_steps, gain = heat.autotune_resident(prec, N, install=True)
+            print(json.dumps({"precision": name, "resident_N": N, "best": cfg,
+                              "gain_1024_steps": round(gain, 3), "min_steps": min_steps}),
+                  flush=True)
         sizes = [int(float(x)) for x in args.batch_sizes.split(",") if x]
         lines = []
         for N in sizes:

@@ -77,8 +77,8 @@ int halo_cells(int64_t steps, int precision, int K);
 int default_register_form(int64_t N, int precision);
 // Launch shape from the tuning table for a ring of length N.
 void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form, int *exchange);
-// The resident kernel's tuned shape for N's bucket (kernel = RESIDENT) and the
-// shortest run it was measured faster on; false if the bucket has none.
+// The resident kernel's tuned shape for N's quarter decade (kernel = RESIDENT)
+// and the shortest run it was measured faster on; false if there is none.
 bool tuned_resident(int64_t N, int precision, heat_config *c, int64_t *min_nt);
 
 // ----------------------------------------------------------- kernels

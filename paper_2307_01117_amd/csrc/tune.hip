@@ -12,8 +12,9 @@
 // A second table holds the batching form's kernel class per (precision,
 // bucket): cells per lane K, waves per tile G and the target round length,
 // picked by the batch autotuner, which times every built class on a
-// synthetic batch of rings of one length.  A third holds, where it won, the
-// resident kernel's shape and the shortest run it is faster on.
+// synthetic batch of rings of one length.  A third holds, per quarter decade
+// of N where it won, the resident kernel's shape and the shortest run it is
+// faster on.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +33,7 @@ namespace heat {
 namespace {
 
 constexpr int NBUCKETS = 10;   // [10^b, 10^(b+1)) for b = 0..8, and >= 1e9
+constexpr int NQUART = 40;     // resident entries: [10^(q/4), 10^((q+1)/4)), and >= 10^9.75
 
 struct TuneEntry {
     int K, T, wpg, form;   // form: 1 in-place, 2 ping-pong, 3 alternating
@@ -53,7 +55,7 @@ struct TuneTable {
     std::mutex mu;
     TuneEntry e[3][NBUCKETS];
     BatchEntry b[3][NBUCKETS];
-    ResidentEntry rs[3][NBUCKETS];
+    ResidentEntry rs[3][NQUART];
     bool env_loaded = false;
     TuneTable() {
         for (int p = 0; p < 3; ++p)
@@ -74,6 +76,26 @@ int bucket_of(int64_t N) {
     return b;
 }
 
+// Quarter-decade bucket: the largest q with N >= ceil(10^(q/4)).
+const int64_t QUARTER_EDGE[NQUART] = {
+        1,         2,          4,          6,          10,         18,         32,
+        57,        100,        178,        317,        563,        1000,       1779,
+        3163,      5624,       10000,      17783,      31623,      56235,      100000,
+        177828,    316228,     562342,     1000000,    1778280,    3162278,    5623414,
+        10000000,  17782795,   31622777,   56234133,   100000000,  177827942,  316227767,
+        562341326, 1000000000, 1778279411, 3162277661LL, 5623413252LL};
+
+int quarter_bucket_of(int64_t N) {
+    int q = 0;
+    while (q + 1 < NQUART && N >= QUARTER_EDGE[q + 1]) ++q;
+    return q;
+}
+
+// First ring length of quarter decade q (q = NQUART: one past the last).
+int64_t quarter_edge(int q) {
+    return q < NQUART ? QUARTER_EDGE[q] : QUARTER_EDGE[NQUART - 1] * 2;
+}
+
 int load_file(const char *path) {
     FILE *f = std::fopen(path, "r");
     if (!f) return fail(HEAT_EINVAL, "cannot open tuning table %s", path);
@@ -83,20 +105,20 @@ int load_file(const char *path) {
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
         if (line[0] == 'r') {
-            // resident shape: "r precision bucket K T G form exchange min_nt"
+            // resident shape: "r precision quarter_bucket K T G form exchange min_nt"
             int p, b, K, T, G, form, xchg;
             long long mn;
             const int got = std::sscanf(line + 1, "%d %d %d %d %d %d %d %lld", &p, &b, &K, &T, &G,
                                         &form, &xchg, &mn);
-            // "r precision bucket 0 0 0 0 0 0": no resident shape for the bucket
-            if (got == 8 && p >= 0 && p <= 2 && b >= 0 && b < NBUCKETS && K == 0 && T == 0 &&
+            // "r precision quarter_bucket 0 0 0 0 0 0": no resident shape for it
+            if (got == 8 && p >= 0 && p <= 2 && b >= 0 && b < NQUART && K == 0 && T == 0 &&
                 G == 0 && form == 0 && xchg == 0 && mn == 0) {
                 std::lock_guard<std::mutex> lk(t.mu);
                 t.rs[p][b] = ResidentEntry{};
                 ++n;
                 continue;
             }
-            if (got != 8 || p < 0 || p > 2 || b < 0 || b >= NBUCKETS ||
+            if (got != 8 || p < 0 || p > 2 || b < 0 || b >= NQUART ||
                 (K != 8 && K != 16 && K != 32 && K != 64) || T < 1 || (T % 4) || 3 * T > 64 * K ||
                 G < 1 || G > 8 || form < 1 || form > 3 || (p != HEAT_FP64 && form != 1) ||
                 xchg < HEAT_EXCHANGE_NONE || xchg > HEAT_EXCHANGE_LDS_DEEP ||
@@ -177,7 +199,7 @@ bool tuned_resident(int64_t N, int precision, heat_config *c, int64_t *min_nt) {
     load_env_once();
     TuneTable &t = table();
     std::lock_guard<std::mutex> lk(t.mu);
-    const ResidentEntry &e = t.rs[precision][bucket_of(N)];
+    const ResidentEntry &e = t.rs[precision][quarter_bucket_of(N)];
     if (e.K == 0) return false;
     *c = heat_config{HEAT_KERNEL_RESIDENT, e.K, e.T, e.G, e.form, e.xchg};
     *min_nt = e.min_nt;
@@ -242,11 +264,11 @@ int heat_tune_save(const char *path) {
         }
     any = false;
     for (int p = 0; p < 3; ++p)
-        for (int b = 0; b < NBUCKETS; ++b) {
+        for (int b = 0; b < NQUART; ++b) {
             const ResidentEntry &e = t.rs[p][b];
             if (!e.K) continue;
             if (!any)
-                std::fprintf(f, "# resident kernel: r precision bucket(log10 N) cells_per_lane "
+                std::fprintf(f, "# resident kernel: r precision quarter_bucket(4 log10 N) cells_per_lane "
                                 "steps_per_round waves_per_group register_form exchange "
                                 "min_steps\n");
             any = true;
@@ -486,20 +508,80 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
                             bc = c;
                         }
                     }
-    // The resident kernel (one launch per run, tiles swapping edges through
-    // memory): every shape that can be resident for this ring, at the same
-    // coefficient, timed over a long run; its best against the round
-    // kernel's winner at a short and a long run.  Each kernel's time is a
-    // fixed cost plus a cost per step, so the two lengths give the run length
-    // from which the resident one is faster; it is kept if it wins the long
-    // run by RESIDENT_TUNE_MARGIN.
-    const int64_t nt_short = 128, nt_long = 1024;
-    auto time_run = [&](const heat_config &c, int64_t nt, double *ms_out) -> int {
-        int rc2 = heat_solve_dev_cfg(a, w, N, 1, r_tune, nt, precision, &c, st, nullptr, nullptr);
-        if (rc2) return rc2;   // also: a resident shape that cannot be resident
+    cleanup();
+    if (install) {
+        TuneTable &t = table();
+        std::lock_guard<std::mutex> lk(t.mu);
+        TuneEntry &en = t.e[precision][bucket_of(N)];
+        en = TuneEntry{bc.cells_per_lane, bc.steps_per_round, bc.waves_per_group, bc.register_form,
+                       bc.exchange};
+        if (precision == HEAT_FP32C) en.T = default_steps_per_round(N, precision);
+    }
+    if (best_out) *best_out = bc;
+    if (best_gcups) *best_gcups = best;
+    return HEAT_OK;
+}
+
+// The resident kernel against the round kernel the planner runs (the
+// table's shape), for N's quarter decade: every resident shape that can be
+// resident there is timed over a long run at both ends of the quarter decade
+// (its speed jumps with the tile count against the CU count, so a shape
+// that fits one end may not fit the other), and the shape whose smaller gain
+// over the round kernel is the largest wins; then it and the round kernel
+// are timed over a short run at both ends too.  Each kernel's time is a fixed
+// cost plus a cost per step, so the two lengths give, at each end, the run
+// length from which the resident one is faster; the larger is recorded.  It
+// is kept if its smaller gain is RESIDENT_TUNE_MARGIN.
+int heat_autotune_resident(int32_t precision, int64_t N, int32_t install, heat_config *best_out,
+                           int64_t *min_steps_out, double *gain_out) {
+    if (precision != HEAT_FP64 && precision != HEAT_FP32 && precision != HEAT_FP32C)
+        return fail(HEAT_EINVAL, "unknown precision %d", precision);
+    if (N < 1 || N > (int64_t(1) << 34)) return fail(HEAT_EINVAL, "N out of range");
+    int rc = device_pool_setup();
+    if (rc) return rc;
+    const int q = quarter_bucket_of(N);
+    const int64_t ends[2] = {quarter_edge(q), std::max(quarter_edge(q), quarter_edge(q + 1) - 1)};
+    hipStream_t st = nullptr;
+    HEAT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    const size_t es = storage_bytes(precision);
+    void *a = nullptr, *w = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (a) (void)hipFreeAsync(a, st);
+        if (w) (void)hipFreeAsync(w, st);
+        (void)hipStreamSynchronize(st);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamDestroy(st);
+    };
+    const int64_t Nmax = ends[1];
+    hipError_t e = hipMallocAsync(&a, (size_t)Nmax * std::max<size_t>(es, 8), st);
+    if (e == hipSuccess) e = hipMallocAsync(&w, (size_t)Nmax * std::max<size_t>(es, 8), st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail_hip(e, "autotune setup");
+    }
+    hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(256), 0, st, (double *)w, Nmax);
+    if (precision == HEAT_FP64)
+        e = hipMemcpyAsync(a, w, (size_t)Nmax * 8, hipMemcpyDeviceToDevice, st);
+    else
+        e = launch_f64_to_f32((const double *)w, (float *)a, Nmax, st);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail_hip(e, "autotune fill");
+    }
+    // the coefficient as in heat_autotune
+    const double r_tune = precision == HEAT_FP32C ? 0.3 : 0.25;
+    // one untimed call (it also refuses a shape that cannot be resident),
+    // then one timed
+    auto time_run = [&](const heat_config &c, int64_t n, int64_t nt, double *ms_out) -> int {
+        int rc2 = heat_solve_dev_cfg(a, w, n, 1, r_tune, nt, precision, &c, st, nullptr, nullptr);
+        if (rc2) return rc2;
         hipError_t e2 = hipEventRecord(e0, st);
         if (e2 == hipSuccess)
-            rc2 = heat_solve_dev_cfg(a, w, N, 1, r_tune, nt, precision, &c, st, nullptr, nullptr);
+            rc2 = heat_solve_dev_cfg(a, w, n, 1, r_tune, nt, precision, &c, st, nullptr, nullptr);
         if (!rc2 && e2 == hipSuccess) e2 = hipEventRecord(e1, st);
         if (!rc2 && e2 == hipSuccess) e2 = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -508,72 +590,85 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
         *ms_out = ms;
         return rc2;
     };
-    ResidentEntry rbest;
-    {
-        const bool comp = precision == HEAT_FP32C;
-        const int T_comp = default_steps_per_round(N, precision);
-        double best_long = -1.0;
-        heat_config rc_best{};
-        struct GX { int G, x; };
-        for (int K : {8, 16, 32})
-            for (GX gx : {GX{1, HEAT_EXCHANGE_NONE}, GX{2, HEAT_EXCHANGE_LDS_DEEP},
-                          GX{4, HEAT_EXCHANGE_LDS}, GX{4, HEAT_EXCHANGE_LDS_DEEP},
-                          GX{8, HEAT_EXCHANGE_LDS_DEEP}})
-                for (int form : {1, 3})
-                    for (int T : {32, 48, 64, 96, 128}) {
-                        if (comp && T != T_comp) continue;
-                        if (precision != HEAT_FP64 && form != 1) continue;
-                        if (3 * T > 64 * K) continue;
-                        if (gx.x == HEAT_EXCHANGE_LDS && K < 16) continue;
-                        heat_config c{HEAT_KERNEL_RESIDENT, K, T, gx.G, form, gx.x};
-                        double ms = 0.0;
-                        rc = time_run(c, nt_long, &ms);
-                        if (rc == HEAT_EINVAL) continue;   // not resident at this size
-                        if (rc) {
+    const int64_t nt_short = 128, nt_long = 1024;
+    const heat_config tb{HEAT_KERNEL_TB, 0, 0, 0, 0, 0};   // what the planner runs
+    double tb_l[2] = {0, 0}, tb_s[2] = {0, 0};
+    for (int k = 0; k < 2 && !rc; ++k) {
+        rc = time_run(tb, ends[k], nt_long, &tb_l[k]);
+        if (!rc) rc = time_run(tb, ends[k], nt_short, &tb_s[k]);
+    }
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    const bool comp = precision == HEAT_FP32C;
+    double best_score = 0.0;
+    double best_l[2] = {0, 0};
+    heat_config rc_best{};
+    struct GX { int G, x; };
+    for (int K : {8, 16, 32})
+        for (GX gx : {GX{1, HEAT_EXCHANGE_NONE}, GX{2, HEAT_EXCHANGE_LDS_DEEP},
+                      GX{4, HEAT_EXCHANGE_LDS}, GX{4, HEAT_EXCHANGE_LDS_DEEP},
+                      GX{8, HEAT_EXCHANGE_LDS_DEEP}})
+            for (int form : {1, 3})
+                for (int T : {32, 48, 64, 96, 128}) {
+                    if (comp && T != default_steps_per_round(N, precision)) continue;
+                    if (precision != HEAT_FP64 && form != 1) continue;
+                    if (3 * T > 64 * K) continue;
+                    if (gx.x == HEAT_EXCHANGE_LDS && K < 16) continue;
+                    heat_config c{HEAT_KERNEL_RESIDENT, K, T, gx.G, form, gx.x};
+                    double ms[2] = {0, 0};
+                    bool fits = true;
+                    for (int k = 0; k < 2 && fits; ++k) {
+                        rc = time_run(c, ends[k], nt_long, &ms[k]);
+                        if (rc == HEAT_EINVAL) fits = false;   // not resident at this size
+                        else if (rc) {
                             cleanup();
                             return rc;
                         }
-                        if (ms > 0.0 && (best_long < 0.0 || ms < best_long)) {
-                            best_long = ms;
-                            rc_best = c;
-                        }
                     }
-        double tb_s = 0.0, tb_l = 0.0, rs_s = 0.0;
-        if (best_long > 0.0) {
-            heat_config tbc = bc;
-            rc = time_run(tbc, nt_short, &tb_s);
-            if (!rc) rc = time_run(tbc, nt_long, &tb_l);
-            if (!rc) rc = time_run(rc_best, nt_short, &rs_s);
-            if (rc) {
-                cleanup();
-                return rc;
-            }
-            if (best_long * RESIDENT_TUNE_MARGIN < tb_l) {
-                // t = a + b * nt for each kernel; the resident one is faster
-                // from nt* = (a_res - a_tb) / (b_tb - b_res) on
-                const double span = (double)(nt_long - nt_short);
-                const double b_tb = (tb_l - tb_s) / span, b_rs = (best_long - rs_s) / span;
-                const double a_tb = tb_s - b_tb * nt_short, a_rs = rs_s - b_rs * nt_short;
-                double cross = b_rs < b_tb ? (a_rs - a_tb) / (b_tb - b_rs) : (double)nt_short;
-                cross = std::min(std::max(cross, 1.0), (double)nt_long);
-                rbest = ResidentEntry{rc_best.cells_per_lane, rc_best.steps_per_round,
-                                      rc_best.waves_per_group, rc_best.register_form,
-                                      rc_best.exchange, (int64_t)std::ceil(cross)};
-            }
+                    if (!fits || ms[0] <= 0.0 || ms[1] <= 0.0) continue;
+                    const double score = std::min(tb_l[0] / ms[0], tb_l[1] / ms[1]);
+                    if (score > best_score) {
+                        best_score = score;
+                        rc_best = c;
+                        best_l[0] = ms[0];
+                        best_l[1] = ms[1];
+                    }
+                }
+    rc = HEAT_OK;
+    ResidentEntry found;
+    if (best_score >= RESIDENT_TUNE_MARGIN) {
+        double cross = 1.0;
+        for (int k = 0; k < 2 && !rc; ++k) {
+            double rs_s = 0.0;
+            rc = time_run(rc_best, ends[k], nt_short, &rs_s);
+            if (rc) break;
+            // t = a + b * nt for each kernel; the resident one is faster from
+            // nt* = (a_res - a_tb) / (b_tb - b_res) on
+            const double span = (double)(nt_long - nt_short);
+            const double b_tb = (tb_l[k] - tb_s[k]) / span, b_rs = (best_l[k] - rs_s) / span;
+            const double a_tb = tb_s[k] - b_tb * nt_short, a_rs = rs_s - b_rs * nt_short;
+            const double c = b_rs < b_tb ? (a_rs - a_tb) / (b_tb - b_rs) : (double)nt_short;
+            cross = std::max(cross, std::min(c, (double)nt_long));
         }
+        if (rc) {
+            cleanup();
+            return rc;
+        }
+        found = ResidentEntry{rc_best.cells_per_lane, rc_best.steps_per_round,
+                              rc_best.waves_per_group, rc_best.register_form, rc_best.exchange,
+                              (int64_t)std::ceil(cross)};
     }
     cleanup();
     if (install) {
         TuneTable &t = table();
         std::lock_guard<std::mutex> lk(t.mu);
-        t.rs[precision][bucket_of(N)] = rbest;
-        TuneEntry &en = t.e[precision][bucket_of(N)];
-        en = TuneEntry{bc.cells_per_lane, bc.steps_per_round, bc.waves_per_group, bc.register_form,
-                       bc.exchange};
-        if (precision == HEAT_FP32C) en.T = default_steps_per_round(N, precision);
+        t.rs[precision][q] = found;
     }
-    if (best_out) *best_out = bc;
-    if (best_gcups) *best_gcups = best;
+    if (best_out) *best_out = best_score > 0.0 ? rc_best : heat_config{};
+    if (min_steps_out) *min_steps_out = found.min_nt;
+    if (gain_out) *gain_out = best_score;
     return HEAT_OK;
 }
 

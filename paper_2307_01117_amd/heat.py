@@ -34,7 +34,7 @@ EXPORTS = [
     "heat_poll", "heat_wait", "heat_cancel", "heat_server_get_stats", "heat_server_destroy",
     "heat_last_error", "heat_version", "heat_device_info", "heat_copy_dev",
     "heat_autotune", "heat_tune_save", "heat_tune_load", "heat_solve_dev_noalloc",
-    "heat_autotune_batch",
+    "heat_autotune_batch", "heat_autotune_resident",
 ]
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # HEAT_NOALLOC_SCRATCH_BYTES
@@ -133,6 +133,7 @@ def load(path: str = LIB_PATH):
         "heat_copy_dev": ([vp, vp, ctypes.c_size_t, vp], i32),
         "heat_autotune": ([i32, i64, i32, P(heat_config), pd], i32),
         "heat_autotune_batch": ([i32, i64, i32, P(i32), P(i32), P(i32), pd], i32),
+        "heat_autotune_resident": ([i32, i64, i32, P(heat_config), P(i64), pd], i32),
         "heat_tune_save": ([ctypes.c_char_p], i32),
         "heat_tune_load": ([ctypes.c_char_p], i32),
     }
@@ -174,6 +175,18 @@ def _cfg(kernel=0, cells_per_lane=0, steps_per_round=0, waves_per_group=0, regis
         return None
     return ctypes.byref(heat_config(kernel, cells_per_lane, steps_per_round, waves_per_group,
                                     register_form, exchange))
+
+
+def autotune_resident(precision: int, N: int, install: bool = True):
+    """Time the resident kernel's shapes at N cells against the round kernel
+    the planner runs; returns (best resident config dict, minimum run length
+    recorded (0: none), round-kernel time / resident time over 1,024 steps)."""
+    cfg = heat_config()
+    mn = ctypes.c_int64()
+    g = ctypes.c_double()
+    _check(load().heat_autotune_resident(int(precision), int(N), int(bool(install)),
+                                         ctypes.byref(cfg), ctypes.byref(mn), ctypes.byref(g)))
+    return {f: getattr(cfg, f) for f, _ in heat_config._fields_}, mn.value, g.value
 
 
 def autotune(precision: int, N: int, install: bool = True):

@@ -272,27 +272,28 @@ def test_planner_deep_exchange_geometry(lib, K, G, T):
 
 
 def test_tune_table_resident_lines(lib, tmp_path):
-    """Resident kernel lines ("r precision bucket K T G form exchange
+    """Resident kernel lines ("r precision quarter_bucket K T G form exchange
     min_steps") load and are written back by heat_tune_save; all-zero fields
-    clear the bucket; inconsistent shapes are refused.  (Bucket 9, rings of
-    1e9 cells and more, which no test runs.)"""
+    clear the quarter decade; inconsistent shapes are refused.  (Quarter
+    decades 9 and 39: rings of 178 to 316 cells, and of 10^9.75 and more.)"""
     good = tmp_path / "good.txt"
-    good.write_text("r 0 9 16 64 4 3 3 400\nr 2 9 32 64 1 1 1 256\n")
+    good.write_text("r 0 39 16 64 4 3 3 400\nr 2 9 32 64 1 1 1 256\n")
     heat.tune_load(str(good))
     out = tmp_path / "out.txt"
     heat.tune_save(str(out))
     text = out.read_text()
-    assert "r 0 9 16 64 4 3 3 400" in text and "r 2 9 32 64 1 1 1 256" in text
+    assert "r 0 39 16 64 4 3 3 400" in text and "r 2 9 32 64 1 1 1 256" in text
     clear = tmp_path / "clear.txt"
-    clear.write_text("r 0 9 0 0 0 0 0 0\nr 2 9 0 0 0 0 0 0\n")
+    clear.write_text("r 0 39 0 0 0 0 0 0\nr 2 9 0 0 0 0 0 0\n")
     heat.tune_load(str(clear))
     heat.tune_save(str(out))
-    assert "r 0 9" not in out.read_text() and "r 2 9" not in out.read_text()
+    assert "r 0 39 " not in out.read_text() and "r 2 9 " not in out.read_text()
     for bad in ("r 0 9 16 64 2 3 1 400\n",      # lone waves with 2 per group
                 "r 1 9 16 64 4 3 3 400\n",      # binary32 in the alternating form
                 "r 0 9 8 64 4 3 2 400\n",       # K/4 exchange with 8 cells per lane
                 "r 0 9 16 66 4 3 3 400\n",      # T not a multiple of 4
-                "r 0 9 16 64 4 3 3 0\n"):       # no minimum run length
+                "r 0 9 16 64 4 3 3 0\n",       # no minimum run length
+                "r 0 40 16 64 4 3 3 400\n"):   # no quarter decade 40
         f = tmp_path / "bad.txt"
         f.write_text(bad)
         with pytest.raises(heat.HeatError) as ei:
