@@ -288,13 +288,13 @@ def test_device_batch_seeded_256_ring_subset():
         assert u[i].item() == oracle.cone(u0, i, s.r, s.nt), (s.N, s.nt, i)
 
 
-@pytest.mark.skipif(os.environ.get("HEAT_FULL_BATCH_PARITY") != "1",
-                    reason="one-off full check, minutes of host CPU: set HEAT_FULL_BATCH_PARITY=1")
 def test_device_batch_full_4096_rings_vs_oracle():
     """Every ring of the full batching workload (4,096 rings, about 3e12 cell
     updates), batched in binary64 as the benchmark runs it, compared bit for
-    bit with the oracle's segmented solver, one host thread per ring and up to
-    16 rings at a time (the C oracle runs without the interpreter lock)."""
+    bit with the oracle's segmented solver (its vectorised sweep, pinned
+    bit-identical to the scalar one), one host thread per ring and up to 16
+    rings at a time (the C oracle runs without the interpreter lock): about a
+    minute of host CPU."""
     specs = inputs.batch_specs(count=4096, seed=4)
     u0s = [inputs.ring_initial(s) for s in specs]
     us = [torch.from_numpy(u).cuda() for u in u0s]
@@ -307,7 +307,7 @@ def test_device_batch_full_4096_rings_vs_oracle():
 
     def check(j):
         s = specs[j]
-        return same_bits(got[j], oracle.solve_threads(u0s[j], 1, s.r, s.nt))
+        return same_bits(got[j], oracle.solve_threads(u0s[j], 1, s.r, s.nt, simd=True))
 
     t0 = time.perf_counter()
     bad, done = [], 0

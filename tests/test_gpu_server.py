@@ -294,16 +294,14 @@ def test_busy_server_classes_equal_alone():
         assert same_bits(res.u, alone(u0, nt, r, prec)), (u0.size, nt, prec)
 
 
-@pytest.mark.skipif(os.environ.get("HEAT_FULL_SERVE_PARITY") != "1",
-                    reason="one-off check, minutes of host CPU: set HEAT_FULL_SERVE_PARITY=1")
 def test_serving_trace_vs_oracle():
-    """The serving workload at 200 requests/s (Poisson arrivals, 20 s unless
+    """The serving workload at 200 requests/s (Poisson arrivals, 10 s unless
     HEAT_SERVE_PARITY_SECONDS says otherwise) through one server: every
     request with N*nt <= 1e9 compared bit for bit with the oracle over the
     whole ring (binary64: the segmented C solver; compensated binary32: its C
     solver with the form's round length), and a seeded 2 % sample of the
     larger ones at 16 cells each through the oracle's light cone."""
-    duration = float(os.environ.get("HEAT_SERVE_PARITY_SECONDS", "20"))
+    duration = float(os.environ.get("HEAT_SERVE_PARITY_SECONDS", "10"))
     P, nmax = 1 << 24, 10_000_000
     pool = np.empty(P + nmax)
     pool[:P] = inputs.serving_pool(P)
@@ -335,7 +333,7 @@ def test_serving_trace_vs_oracle():
         u0 = pool[q.offset:q.offset + q.N]
         if w:
             if q.precision == heat.FP64:
-                want = oracle.solve_threads(u0, 1, q.r, q.nt)
+                want = oracle.solve_threads(u0, 1, q.r, q.nt, simd=True)
             else:
                 want = oracle.solve_f32c(u0.astype(np.float32), q.r, q.nt, T[j])
             return j, q, same_bits(res.u, want)
