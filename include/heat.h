@@ -202,10 +202,19 @@ int heat_solve_dev_cfg(void *d_u, void *d_work, int64_t N, int32_t nparts, doubl
  * Planner: what heat_solve_dev_cfg would run for this problem, in a call that
  * asks for the sums.  With every heat_config field zero (or cfg NULL), calls
  * that wait for their result -- those asking for the sums, and heat_solve --
- * take the resident kernel where the tuning table has a resident shape for
- * N's quarter decade, the run has at least its number of steps and the grid
- * can be resident on the current device; other calls take the round kernel, with
- * the same results.  No device work (it may query the device's occupancy).
+ * may take the resident kernel: the tuning table records up to six
+ * resident shapes for N's quarter decade, each with its shortest winning run
+ * and its gain over the round kernel at full SIMD load at three points of
+ * the quarter decade (see heat_autotune_resident; both are taken linear in
+ * log N between the points).  Each shape the run is long enough for is
+ * fitted to N -- a CU holds ceil(tiles / CUs) workgroups
+ * and every tile waits for the slowest, so for HEAT_FP64 and HEAT_FP32
+ * (whose results do not depend on T) the exchange interval, from the tuned
+ * T down to half of it, whose tiles put the fewest waves on the busiest SIMD
+ * is taken -- and must fit the device at once; the shape whose gain at full
+ * load at N times its load efficiency at N (mean over busiest waves per
+ * SIMD) is the largest is taken if that is at least 1.03.  Other calls take the round kernel, with the same results.
+ * No device work (it may query the device's occupancy).
  */
 int heat_plan(int64_t N, int64_t nt, int32_t precision, const heat_config *cfg,
               heat_plan_info *out);
@@ -395,20 +404,29 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
 
 /*
  * Resident-kernel autotuner for N's quarter decade [10^(q/4), 10^((q+1)/4)):
- * times every HEAT_KERNEL_RESIDENT shape that can be resident there over
- * 1,024 steps at both ends of the quarter decade (coefficients as
- * heat_autotune), against the round kernel the planner runs (the tuning
- * table's shape); the shape whose smaller gain is the largest wins.  If that
- * gain is at least 3 %, `install` records the shape for the quarter decade
- * with the run length from which it is faster at both ends (from the two
+ * times every HEAT_KERNEL_RESIDENT shape over 1,024 steps at three points of
+ * the quarter decade (its two ends and their geometric middle), each fitted
+ * to the point as heat_plan fits it, against the round kernel the planner
+ * runs (the tuning table's shape); coefficients as heat_autotune, HEAT_FP32C
+ * also at r = 1/4 (whose kernel drops the coefficient's low part), the
+ * smaller gain counting; each time the fastest of three calls.  Each shape's
+ * gain at each point over its load efficiency there is its gain at full
+ * load; heat_plan's model (that gain interpolated, times the load efficiency
+ * at N) then picks a shape at each of 64 ring lengths spread over the
+ * quarter decade, where one predicts a gain of at least 3 %.  `install`
+ * records up to six shapes -- the fastest at each point where it gains at
+ * least 3 %, then those the model picks most often (none clears the quarter
+ * decade) -- each with its gain at full load at each point and, at each
+ * point where it gains, the run length from which it is faster (from both
  * kernels' times over 128 and 1,024 steps, each taken as a fixed cost plus a
- * cost per step); otherwise `install` clears the entry.  Calls that wait for
- * their result then take it (see heat_plan).  *best_out: the winning shape
- * (all zero if none can be resident); *min_steps_out: the run length
- * recorded (0: none); *gain_out: the smaller of the round kernel's time over
- * the resident time at the two ends, over 1,024 steps (0 if no shape fits).
- * Any output may be NULL.  Allocates and frees 2 * 10^((q+1)/4) * 8 bytes of
- * device memory.  Blocking.
+ * cost per step).
+ * Calls that wait for their result then choose among them.  *best_out: the
+ * first shape recorded (else the fastest at the lower end; all zero if none
+ * can be resident); *min_steps_out: the largest run length recorded (0: none);
+ * *gain_out: the smallest over the three points of the best gain measured
+ * there, the round kernel's time over the resident time over 1,024 steps
+ * (0 if some point fits no shape).  Any output may be NULL.  Allocates and
+ * frees 2 * 10^((q+1)/4) * 8 bytes of device memory.  Blocking.
  */
 int heat_autotune_resident(int32_t precision, int64_t N, int32_t install, heat_config *best_out,
                            int64_t *min_steps_out, double *gain_out);

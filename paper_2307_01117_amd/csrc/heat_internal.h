@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include <string>
 
 #include "heat.h"
@@ -77,9 +79,57 @@ int halo_cells(int64_t steps, int precision, int K);
 int default_register_form(int64_t N, int precision);
 // Launch shape from the tuning table for a ring of length N.
 void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form, int *exchange);
-// The resident kernel's tuned shape for N's quarter decade (kernel = RESIDENT)
-// and the shortest run it was measured faster on; false if there is none.
-bool tuned_resident(int64_t N, int precision, heat_config *c, int64_t *min_nt);
+// Resident shapes the tuning table keeps per quarter decade (the planner
+// picks one per call), and the points of a quarter decade the tuner
+// measures them at: its two ends and their geometric middle.
+constexpr int RESIDENT_SHAPES = 6;
+constexpr int RESIDENT_POINTS = 3;
+struct ResidentChoice {
+    heat_config c;                   // kernel = RESIDENT, the tuned T
+    double min_nt[RESIDENT_POINTS];  // at each point, the run length from which it is
+                                     // faster (0: it does not gain there)
+    double gain[RESIDENT_POINTS];    // gain over the round kernel at full SIMD load at
+                                     // each point (0: cannot run there; all 0: not recorded)
+};
+// The resident shapes recorded for N's quarter decade; returns how many.
+int tuned_resident(int64_t N, int precision, ResidentChoice (&out)[RESIDENT_SHAPES]);
+// The measuring points of N's quarter decade.
+void resident_points(int64_t N, int64_t (&pts)[RESIDENT_POINTS]);
+// A quantity recorded at the points (a shape's gain at full load, or its
+// shortest winning run) at N: linear in log N between the points, constant
+// beyond them; a point where it is 0 (not measured) is skipped.
+inline double resident_interp(const double (&g)[RESIDENT_POINTS],
+                              const int64_t (&pts)[RESIDENT_POINTS], int64_t N) {
+    double xs[RESIDENT_POINTS], ys[RESIDENT_POINTS];
+    int n = 0;
+    for (int k = 0; k < RESIDENT_POINTS; ++k) {
+        const double x = std::log((double)pts[k]);
+        if (g[k] > 0.0 && (n == 0 || x > xs[n - 1])) {
+            xs[n] = x;
+            ys[n++] = g[k];
+        }
+    }
+    if (n == 0) return 0.0;
+    const double x = std::log((double)N);
+    if (x <= xs[0]) return ys[0];
+    for (int i = 1; i < n; ++i)
+        if (x <= xs[i]) return ys[i - 1] + (ys[i] - ys[i - 1]) * (x - xs[i - 1]) / (xs[i] - xs[i - 1]);
+    return ys[n - 1];
+}
+
+// Gain the resident kernel must show over the round kernel on a long run.
+constexpr double RESIDENT_TUNE_MARGIN = 1.03;
+
+// A resident shape fitted to N: for binary64 and binary32 (whose results do
+// not depend on T) the exchange interval, from the tuned T down to half of
+// it, whose tiles put the fewest waves on the busiest SIMD (a CU takes
+// ceil(tiles / CUs) workgroups, whose waves share its 4 SIMDs, and every
+// tile waits for the slowest); the longest on a tie.  *fitted: that shape;
+// *eff: its load efficiency, the mean number of waves per SIMD over the
+// busiest SIMD's, in (0, 1].  HEAT_EINVAL if no interval lets every tile be
+// resident at once.
+int resident_fit(int64_t N, int64_t nt, int precision, const heat_config &c,
+                 heat_config *fitted, double *eff);
 
 // ----------------------------------------------------------- kernels
 
@@ -147,7 +197,7 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
 // One launch of the resident kernel (resident.h): every tile's window stays
 // in registers for all nt steps; tiles swap edges through buf[] every T steps.
 struct ResidentArgs {
-    void *buf[2];            // buf[0]: state in and out; buf[1]: scratch of N cells
+    void *u;                 // state in and out, N cells
     int64_t N;
     int64_t W;               // output cells per tile
     int64_t tiles;
@@ -155,14 +205,21 @@ struct ResidentArgs {
     int32_t H;               // halo cells per side (>= T)
     int32_t T;               // steps between edge exchanges
     double r;
+    uint64_t *xa;            // exchange area, resident_area_words(); every tag <= epoch_base
     uint32_t *flags;         // [tiles] epoch counters, all <= epoch_base at launch
     uint32_t epoch_base;     // this launch's epochs are epoch_base + 1, 2, ...
     uint32_t *status;        // [1] zero at launch; nonzero once a wait timed out
     int64_t spin_limit;
     double *part_in;         // per-wave sums of the input, or NULL
     double *part_out;        // per-wave sums of the output, or NULL
-    int32_t vec_ok;          // buf[0] and buf[1] 16-byte aligned
+    int32_t vec_ok;          // u 16-byte aligned
 };
+// 64-bit words of a resident launch's exchange area: two parities, per tile
+// its first and its last H owned cells, each cell one word per 32 bits of its
+// storage type (32 bits of the value beside a 32-bit epoch tag).
+inline int64_t resident_area_words(int64_t tiles, int H, int cell_bytes) {
+    return 2 * tiles * 2 * (int64_t)H * (cell_bytes / 4);
+}
 // Launch (or, with blocks_per_cu set, report how many workgroups of that
 // shape one CU holds) for a precision, cells per lane, register form,
 // waves per group and exchange depth (0, 4 or 2).  kernels_resident.hip

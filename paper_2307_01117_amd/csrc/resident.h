@@ -11,21 +11,27 @@
 // every round).
 //
 // Edge exchange.  After every T steps each tile writes the first H and the
-// last H cells it owns into the ring buffer buf[e & 1] (e = the number of
-// exchanges so far, counting this one), raises its epoch counter to e, waits
-// until every tile within H cells of it on the ring has reached e, and reads
-// its outer halo -- the H cells left of its output and the H cells right of
-// it -- from that buffer.  The two buffers alternate, so a buffer is written
-// again only two exchanges later, when every reader has moved on: a tile
-// writes buf[e & 1] at exchange e + 2 only after its neighbours reached
-// e + 1, and they read buf[e & 1] before they could.  At the end every tile
-// writes its whole output into buf[0]; buf[0] was last written at the last
-// even exchange, and its readers have used it once they reach the next
-// epoch, so a tile whose final epoch R is odd first waits for its
-// neighbours to reach R (each tile raises its counter to R when done).
+// last H cells it owns into its slots of parity e & 1 in an exchange area (e =
+// the number of exchanges so far, counting this one), every value as 64-bit
+// words of 32 value bits beside the 32-bit tag epoch_base + e, and then
+// reads its outer halo -- the H cells left of its output and the H cells
+// right of it -- from its neighbours' slots, polling each word until its tag
+// reads e.  A 64-bit store and load are single-copy atomic, so a word with
+// the right tag holds that epoch's bits: no counter, fence or wait for the
+// stores' completion stands between a tile's edges and its neighbours'
+// reads.  The two parities alternate, so a slot is written again only two
+// exchanges later, when every reader has moved on: a tile writes parity e & 1
+// at exchange e + 2 only after it has read its neighbours' exchange e + 1,
+// which they wrote after their reads of exchange e.  At the end every tile
+// writes its output back into the ring.  Its neighbours loaded their
+// windows from the ring before their first exchange; a run that makes no
+// exchange (nt <= T) orders them by epoch counters instead: every tile
+// raises its counter once loaded and waits for its neighbours' before it
+// stores.
 //
-// The counters are not cleared between launches: a launch counts on from
-// epoch_base, which every counter of the previous launch ended at or below.
+// Tags and counters are not cleared between launches: a launch counts on
+// from epoch_base, which every tag and counter of the previous launch ended
+// at or below.
 //
 // Every tile must be resident at once (the waits are across workgroups):
 // the launcher refuses grids larger than the occupancy allows, and a wait
@@ -44,8 +50,9 @@
 
 namespace heat {
 
-// Poll an epoch counter until it reaches `need` (relaxed polls: the caller
-// issues one acquire fence after all of its waits).
+// Poll an epoch counter until it reaches `need`.  The counters only order
+// a tile's final stores after its neighbours' window loads, whose values
+// were in registers before the neighbours raised them: relaxed polls do.
 __device__ __forceinline__ bool resident_wait(const ResidentArgs &a, int64_t tile,
                                               uint32_t need) {
     int64_t spins = 0;
@@ -86,6 +93,74 @@ __device__ __forceinline__ bool resident_wait_neighbours(const ResidentArgs &a, 
         acc += q == a.tiles - 1 ? last_len : a.W;
     }
     return true;
+}
+
+// An edge cell in the exchange area: one 64-bit word per 32 bits of the
+// value, its high half the epoch tag.
+template <class T>
+struct EdgeWord;
+template <>
+struct EdgeWord<double> {
+    static constexpr int WORDS = 2;
+    __device__ static void put(uint64_t *s, double x, uint32_t tag) {
+        const uint64_t bits = (uint64_t)__double_as_longlong(x);
+        const uint64_t t = (uint64_t)tag << 32;
+        __hip_atomic_store(s, (bits & 0xffffffffu) | t, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(s + 1, (bits >> 32) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static bool get(const uint64_t *s, uint32_t tag, double &x) {
+        const uint64_t lo = __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t hi = __hip_atomic_load(s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(lo >> 32) != tag || (uint32_t)(hi >> 32) != tag) return false;
+        x = __longlong_as_double((long long)((lo & 0xffffffffu) | (hi << 32)));
+        return true;
+    }
+};
+template <>
+struct EdgeWord<float> {
+    static constexpr int WORDS = 1;
+    __device__ static void put(uint64_t *s, float x, uint32_t tag) {
+        __hip_atomic_store(s, (uint64_t)__float_as_uint(x) | (uint64_t)tag << 32,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static bool get(const uint64_t *s, uint32_t tag, float &x) {
+        const uint64_t w = __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(w >> 32) != tag) return false;
+        x = __uint_as_float((uint32_t)w);
+        return true;
+    }
+};
+
+// Slot (cells from the start of a parity) that halo cell i of tile t is
+// read from.  i < H: the cell H - i left of the tile's output, among the
+// last H owned cells (side 1) of the tile it falls in; i >= H: the cell
+// i - H right of its end, among the first H (side 0).  Tile q's slots are
+// [q * 2H, q * 2H + H) for side 0 and the next H for side 1; side 1 slot j
+// holds owned cell L - H + j of a tile of L cells.  Only the last tile can
+// be shorter than H, so the walks visit two tiles at most.
+__device__ __forceinline__ int64_t edge_source(const ResidentArgs &a, int64_t t, int i,
+                                               int64_t last_len) {
+    const int H = a.H;
+    int64_t q = t;
+    if (i < H) {
+        int64_t d = H - i;
+        for (int64_t g = 0; g < a.tiles; ++g) {
+            q = q == 0 ? a.tiles - 1 : q - 1;
+            const int64_t L = q == a.tiles - 1 ? last_len : a.W;
+            if (d <= L) break;
+            d -= L;
+        }
+        return q * 2 * H + H + (H - d);
+    }
+    int64_t d = i - H;
+    for (int64_t g = 0; g < a.tiles; ++g) {
+        q = q + 1 == a.tiles ? 0 : q + 1;
+        const int64_t L = q == a.tiles - 1 ? last_len : a.W;
+        if (d < L) break;
+        d -= L;
+    }
+    return q * 2 * H + d;
 }
 
 // The LDS copy of a tile: window cells of tile coordinate c (c = H + output
@@ -158,7 +233,7 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
     const bool fast = a.vec_ok && b - H >= 0 && b + W + H <= N && wlen == W;
     const T r = (T)a.r;
     const T rl = P::LOW ? (T)(a.r - (double)r) : T(0);
-    T *const ring0 = reinterpret_cast<T *>(a.buf[0]);
+    T *const ring0 = reinterpret_cast<T *>(a.u);
     if (threadIdx.x == 0) abort_flag = 0;
 
     T v[K], e[K];
@@ -183,6 +258,8 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
     const bool halo_lane =
         runs_meet(c0, c0 + K, 0, H) || runs_meet(c0, c0 + K, wl + H, wl + 2 * H);
     const int nthr = blockDim.x;
+    constexpr int WORDS = EdgeWord<T>::WORDS;
+    const int64_t last_len = N - (a.tiles - 1) * W;
     int xbuf = 0;
     uint32_t epoch = 0;
     int64_t done = 0;
@@ -224,56 +301,56 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
             exchange_take<K, XD>(v, xu, xbuf, G, w, lane);
             xbuf ^= 1;
         }
-        // publish the first and the last H owned cells through the tile copy
-        T *pub = reinterpret_cast<T *>(a.buf[epoch & 1]);
+        // publish the first and the last H owned cells through the tile copy,
+        // then read the outer halo (output positions [-H, 0) and [wl, wl + H),
+        // tile coordinates [0, H) and [wl + H, wl + 2H)) from the neighbours'
+        // slots of this parity
+        const uint32_t tag = a.epoch_base + epoch;
+        uint64_t *const area = a.xa + (int64_t)(epoch & 1) * a.tiles * 2 * H * WORDS;
         if (io_lane) tile_lds_put<P, K>(tl, c0, v);
         __syncthreads();
-        // Edge cells cross the device as agent-scope atomic stores and loads,
-        // which are coherent across the XCDs' L2 caches by themselves: no
-        // L2 writeback or invalidation is needed, only the order -- every
-        // wave waits for its edge stores to complete before the barrier, so
-        // they are visible before the counter that announces them.
         for (int i = threadIdx.x; i < 2 * H; i += nthr) {
             const int p = i < H ? i : wl - 2 * H + i;
-            if (p >= 0 && p < wl)
-                __hip_atomic_store(pub + b + p, tl[H + p], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (p >= 0 && p < wl) EdgeWord<T>::put(area + (tile * 2 * H + i) * WORDS, tl[H + p], tag);
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __hip_atomic_store(a.flags + tile, a.epoch_base + epoch, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            if (!resident_wait_neighbours(a, tile, a.epoch_base + epoch)) abort_flag = 1;
+        for (int i = threadIdx.x; i < 2 * H; i += nthr) {
+            const uint64_t *src = area + edge_source(a, tile, i, last_len) * WORDS;
+            T x = T(0);
+            int64_t spins = 0;
+            while (!EdgeWord<T>::get(src, tag, x)) {
+                if (++spins > a.spin_limit) {
+                    __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    abort_flag = 1;
+                    break;
+                }
+                if ((spins & 63) == 0 &&
+                    __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    abort_flag = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            tl[i < H ? i : wl + i] = x;
         }
         __syncthreads();
         if (abort_flag) return;
-        // the outer halo, output positions [-H, 0) and [wl, wl + H) (the ring
-        // wraps at most once: H <= N)
-        for (int i = threadIdx.x; i < 2 * H; i += nthr) {
-            const int p = i < H ? i - H : wl + i - H;
-            int64_t q = b + p;
-            if (q < 0) q += N;
-            if (q >= N) q -= N;
-            tl[H + p] = __hip_atomic_load(pub + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
         if (halo_lane) tile_lds_get<P, K>(tl, c0, v);
     }
     if (a.part_out) {
         const double s = tile_sum<K>(v, lane, lo, hi, off, H, wlen);
         if (lane == 0) a.part_out[tile * G + w] = s;
     }
-    // final epoch: R = exchanges + 1; buf[0]'s last readers are done once
-    // their neighbours reach the next epoch (see above)
-    const uint32_t R = epoch + 1;
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(a.flags + tile, a.epoch_base + R, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        if ((R & 1) && !resident_wait_neighbours(a, tile, a.epoch_base + R)) abort_flag = 1;
+    if (epoch == 0) {
+        // no exchange: a neighbour may still be loading its window from the
+        // cells this tile is about to store
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(a.flags + tile, a.epoch_base + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            if (!resident_wait_neighbours(a, tile, a.epoch_base + 1)) abort_flag = 1;
+        }
+        __syncthreads();
+        if (abort_flag) return;
     }
-    __syncthreads();
-    if (abort_flag) return;
     window_store<P, K>(ring0, g0, lo, hi, off, H, wlen, fast, lane, v);
 }
 

@@ -249,16 +249,18 @@ struct SumArea {
     double *d_out = nullptr;     // 2 doubles
 };
 
-// Epoch counters and status word of the resident kernel, per thread and
-// device, with a pinned host word for the status: grown on demand and kept
-// (a resident call waits for its stream before it returns, so the next call
-// from the same thread finds them idle).  The counters are never cleared
-// between calls: each call counts on from `base`, the highest value the
-// previous one left; they are cleared when the buffer is new, after a call
-// that failed, and before `base` could wrap.
+// Exchange area, epoch counters and status word of the resident kernel, per
+// thread and device, with a pinned host word for the status: grown on demand
+// and kept (a resident call waits for its stream before it returns, so the
+// next call from the same thread finds them idle).  Tags and counters are
+// never cleared between calls: each call counts on from `base`, the highest
+// value the previous one left; they are cleared when a buffer is new, after
+// a call that failed, and before `base` could wrap.
 struct ResidentCache {
     uint32_t *d = nullptr;   // device: [0] status, [1, 1 + tiles) epochs
     size_t cap = 0;          // words held by d
+    uint64_t *x = nullptr;   // device: exchange area
+    size_t xcap = 0;         // words held by x
     uint32_t *h = nullptr;   // pinned host: status
     uint32_t base = 0;       // every counter is <= base
     int cus = 0;             // compute units of the device
@@ -317,23 +319,35 @@ static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t
                     "shape fits %lld on the device (fewer cells per tile: a longer window, or "
                     "use HEAT_KERNEL_TB)", (long long)pl.tiles, (long long)capacity);
     const size_t words = (size_t)pl.tiles + 1;
+    const size_t xwords =
+        (size_t)resident_area_words(pl.tiles, pl.H, (int)storage_bytes(precision));
     const int64_t epochs = (nt + pl.T - 1) / pl.T;   // exchanges + 1
     if (!c.h) HEAT_HIP(hipHostMalloc((void **)&c.h, sizeof(uint32_t), hipHostMallocDefault));
     bool clear = false;
+    // idle buffers: the last call waited for its stream
     if (c.cap < words) {
-        if (c.d) HEAT_HIP(hipFree(c.d));   // idle: the last call waited for its stream
+        if (c.d) HEAT_HIP(hipFree(c.d));
         c.d = nullptr;
         c.cap = 0;
         HEAT_HIP(hipMalloc((void **)&c.d, words * sizeof(uint32_t)));
         c.cap = words;
         clear = true;
     }
+    if (c.xcap < xwords) {
+        if (c.x) HEAT_HIP(hipFree(c.x));
+        c.x = nullptr;
+        c.xcap = 0;
+        HEAT_HIP(hipMalloc((void **)&c.x, xwords * sizeof(uint64_t)));
+        c.xcap = xwords;
+        clear = true;
+    }
     if (clear || (int64_t)c.base + epochs >= (int64_t(1) << 31)) {
         HEAT_HIP(launch_fill_u32(c.d, (int64_t)c.cap, 0u, st));
+        HEAT_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(c.x), 2 * (int64_t)c.xcap, 0u, st));
         c.base = 0;
     }
-    ra.buf[0] = a;
-    ra.buf[1] = b;
+    (void)b;   // the resident kernel keeps the state in registers and the ring
+    ra.u = a;
     ra.N = N;
     ra.tiles = pl.tiles;
     ra.nt = nt;
@@ -341,22 +355,25 @@ static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t
     ra.r = r;
     ra.status = c.d;
     ra.flags = c.d + 1;
+    ra.xa = c.x;
     ra.epoch_base = c.base;
     ra.spin_limit = RESIDENT_SPIN_LIMIT;
     ra.part_in = sums ? sums->partial : nullptr;
     ra.part_out = sums ? sums->partial + pl.parts : nullptr;
-    // the vector paths read and write both buffers
-    ra.vec_ok = ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
+    ra.vec_ok = (reinterpret_cast<uintptr_t>(a) & 15) == 0;
     HEAT_HIP(launch_resident(precision, ra, pl.K, pl.form, pl.wpg, pl.xd, st, nullptr));
     if (sums) HEAT_HIP(launch_sum_partials(sums->partial, pl.parts, 2, sums->d_out, st));
     HEAT_HIP(hipMemcpyAsync(c.h, c.d, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HEAT_HIP(hipStreamSynchronize(st));
     c.base += (uint32_t)epochs;
     if (*c.h != 0) {
-        // counters in any state: clear them (and the status) next time
+        // tags and counters in any state: clear them (and the status) next time
         c.cap = 0;
         (void)hipFree(c.d);
         c.d = nullptr;
+        c.xcap = 0;
+        (void)hipFree(c.x);
+        c.x = nullptr;
         return fail(HEAT_EDEVICE, "resident kernel: a tile waited too long for its neighbours "
                     "(were all %lld tiles resident? another launch may hold the CUs); the "
                     "state is undefined", (long long)pl.tiles);
@@ -627,24 +644,109 @@ static bool config_is_auto(const heat_config *cfg) {
                      cfg->waves_per_group || cfg->register_form || cfg->exchange);
 }
 
+// Waves on the busiest SIMD of a resident plan, and its load efficiency.
+static int64_t busiest_simd(const Plan &q, int cus) {
+    const int64_t per_cu = (q.tiles + cus - 1) / cus;
+    return (per_cu * q.wpg + 3) / 4;
+}
+static double load_efficiency(const Plan &q, int cus) {
+    const int64_t busiest = busiest_simd(q, cus);
+    return busiest > 0 ? (double)q.tiles * q.wpg / (4.0 * cus) / (double)busiest : 0.0;
+}
+
+static int device_cus(int *cus) {
+    int dev = 0;
+    HEAT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(HEAT_EDEVICE, "device %d out of range", dev);
+    ResidentCache &c = g_resident_cache[dev];
+    if (c.cus == 0) {
+        hipDeviceProp_t prop;
+        HEAT_HIP(hipGetDeviceProperties(&prop, dev));
+        c.cus = prop.multiProcessorCount;
+    }
+    *cus = c.cus;
+    return HEAT_OK;
+}
+
+// The fitting of resident_fit on a plan; false if no interval fits.
+static bool fit_resident_plan(int64_t N, int64_t nt, int precision, const heat_config &c, int cus,
+                              Plan *out, int *T_out = nullptr) {
+    const int T0 = c.steps_per_round;
+    int64_t best_load = 0;
+    bool have = false;
+    for (int T : {T0, 96, 64, 48, 32, 24, 16}) {
+        if (T > T0 || 2 * T < T0 || (T != T0 && precision == HEAT_FP32C)) continue;
+        if (have && T == T0) continue;
+        heat_config f = c;
+        f.steps_per_round = T;
+        Plan q;
+        if (make_plan(N, nt, precision, &f, &q) != HEAT_OK || q.kernel != HEAT_KERNEL_RESIDENT)
+            continue;
+        int64_t capacity = 0;
+        if (resident_capacity(q, precision, &capacity) != HEAT_OK || q.tiles > capacity)
+            continue;
+        const int64_t load = busiest_simd(q, cus);
+        if (!have || load < best_load) {
+            *out = q;
+            if (T_out) *T_out = T;
+            best_load = load;
+            have = true;
+        }
+    }
+    return have;
+}
+
+int resident_fit(int64_t N, int64_t nt, int precision, const heat_config &c,
+                 heat_config *fitted, double *eff) {
+    int cus = 0;
+    int rc = device_cus(&cus);
+    if (rc) return rc;
+    Plan q;
+    int T = 0;
+    if (!fit_resident_plan(N, nt, precision, c, cus, &q, &T))
+        return fail(HEAT_EINVAL, "the resident shape cannot run %lld cells", (long long)N);
+    *fitted = c;
+    fitted->steps_per_round = T;
+    *eff = load_efficiency(q, cus);
+    return HEAT_OK;
+}
+
 // The plan a call runs: make_plan's, except that a call that waits for its
-// result (`waits`) with an all-automatic configuration takes the resident
-// kernel where the tuning table has a resident shape for N's bucket, the run
-// is at least as long as the shortest one that shape won, and the grid fits
-// the device at once.
+// result (`waits`) with an all-automatic configuration may take the resident
+// kernel: every shape the tuning table records for N's quarter decade whose
+// shortest winning run at N is no longer than nt is fitted to N
+// (resident_fit), and the one whose gain at full SIMD load at N times its
+// load efficiency at N is the largest is taken, if that is at least the
+// margin (the shortest run and the gain interpolated between the points the
+// tuner measured).  At the measured points this is
+// the measured gain; in between, the model follows the tiles as they fall
+// on the SIMDs.
 static int choose_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, bool waits,
                        Plan *pl) {
     int rc = make_plan(N, nt, precision, cfg, pl);
     if (rc || !waits || nt < 1 || !config_is_auto(cfg)) return rc;
-    heat_config rcfg;
-    int64_t min_nt = 0;
-    if (!tuned_resident(N, precision, &rcfg, &min_nt) || nt < min_nt) return HEAT_OK;
-    Plan q;
-    if (make_plan(N, nt, precision, &rcfg, &q) != HEAT_OK) return HEAT_OK;
-    int64_t capacity = 0;
-    if (resident_capacity(q, precision, &capacity) != HEAT_OK || q.tiles > capacity)
-        return HEAT_OK;
-    *pl = q;
+    ResidentChoice ch[RESIDENT_SHAPES];
+    const int n = tuned_resident(N, precision, ch);
+    int cus = 0;
+    if (n == 0 || device_cus(&cus) != HEAT_OK || cus < 1) return HEAT_OK;
+    int64_t pts[RESIDENT_POINTS];
+    resident_points(N, pts);
+    double best_score = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double min_nt = resident_interp(ch[i].min_nt, pts, N);
+        if (min_nt <= 0.0 || (double)nt < min_nt) continue;
+        Plan q;
+        if (!fit_resident_plan(N, nt, precision, ch[i].c, cus, &q)) continue;
+        // a shape recorded without its gains stands for the margin
+        const bool recorded = ch[i].gain[0] > 0.0 || ch[i].gain[1] > 0.0 || ch[i].gain[2] > 0.0;
+        const double score = recorded
+                                 ? resident_interp(ch[i].gain, pts, N) * load_efficiency(q, cus)
+                                 : RESIDENT_TUNE_MARGIN;
+        if (score > best_score) {
+            best_score = score;
+            if (score >= RESIDENT_TUNE_MARGIN) *pl = q;
+        }
+    }
     return HEAT_OK;
 }
 

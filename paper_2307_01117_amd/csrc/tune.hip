@@ -48,14 +48,21 @@ struct BatchEntry {
 // measured faster on (K = 0: the round kernel always).
 struct ResidentEntry {
     int K = 0, T = 0, G = 0, form = 0, xchg = 0;
-    int64_t min_nt = 0;
+    int64_t min_nt[RESIDENT_POINTS] = {0, 0, 0};   // shortest winning run per point
+                                                   // (0: it does not gain there)
+    int gain_milli[RESIDENT_POINTS] = {0, 0, 0};   // gain at full SIMD load per point,
+                                                   // thousandths (0: cannot run there)
+};
+struct ResidentSet {
+    ResidentEntry s[RESIDENT_SHAPES];
+    int n = 0;
 };
 
 struct TuneTable {
     std::mutex mu;
     TuneEntry e[3][NBUCKETS];
     BatchEntry b[3][NBUCKETS];
-    ResidentEntry rs[3][NQUART];
+    ResidentSet rs[3][NQUART];
     bool env_loaded = false;
     TuneTable() {
         for (int p = 0; p < 3; ++p)
@@ -102,19 +109,52 @@ int load_file(const char *path) {
     TuneTable &t = table();
     char line[256];
     int n = 0, rc = HEAT_OK;
+    // a file's r-lines replace the quarter decades they name
+    bool named[3][NQUART] = {};
     while (std::fgets(line, sizeof line, f)) {
+        if (!std::strchr(line, '\n') && !std::feof(f)) {
+            // longer than the buffer: a comment's rest is skipped, anything
+            // else is refused
+            int ch;
+            while ((ch = std::fgetc(f)) != EOF && ch != '\n') {
+            }
+            if (line[0] != '#') {
+                rc = fail(HEAT_EINVAL, "tuning table line too long: %.40s...", line);
+                break;
+            }
+            continue;
+        }
         if (line[0] == '#' || line[0] == '\n') continue;
         if (line[0] == 'r') {
-            // resident shape: "r precision quarter_bucket K T G form exchange min_nt"
-            int p, b, K, T, G, form, xchg;
-            long long mn;
-            const int got = std::sscanf(line + 1, "%d %d %d %d %d %d %d %lld", &p, &b, &K, &T, &G,
-                                        &form, &xchg, &mn);
+            // resident shape: "r precision quarter_bucket K T G form exchange
+            // min_nt" (one shortest winning run for the whole quarter decade)
+            // or "... min_nt at each point, gain_milli at each point"
+            int p, b, K, T, G, form, xchg, gm[RESIDENT_POINTS] = {0, 0, 0};
+            long long m3[RESIDENT_POINTS] = {0, 0, 0};
+            int got = std::sscanf(line + 1, "%d %d %d %d %d %d %d %lld %lld %lld %d %d %d", &p,
+                                  &b, &K, &T, &G, &form, &xchg, &m3[0], &m3[1], &m3[2], &gm[0],
+                                  &gm[1], &gm[2]);
+            long long mn = m3[0];
+            if (got == 8) {
+                m3[1] = m3[2] = mn;
+            } else if (got == 13) {
+                // every number >= 0, a shortest run recorded at some point
+                bool ok = gm[0] >= 0 && gm[1] >= 0 && gm[2] >= 0;
+                mn = 0;
+                for (long long m : m3) {
+                    ok = ok && m >= 0;
+                    mn = std::max(mn, m);
+                }
+                got = ok ? 8 : -1;
+            } else {
+                got = -1;
+            }
             // "r precision quarter_bucket 0 0 0 0 0 0": no resident shape for it
             if (got == 8 && p >= 0 && p <= 2 && b >= 0 && b < NQUART && K == 0 && T == 0 &&
                 G == 0 && form == 0 && xchg == 0 && mn == 0) {
                 std::lock_guard<std::mutex> lk(t.mu);
-                t.rs[p][b] = ResidentEntry{};
+                t.rs[p][b] = ResidentSet{};
+                named[p][b] = true;
                 ++n;
                 continue;
             }
@@ -129,7 +169,17 @@ int load_file(const char *path) {
                 break;
             }
             std::lock_guard<std::mutex> lk(t.mu);
-            t.rs[p][b] = ResidentEntry{K, T, G, form, xchg, (int64_t)mn};
+            ResidentSet &set = t.rs[p][b];
+            if (!named[p][b]) set = ResidentSet{};
+            named[p][b] = true;
+            if (set.n == RESIDENT_SHAPES) {
+                rc = fail(HEAT_EINVAL, "more than %d resident shapes for one quarter decade: %s",
+                          RESIDENT_SHAPES, line);
+                break;
+            }
+            set.s[set.n++] = ResidentEntry{K, T, G, form, xchg,
+                                           {(int64_t)m3[0], (int64_t)m3[1], (int64_t)m3[2]},
+                                           {gm[0], gm[1], gm[2]}};
             ++n;
             continue;
         }
@@ -194,16 +244,28 @@ bool tuned_batch_class(int64_t N, int precision, int *K, int *G, int *T) {
     return true;
 }
 
-bool tuned_resident(int64_t N, int precision, heat_config *c, int64_t *min_nt) {
-    if (precision < 0 || precision > 2) return false;
+int tuned_resident(int64_t N, int precision, ResidentChoice (&out)[RESIDENT_SHAPES]) {
+    if (precision < 0 || precision > 2) return 0;
     load_env_once();
     TuneTable &t = table();
     std::lock_guard<std::mutex> lk(t.mu);
-    const ResidentEntry &e = t.rs[precision][quarter_bucket_of(N)];
-    if (e.K == 0) return false;
-    *c = heat_config{HEAT_KERNEL_RESIDENT, e.K, e.T, e.G, e.form, e.xchg};
-    *min_nt = e.min_nt;
-    return true;
+    const ResidentSet &set = t.rs[precision][quarter_bucket_of(N)];
+    for (int i = 0; i < set.n; ++i) {
+        const ResidentEntry &e = set.s[i];
+        out[i] = ResidentChoice{heat_config{HEAT_KERNEL_RESIDENT, e.K, e.T, e.G, e.form, e.xchg},
+                                {(double)e.min_nt[0], (double)e.min_nt[1], (double)e.min_nt[2]},
+                                {e.gain_milli[0] / 1000.0, e.gain_milli[1] / 1000.0,
+                                 e.gain_milli[2] / 1000.0}};
+    }
+    return set.n;
+}
+
+void resident_points(int64_t N, int64_t (&pts)[RESIDENT_POINTS]) {
+    const int q = quarter_bucket_of(N);
+    const int64_t lo = quarter_edge(q), hi = std::max(lo, quarter_edge(q + 1) - 1);
+    pts[0] = lo;
+    pts[1] = (int64_t)std::llround(std::sqrt((double)lo * (double)hi));
+    pts[2] = hi;
 }
 
 void tuned_shape(int64_t N, int precision, int *K, int *T, int *wpg, int *form, int *exchange) {
@@ -264,25 +326,28 @@ int heat_tune_save(const char *path) {
         }
     any = false;
     for (int p = 0; p < 3; ++p)
-        for (int b = 0; b < NQUART; ++b) {
-            const ResidentEntry &e = t.rs[p][b];
-            if (!e.K) continue;
-            if (!any)
-                std::fprintf(f, "# resident kernel: r precision quarter_bucket(4 log10 N) cells_per_lane "
-                                "steps_per_round waves_per_group register_form exchange "
-                                "min_steps\n");
-            any = true;
-            std::fprintf(f, "r %d %d %d %d %d %d %d %lld\n", p, b, e.K, e.T, e.G, e.form, e.xchg,
-                         (long long)e.min_nt);
-        }
+        for (int b = 0; b < NQUART; ++b)
+            for (int i = 0; i < t.rs[p][b].n; ++i) {
+                const ResidentEntry &e = t.rs[p][b].s[i];
+                if (!any)
+                    std::fprintf(f, "# resident kernel: r precision quarter_bucket(4 log10 N) "
+                                    "cells_per_lane steps_per_round waves_per_group "
+                                    "register_form exchange,\n# then at the quarter decade's "
+                                    "lower end, middle and upper end its shortest winning run "
+                                    "(0: none),\n# then there its gain at full load "
+                                    "(thousandths)\n");
+                any = true;
+                std::fprintf(f, "r %d %d %d %d %d %d %d %lld %lld %lld %d %d %d\n", p, b, e.K,
+                             e.T, e.G, e.form, e.xchg, (long long)e.min_nt[0],
+                             (long long)e.min_nt[1], (long long)e.min_nt[2], e.gain_milli[0],
+                             e.gain_milli[1], e.gain_milli[2]);
+            }
     std::fclose(f);
     return HEAT_OK;
 }
 
 // Gain a tuned batch class must show over the rule on the synthetic batch.
 constexpr double BATCH_TUNE_MARGIN = 1.03;
-// Gain the resident kernel must show over the round kernel on a long run.
-constexpr double RESIDENT_TUNE_MARGIN = 1.03;
 
 int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *K_out,
                         int32_t *G_out, int32_t *T_out, double *best_gcups) {
@@ -526,12 +591,17 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
 // table's shape), for N's quarter decade: every resident shape that can be
 // resident there is timed over a long run at both ends of the quarter decade
 // (its speed jumps with the tile count against the CU count, so a shape
-// that fits one end may not fit the other), and the shape whose smaller gain
-// over the round kernel is the largest wins; then it and the round kernel
-// are timed over a short run at both ends too.  Each kernel's time is a fixed
-// cost plus a cost per step, so the two lengths give, at each end, the run
-// length from which the resident one is faster; the larger is recorded.  It
-// is kept if its smaller gain is RESIDENT_TUNE_MARGIN.
+// that fits one end may not fit the other; each time the fastest of three
+// calls, the compensated form's shapes also at a binary32 coefficient, whose
+// kernel differs).  Among the shapes whose smallest gain over the round
+// kernel is at least RESIDENT_TUNE_MARGIN, the one whose smallest gain at full
+// SIMD load (each end's gain over its load efficiency: the ends sample a
+// saw-tooth of tile counts against CUs, which the planner evaluates at the
+// N of each call) is the largest wins; that gain is recorded.  Then it and
+// the round kernel are timed over a short run at both ends too.  Each
+// kernel's time is a fixed cost plus a cost per step, so the two lengths
+// give, in each case, the run length from which the resident one is faster;
+// the largest is recorded.
 int heat_autotune_resident(int32_t precision, int64_t N, int32_t install, heat_config *best_out,
                            int64_t *min_steps_out, double *gain_out) {
     if (precision != HEAT_FP64 && precision != HEAT_FP32 && precision != HEAT_FP32C)
@@ -540,7 +610,10 @@ int heat_autotune_resident(int32_t precision, int64_t N, int32_t install, heat_c
     int rc = device_pool_setup();
     if (rc) return rc;
     const int q = quarter_bucket_of(N);
-    const int64_t ends[2] = {quarter_edge(q), std::max(quarter_edge(q), quarter_edge(q + 1) - 1)};
+    constexpr int NPOINT = RESIDENT_POINTS;
+    int64_t pts[NPOINT];
+    resident_points(N, pts);
+    const int64_t hi = pts[NPOINT - 1];
     hipStream_t st = nullptr;
     HEAT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     const size_t es = storage_bytes(precision);
@@ -554,7 +627,7 @@ int heat_autotune_resident(int32_t precision, int64_t N, int32_t install, heat_c
         if (e1) (void)hipEventDestroy(e1);
         (void)hipStreamDestroy(st);
     };
-    const int64_t Nmax = ends[1];
+    const int64_t Nmax = hi;
     hipError_t e = hipMallocAsync(&a, (size_t)Nmax * std::max<size_t>(es, 8), st);
     if (e == hipSuccess) e = hipMallocAsync(&w, (size_t)Nmax * std::max<size_t>(es, 8), st);
     if (e == hipSuccess) e = hipEventCreate(&e0);
@@ -572,103 +645,204 @@ int heat_autotune_resident(int32_t precision, int64_t N, int32_t install, heat_c
         cleanup();
         return fail_hip(e, "autotune fill");
     }
-    // the coefficient as in heat_autotune
-    const double r_tune = precision == HEAT_FP32C ? 0.3 : 0.25;
+    // the coefficients: heat_autotune's, and for the compensated form also
+    // one that is a binary32 number (its kernel then drops the coefficient's
+    // low part, and with it some registers): a shape must gain with both
+    const bool comp = precision == HEAT_FP32C;
+    const double r_list[2] = {comp ? 0.3 : 0.25, 0.25};
+    const int nr = comp ? 2 : 1;
     // one untimed call (it also refuses a shape that cannot be resident),
-    // then one timed
-    auto time_run = [&](const heat_config &c, int64_t n, int64_t nt, double *ms_out) -> int {
-        int rc2 = heat_solve_dev_cfg(a, w, n, 1, r_tune, nt, precision, &c, st, nullptr, nullptr);
+    // then the fastest of three timed ones
+    auto time_run = [&](const heat_config &c, int64_t n, int64_t nt, double r,
+                        double *ms_out) -> int {
+        int rc2 = heat_solve_dev_cfg(a, w, n, 1, r, nt, precision, &c, st, nullptr, nullptr);
         if (rc2) return rc2;
-        hipError_t e2 = hipEventRecord(e0, st);
-        if (e2 == hipSuccess)
-            rc2 = heat_solve_dev_cfg(a, w, n, 1, r_tune, nt, precision, &c, st, nullptr, nullptr);
-        if (!rc2 && e2 == hipSuccess) e2 = hipEventRecord(e1, st);
-        if (!rc2 && e2 == hipSuccess) e2 = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (!rc2 && e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, e0, e1);
-        if (!rc2 && e2 != hipSuccess) rc2 = fail_hip(e2, "autotune timing");
-        *ms_out = ms;
-        return rc2;
+        double best_ms = 0.0;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipError_t e2 = hipEventRecord(e0, st);
+            if (e2 == hipSuccess)
+                rc2 = heat_solve_dev_cfg(a, w, n, 1, r, nt, precision, &c, st, nullptr, nullptr);
+            if (!rc2 && e2 == hipSuccess) e2 = hipEventRecord(e1, st);
+            if (!rc2 && e2 == hipSuccess) e2 = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (!rc2 && e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, e0, e1);
+            if (!rc2 && e2 != hipSuccess) rc2 = fail_hip(e2, "autotune timing");
+            if (rc2) return rc2;
+            if (rep == 0 || ms < best_ms) best_ms = ms;
+        }
+        *ms_out = best_ms;
+        return HEAT_OK;
     };
     const int64_t nt_short = 128, nt_long = 1024;
     const heat_config tb{HEAT_KERNEL_TB, 0, 0, 0, 0, 0};   // what the planner runs
-    double tb_l[2] = {0, 0}, tb_s[2] = {0, 0};
-    for (int k = 0; k < 2 && !rc; ++k) {
-        rc = time_run(tb, ends[k], nt_long, &tb_l[k]);
-        if (!rc) rc = time_run(tb, ends[k], nt_short, &tb_s[k]);
-    }
+    // [point][coefficient]
+    double tb_l[NPOINT][2] = {}, tb_s[NPOINT][2] = {};
+    for (int k = 0; k < NPOINT && !rc; ++k)
+        for (int ri = 0; ri < nr && !rc; ++ri) {
+            rc = time_run(tb, pts[k], nt_long, r_list[ri], &tb_l[k][ri]);
+            if (!rc) rc = time_run(tb, pts[k], nt_short, r_list[ri], &tb_s[k][ri]);
+        }
     if (rc) {
         cleanup();
         return rc;
     }
-    const bool comp = precision == HEAT_FP32C;
-    double best_score = 0.0;
-    double best_l[2] = {0, 0};
-    heat_config rc_best{};
+    // every shape that can run at some point: its smallest gain over the
+    // coefficients at each point, over its load efficiency there
+    struct Cand {
+        heat_config c{};
+        double full[NPOINT] = {0, 0, 0};
+        double gain[NPOINT] = {0, 0, 0};
+        int wins = 0;
+    };
+    std::vector<Cand> cands;
     struct GX { int G, x; };
     for (int K : {8, 16, 32})
         for (GX gx : {GX{1, HEAT_EXCHANGE_NONE}, GX{2, HEAT_EXCHANGE_LDS_DEEP},
                       GX{4, HEAT_EXCHANGE_LDS}, GX{4, HEAT_EXCHANGE_LDS_DEEP},
                       GX{8, HEAT_EXCHANGE_LDS_DEEP}})
             for (int form : {1, 3})
-                for (int T : {32, 48, 64, 96, 128}) {
+                for (int T : {16, 24, 32, 48, 64, 96, 128}) {
                     if (comp && T != default_steps_per_round(N, precision)) continue;
                     if (precision != HEAT_FP64 && form != 1) continue;
                     if (3 * T > 64 * K) continue;
                     if (gx.x == HEAT_EXCHANGE_LDS && K < 16) continue;
-                    heat_config c{HEAT_KERNEL_RESIDENT, K, T, gx.G, form, gx.x};
-                    double ms[2] = {0, 0};
-                    bool fits = true;
-                    for (int k = 0; k < 2 && fits; ++k) {
-                        rc = time_run(c, ends[k], nt_long, &ms[k]);
-                        if (rc == HEAT_EINVAL) fits = false;   // not resident at this size
-                        else if (rc) {
+                    Cand cd;
+                    cd.c = heat_config{HEAT_KERNEL_RESIDENT, K, T, gx.G, form, gx.x};
+                    bool runs = false;
+                    for (int k = 0; k < NPOINT; ++k) {
+                        // run as the planner would at this length
+                        heat_config fitted;
+                        double eff = 0.0;
+                        rc = resident_fit(pts[k], nt_long, precision, cd.c, &fitted, &eff);
+                        if (rc == HEAT_EINVAL) continue;   // cannot be resident here
+                        double g = 1e300;
+                        for (int ri = 0; ri < nr && !rc; ++ri) {
+                            double ms = 0.0;
+                            rc = time_run(fitted, pts[k], nt_long, r_list[ri], &ms);
+                            if (!rc) g = ms > 0.0 ? std::min(g, tb_l[k][ri] / ms) : 0.0;
+                        }
+                        if (rc == HEAT_EINVAL) continue;
+                        if (rc) {
                             cleanup();
                             return rc;
                         }
+                        if (g > 0.0 && eff > 0.0) {
+                            cd.gain[k] = g;
+                            cd.full[k] = g / eff;
+                            runs = true;
+                        }
                     }
-                    if (!fits || ms[0] <= 0.0 || ms[1] <= 0.0) continue;
-                    const double score = std::min(tb_l[0] / ms[0], tb_l[1] / ms[1]);
-                    if (score > best_score) {
-                        best_score = score;
-                        rc_best = c;
-                        best_l[0] = ms[0];
-                        best_l[1] = ms[1];
-                    }
+                    rc = HEAT_OK;
+                    if (runs) cands.push_back(cd);
                 }
-    rc = HEAT_OK;
-    ResidentEntry found;
-    if (best_score >= RESIDENT_TUNE_MARGIN) {
-        double cross = 1.0;
-        for (int k = 0; k < 2 && !rc; ++k) {
-            double rs_s = 0.0;
-            rc = time_run(rc_best, ends[k], nt_short, &rs_s);
-            if (rc) break;
-            // t = a + b * nt for each kernel; the resident one is faster from
-            // nt* = (a_res - a_tb) / (b_tb - b_res) on
-            const double span = (double)(nt_long - nt_short);
-            const double b_tb = (tb_l[k] - tb_s[k]) / span, b_rs = (best_l[k] - rs_s) / span;
-            const double a_tb = tb_s[k] - b_tb * nt_short, a_rs = rs_s - b_rs * nt_short;
-            const double c = b_rs < b_tb ? (a_rs - a_tb) / (b_tb - b_rs) : (double)nt_short;
-            cross = std::max(cross, std::min(c, (double)nt_long));
+    // the model over the quarter decade: at each N of a fine grid, the shape
+    // whose interpolated gain at full load times its load efficiency there is
+    // the largest wins, if that is at least the margin
+    constexpr int NGRID = 64;
+    for (int j = 0; j < NGRID; ++j) {
+        const int64_t n = (int64_t)std::llround(
+            std::exp(std::log((double)pts[0]) +
+                     (std::log((double)hi) - std::log((double)pts[0])) * j / (NGRID - 1)));
+        double best_pred = 0.0;
+        int best_i = -1;
+        for (size_t i = 0; i < cands.size(); ++i) {
+            heat_config fitted;
+            double eff = 0.0;
+            if (resident_fit(n, nt_long, precision, cands[i].c, &fitted, &eff) != HEAT_OK)
+                continue;
+            const double pred = resident_interp(cands[i].full, pts, n) * eff;
+            if (pred > best_pred) {
+                best_pred = pred;
+                best_i = (int)i;
+            }
         }
-        if (rc) {
-            cleanup();
-            return rc;
+        if (best_i >= 0 && best_pred >= RESIDENT_TUNE_MARGIN) ++cands[best_i].wins;
+    }
+    // recorded: the fastest shape at each point (where it gains), then the
+    // others the model picks, most often first
+    std::vector<size_t> order;
+    auto take = [&](size_t i) {
+        if (order.size() < (size_t)RESIDENT_SHAPES &&
+            std::find(order.begin(), order.end(), i) == order.end())
+            order.push_back(i);
+    };
+    for (int k = 0; k < NPOINT; ++k) {
+        int best_i = -1;
+        for (size_t i = 0; i < cands.size(); ++i)
+            if (cands[i].gain[k] >= RESIDENT_TUNE_MARGIN &&
+                (best_i < 0 || cands[i].gain[k] > cands[best_i].gain[k]))
+                best_i = (int)i;
+        if (best_i >= 0) take((size_t)best_i);
+    }
+    std::vector<size_t> by_wins;
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (cands[i].wins > 0) by_wins.push_back(i);
+    std::stable_sort(by_wins.begin(), by_wins.end(),
+                     [&](size_t a, size_t b) { return cands[a].wins > cands[b].wins; });
+    for (size_t i : by_wins) take(i);
+    // each recorded shape with the run length from which it is faster at the
+    // points where it gains (else at its best point)
+    ResidentSet found;
+    int64_t min_steps = 0;
+    for (size_t oi = 0; oi < order.size() && !rc; ++oi) {
+        const Cand &cd = cands[order[oi]];
+        ResidentEntry f{cd.c.cells_per_lane, cd.c.steps_per_round, cd.c.waves_per_group,
+                        cd.c.register_form, cd.c.exchange, {0, 0, 0}, {0, 0, 0}};
+        int top = 0;
+        for (int k = 1; k < NPOINT; ++k)
+            if (cd.gain[k] > cd.gain[top]) top = k;
+        for (int k = 0; k < NPOINT && !rc; ++k) {
+            f.gain_milli[k] = (int)std::lround(cd.full[k] * 1000.0);
+            if (cd.gain[k] <= 0.0 || (cd.gain[k] < 1.0 && k != top)) continue;
+            heat_config fitted;
+            double eff = 0.0;
+            if (resident_fit(pts[k], nt_long, precision, cd.c, &fitted, &eff) != HEAT_OK) continue;
+            double cross = 1.0;
+            for (int ri = 0; ri < nr && !rc; ++ri) {
+                double rs_s = 0.0, rs_l = 0.0;
+                rc = time_run(fitted, pts[k], nt_short, r_list[ri], &rs_s);
+                if (!rc) rc = time_run(fitted, pts[k], nt_long, r_list[ri], &rs_l);
+                if (rc) break;
+                // t = a + b * nt for each kernel; the resident one is faster
+                // from nt* = (a_res - a_tb) / (b_tb - b_res) on
+                const double span = (double)(nt_long - nt_short);
+                const double tl = tb_l[k][ri], ts = tb_s[k][ri];
+                const double b_tb = (tl - ts) / span, b_rs = (rs_l - rs_s) / span;
+                const double a_tb = ts - b_tb * nt_short, a_rs = rs_s - b_rs * nt_short;
+                const double x = b_rs < b_tb ? (a_rs - a_tb) / (b_tb - b_rs) : (double)nt_short;
+                cross = std::max(cross, std::min(x, (double)nt_long));
+            }
+            f.min_nt[k] = std::max<int64_t>(1, (int64_t)std::ceil(cross));
+            min_steps = std::max(min_steps, f.min_nt[k]);
         }
-        found = ResidentEntry{rc_best.cells_per_lane, rc_best.steps_per_round,
-                              rc_best.waves_per_group, rc_best.register_form, rc_best.exchange,
-                              (int64_t)std::ceil(cross)};
+        found.s[found.n++] = f;
     }
     cleanup();
+    if (rc) return rc;
     if (install) {
         TuneTable &t = table();
         std::lock_guard<std::mutex> lk(t.mu);
         t.rs[precision][q] = found;
     }
-    if (best_out) *best_out = best_score > 0.0 ? rc_best : heat_config{};
-    if (min_steps_out) *min_steps_out = found.min_nt;
-    if (gain_out) *gain_out = best_score;
+    // reported: the first recorded shape (else the fastest at the lower
+    // end), and the smallest over the points of the best gain measured there
+    double worst = 1e300;
+    heat_config lead{};
+    double lead_gain = 0.0;
+    for (int k = 0; k < NPOINT; ++k) {
+        double g = 0.0;
+        for (const Cand &cd : cands) g = std::max(g, cd.gain[k]);
+        worst = std::min(worst, g);
+    }
+    for (const Cand &cd : cands)
+        if (cd.gain[0] > lead_gain) {
+            lead_gain = cd.gain[0];
+            lead = cd.c;
+        }
+    if (!order.empty()) lead = cands[order[0]].c;
+    if (best_out) *best_out = lead;
+    if (min_steps_out) *min_steps_out = found.n ? min_steps : 0;
+    if (gain_out) *gain_out = cands.empty() ? 0.0 : worst;
     return HEAT_OK;
 }
 

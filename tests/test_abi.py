@@ -273,16 +273,45 @@ def test_planner_deep_exchange_geometry(lib, K, G, T):
 
 def test_tune_table_resident_lines(lib, tmp_path):
     """Resident kernel lines ("r precision quarter_bucket K T G form exchange
-    min_steps") load and are written back by heat_tune_save; all-zero fields
-    clear the quarter decade; inconsistent shapes are refused.  (Quarter
-    decades 9 and 39: rings of 178 to 316 cells, and of 10^9.75 and more.)"""
+    min_steps", or with the shortest winning run and the gain at full load at
+    each of three points, up to six per quarter decade) load and are written
+    back by heat_tune_save (a line with one run length as that length at
+    every point and gains 0, not recorded); all-zero fields clear the quarter
+    decade; inconsistent shapes are refused.
+    (Quarter decades 9 and 39: rings of 178 to 316 cells, and of 10^9.75 and
+    more.)"""
     good = tmp_path / "good.txt"
-    good.write_text("r 0 39 16 64 4 3 3 400\nr 2 9 32 64 1 1 1 256\n")
+    good.write_text("r 0 39 16 64 4 3 3 400 500 0 1250 1300 0\n"
+                    "r 0 39 8 32 1 3 1 300 0 600 1100 1000 1200\nr 2 9 32 64 1 1 1 256\n")
     heat.tune_load(str(good))
     out = tmp_path / "out.txt"
     heat.tune_save(str(out))
     text = out.read_text()
-    assert "r 0 39 16 64 4 3 3 400" in text and "r 2 9 32 64 1 1 1 256" in text
+    assert ("r 0 39 16 64 4 3 3 400 500 0 1250 1300 0\n"
+            "r 0 39 8 32 1 3 1 300 0 600 1100 1000 1200\n") in text
+    assert "r 2 9 32 64 1 1 1 256 256 256 0 0 0\n" in text
+    # a file's lines replace the shapes of the quarter decades it names
+    one = tmp_path / "one.txt"
+    one.write_text("r 0 39 32 64 4 3 3 200 200 200 1300 1300 1300\n")
+    heat.tune_load(str(one))
+    heat.tune_save(str(out))
+    text = out.read_text()
+    assert "r 0 39 32 64 4 3 3 200 200 200 1300 1300 1300\n" in text
+    assert "r 0 39 16 " not in text and "r 0 39 8 " not in text
+    assert "r 2 9 32 64 1 1 1 256 256 256 0 0 0\n" in text
+    # a comment longer than the loader's line buffer is skipped whole
+    lengthy = tmp_path / "long.txt"
+    lengthy.write_text("# " + "x" * 600 + "\nr 2 9 32 64 1 1 1 128\n")
+    heat.tune_load(str(lengthy))
+    heat.tune_save(str(out))
+    assert "r 2 9 32 64 1 1 1 128 128 128 0 0 0\n" in out.read_text()
+    seven = tmp_path / "seven.txt"
+    seven.write_text("".join("r 1 9 %d %d 4 1 3 100\n" % (K, T)
+                             for K, T in ((16, 16), (16, 32), (16, 48), (16, 64), (32, 16),
+                                          (32, 32), (32, 48))))
+    with pytest.raises(heat.HeatError) as ei:
+        heat.tune_load(str(seven))
+    assert ei.value.code == heat.HEAT_EINVAL and "more than 6" in str(ei.value)
     clear = tmp_path / "clear.txt"
     clear.write_text("r 0 39 0 0 0 0 0 0\nr 2 9 0 0 0 0 0 0\n")
     heat.tune_load(str(clear))
@@ -293,6 +322,9 @@ def test_tune_table_resident_lines(lib, tmp_path):
                 "r 0 9 8 64 4 3 2 400\n",       # K/4 exchange with 8 cells per lane
                 "r 0 9 16 66 4 3 3 400\n",      # T not a multiple of 4
                 "r 0 9 16 64 4 3 3 0\n",       # no minimum run length
+                "r 0 9 16 64 4 3 3 400 400 400 1 -5 1\n",  # negative gain
+                "r 0 9 16 64 4 3 3 0 0 0 1 1 1\n",         # no winning run anywhere
+                "r 0 9 16 64 4 3 3 400 1200\n",            # a partial line
                 "r 0 40 16 64 4 3 3 400\n"):   # no quarter decade 40
         f = tmp_path / "bad.txt"
         f.write_text(bad)

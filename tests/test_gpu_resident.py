@@ -158,3 +158,79 @@ def test_resident_calls_in_a_row_count_on():
         u0 = inputs.uniform_ring(N, (36, i))
         got, _ = run_resident(u0, nt, 0.375, heat.FP64, **shape)
         assert same_bits(got, oracle.solve(u0, 0.375, nt)), (i, N, nt)
+
+
+def test_planner_fits_the_tuned_shapes_to_n(tmp_path):
+    """The tuned shapes of a quarter decade fitted to N.  A CU holds
+    ceil(tiles / CUs) workgroups and every tile waits for the slowest: for
+    binary64 and binary32 the planner takes the longest exchange interval, at
+    most the tuned one and at least half of it, that puts the fewest waves on
+    the busiest SIMD; among the recorded shapes it takes the one whose gain
+    at full load at N (linear in log N between the quarter decade's lower
+    end, geometric middle and upper end) times its load efficiency at N is
+    the largest, if that is at least 1.03, else the round kernel (the
+    compensated form keeps its T)."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def busiest(p):
+        return (-(-p["tiles"] // cus) * p["waves_per_group"] + 3) // 4
+
+    def efficiency(p):
+        return p["tiles"] * p["waves_per_group"] / (4 * cus) / busiest(p)
+
+    def fitted(N, prec, K, T0, G, x, form):
+        Ts = [T0] if prec == heat.FP32C else [T for T in (T0, 96, 64, 48, 32, 24, 16)
+                                              if T <= T0 and 2 * T >= T0]
+        cand = {T: plan_of(N, 1000, prec, K, G, x, form, T) for T in Ts}
+        T = min(cand, key=lambda T: (busiest(cand[T]), -T))
+        return cand[T]
+
+    def gain_at(g, b, N):
+        lo, hi = math.ceil(10 ** (b / 4)), math.ceil(10 ** ((b + 1) / 4)) - 1
+        pts = [lo, round(math.sqrt(lo * hi)), hi]
+        x = np.log(N)
+        xs, ys = np.log(pts), np.array(g) / 1000
+        return float(np.interp(x, xs, ys))
+
+    saved = tmp_path / "orig.txt"
+    heat.tune_save(str(saved))
+    try:
+        f = tmp_path / "r.txt"
+        # quarter decades 24 and 25: 10^6 to 10^6.25 and 10^6.25 to 10^6.5 cells
+        lines = {(heat.FP64, 24): [(16, 48, 4, heat.EXCHANGE_LDS_DEEP, 3, (1200, 1100, 1000)),
+                                   (8, 48, 4, heat.EXCHANGE_LDS_DEEP, 3, (1150, 1150, 1150))],
+                 (heat.FP32, 25): [(16, 128, 4, heat.EXCHANGE_LDS_DEEP, 1, (1500, 1500, 1500)),
+                                   (16, 96, 1, heat.EXCHANGE_NONE, 1, (1400, 1300, 1300))],
+                 (heat.FP32C, 25): [(16, 64, 1, heat.EXCHANGE_NONE, 1, (1200, 1200, 1200))]}
+        f.write_text("".join("r %d %d %d %d %d %d %d 100 100 100 %d %d %d\n"
+                             % (p, b, K, T, G, form, x, *g)
+                             for (p, b), shapes in lines.items()
+                             for K, T, G, x, form, g in shapes))
+        heat.tune_load(str(f))
+        checked = 0
+        for (prec, b), shapes in lines.items():
+            for N in (1_000_000, 1_200_000, 1_330_000, 1_780_000, 2_000_000, 2_500_000,
+                      3_000_000):
+                if int(4 * np.log10(N)) != b:
+                    continue
+                score, want = 0.0, None
+                for K, T, G, x, form, g in shapes:
+                    p = fitted(N, prec, K, T, G, x, form)
+                    sc = gain_at(g, b, N) * efficiency(p)
+                    if sc > score:
+                        score, want = sc, p
+                got = heat.plan(N, 1000, prec)
+                assert abs(score - 1.03) > 1e-6, "too close to the margin to test"
+                if score >= 1.03:
+                    assert got["kernel"] == heat.KERNEL_RESIDENT, (prec, N)
+                    for key in ("cells_per_lane", "steps_per_round", "waves_per_group",
+                                "tiles"):
+                        assert got[key] == want[key], (prec, N, key)
+                else:
+                    assert got["kernel"] == heat.KERNEL_TB, (prec, N)
+                checked += 1
+        assert checked == 11
+        # short runs keep the round kernel
+        assert heat.plan(2_000_000, 99, heat.FP32)["kernel"] == heat.KERNEL_TB
+    finally:
+        heat.tune_load(str(saved))

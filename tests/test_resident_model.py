@@ -1,16 +1,20 @@
 """Host model of the resident kernel's tile geometry and edge exchange.
 
 The resident kernel (csrc/resident.h) keeps every tile's windows in
-registers for all steps and swaps tile edges through two ring buffers,
-ordered by per-tile epoch counters.  This model re-implements its index
-arithmetic in NumPy -- windows of 64*K cells per wave whose ends go stale by
-one cell per step (the lane rotation wraps inside the window), the waves'
-S-cell edge swaps, the LDS copy of the tile that edge and halo cells pass
-through, the publication of the first and last H owned cells into buf[e & 1],
-the halo reads, and the final store into buf[0] -- and runs the tiles as
-independent actors in a random order that respects only the kernel's waits.
-Every interleaving must give the oracle's bits (Section 2, Eq.
-(heat:discrete) on the periodic ring); a model with a wait dropped must not.
+registers for all steps and swaps tile edges through a tagged exchange area:
+every exchange e writes the tile's first and last H owned cells into slots of
+parity e & 1, each value carrying the tag of its epoch, and a tile reads its
+halo from its neighbours' slots once their tags read e.  This model
+re-implements its index arithmetic in NumPy -- windows of 64*K cells per wave
+whose ends go stale by one cell per step (the lane rotation wraps inside the
+window), the waves' S-cell edge swaps, the LDS copy of the tile that edge and
+halo cells pass through, the slots each halo cell is read from (a walk over
+the neighbouring tiles, the short last tile included), and the final store
+into the ring -- and runs the tiles as independent actors in a random order
+that respects only the kernel's waits.  Every interleaving must give the
+oracle's bits (Section 2, Eq. (heat:discrete) on the periodic ring); a model
+without the one-epoch run's final wait must not, and one with a single
+parity of slots must deadlock or go wrong.
 """
 from __future__ import annotations
 
@@ -28,8 +32,12 @@ def step_window(v, r):
     return v + r * ((left - 2.0 * v) + right)
 
 
+class Deadlock(Exception):
+    pass
+
+
 class Ring:
-    def __init__(self, u0, K, G, XD, H, T, nt, r, final_wait=True):
+    def __init__(self, u0, K, G, XD, H, T, nt, r, final_wait=True, parities=2):
         self.N = N = len(u0)
         self.K, self.G, self.XD, self.H, self.T, self.nt, self.r = K, G, XD, H, T, nt, r
         self.S = K // XD if XD else 0
@@ -37,36 +45,63 @@ class Ring:
         self.W = G * self.WIN - 2 * (G - 1) * self.S - 2 * H
         assert self.W >= H and N >= H
         self.tiles = -(-N // self.W)
-        self.buf = [np.array(u0, dtype=np.float64), np.full(N, np.nan)]
+        self.ring = np.array(u0, dtype=np.float64)
+        self.slots = {}          # (parity, tile, side, j) -> (tag, value)
         self.flags = [0] * self.tiles
         self.final_wait = final_wait
+        self.parities = parities
+
+    def length(self, t):
+        return min(self.W, self.N - t * self.W)
 
     def neighbours(self, t):
         """Tiles whose output lies within H of tile t (resident_wait_neighbours)."""
         out = []
         if self.tiles == 1:
             return out
-        last_len = self.N - (self.tiles - 1) * self.W
         for direction in (-1, 1):
             acc, q, g = 0, t, 0
             while g + 1 < self.tiles and acc < self.H:
                 q = (q + direction) % self.tiles
                 out.append(q)
-                acc += last_len if q == self.tiles - 1 else self.W
+                acc += self.length(q)
                 g += 1
         return out
 
+    def halo_slot(self, t, i):
+        """(tile, side, j) of halo cell i of tile t (edge_source): i < H is the
+        cell H - i left of the tile, read from the last H cells (side 1) of the
+        tile it falls in; i >= H the cell i - H right of its end, from the first
+        H (side 0)."""
+        H = self.H
+        if i < H:
+            d, q = H - i, t
+            while True:
+                q = (q - 1) % self.tiles
+                L = self.length(q)
+                if d <= L:
+                    return q, 1, H - d
+                d -= L
+        d, q = i - H, t
+        while True:
+            q = (q + 1) % self.tiles
+            L = self.length(q)
+            if d < L:
+                return q, 0, d
+            d -= L
+
     def tile(self, t):
-        """The kernel's work for tile t as a generator: it yields ('wait', need)
-        where the kernel polls its neighbours' counters, and runs everything
-        else (reads and writes of the shared buffers) between yields."""
+        """The kernel's work for tile t as a generator: it yields ('slots',
+        [(key, tag), ...]) where the kernel polls its halo slots and ('flags',
+        need) where it polls its neighbours' counters, and runs everything
+        else (reads and writes of the shared memory) between yields."""
         N, K, G, XD, H, S, WIN, W = (self.N, self.K, self.G, self.XD, self.H, self.S,
                                      self.WIN, self.W)
         b = t * W
-        wl = min(W, N - b)
+        wl = self.length(t)
         offs = [w * (WIN - 2 * S) if XD else 0 for w in range(G)]
-        # window load from buf[0] (modulo N)
-        v = [self.buf[0][(b - H + off + np.arange(WIN)) % N].copy() for off in offs]
+        # window load from the ring (modulo N)
+        v = [self.ring[(b - H + off + np.arange(WIN)) % N].copy() for off in offs]
         tl = np.full(W + 2 * H, np.nan)
 
         def exchange():
@@ -106,54 +141,64 @@ class Ring:
                 break
             epoch += 1
             exchange()
-            pub = self.buf[epoch & 1]
+            par = epoch % self.parities
             for w, lane, c0 in lane_runs(lambda c: meets(c, 0, 2 * H) or meets(c, wl, wl + 2 * H)):
                 tl[c0:c0 + K] = v[w][lane * K:lane * K + K]
             for i in range(2 * H):
-                p = i if i < H else wl - 2 * H + i
+                side, j = (0, i) if i < H else (1, i - H)
+                p = j if side == 0 else wl - H + j
                 if 0 <= p < wl:
-                    pub[b + p] = tl[H + p]
-            self.flags[t] = epoch
-            yield ("wait", epoch)
-            for i in range(2 * H):
+                    self.slots[(par, t, side, j)] = (epoch, tl[H + p])
+            keys = [(par,) + self.halo_slot(t, i) for i in range(2 * H)]
+            yield ("slots", [(k, epoch) for k in keys])
+            for i, k in enumerate(keys):
+                tag, x = self.slots[k]
+                assert tag == epoch
                 p = i - H if i < H else wl + i - H
-                q = b + p
-                q = q + N if q < 0 else q - N if q >= N else q
-                tl[H + p] = pub[q]
+                tl[H + p] = x
             for w, lane, c0 in lane_runs(lambda c: meets(c, 0, H) or meets(c, wl + H, wl + 2 * H)):
                 v[w][lane * K:lane * K + K] = tl[c0:c0 + K]
-        R = epoch + 1
-        self.flags[t] = R
-        if R & 1 and self.final_wait:
-            yield ("wait", R)
+        if epoch == 0:
+            # no exchange: a neighbour may not have loaded its window yet
+            self.flags[t] = 1
+            if self.final_wait:
+                yield ("flags", 1)
         for w, off in enumerate(offs):
             lo = S if XD and w > 0 else H
             hi = WIN - S if XD and w + 1 < G else WIN - H
             for pos in range(lo, hi):
                 pg = off + pos
                 if H <= pg < H + wl:
-                    self.buf[0][b + pg - H] = v[w][pos]
+                    self.ring[b + pg - H] = v[w][pos]
+
+    def ready(self, t, wait):
+        if wait is None:
+            return True
+        kind, need = wait
+        if kind == "flags":
+            return all(self.flags[q] >= need for q in self.neighbours(t))
+        return all(self.slots.get(k, (0,))[0] == tag for k, tag in need)
 
     def run(self, seed):
         rng = np.random.default_rng(seed)
         gens = {t: self.tile(t) for t in range(self.tiles)}
-        waiting = {t: None for t in gens}   # need, or None = ready to run
+        waiting = {t: None for t in gens}
         while gens:
-            ready = [t for t in gens if waiting[t] is None or
-                     all(self.flags[q] >= waiting[t] for q in self.neighbours(t))]
-            assert ready, "deadlock"
+            ready = [t for t in gens if self.ready(t, waiting[t])]
+            if not ready:
+                raise Deadlock()
             t = ready[rng.integers(len(ready))]
             try:
-                _, need = next(gens[t])
-                waiting[t] = need
+                waiting[t] = next(gens[t])
             except StopIteration:
                 del gens[t]
-        return self.buf[0]
+        return self.ring
 
 
 CASES = [
     # N, K, G, XD, H, T, nt: lone waves, both exchange depths, a short last tile
-    # (shorter than H too), a single tile, odd and even exchange counts
+    # (shorter than H too), a single tile, odd and even exchange counts, runs
+    # of T steps or fewer
     (3000, 8, 1, 0, 16, 16, 70),
     (2900, 8, 1, 0, 32, 24, 49),
     (5000, 16, 4, 4, 32, 32, 100),
@@ -162,6 +207,8 @@ CASES = [
     (4040 * 2 + 10, 16, 4, 4, 16, 16, 33),
     (3900, 16, 4, 4, 32, 20, 41),
     (900, 8, 2, 2, 16, 16, 50),
+    (3000, 8, 1, 0, 16, 16, 12),         # no exchange: the counters' wait
+    (4040 * 2 + 10, 16, 4, 4, 16, 16, 16),
 ]
 
 
@@ -177,15 +224,35 @@ def test_resident_model_matches_oracle_any_order(case):
 
 
 def test_resident_model_without_the_final_wait_fails():
-    """The final store into buf[0] after an odd number of epochs must wait
-    for the neighbours' last halo reads: a model without that wait lets a
-    fast tile overwrite edges a slow neighbour still has to read."""
-    N, K, G, XD, H, T, nt = 3000, 8, 1, 0, 16, 16, 40     # 3 rounds: R odd
+    """A run of T steps or fewer makes no exchange, so nothing orders a tile's
+    final store after its neighbours' window loads: a model without the
+    counters' wait lets a fast tile overwrite cells a slow neighbour has still
+    to load as halo."""
+    N, K, G, XD, H, T, nt = 3000, 8, 1, 0, 16, 16, 12
     u0 = inputs.uniform_ring(N, 22)
     r = 0.4375
     want = oracle.solve(u0, r, nt)
+    assert np.array_equal(Ring(u0, K, G, XD, H, T, nt, r).run(0), want)
     bad = 0
     for seed in range(40):
         got = Ring(u0, K, G, XD, H, T, nt, r, final_wait=False).run(seed)
         bad += not np.array_equal(got, want)
+    assert bad > 0
+
+
+def test_resident_model_with_one_parity_fails():
+    """With one parity of slots a fast tile overwrites epoch e's edges with
+    e + 1's before a slow neighbour has read them: the neighbour then polls
+    for a tag that never comes back."""
+    N, K, G, XD, H, T, nt = 3000, 8, 1, 0, 16, 16, 70
+    u0 = inputs.uniform_ring(N, 23)
+    r = 0.4375
+    want = oracle.solve(u0, r, nt)
+    bad = 0
+    for seed in range(40):
+        try:
+            got = Ring(u0, K, G, XD, H, T, nt, r, parities=1).run(seed)
+            bad += not np.array_equal(got, want)
+        except Deadlock:
+            bad += 1
     assert bad > 0
