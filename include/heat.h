@@ -74,9 +74,9 @@ enum heat_kernel_choice {
                                per workgroup) keeps its window in registers
                                for all nt steps and swaps its H edge cells
                                with its neighbour tiles through memory every T
-                               steps, ordered by per-tile epoch counters (the
-                               segments' ghost-zone exchange of Section 2, H
-                               cells deep).  Every tile must be resident at
+                               steps, each value tagged with its exchange's
+                               epoch (the segments' ghost-zone exchange of
+                               Section 2, H cells deep).  Every tile must be resident at
                                once: the call fails with HEAT_EINVAL if the
                                ring needs more workgroups than the device
                                holds, and with HEAT_EDEVICE if a wait times

@@ -93,6 +93,8 @@ struct ResidentChoice {
 };
 // The resident shapes recorded for N's quarter decade; returns how many.
 int tuned_resident(int64_t N, int precision, ResidentChoice (&out)[RESIDENT_SHAPES]);
+// Changes whenever the tuning table may have changed.
+uint64_t tune_generation();
 // The measuring points of N's quarter decade.
 void resident_points(int64_t N, int64_t (&pts)[RESIDENT_POINTS]);
 // A quantity recorded at the points (a shape's gain at full load, or its
@@ -208,7 +210,7 @@ struct ResidentArgs {
     uint64_t *xa;            // exchange area, resident_area_words(); every tag <= epoch_base
     uint32_t *flags;         // [tiles] epoch counters, all <= epoch_base at launch
     uint32_t epoch_base;     // this launch's epochs are epoch_base + 1, 2, ...
-    uint32_t *status;        // [1] zero at launch; nonzero once a wait timed out
+    uint32_t *status;        // [1] pinned host word: zero at launch; nonzero once a wait timed out
     int64_t spin_limit;
     double *part_in;         // per-wave sums of the input, or NULL
     double *part_out;        // per-wave sums of the output, or NULL

@@ -35,7 +35,8 @@
 //
 // Every tile must be resident at once (the waits are across workgroups):
 // the launcher refuses grids larger than the occupancy allows, and a wait
-// longer than spin_limit polls sets status[0] and every wavefront leaves, so
+// longer than spin_limit polls sets status[0] (a pinned host word the host
+// reads once the launch is done) and every wavefront leaves, so
 // a grid that cannot be resident (another launch holding the CUs) ends with
 // an error instead of hanging.
 #pragma once
@@ -61,11 +62,11 @@ __device__ __forceinline__ bool resident_wait(const ResidentArgs &a, int64_t til
             __hip_atomic_load(a.flags + tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (v >= need) return true;
         if (++spins > a.spin_limit) {
-            __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             return false;
         }
         if ((spins & 63) == 0 &&
-            __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
             return false;
         __builtin_amdgcn_s_sleep(2);
     }
@@ -319,12 +320,12 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
             int64_t spins = 0;
             while (!EdgeWord<T>::get(src, tag, x)) {
                 if (++spins > a.spin_limit) {
-                    __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     abort_flag = 1;
                     break;
                 }
                 if ((spins & 63) == 0 &&
-                    __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0) {
                     abort_flag = 1;
                     break;
                 }

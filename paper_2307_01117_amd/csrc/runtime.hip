@@ -257,11 +257,11 @@ struct SumArea {
 // value the previous one left; they are cleared when a buffer is new, after
 // a call that failed, and before `base` could wrap.
 struct ResidentCache {
-    uint32_t *d = nullptr;   // device: [0] status, [1, 1 + tiles) epochs
+    uint32_t *d = nullptr;   // device: [1, 1 + tiles) epochs
     size_t cap = 0;          // words held by d
     uint64_t *x = nullptr;   // device: exchange area
     size_t xcap = 0;         // words held by x
-    uint32_t *h = nullptr;   // pinned host: status
+    uint32_t *h = nullptr;   // pinned host: the status word, written by the kernel
     uint32_t base = 0;       // every counter is <= base
     int cus = 0;             // compute units of the device
     std::unordered_map<uint64_t, int> per_cu;   // workgroups per CU by shape
@@ -302,8 +302,43 @@ static int resident_capacity(const Plan &pl, int precision, int64_t *capacity) {
     return HEAT_OK;
 }
 
+// A resident launch whose status is still to be read: the caller waits for
+// the stream once (for this and for whatever else it copies back) and then
+// settles it.
+struct ResidentPending {
+    ResidentCache *c = nullptr;
+    int64_t tiles = 0;
+    int64_t epochs = 0;
+};
+
+// After the stream is idle: count the epochs on, and report a wait that
+// timed out (then the counters and tags are in any state: they are cleared
+// on the next call).
+static int resident_settle(const ResidentPending &p) {
+    ResidentCache &c = *p.c;
+    c.base += (uint32_t)p.epochs;
+    if (*c.h != 0) {
+        // a fresh status word next time (the launch is done)
+        (void)hipHostFree(c.h);
+        c.h = nullptr;
+        c.cap = 0;
+        (void)hipFree(c.d);
+        c.d = nullptr;
+        c.xcap = 0;
+        (void)hipFree(c.x);
+        c.x = nullptr;
+        return fail(HEAT_EDEVICE, "resident kernel: a tile waited too long for its neighbours "
+                    "(were all %lld tiles resident? another launch may hold the CUs); the "
+                    "state is undefined", (long long)p.tiles);
+    }
+    return HEAT_OK;
+}
+
+// With `defer` set the status copy is queued and the wait left to the caller
+// (who must settle *defer after it); otherwise waits and settles here.
 static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t N, double r,
-                        int64_t nt, hipStream_t st, const SumArea *sums) {
+                        int64_t nt, hipStream_t st, const SumArea *sums,
+                        ResidentPending *defer = nullptr) {
     int dev = 0;
     HEAT_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(HEAT_EDEVICE, "device %d out of range", dev);
@@ -322,7 +357,10 @@ static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t
     const size_t xwords =
         (size_t)resident_area_words(pl.tiles, pl.H, (int)storage_bytes(precision));
     const int64_t epochs = (nt + pl.T - 1) / pl.T;   // exchanges + 1
-    if (!c.h) HEAT_HIP(hipHostMalloc((void **)&c.h, sizeof(uint32_t), hipHostMallocDefault));
+    if (!c.h) {
+        HEAT_HIP(hipHostMalloc((void **)&c.h, sizeof(uint32_t), hipHostMallocDefault));
+        *c.h = 0;
+    }
     bool clear = false;
     // idle buffers: the last call waited for its stream
     if (c.cap < words) {
@@ -353,7 +391,7 @@ static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t
     ra.nt = nt;
     ra.T = pl.T;
     ra.r = r;
-    ra.status = c.d;
+    ra.status = c.h;
     ra.flags = c.d + 1;
     ra.xa = c.x;
     ra.epoch_base = c.base;
@@ -362,29 +400,31 @@ static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t
     ra.part_out = sums ? sums->partial + pl.parts : nullptr;
     ra.vec_ok = (reinterpret_cast<uintptr_t>(a) & 15) == 0;
     HEAT_HIP(launch_resident(precision, ra, pl.K, pl.form, pl.wpg, pl.xd, st, nullptr));
-    if (sums) HEAT_HIP(launch_sum_partials(sums->partial, pl.parts, 2, sums->d_out, st));
-    HEAT_HIP(hipMemcpyAsync(c.h, c.d, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HEAT_HIP(hipStreamSynchronize(st));
-    c.base += (uint32_t)epochs;
-    if (*c.h != 0) {
-        // tags and counters in any state: clear them (and the status) next time
-        c.cap = 0;
-        (void)hipFree(c.d);
-        c.d = nullptr;
-        c.xcap = 0;
-        (void)hipFree(c.x);
-        c.x = nullptr;
-        return fail(HEAT_EDEVICE, "resident kernel: a tile waited too long for its neighbours "
-                    "(were all %lld tiles resident? another launch may hold the CUs); the "
-                    "state is undefined", (long long)pl.tiles);
+    hipError_t e = sums ? launch_sum_partials(sums->partial, pl.parts, 2, sums->d_out, st)
+                        : hipSuccess;
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);
+        c.base += (uint32_t)epochs;   // counted on whatever happened, so no tag repeats
+        return fail_hip(e, "resident kernel: checksum");
     }
-    return HEAT_OK;
+    const ResidentPending p{&c, pl.tiles, epochs};
+    if (defer) {
+        *defer = p;
+        return HEAT_OK;
+    }
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        c.base += (uint32_t)epochs;   // counted on whatever happened, so no tag repeats
+        return fail_hip(e, "resident kernel: wait");
+    }
+    return resident_settle(p);
 }
 
 static int run_rounds(const Plan &pl, int precision, void *a, void *b, int64_t N, double r,
-                      int64_t nt, hipStream_t st, const SumArea *sums) {
+                      int64_t nt, hipStream_t st, const SumArea *sums,
+                      ResidentPending *defer = nullptr) {
     if (pl.kernel == HEAT_KERNEL_RESIDENT && nt > 0)
-        return run_resident(pl, precision, a, b, N, r, nt, st, sums);
+        return run_resident(pl, precision, a, b, N, r, nt, st, sums, defer);
     void *cur = a, *oth = b;
     const bool fused = sums && pl.kernel == HEAT_KERNEL_TB && nt > 0;
     if (sums && !fused) HEAT_HIP(launch_sum(precision, a, N, sums->partial, sums->d_out, st));
@@ -434,14 +474,15 @@ struct DevBuf {   // stream-ordered scratch, freed on the same stream
     }
 };
 
-// Checksum scratch per thread and device: device partials and results, and
-// a pinned host landing spot for the two sums.  A call that asks for sums
-// waits for its stream before it returns, so the next call from the same
-// thread always finds the buffers idle.  Grown on demand and kept until the
-// process ends (never freed: the runtime may be gone by thread exit), so a
-// small ring's pass makes no allocation call.
+// Checksum scratch per thread and device: device partials, and pinned host
+// memory for the two sums, which the final reduction writes directly (no
+// copy after it).  A call that asks for sums waits for its stream before it
+// returns, so the next call from the same thread always finds the buffers
+// idle.  Grown on demand and kept until the process ends (never freed: the
+// runtime may be gone by thread exit), so a small ring's pass makes no
+// allocation call.
 struct SumCache {
-    double *d = nullptr;   // device: partials + 2 results
+    double *d = nullptr;   // device: partials
     size_t cap = 0;        // doubles held by d
     double *h = nullptr;   // pinned host: 2 doubles
 };
@@ -711,6 +752,19 @@ int resident_fit(int64_t N, int64_t nt, int precision, const heat_config &c,
     return HEAT_OK;
 }
 
+// The last resident choice of each thread, kept until the tuning table
+// changes (a loop of calls on one ring chooses once).
+struct ResidentChoiceCache {
+    bool valid = false, resident = false;
+    int dev = -1, precision = -1;
+    int64_t N = 0, nt = 0;
+    uint64_t generation = 0;
+    Plan plan;
+};
+static thread_local ResidentChoiceCache g_choice;
+
+static int choose_resident(int64_t N, int64_t nt, int precision, Plan *pl);
+
 // The plan a call runs: make_plan's, except that a call that waits for its
 // result (`waits`) with an all-automatic configuration may take the resident
 // kernel: every shape the tuning table records for N's quarter decade whose
@@ -718,13 +772,36 @@ int resident_fit(int64_t N, int64_t nt, int precision, const heat_config &c,
 // (resident_fit), and the one whose gain at full SIMD load at N times its
 // load efficiency at N is the largest is taken, if that is at least the
 // margin (the shortest run and the gain interpolated between the points the
-// tuner measured).  At the measured points this is
-// the measured gain; in between, the model follows the tiles as they fall
-// on the SIMDs.
+// tuner measured).  At the measured points this is the measured gain; in
+// between, the model follows the tiles as they fall on the SIMDs.  The
+// choice is cached per thread (g_choice).
 static int choose_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, bool waits,
                        Plan *pl) {
     int rc = make_plan(N, nt, precision, cfg, pl);
     if (rc || !waits || nt < 1 || !config_is_auto(cfg)) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HEAT_OK;
+    const uint64_t gen = tune_generation();
+    ResidentChoiceCache &m = g_choice;
+    if (!(m.valid && m.dev == dev && m.N == N && m.nt == nt && m.precision == precision &&
+          m.generation == gen)) {
+        Plan q = *pl;
+        choose_resident(N, nt, precision, &q);
+        m.valid = true;
+        m.dev = dev;
+        m.N = N;
+        m.nt = nt;
+        m.precision = precision;
+        m.generation = gen;
+        m.resident = q.kernel == HEAT_KERNEL_RESIDENT;
+        m.plan = q;
+    }
+    if (m.resident) *pl = m.plan;
+    return HEAT_OK;
+}
+
+// choose_plan's resident step: *pl is replaced where a recorded shape wins.
+static int choose_resident(int64_t N, int64_t nt, int precision, Plan *pl) {
     ResidentChoice ch[RESIDENT_SHAPES];
     const int n = tuned_resident(N, precision, ch);
     int cus = 0;
@@ -773,25 +850,36 @@ static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, do
     SumCache *cache = nullptr;
     if (want_sums) {
         const int64_t np = std::max<int64_t>(SUM_BLOCKS, 2 * pl.parts);
-        rc = sum_scratch((size_t)(np + 2), &cache);
+        rc = sum_scratch((size_t)np, &cache);
         if (rc) return rc;
         area.partial = cache->d;
-        area.d_out = area.partial + np;
+        area.d_out = cache->h;   // the final reduction writes the pinned host words
     }
     void *b = d_work;
-    if (nt > 0 && !b) {
+    // the resident kernel keeps the state in registers and needs no second buffer
+    if (nt > 0 && !b && pl.kernel != HEAT_KERNEL_RESIDENT) {
         HEAT_HIP(hipMallocAsync(&work.p, bytes, st));
         b = work.p;
     }
-    rc = run_rounds(pl, precision, d_u, b, N, r, nt, st, want_sums ? &area : nullptr);
+    // one wait for the sums and the resident kernel's status together
+    ResidentPending pend;
+    rc = run_rounds(pl, precision, d_u, b, N, r, nt, st, want_sums ? &area : nullptr, &pend);
     if (rc) {
         // the cached scratch must be idle when this thread calls again
-        if (want_sums) (void)hipStreamSynchronize(st);
+        if (want_sums || pend.c) (void)hipStreamSynchronize(st);
+        if (pend.c) pend.c->base += (uint32_t)pend.epochs;
         return rc;
     }
+    hipError_t e = hipSuccess;
+    if (want_sums || pend.c) e = hipStreamSynchronize(st);
+    if (pend.c) {
+        // the epochs are counted on whatever happened, so no tag repeats
+        if (e != hipSuccess) pend.c->base += (uint32_t)pend.epochs;
+        else rc = resident_settle(pend);
+    }
+    if (e != hipSuccess) return fail_hip(e, "solve: wait");
+    if (rc) return rc;
     if (want_sums) {
-        HEAT_HIP(hipMemcpyAsync(cache->h, area.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        HEAT_HIP(hipStreamSynchronize(st));
         if (sum0_out) *sum0_out = cache->h[0];
         if (sum_out) *sum_out = cache->h[1];
     }

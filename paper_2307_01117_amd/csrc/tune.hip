@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -71,6 +72,10 @@ struct TuneTable {
                 e[p][b] = TuneEntry{32, p == HEAT_FP32C ? 64 : 96, 2, 3, HEAT_EXCHANGE_NONE};
     }
 };
+
+// Bumped whenever the table may have changed (a file loaded, an autotuner
+// installed), so callers can cache what they derived from it.
+std::atomic<uint64_t> g_generation{0};
 
 TuneTable &table() {
     static TuneTable t;
@@ -215,6 +220,7 @@ int load_file(const char *path) {
         ++n;
     }
     std::fclose(f);
+    g_generation.fetch_add(1);
     return rc;
 }
 
@@ -258,6 +264,11 @@ int tuned_resident(int64_t N, int precision, ResidentChoice (&out)[RESIDENT_SHAP
                                  e.gain_milli[2] / 1000.0}};
     }
     return set.n;
+}
+
+uint64_t tune_generation() {
+    load_env_once();
+    return g_generation.load();
 }
 
 void resident_points(int64_t N, int64_t (&pts)[RESIDENT_POINTS]) {
@@ -481,6 +492,7 @@ int heat_autotune_batch(int32_t precision, int64_t N, int32_t install, int32_t *
         TuneTable &t = table();
         std::lock_guard<std::mutex> lk(t.mu);
         t.b[precision][bucket_of(N)] = BatchEntry{bK, bG, bT};
+        g_generation.fetch_add(1);
     }
     if (K_out) *K_out = bK;
     if (G_out) *G_out = bG;
@@ -581,6 +593,7 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
         en = TuneEntry{bc.cells_per_lane, bc.steps_per_round, bc.waves_per_group, bc.register_form,
                        bc.exchange};
         if (precision == HEAT_FP32C) en.T = default_steps_per_round(N, precision);
+        g_generation.fetch_add(1);
     }
     if (best_out) *best_out = bc;
     if (best_gcups) *best_gcups = best;
@@ -823,6 +836,7 @@ int heat_autotune_resident(int32_t precision, int64_t N, int32_t install, heat_c
         TuneTable &t = table();
         std::lock_guard<std::mutex> lk(t.mu);
         t.rs[precision][q] = found;
+        g_generation.fetch_add(1);
     }
     // reported: the first recorded shape (else the fastest at the lower
     // end), and the smallest over the points of the best gain measured there
