@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
@@ -273,6 +274,18 @@ static thread_local ResidentCache g_resident_cache[64];
 // co-resident grid.
 constexpr int64_t RESIDENT_SPIN_LIMIT = int64_t(1) << 22;
 
+// HEAT_RESIDENT_SPIN_LIMIT (polls, >= 0) lowers it, read at every call: a
+// test of the failure path sets 0, so a tile gives up at its first poll that
+// finds a neighbour not yet there and the call fails with every wave exiting.
+static int64_t resident_spin_limit() {
+    const char *s = std::getenv("HEAT_RESIDENT_SPIN_LIMIT");
+    if (!s || !*s) return RESIDENT_SPIN_LIMIT;
+    char *end = nullptr;
+    const long long v = std::strtoll(s, &end, 10);
+    return (end && *end == '\0' && v >= 0 && v < RESIDENT_SPIN_LIMIT) ? (int64_t)v
+                                                                     : RESIDENT_SPIN_LIMIT;
+}
+
 // Tiles of a resident plan's shape the current device holds at once (the
 // LDS a group takes depends on its tile span W + 2H, so the occupancy is
 // asked for each shape, once per thread).
@@ -395,7 +408,7 @@ static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t
     ra.flags = c.d + 1;
     ra.xa = c.x;
     ra.epoch_base = c.base;
-    ra.spin_limit = RESIDENT_SPIN_LIMIT;
+    ra.spin_limit = resident_spin_limit();
     ra.part_in = sums ? sums->partial : nullptr;
     ra.part_out = sums ? sums->partial + pl.parts : nullptr;
     ra.vec_ok = (reinterpret_cast<uintptr_t>(a) & 15) == 0;

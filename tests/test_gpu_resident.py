@@ -234,3 +234,29 @@ def test_planner_fits_the_tuned_shapes_to_n(tmp_path):
         assert heat.plan(2_000_000, 99, heat.FP32)["kernel"] == heat.KERNEL_TB
     finally:
         heat.tune_load(str(saved))
+
+
+def test_resident_wait_timeout_fails_cleanly(monkeypatch):
+    """The failure path, forced from the host: with HEAT_RESIDENT_SPIN_LIMIT=0
+    a tile gives up at its first poll that finds a neighbour's edges not yet
+    there, sets the status word and leaves, and so does every other wave; the
+    call reports HEAT_EDEVICE.  The next calls (limit restored) start from
+    cleared tags and counters and a fresh status word, and are bitwise."""
+    N, nt = 2_000_003, 200
+    shape = dict(cells_per_lane=8, waves_per_group=1, exchange=heat.EXCHANGE_NONE,
+                 register_form=3, steps_per_round=16)
+    u0 = inputs.uniform_ring(N, 37)
+    want = oracle.solve_threads(u0, 16, 0.5, nt)
+    monkeypatch.setenv("HEAT_RESIDENT_SPIN_LIMIT", "0")
+    failed = 0
+    for _ in range(3):
+        try:
+            run_resident(u0, nt, 0.5, heat.FP64, **shape)
+        except heat.HeatError as e:
+            assert e.code == heat.HEAT_EDEVICE and "waited too long" in str(e)
+            failed += 1
+    assert failed > 0
+    monkeypatch.delenv("HEAT_RESIDENT_SPIN_LIMIT")
+    for _ in range(2):
+        got, _ = run_resident(u0, nt, 0.5, heat.FP64, **shape)
+        assert same_bits(got, want)
