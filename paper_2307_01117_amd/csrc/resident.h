@@ -164,17 +164,20 @@ __device__ __forceinline__ int64_t edge_source(const ResidentArgs &a, int64_t t,
     return q * 2 * H + d;
 }
 
-// The LDS copy of a tile: window cells of tile coordinate c (c = H + output
-// position, [0, W + 2H)) at tl[c].  A lane that holds any cell of `c_lo ..
-// c_hi` ranges moves its whole run of K cells (one predicate per lane, not
-// per cell).
+// The LDS copy of a tile holds what passes through it: whole K-cell runs of
+// the lanes that hold edge or halo cells (one predicate per lane, not per
+// cell), in tile coordinates c = H + output position.  Runs that meet the
+// first 2H coordinates lie in [0, 2H + K) (region A); runs that meet
+// [wl, wl + 2H) lie above b_lo = (wl - K) rounded down to 4 cells (region B,
+// 16-byte accesses), which follows region A when the two are disjoint; a
+// short tile's copy is indexed by tile coordinate, which then stays under the
+// same bound.  Cells of the copy: resident_tile_cells.
 template <class P, int K>
-__device__ __forceinline__ void tile_lds_put(typename P::T *tl, int c0,
-                                             const typename P::T (&v)[K]) {
+__device__ __forceinline__ void tile_lds_put(typename P::T *dst, const typename P::T (&v)[K]) {
     using T = typename P::T;
     using VT = typename Vec16<T>::type;
     constexpr int VEC = P::VEC;
-    VT *p = reinterpret_cast<VT *>(tl + c0);
+    VT *p = reinterpret_cast<VT *>(dst);
 #pragma unroll
     for (int j = 0; j < K / VEC; ++j) {
         VT x;
@@ -184,12 +187,11 @@ __device__ __forceinline__ void tile_lds_put(typename P::T *tl, int c0,
     }
 }
 template <class P, int K>
-__device__ __forceinline__ void tile_lds_get(const typename P::T *tl, int c0,
-                                             typename P::T (&v)[K]) {
+__device__ __forceinline__ void tile_lds_get(const typename P::T *src, typename P::T (&v)[K]) {
     using T = typename P::T;
     using VT = typename Vec16<T>::type;
     constexpr int VEC = P::VEC;
-    const VT *p = reinterpret_cast<const VT *>(tl + c0);
+    const VT *p = reinterpret_cast<const VT *>(src);
 #pragma unroll
     for (int j = 0; j < K / VEC; ++j) {
         const VT x = p[j];
@@ -197,16 +199,19 @@ __device__ __forceinline__ void tile_lds_get(const typename P::T *tl, int c0,
         for (int k = 0; k < VEC; ++k) v[j * VEC + k] = x[k];
     }
 }
+__host__ __device__ constexpr int64_t resident_tile_cells(int64_t W, int H, int K) {
+    return W + 2 * H < 4 * (int64_t)H + 3 * K + 4 ? W + 2 * H : 4 * (int64_t)H + 3 * K + 4;
+}
 __device__ __forceinline__ bool runs_meet(int a0, int a1, int b0, int b1) {
     return a0 < b1 && b0 < a1;
 }
 
 // LDS bytes of a resident workgroup: the waves' edge exchange (XD), then the
-// tile copy (W + 2H cells, 16-byte aligned).
+// tile copy (resident_tile_cells, 16-byte aligned).
 template <class P>
-constexpr int resident_lds_bytes(int K, int G, int XD, int tile_span) {
+constexpr int resident_lds_bytes(int K, int G, int XD, int tile_cells) {
     return (XD ? (exchange_lds_bytes<P>(K, G, XD) + 15) / 16 * 16 : 0) +
-           tile_span * (int)sizeof(typename P::T);
+           tile_cells * (int)sizeof(typename P::T);
 }
 
 // One workgroup per tile; G = blockDim.x / 64 waves share it (XD = 4 or 2:
@@ -253,6 +258,10 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
         heat_xlds + (XCHG ? (exchange_lds_bytes<P>(K, G, XD) + 15) / 16 * 16 : 0));
     const int c0 = (int)off + lane * K;   // tile coordinate of this lane's first cell
     const int wl = (int)wlen;
+    // LDS index of tile coordinate c (see tile_lds_put)
+    const int a_end = 2 * H + K, b_lo = (wl - K) & ~3;
+    const bool split = resident_tile_cells(W, H, K) < W + 2 * H && b_lo >= a_end;
+    auto at = [=](int c) { return split && c >= a_end ? c - b_lo + a_end : c; };
     // lanes holding edge cells (tile coordinates [H, 2H), [wl, wl + H)) or
     // halo cells ([0, H), [wl + H, wl + 2H))
     const bool io_lane = runs_meet(c0, c0 + K, 0, 2 * H) || runs_meet(c0, c0 + K, wl, wl + 2 * H);
@@ -308,11 +317,12 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
         // slots of this parity
         const uint32_t tag = a.epoch_base + epoch;
         uint64_t *const area = a.xa + (int64_t)(epoch & 1) * a.tiles * 2 * H * WORDS;
-        if (io_lane) tile_lds_put<P, K>(tl, c0, v);
+        if (io_lane) tile_lds_put<P, K>(tl + at(c0), v);
         __syncthreads();
         for (int i = threadIdx.x; i < 2 * H; i += nthr) {
             const int p = i < H ? i : wl - 2 * H + i;
-            if (p >= 0 && p < wl) EdgeWord<T>::put(area + (tile * 2 * H + i) * WORDS, tl[H + p], tag);
+            if (p >= 0 && p < wl)
+                EdgeWord<T>::put(area + (tile * 2 * H + i) * WORDS, tl[at(H + p)], tag);
         }
         for (int i = threadIdx.x; i < 2 * H; i += nthr) {
             const uint64_t *src = area + edge_source(a, tile, i, last_len) * WORDS;
@@ -331,11 +341,11 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            tl[i < H ? i : wl + i] = x;
+            tl[at(i < H ? i : wl + i)] = x;
         }
         __syncthreads();
         if (abort_flag) return;
-        if (halo_lane) tile_lds_get<P, K>(tl, c0, v);
+        if (halo_lane) tile_lds_get<P, K>(tl + at(c0), v);
     }
     if (a.part_out) {
         const double s = tile_sum<K>(v, lane, lo, hi, off, H, wlen);
@@ -363,12 +373,12 @@ constexpr bool resident_fits() {
 
 // Workgroups of this instantiation one CU can hold at once.
 template <class P, int K, int FORM, int XD>
-int resident_blocks_per_cu(int G, int tile_span) {
+int resident_blocks_per_cu(int G, int tile_cells) {
     if constexpr (!resident_fits<P, K, FORM, XD>()) {
         return 0;
     } else {
         int n = 0;
-        const size_t lds = (size_t)resident_lds_bytes<P>(K, G, XD, tile_span);
+        const size_t lds = (size_t)resident_lds_bytes<P>(K, G, XD, tile_cells);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_resident<P, K, FORM, XD>, 64 * G,
                                                          lds) != hipSuccess)
             return 0;
@@ -381,7 +391,8 @@ hipError_t launch_resident_t(const ResidentArgs &a, int G, hipStream_t st) {
     if constexpr (!resident_fits<P, K, FORM, XD>()) {
         return hipErrorInvalidValue;
     } else {
-        const unsigned lds = (unsigned)resident_lds_bytes<P>(K, G, XD, (int)(a.W + 2 * a.H));
+        const unsigned lds =
+            (unsigned)resident_lds_bytes<P>(K, G, XD, (int)resident_tile_cells(a.W, a.H, K));
         hipLaunchKernelGGL((k_resident<P, K, FORM, XD>), dim3((unsigned)a.tiles), dim3(64 * G),
                            lds, st, a);
         return hipGetLastError();
@@ -397,7 +408,8 @@ hipError_t resident_dispatch(const ResidentArgs &a, int K, int form, int G, hipS
     if constexpr ((FORMS >> FF) & 1) {                                               \
         if (K == KK && form == FF) {                                                 \
             if (blocks) {                                                            \
-                *blocks = resident_blocks_per_cu<P, KK, FF, XD>(G, (int)(a.W + 2 * a.H)); \
+                *blocks = resident_blocks_per_cu<P, KK, FF, XD>(                     \
+                    G, (int)resident_tile_cells(a.W, a.H, KK));                      \
                 return hipSuccess;                                                   \
             }                                                                        \
             return launch_resident_t<P, KK, FF, XD>(a, G, st);                       \

@@ -287,7 +287,7 @@ static int64_t resident_spin_limit() {
 }
 
 // Tiles of a resident plan's shape the current device holds at once (the
-// LDS a group takes depends on its tile span W + 2H, so the occupancy is
+// LDS a group takes depends on its tile's W and H, so the occupancy is
 // asked for each shape, once per thread).
 static int resident_capacity(const Plan &pl, int precision, int64_t *capacity) {
     int dev = 0;
@@ -296,7 +296,7 @@ static int resident_capacity(const Plan &pl, int precision, int64_t *capacity) {
     ResidentCache &c = g_resident_cache[dev];
     const uint64_t key = (uint64_t)precision | (uint64_t)pl.K << 4 | (uint64_t)pl.form << 12 |
                          (uint64_t)pl.wpg << 16 | (uint64_t)pl.xd << 20 |
-                         (uint64_t)(pl.W + 2 * pl.H) << 24;
+                         (uint64_t)(pl.W + 2 * pl.H) << 24 | (uint64_t)pl.H << 44;
     auto it = c.per_cu.find(key);
     if (it == c.per_cu.end()) {
         ResidentArgs probe{};

@@ -7,8 +7,8 @@ parity e & 1, each value carrying the tag of its epoch, and a tile reads its
 halo from its neighbours' slots once their tags read e.  This model
 re-implements its index arithmetic in NumPy -- windows of 64*K cells per wave
 whose ends go stale by one cell per step (the lane rotation wraps inside the
-window), the waves' S-cell edge swaps, the LDS copy of the tile that edge and
-halo cells pass through, the slots each halo cell is read from (a walk over
+window), the waves' S-cell edge swaps, the LDS copy of the tile's two edge
+regions that edge and halo cells pass through, the slots each halo cell is read from (a walk over
 the neighbouring tiles, the short last tile included), and the final store
 into the ring -- and runs the tiles as independent actors in a random order
 that respects only the kernel's waits.  Every interleaving must give the
@@ -102,7 +102,38 @@ class Ring:
         offs = [w * (WIN - 2 * S) if XD else 0 for w in range(G)]
         # window load from the ring (modulo N)
         v = [self.ring[(b - H + off + np.arange(WIN)) % N].copy() for off in offs]
-        tl = np.full(W + 2 * H, np.nan)
+        # the LDS copy holds two regions (resident_tile_cells): the runs that
+        # meet tile coordinates [0, 2H) lie in [0, 2H + K), those that meet
+        # [wl, wl + 2H) above b_lo; region B follows region A when disjoint
+        cells = min(W + 2 * H, 4 * H + 3 * K + 4)
+        a_end, b_lo = 2 * H + K, (wl - K) & ~3
+        split = cells < W + 2 * H and b_lo >= a_end
+
+        def at(c):
+            return c - b_lo + a_end if split and c >= a_end else c
+
+        class Lds:
+            def __init__(self):
+                self.m = np.full(cells, np.nan)
+
+            def __setitem__(self, key, val):
+                if isinstance(key, slice):
+                    lo = at(key.start)
+                    assert 0 <= lo and lo + (key.stop - key.start) <= cells
+                    self.m[lo:lo + key.stop - key.start] = val
+                else:
+                    assert 0 <= at(key) < cells
+                    self.m[at(key)] = val
+
+            def __getitem__(self, key):
+                if isinstance(key, slice):
+                    lo = at(key.start)
+                    assert 0 <= lo and lo + (key.stop - key.start) <= cells
+                    return self.m[lo:lo + key.stop - key.start]
+                assert 0 <= at(key) < cells
+                return self.m[at(key)]
+
+        tl = Lds()
 
         def exchange():
             if not XD:
@@ -208,6 +239,8 @@ CASES = [
     (3900, 16, 4, 4, 32, 20, 41),
     (900, 8, 2, 2, 16, 16, 50),
     (3000, 8, 1, 0, 16, 16, 12),         # no exchange: the counters' wait
+    (3 * 480 + 44, 8, 1, 0, 16, 16, 40),  # last tile just short of the LDS split: one region
+    (3 * 480 + 48, 8, 1, 0, 16, 16, 40),  # the shortest that splits: two
     (4040 * 2 + 10, 16, 4, 4, 16, 16, 16),
 ]
 
