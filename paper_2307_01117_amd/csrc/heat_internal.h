@@ -215,6 +215,8 @@ struct ResidentArgs {
     double *part_in;         // per-wave sums of the input, or NULL
     double *part_out;        // per-wave sums of the output, or NULL
     int32_t vec_ok;          // u 16-byte aligned
+    int32_t lds_edges;       // 1: the LDS tile copy holds the two edge regions only
+                             // (resident_tile_cells); 0: the whole tile span W + 2H
 };
 // 64-bit words of a resident launch's exchange area: two parities, per tile
 // its first and its last H owned cells, each cell one word per 32 bits of its

@@ -202,6 +202,16 @@ __device__ __forceinline__ void tile_lds_get(const typename P::T *src, typename 
 __host__ __device__ constexpr int64_t resident_tile_cells(int64_t W, int H, int K) {
     return W + 2 * H < 4 * (int64_t)H + 3 * K + 4 ? W + 2 * H : 4 * (int64_t)H + 3 * K + 4;
 }
+// Cells of a launch's LDS tile copy: the two edge regions, or the whole span
+__host__ __device__ constexpr int64_t resident_lds_cells(int64_t W, int H, int K, bool edges) {
+    return edges ? resident_tile_cells(W, H, K) : W + 2 * H;
+}
+// LDS index of tile coordinate c in a tile of wl output cells (of W at most)
+__device__ __forceinline__ int tile_lds_at(int c, int64_t W, int H, int K, int wl, bool edges) {
+    const int a_end = 2 * H + K, b_lo = (wl - K) & ~3;
+    const bool split = edges && resident_tile_cells(W, H, K) < W + 2 * H && b_lo >= a_end;
+    return split && c >= a_end ? c - b_lo + a_end : c;
+}
 __device__ __forceinline__ bool runs_meet(int a0, int a1, int b0, int b1) {
     return a0 < b1 && b0 < a1;
 }
@@ -258,16 +268,14 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
         heat_xlds + (XCHG ? (exchange_lds_bytes<P>(K, G, XD) + 15) / 16 * 16 : 0));
     const int c0 = (int)off + lane * K;   // tile coordinate of this lane's first cell
     const int wl = (int)wlen;
-    // LDS index of tile coordinate c (see tile_lds_put)
-    const int a_end = 2 * H + K, b_lo = (wl - K) & ~3;
-    const bool split = resident_tile_cells(W, H, K) < W + 2 * H && b_lo >= a_end;
-    auto at = [=](int c) { return split && c >= a_end ? c - b_lo + a_end : c; };
+
     // lanes holding edge cells (tile coordinates [H, 2H), [wl, wl + H)) or
     // halo cells ([0, H), [wl + H, wl + 2H))
     const bool io_lane = runs_meet(c0, c0 + K, 0, 2 * H) || runs_meet(c0, c0 + K, wl, wl + 2 * H);
     const bool halo_lane =
         runs_meet(c0, c0 + K, 0, H) || runs_meet(c0, c0 + K, wl + H, wl + 2 * H);
     const int nthr = blockDim.x;
+    const bool edges = a.lds_edges != 0;
     constexpr int WORDS = EdgeWord<T>::WORDS;
     const int64_t last_len = N - (a.tiles - 1) * W;
     int xbuf = 0;
@@ -317,12 +325,13 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
         // slots of this parity
         const uint32_t tag = a.epoch_base + epoch;
         uint64_t *const area = a.xa + (int64_t)(epoch & 1) * a.tiles * 2 * H * WORDS;
-        if (io_lane) tile_lds_put<P, K>(tl + at(c0), v);
+        if (io_lane) tile_lds_put<P, K>(tl + tile_lds_at(c0, W, H, K, wl, edges), v);
         __syncthreads();
         for (int i = threadIdx.x; i < 2 * H; i += nthr) {
             const int p = i < H ? i : wl - 2 * H + i;
             if (p >= 0 && p < wl)
-                EdgeWord<T>::put(area + (tile * 2 * H + i) * WORDS, tl[at(H + p)], tag);
+                EdgeWord<T>::put(area + (tile * 2 * H + i) * WORDS,
+                                 tl[tile_lds_at(H + p, W, H, K, wl, edges)], tag);
         }
         for (int i = threadIdx.x; i < 2 * H; i += nthr) {
             const uint64_t *src = area + edge_source(a, tile, i, last_len) * WORDS;
@@ -341,11 +350,11 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            tl[at(i < H ? i : wl + i)] = x;
+            tl[tile_lds_at(i < H ? i : wl + i, W, H, K, wl, edges)] = x;
         }
         __syncthreads();
         if (abort_flag) return;
-        if (halo_lane) tile_lds_get<P, K>(tl + at(c0), v);
+        if (halo_lane) tile_lds_get<P, K>(tl + tile_lds_at(c0, W, H, K, wl, edges), v);
     }
     if (a.part_out) {
         const double s = tile_sum<K>(v, lane, lo, hi, off, H, wlen);
@@ -391,8 +400,8 @@ hipError_t launch_resident_t(const ResidentArgs &a, int G, hipStream_t st) {
     if constexpr (!resident_fits<P, K, FORM, XD>()) {
         return hipErrorInvalidValue;
     } else {
-        const unsigned lds =
-            (unsigned)resident_lds_bytes<P>(K, G, XD, (int)resident_tile_cells(a.W, a.H, K));
+        const unsigned lds = (unsigned)resident_lds_bytes<P>(
+            K, G, XD, (int)resident_lds_cells(a.W, a.H, K, a.lds_edges != 0));
         hipLaunchKernelGGL((k_resident<P, K, FORM, XD>), dim3((unsigned)a.tiles), dim3(64 * G),
                            lds, st, a);
         return hipGetLastError();
@@ -409,7 +418,7 @@ hipError_t resident_dispatch(const ResidentArgs &a, int K, int form, int G, hipS
         if (K == KK && form == FF) {                                                 \
             if (blocks) {                                                            \
                 *blocks = resident_blocks_per_cu<P, KK, FF, XD>(                     \
-                    G, (int)resident_tile_cells(a.W, a.H, KK));                      \
+                    G, (int)resident_lds_cells(a.W, a.H, KK, a.lds_edges != 0));     \
                 return hipSuccess;                                                   \
             }                                                                        \
             return launch_resident_t<P, KK, FF, XD>(a, G, st);                       \

@@ -288,30 +288,42 @@ static int64_t resident_spin_limit() {
 
 // Tiles of a resident plan's shape the current device holds at once (the
 // LDS a group takes depends on its tile's W and H, so the occupancy is
-// asked for each shape, once per thread).
-static int resident_capacity(const Plan &pl, int precision, int64_t *capacity) {
+// asked for each shape and LDS layout, once per thread), and whether the
+// plan's grid needs the LDS copy of the edge regions only to fit.
+static int resident_capacity(const Plan &pl, int precision, int64_t *capacity,
+                             bool *edges_only = nullptr) {
     int dev = 0;
     HEAT_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(HEAT_EDEVICE, "device %d out of range", dev);
     ResidentCache &c = g_resident_cache[dev];
-    const uint64_t key = (uint64_t)precision | (uint64_t)pl.K << 4 | (uint64_t)pl.form << 12 |
-                         (uint64_t)pl.wpg << 16 | (uint64_t)pl.xd << 20 |
-                         (uint64_t)(pl.W + 2 * pl.H) << 24 | (uint64_t)pl.H << 44;
-    auto it = c.per_cu.find(key);
-    if (it == c.per_cu.end()) {
-        ResidentArgs probe{};
-        probe.W = pl.W;
-        probe.H = pl.H;
-        int n = 0;
-        HEAT_HIP(launch_resident(precision, probe, pl.K, pl.form, pl.wpg, pl.xd, nullptr, &n));
-        it = c.per_cu.emplace(key, n).first;
-    }
     if (c.cus == 0) {
         hipDeviceProp_t prop;
         HEAT_HIP(hipGetDeviceProperties(&prop, dev));
         c.cus = prop.multiProcessorCount;
     }
-    *capacity = it->second > 0 ? (int64_t)it->second * c.cus : 0;
+    int64_t cap[2] = {0, 0};
+    for (int edges = 0; edges < 2; ++edges) {
+        const uint64_t key = (uint64_t)precision | (uint64_t)pl.K << 4 | (uint64_t)pl.form << 12 |
+                             (uint64_t)pl.wpg << 16 | (uint64_t)pl.xd << 20 |
+                             (uint64_t)(pl.W + 2 * pl.H) << 24 | (uint64_t)pl.H << 44 |
+                             (uint64_t)edges << 60;
+        auto it = c.per_cu.find(key);
+        if (it == c.per_cu.end()) {
+            ResidentArgs probe{};
+            probe.W = pl.W;
+            probe.H = pl.H;
+            probe.lds_edges = edges;
+            int n = 0;
+            HEAT_HIP(launch_resident(precision, probe, pl.K, pl.form, pl.wpg, pl.xd, nullptr, &n));
+            it = c.per_cu.emplace(key, n).first;
+        }
+        cap[edges] = it->second > 0 ? (int64_t)it->second * c.cus : 0;
+    }
+    // the whole tile copy where the grid fits with it (its indexing is the
+    // cheaper), else the edge regions only
+    const bool edges = pl.tiles > cap[0];
+    *capacity = edges ? cap[1] : cap[0];
+    if (edges_only) *edges_only = edges;
     return HEAT_OK;
 }
 
@@ -357,11 +369,13 @@ static int run_resident(const Plan &pl, int precision, void *a, void *b, int64_t
     if (dev < 0 || dev >= 64) return fail(HEAT_EDEVICE, "device %d out of range", dev);
     ResidentCache &c = g_resident_cache[dev];
     int64_t capacity = 0;
-    int rc = resident_capacity(pl, precision, &capacity);
+    bool edges_only = false;
+    int rc = resident_capacity(pl, precision, &capacity, &edges_only);
     if (rc) return rc;
     ResidentArgs ra{};
     ra.W = pl.W;
     ra.H = pl.H;
+    ra.lds_edges = edges_only ? 1 : 0;
     if (pl.tiles > capacity)
         return fail(HEAT_EINVAL, "the resident kernel needs all %lld tiles resident at once; this "
                     "shape fits %lld on the device (fewer cells per tile: a longer window, or "

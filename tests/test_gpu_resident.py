@@ -260,3 +260,31 @@ def test_resident_wait_timeout_fails_cleanly(monkeypatch):
     for _ in range(2):
         got, _ = run_resident(u0, nt, 0.5, heat.FP64, **shape)
         assert same_bits(got, want)
+
+
+@pytest.mark.parametrize("prec,K,G,x,form,T,N,nt", [
+    # 1,277 tiles of 3,984 cells, the last of 10 (shorter than H): more than
+    # a CU holds with the whole tile copy in LDS
+    (heat.FP64, 16, 4, heat.EXCHANGE_LDS_DEEP, 3, 32, 1276 * 3984 + 10, 70),
+    # 1,130 tiles of 7,968 cells, 33 KB of LDS each with the whole copy
+    (heat.FP32, 32, 4, heat.EXCHANGE_LDS_DEEP, 1, 64, 9_000_037, 150),
+])
+def test_resident_edge_lds_layout_bitwise(prec, K, G, x, form, T, N, nt):
+    """Grids that fit only with the LDS copy of the tiles' two edge regions
+    (the split layout): whole rings bitwise against the oracle."""
+    p = plan_of(N, nt, prec, K, G, x, form, T)
+    # with the whole tile span W + 2H in LDS, after the waves' exchange area
+    # (160 KB per CU), they would not
+    S, cell = p["exchange_steps"], 8 if prec == heat.FP64 else 4
+    span = G * 64 * K - (G - 1) * 2 * S
+    per_cu = (160 * 1024) // (span * cell + 2 * G * 2 * S * cell)
+    assert p["tiles"] > per_cu * torch.cuda.get_device_properties(0).multi_processor_count
+    u0 = inputs.uniform_ring(N, (38, K))
+    if prec == heat.FP64:
+        want = oracle.solve_threads(u0, 16, 0.5, nt)
+    else:
+        u0 = u0.astype(np.float32)
+        want = oracle.solve_f32(u0, 0.5, nt)
+    got, _ = run_resident(u0, nt, 0.5, prec, cells_per_lane=K, waves_per_group=G, exchange=x,
+                          register_form=form, steps_per_round=T)
+    assert same_bits(got, want)
