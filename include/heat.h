@@ -409,7 +409,8 @@ int heat_autotune(int32_t precision, int64_t N, int32_t install, heat_config *be
  * to the point as heat_plan fits it, against the round kernel the planner
  * runs (the tuning table's shape); coefficients as heat_autotune, HEAT_FP32C
  * also at r = 1/4 (whose kernel drops the coefficient's low part), the
- * smaller gain counting; each time the fastest of three calls.  Each shape's
+ * smaller gain counting; each time the fastest of three calls that ask for
+ * the sums and so wait, as the calls that take the resident kernel do.  Each shape's
  * gain at each point over its load efficiency there is its gain at full
  * load; heat_plan's model (that gain interpolated, times the load efficiency
  * at N) then picks a shape at each of 64 ring lengths spread over the

@@ -665,16 +665,19 @@ int heat_autotune_resident(int32_t precision, int64_t N, int32_t install, heat_c
     const double r_list[2] = {comp ? 0.3 : 0.25, 0.25};
     const int nr = comp ? 2 : 1;
     // one untimed call (it also refuses a shape that cannot be resident),
-    // then the fastest of three timed ones
+    // then the fastest of three timed ones; every call asks for the sums and
+    // so waits for its result, as the calls the resident kernel is chosen
+    // for do (the round kernel then pays the same wait)
+    double s0 = 0.0, s1 = 0.0;
     auto time_run = [&](const heat_config &c, int64_t n, int64_t nt, double r,
                         double *ms_out) -> int {
-        int rc2 = heat_solve_dev_cfg(a, w, n, 1, r, nt, precision, &c, st, nullptr, nullptr);
+        int rc2 = heat_solve_dev_cfg(a, w, n, 1, r, nt, precision, &c, st, &s0, &s1);
         if (rc2) return rc2;
         double best_ms = 0.0;
         for (int rep = 0; rep < 3; ++rep) {
             hipError_t e2 = hipEventRecord(e0, st);
             if (e2 == hipSuccess)
-                rc2 = heat_solve_dev_cfg(a, w, n, 1, r, nt, precision, &c, st, nullptr, nullptr);
+                rc2 = heat_solve_dev_cfg(a, w, n, 1, r, nt, precision, &c, st, &s0, &s1);
             if (!rc2 && e2 == hipSuccess) e2 = hipEventRecord(e1, st);
             if (!rc2 && e2 == hipSuccess) e2 = hipEventSynchronize(e1);
             float ms = 0.f;
