@@ -268,7 +268,6 @@ __global__ void __launch_bounds__(512) k_resident(ResidentArgs a) {
         heat_xlds + (XCHG ? (exchange_lds_bytes<P>(K, G, XD) + 15) / 16 * 16 : 0));
     const int c0 = (int)off + lane * K;   // tile coordinate of this lane's first cell
     const int wl = (int)wlen;
-
     // lanes holding edge cells (tile coordinates [H, 2H), [wl, wl + H)) or
     // halo cells ([0, H), [wl + H, wl + 2H))
     const bool io_lane = runs_meet(c0, c0 + K, 0, 2 * H) || runs_meet(c0, c0 + K, wl, wl + 2 * H);
