@@ -168,7 +168,9 @@ int heat_solve_dev(void *d_u, int64_t N, int32_t nparts, double r, int64_t nt,
  * Device form that allocates nothing, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation).  As heat_solve_dev with the planner's
- * default shape, except:
+ * default shape (the round kernel: a call of heat_solve_dev that waits may
+ * take the resident kernel, same state bits, checksums equal up to the
+ * rounding of their partial sums), except:
  *   - its scratch (the ping-pong state buffer and the checksum partials) is
  *     one static device array of HEAT_NOALLOC_SCRATCH_BYTES per device, held
  *     from the library's first use on that device until the process ends;

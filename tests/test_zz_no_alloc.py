@@ -1,7 +1,12 @@
 """GPU check of heat_solve_dev_noalloc, the device form that allocates
 nothing (its scratch is a static device array of the library): its results
-and checksums equal those of heat_solve_dev bit for bit, on consecutive calls
-that reuse the same scratch, the second on a smaller ring."""
+equal those of heat_solve_dev bit for bit, on consecutive calls that reuse
+the same scratch, the second on a smaller ring; so do its checksums where
+both calls run the round kernel (a call of heat_solve_dev that waits may take
+the resident kernel, whose tiles group the partial sums differently: equal up
+to rounding then, and both within rounding of the exact sums)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -49,8 +54,17 @@ def test_noalloc_equals_device_form(case):
         torch.cuda.synchronize()
         assert np.array_equal(bits(a), bits(b)), (case, k)
         got = d_sums.cpu().numpy()
-        assert np.array_equal(got.view(np.uint64), np.array([s0, s1]).view(np.uint64)), \
-            (case, k, got, s0, s1)
+        if heat.plan(N, nt, prec)["kernel"] == heat.KERNEL_RESIDENT:
+            for x, y in zip(got, (s0, s1)):
+                assert abs(x - y) <= 1e-13 * abs(y), (case, k, got, s0, s1)
+        else:
+            assert np.array_equal(got.view(np.uint64), np.array([s0, s1]).view(np.uint64)), \
+                (case, k, got, s0, s1)
+        x0 = u0 if prec == heat.FP64 else u0.astype(np.float32)
+        exact0 = math.fsum(x0.astype(np.float64))
+        assert abs(got[0] - exact0) <= 1e-13 * abs(exact0), (case, k, got[0], exact0)
+        exact1 = math.fsum(b.cpu().numpy().astype(np.float64))
+        assert abs(got[1] - exact1) <= 1e-13 * abs(exact1), (case, k, got[1], exact1)
         if N * nt <= 5e8:
             if prec == heat.FP64:
                 want = oracle.solve(u0, r, nt)
