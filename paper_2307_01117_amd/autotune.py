@@ -4,8 +4,10 @@ Usage: python -m paper_2307_01117_amd.autotune [--out FILE] [--sizes 1e4,1e5,...
 
 For every precision and ring length it calls heat_autotune (which times each
 temporal-blocking shape with HIP events) and installs the winner for that
-decade, then heat_autotune_resident per quarter decade (the resident kernel
-against the round kernel just installed), then heat_autotune_batch for the
+decade, then heat_autotune_resident per quarter decade (every resident shape
+timed at the quarter decade's ends and middle against the round kernel just
+installed; up to six shapes recorded for the planner to choose from per
+call), then heat_autotune_batch for the
 batching form's kernel classes; the table is then written with
 heat_tune_save.  The binding loads
 tune_mi355x.txt next to the library at start-up unless HEAT_TUNE_TABLE names
@@ -32,8 +34,8 @@ def main():
                     help="ring lengths for the batching form's classes ('' skips them)")
     ap.add_argument("--resident-sizes",
                     default="1e5,1.78e5,3.17e5,5.63e5,1e6,1.78e6,3.17e6,5.63e6,1e7",
-                    help="ring lengths (one per quarter decade) at which the resident kernel is "
-                         "timed against the round kernel ('' skips it)")
+                    help="one ring length per quarter decade to tune the resident kernel for "
+                         "(timed at that quarter decade's ends and middle; '' skips it)")
     ap.add_argument("--no-plain", action="store_true",
                     help="tune the batching form's classes (and resident shapes) only")
     ap.add_argument("--no-verify", action="store_true",
