@@ -232,6 +232,11 @@ def test_planner_fits_the_tuned_shapes_to_n(tmp_path):
         assert checked == 11
         # short runs keep the round kernel
         assert heat.plan(2_000_000, 99, heat.FP32)["kernel"] == heat.KERNEL_TB
+        # the choice cached for a ring goes with the table it came from
+        assert heat.plan(2_000_000, 1000, heat.FP32)["kernel"] == heat.KERNEL_RESIDENT
+        f.write_text("r 1 25 0 0 0 0 0 0\n")
+        heat.tune_load(str(f))
+        assert heat.plan(2_000_000, 1000, heat.FP32)["kernel"] == heat.KERNEL_TB
     finally:
         heat.tune_load(str(saved))
 
