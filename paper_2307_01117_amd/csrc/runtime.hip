@@ -790,7 +790,7 @@ struct ResidentChoiceCache {
 };
 static thread_local ResidentChoiceCache g_choice;
 
-static int choose_resident(int64_t N, int64_t nt, int precision, Plan *pl);
+static void choose_resident(int64_t N, int64_t nt, int precision, Plan *pl);
 
 // The plan a call runs: make_plan's, except that a call that waits for its
 // result (`waits`) with an all-automatic configuration may take the resident
@@ -828,14 +828,15 @@ static int choose_plan(int64_t N, int64_t nt, int precision, const heat_config *
 }
 
 // choose_plan's resident step: *pl is replaced where a recorded shape wins.
-static int choose_resident(int64_t N, int64_t nt, int precision, Plan *pl) {
+static void choose_resident(int64_t N, int64_t nt, int precision, Plan *pl) {
     ResidentChoice ch[RESIDENT_SHAPES];
     const int n = tuned_resident(N, precision, ch);
     int cus = 0;
-    if (n == 0 || device_cus(&cus) != HEAT_OK || cus < 1) return HEAT_OK;
+    if (n == 0 || device_cus(&cus) != HEAT_OK || cus < 1) return;
     int64_t pts[RESIDENT_POINTS];
     resident_points(N, pts);
     double best_score = 0.0;
+    Plan best;
     for (int i = 0; i < n; ++i) {
         const double min_nt = resident_interp(ch[i].min_nt, pts, N);
         if (min_nt <= 0.0 || (double)nt < min_nt) continue;
@@ -848,10 +849,10 @@ static int choose_resident(int64_t N, int64_t nt, int precision, Plan *pl) {
                                  : RESIDENT_TUNE_MARGIN;
         if (score > best_score) {
             best_score = score;
-            if (score >= RESIDENT_TUNE_MARGIN) *pl = q;
+            best = q;
         }
     }
-    return HEAT_OK;
+    if (best_score >= RESIDENT_TUNE_MARGIN) *pl = best;
 }
 
 static int solve_dev_impl(void *d_u, void *d_work, int64_t N, int32_t nparts, double r, int64_t nt,
