@@ -293,3 +293,16 @@ def test_resident_edge_lds_layout_bitwise(prec, K, G, x, form, T, N, nt):
     got, _ = run_resident(u0, nt, 0.5, prec, cells_per_lane=K, waves_per_group=G, exchange=x,
                           register_form=form, steps_per_round=T)
     assert same_bits(got, want)
+
+
+def test_host_form_takes_the_resident_kernel():
+    """heat_solve (a host array; the call always waits) on a mid-size ring
+    takes the resident kernel as the planner picks it: bitwise against the
+    oracle, and the input untouched."""
+    N, nt, r = 2_000_003, 300, 0.5
+    assert heat.plan(N, nt, heat.FP64)["kernel"] == heat.KERNEL_RESIDENT
+    u0 = inputs.uniform_ring(N, 39)
+    keep = u0.copy()
+    got = heat.solve(u0, 4, r, nt)
+    assert same_bits(u0, keep)
+    assert same_bits(got, oracle.solve_threads(u0, 16, r, nt))
