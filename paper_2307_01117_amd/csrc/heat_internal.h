@@ -68,11 +68,10 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
 // is a pure function of (N, precision) -- never of timing or of a batch mix.
 int default_steps_per_round(int64_t N, int precision);
 int default_cells_per_lane(int64_t N, int precision);
-// Steps per round actually used by default for a run of nt steps (T for the
-// compensated form; a result-neutral even split near T otherwise).
-int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision);
-// The same split for a given target round length T (T itself for the
-// compensated form, whose round length is part of its result).
+// Steps per round used for a run of nt steps with target round length T: a
+// result-neutral even split near T for binary64 and plain binary32; T itself
+// (or nt, if shorter) for the compensated form, whose round length is part
+// of its result.
 int64_t balanced_steps_per_round(int64_t nt, int64_t T, int precision);
 // Halo depth H >= steps for a window of 64*K cells (line-aligned when possible).
 int halo_cells(int64_t steps, int precision, int K);

@@ -78,10 +78,6 @@ static int default_exchange(int64_t N, int precision) {
     return xchg;
 }
 
-int64_t planned_steps_per_round(int64_t N, int64_t nt, int precision) {
-    return balanced_steps_per_round(nt, default_steps_per_round(N, precision), precision);
-}
-
 int64_t balanced_steps_per_round(int64_t nt, int64_t T, int precision) {
     // a run shorter than one round is a single round of nt steps
     int64_t Teff = nt > 0 ? std::min<int64_t>(T, nt) : 1;
@@ -191,6 +187,11 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     if (T < 1) return fail(HEAT_EINVAL, "steps_per_round must be >= 1 (got %d)", T);
     if (c.steps_per_round && (T % 4) != 0)
         return fail(HEAT_EINVAL, "steps_per_round must be a multiple of 4 (got %d)", T);
+    if (!c.steps_per_round && 3 * ceil4(T) > 64 * (int64_t)q.K) {
+        // the tuned rounds are too deep for an overridden K: the deepest that
+        // fits (the compensated form's 64 fits every K)
+        T = (64 * q.K / 3) & ~3;
+    }
     // the window must keep W >= H so a tile only reads its two neighbours
     if (3 * ceil4(T) > 64 * (int64_t)q.K)
         return fail(HEAT_EINVAL, "steps_per_round %d too deep for %d cells per lane", T, q.K);
@@ -199,7 +200,7 @@ int make_plan(int64_t N, int64_t nt, int precision, const heat_config *cfg, Plan
     const int64_t Teff =
         c.steps_per_round || kernel == HEAT_KERNEL_RESIDENT
             ? (nt > 0 ? std::min<int64_t>(T, nt) : 1)
-            : planned_steps_per_round(N, nt, precision);
+            : balanced_steps_per_round(nt, T, precision);
     q.T = (int)Teff;
     q.H = halo_cells(Teff, precision, q.K);
     q.W = window_tile_cells(q.K, q.H, q.wpg, q.xd);

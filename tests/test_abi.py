@@ -90,6 +90,23 @@ def test_planner_geometry(lib):
     assert heat.plan(1000, 0, heat.FP32C)["rounds"] == 0
 
 
+def test_overridden_cells_per_lane_takes_rounds_that_fit(lib):
+    """A tuned round length too deep for a caller's cells_per_lane (e.g. the
+    binary64 1e8-cell rounds of 320 steps with 8-cell lanes) is cut to the
+    deepest that fits instead of failing; an explicit one is still checked."""
+    for prec in (heat.FP64, heat.FP32, heat.FP32C):
+        for N in (10**3, 10**5, 3 * 10**6, 10**8):
+            for K in (8, 16, 32, 64):
+                if K == 64 and prec == heat.FP32C:
+                    continue
+                p = heat.plan(N, 1000, prec, kernel=heat.KERNEL_TB, cells_per_lane=K)
+                T = p["steps_per_round"]
+                assert p["cells_per_lane"] == K and 3 * ((T + 3) // 4 * 4) <= 64 * K, (prec, N, K)
+                assert p["rounds"] * T >= 1000
+    with pytest.raises(heat.HeatError):
+        heat.plan(10**8, 1000, heat.FP64, cells_per_lane=8, steps_per_round=320)
+
+
 def test_compensated_round_length_is_fixed(lib):
     """The compensated form's round length T is part of its result; it must
     not depend on N or on the configuration of tiles."""
