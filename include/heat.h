@@ -115,7 +115,10 @@ typedef struct heat_config {
                                 step; binary32 needs no copies),
                                 2 = ping-pong (2K registers, no copies),
                                 3 = alternating forward/backward in-place sweeps
-                                (K + 1 registers, no copies)                   */
+                                (K + 1 registers, no copies).  HEAT_FP32C with
+                                a binary32 coefficient, 32 cells per lane and
+                                lone waves: 1 and 2 both run the ping-pong
+                                sweep (measured faster there; same bits)      */
     int32_t exchange;        /* TB: heat_exchange                               */
 } heat_config;
 

@@ -33,9 +33,48 @@ static hipError_t launch_window_comp(const WindowLaunch &a, hipStream_t st) {
     }
 }
 
+// The lighter kernel's 32-cell lone waves, in place or ping-pong, run the
+// ping-pong sweep held to 3 waves per SIMD.  Its state (u, e and their
+// second copies: 4 x 32 registers) takes 171 VGPRs unconstrained, so 2
+// waves per SIMD; with the cap 170 and 3 waves, and then it outruns the
+// in-place sweep (140 VGPRs, 3 waves) at every ring length and group size
+// measured on MI355X: 1e5 to 1e8 cells, 1 to 8 waves per group, +2.5 % to
+// +9.5 % (1e8 cells: 6,906 against 6,458 GCUP/s).  Under the cap the
+// compiler keeps one 64-bit per-lane value in scratch memory across the
+// step loop (8 bytes written and read once per lane and launch: 6 % over
+// the round's algorithmic HBM bytes, on a kernel bound by its arithmetic).
+// The general form's kernel (with the low-part term) ran slower under the
+// same cap and keeps its own.  The sweep order changes no bit of the result.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+k_window_c0_lone32(const float *__restrict__ src, float *__restrict__ dst, int64_t N, int32_t H,
+                   int32_t steps, double r, int64_t tiles, int64_t W, int32_t vec_ok,
+                   double *part_in, double *part_out) {
+    const int lane = threadIdx.x & 63;
+    const int wpg = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int64_t part = xcd_remap(blockIdx.x, gridDim.x) * wpg + wave;
+    if (part >= tiles) return;
+    window_tile<F32C0, 32, FORM_PINGPONG, 0>(src, dst, N, H, steps, r, part * W, W, vec_ok != 0,
+                                             lane, part_in, part_out, part, wpg, wave);
+}
+
+static hipError_t launch_window_c0_lone32(const WindowLaunch &a, hipStream_t st) {
+    const int64_t W = window_tile_cells(32, a.H, a.wpg, 0);
+    const int64_t tiles = (a.N + W - 1) / W;
+    const int64_t blocks = (tiles + a.wpg - 1) / a.wpg;
+    const int vec_ok = aligned16(a.src) && aligned16(a.dst);
+    hipLaunchKernelGGL(k_window_c0_lone32, dim3((unsigned)blocks), dim3(64 * a.wpg), 0, st,
+                       reinterpret_cast<const float *>(a.src), reinterpret_cast<float *>(a.dst), a.N,
+                       a.H, a.steps, a.r, tiles, W, vec_ok, a.part_in, a.part_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_window_fp32c(const WindowLaunch &a, hipStream_t st) {
     if (a.precision != HEAT_FP32C) return hipErrorInvalidValue;
-    return low_part_zero(a.r) ? launch_window_comp<F32C0>(a, st) : launch_window_comp<F32C>(a, st);
+    if (!low_part_zero(a.r)) return launch_window_comp<F32C>(a, st);
+    if (a.xd == 0 && a.K == 32 && (a.form == FORM_INPLACE || a.form == FORM_PINGPONG))
+        return launch_window_c0_lone32(a, st);
+    return launch_window_comp<F32C0>(a, st);
 }
 
 // The resident kernel in the in-place form, for both coefficient classes.
