@@ -197,6 +197,36 @@ def test_midsize_fp32c_bitwise(N):
             assert same_bits(got, want), (K, form, wpg, x, N, nt)
 
 
+@pytest.mark.parametrize("wpg", [1, 2, 4, 8])
+def test_fp32c_binary32_coefficient_lone32(wpg):
+    """The compensated form's binary32-coefficient kernel for 32-cell lone
+    waves (the ping-pong sweep held to 3 waves per SIMD, taken for register
+    forms 1 and 2): the oracle's bits over many tiles with a ragged tail, odd
+    step counts (the sweep's single-step tail), an array that is not 16-byte
+    aligned (the cell-by-cell path) and the fused checksums; and the same bits
+    as the alternating form, which runs the general kernel family."""
+    N = 200_003
+    u0 = inputs.perturbed_ring(N, (27, wpg)).astype(np.float32)
+    T = heat.plan(N, 10**6, heat.FP32C)["steps_per_round"]   # the form's fixed round length
+    for r in (0.25, 0.375, 0.125):
+        for nt in (7, 64, 129):
+            want = oracle.solve_f32c(u0, r, nt, T)
+            cfgs = [dict(cells_per_lane=32, waves_per_group=wpg, exchange=heat.EXCHANGE_NONE,
+                         register_form=f, steps_per_round=T) for f in (1, 2, 3)]
+            for cfg in cfgs:
+                got = run_dev(u0, nt, r, precision=heat.FP32C, **cfg)
+                assert same_bits(got, want), (cfg, r, nt)
+            # unaligned: one cell into a larger buffer
+            buf = torch.zeros(N + 1, dtype=torch.float32, device="cuda")
+            d = buf[1:]
+            d.copy_(torch.from_numpy(u0))
+            s0, s1 = heat.solve_dev(d, 1, r, nt, precision=heat.FP32C, sums=True, **cfgs[0])
+            assert same_bits(d.cpu().numpy(), want), ("unaligned", r, nt)
+            assert abs(s0 - math.fsum(u0.astype(np.float64))) <= 1e-12 * abs(s0)
+            assert abs(s1 - math.fsum(want.astype(np.float64))) <= 1e-12 * abs(s1)
+            del buf, d
+
+
 def test_signed_zeros_fp32_forms():
     """A state of +0 and -0 cells among small dyadic values: both binary32
     forms reach the oracle's bits, the signs of zeros included, on the
