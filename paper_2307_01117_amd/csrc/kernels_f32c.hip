@@ -36,7 +36,7 @@ static hipError_t launch_window_comp(const WindowLaunch &a, hipStream_t st) {
 // The lighter kernel's 32-cell lone waves, in place or ping-pong, run the
 // ping-pong sweep held to 3 waves per SIMD.  Its state (u, e and their
 // second copies: 4 x 32 registers) takes 171 VGPRs unconstrained, so 2
-// waves per SIMD; with the cap 170 and 3 waves, and then it outruns the
+// waves per SIMD; with the cap 168 and 3 waves, and then it outruns the
 // in-place sweep (140 VGPRs, 3 waves) at every ring length and group size
 // measured on MI355X: 1e5 to 1e8 cells, 1 to 8 waves per group, +2.5 % to
 // +9.5 % (1e8 cells: 6,906 against 6,458 GCUP/s).  Under the cap the
