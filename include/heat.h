@@ -129,7 +129,9 @@ typedef struct heat_plan_info {
     int32_t steps_per_round; /* T: steps per round (1 for STEP; RESIDENT: steps
                                 between edge exchanges)                        */
     int32_t waves_per_group;
-    int32_t register_form;   /* 1 in-place, 2 ping-pong, 3 alternating (TB)      */
+    int32_t register_form;   /* 1 in-place, 2 ping-pong, 3 alternating (TB; the
+                                form planned: heat_config names the one case
+                                whose kernel sweeps in another)                */
     int32_t exchange_steps;  /* S: steps between LDS edge exchanges of the
                                 waves of a tile (K/4 or K/2); 0 = one tile per
                                 wave (TB)                                      */
