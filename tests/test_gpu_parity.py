@@ -187,7 +187,8 @@ def test_midsize_fp32c_bitwise(N):
         T = heat.plan(N, nt, heat.FP32C)["steps_per_round"]
         want = oracle.solve_f32c(u0, r, nt, T)
         for K, form, wpg, x in ((8, 1, 0, 0), (16, 2, 0, 0), (32, 3, 0, 0), (64, 3, 0, 0),
-                                (64, 1, 0, 0), (16, 3, 2, heat.EXCHANGE_LDS),
+                                (64, 1, 0, 0), (32, 1, 4, heat.EXCHANGE_NONE),
+                                (32, 2, 1, heat.EXCHANGE_NONE), (16, 3, 2, heat.EXCHANGE_LDS),
                                 (32, 2, 4, heat.EXCHANGE_LDS), (32, 3, 8, heat.EXCHANGE_LDS),
                                 (64, 3, 4, heat.EXCHANGE_LDS), (8, 1, 8, heat.EXCHANGE_LDS_DEEP),
                                 (16, 3, 4, heat.EXCHANGE_LDS_DEEP),
