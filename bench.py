@@ -420,6 +420,13 @@ def run_plain(args, workload, prec_name, steps, warmup, cfg, host=True):
                                                   / (HBM_PEAK_GBS * 1e9 / (2 * es)), 2)}
     roof["kernel"] = {heat.KERNEL_STEP: "k_step",
                       heat.KERNEL_RESIDENT: "k_resident"}.get(pl["kernel"], "k_window")
+    # the library's one kernel of its own among the round kernels: the
+    # compensated form's binary32-coefficient sweep for 32-cell lone waves
+    # (register forms 1 and 2)
+    if (roof["kernel"] == "k_window" and prec_name == "fp32c" and cup_costs(prec_name, r)[1] == 8
+            and pl["cells_per_lane"] == 32 and not pl["exchange_steps"]
+            and pl["register_form"] in (1, 2)):
+        roof["kernel"] = "k_window_c0_lone32"
     roof["traffic"] = measured_traffic(roof["kernel"], workload, prec_name, pl)
     roof["avg_launch_ms"] = round(k_avg_ms, 4)
     roof["avg_launch_ms_kernel_only"] = round(k_alone_ms, 4)
